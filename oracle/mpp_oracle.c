@@ -1,0 +1,762 @@
+/*
+ * mpp_oracle.c -- plain, slow FP64 CPU oracle for the variable-density
+ * pressure-projection solve
+ *
+ *        div( (1/rho) grad p ) = f         on [0,1]^3, homogeneous Neumann walls,
+ *
+ * with a sharp ghost-fluid treatment of the density jump at a level-set interface
+ * and the surface-tension pressure jump [p] = sigma*kappa folded into the right-hand
+ * side.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the checker of the GPU path and nothing
+ * else: only the test-suite, the package's smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or helper with the GPU
+ * library, and the GPU library never links, loads or calls it.
+ *
+ * What the paper fixes (Flash-X, arXiv 2312.11740):
+ *   - Sec. 2 and the caption of Fig. 2: a staggered stencil with scalars (pressure,
+ *     density, the level set) at cell centres and vector quantities on faces; the
+ *     interface is the zero set of a signed distance phi, positive in air and
+ *     negative in liquid.
+ *   - Sec. 3 (IncompNS varDens, Multiphase, StencilsLevelSet, Grid_solvePoisson):
+ *     a fractional-step projection whose pressure equation has the variable
+ *     coefficient 1/rho set from the level set, solved by multigrid.
+ *   - Sec. 4, Fig. 13 (TOML parameters): unit domain, gas/liquid density ratio 1e-3.
+ * Everything else is a stated reading (not in the paper):
+ *   - face coefficient on a face crossed by the interface: the series-resistance
+ *     ghost-fluid coefficient of Liu, Fedkiw & Kang (J. Comput. Phys. 160, 2000);
+ *   - jump [p] = p(phi>0) - p(phi<=0) = sigma*kappa with kappa = -div(grad phi/|grad phi|),
+ *     as in the ghost-fluid multiphase method of Kang, Fedkiw & Liu (J. Sci. Comput. 15,
+ *     2000); this gives Young-Laplace p_in - p_out = 2 sigma / R for a sphere under
+ *     either orientation of phi;
+ *   - a cell with phi == 0 belongs to the phi <= 0 side.
+ *
+ * Conventions (shared with the GPU library only through this description):
+ *   n^3 cells, h = 1/n, cell (i,j,k) centre ((i+1/2)h, (j+1/2)h, (k+1/2)h),
+ *   linear index i + n*(j + n*k) (x fastest).  Face arrays hold the LOW face of each
+ *   cell: bx[i,j,k] is the coefficient between (i-1,j,k) and (i,j,k); bx[0,j,k] = 0
+ *   (wall).  High wall faces are implicit zeros.
+ *   (A x)_c = sum over the six faces of beta_f (x_nb - x_c) / h^2.
+ *
+ * Every routine here is a direct statement of its definition: no blocking, fusion or
+ * reordering beyond an OpenMP split over independent cells.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_ENOTCONVERGED (-4)
+#define ORC_EBREAKDOWN (-5)
+
+static size_t ix(int n, int i, int j, int k)
+{
+    return (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Level set, sides and the ghost-fluid face coefficient                     */
+/* ------------------------------------------------------------------------ */
+
+/* side "+" (gas in the paper's orientation) iff phi > 0; phi == 0 goes to "-". */
+static int is_plus(double phi) { return phi > 0.0; }
+
+/* Fraction of the segment from cell a to cell b that lies on a's side of the
+ * interface, from linear interpolation of phi between the two centres. */
+static double crossing_theta(double phi_a, double phi_b)
+{
+    return fabs(phi_a) / (fabs(phi_a) + fabs(phi_b));
+}
+
+/* Coefficient 1/rho of the face between centres a and b.  Same side: the phase
+ * value.  Crossing: resistances rho*length in series over the two pieces of the
+ * segment (Liu-Fedkiw-Kang), 1 / (theta*rho_a + (1-theta)*rho_b). */
+static double face_beta(double phi_a, double phi_b, double rho_neg, double rho_pos)
+{
+    double rho_a = is_plus(phi_a) ? rho_pos : rho_neg;
+    double rho_b = is_plus(phi_b) ? rho_pos : rho_neg;
+    if (is_plus(phi_a) == is_plus(phi_b))
+        return 1.0 / rho_a;
+    double theta = crossing_theta(phi_a, phi_b);
+    return 1.0 / (theta * rho_a + (1.0 - theta) * rho_b);
+}
+
+int orc_faces(int n, const double *phi, double rho_neg, double rho_pos, double *bx,
+              double *by, double *bz)
+{
+    if (n < 1 || !phi || !bx || !by || !bz)
+        return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t c = ix(n, i, j, k);
+                bx[c] = (i == 0) ? 0.0 : face_beta(phi[ix(n, i - 1, j, k)], phi[c], rho_neg, rho_pos);
+                by[c] = (j == 0) ? 0.0 : face_beta(phi[ix(n, i, j - 1, k)], phi[c], rho_neg, rho_pos);
+                bz[c] = (k == 0) ? 0.0 : face_beta(phi[ix(n, i, j, k - 1)], phi[c], rho_neg, rho_pos);
+            }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Curvature kappa = -div(grad phi / |grad phi|)                             */
+/* ------------------------------------------------------------------------ */
+
+/* phi with linear extrapolation beyond the walls: phi(-1) = 2 phi(0) - phi(1),
+ * phi(n) = 2 phi(n-1) - phi(n-2), applied axis by axis. */
+static double phi_ext(int n, const double *phi, int i, int j, int k)
+{
+    if (i < 0)
+        return 2.0 * phi_ext(n, phi, 0, j, k) - phi_ext(n, phi, 1, j, k);
+    if (i > n - 1)
+        return 2.0 * phi_ext(n, phi, n - 1, j, k) - phi_ext(n, phi, n - 2, j, k);
+    if (j < 0)
+        return 2.0 * phi_ext(n, phi, i, 0, k) - phi_ext(n, phi, i, 1, k);
+    if (j > n - 1)
+        return 2.0 * phi_ext(n, phi, i, n - 1, k) - phi_ext(n, phi, i, n - 2, k);
+    if (k < 0)
+        return 2.0 * phi_ext(n, phi, i, j, 0) - phi_ext(n, phi, i, j, 1);
+    if (k > n - 1)
+        return 2.0 * phi_ext(n, phi, i, j, n - 1) - phi_ext(n, phi, i, j, n - 2);
+    return phi[ix(n, i, j, k)];
+}
+
+/* Mean curvature of the level sets of phi at the centre of cell (i,j,k):
+ * second-order central differences for the gradient and the Hessian, then
+ *   kappa = -[ (pyy+pzz) px^2 + (pxx+pzz) py^2 + (pxx+pyy) pz^2
+ *              - 2 px py pxy - 2 px pz pxz - 2 py pz pyz ] / |grad phi|^3,
+ * and 0 where |grad phi| < 1e-12. */
+static double curvature_at(int n, const double *phi, int i, int j, int k)
+{
+    double h = 1.0 / n;
+#define P(a, b, c) phi_ext(n, phi, i + (a), j + (b), k + (c))
+    double p0 = P(0, 0, 0);
+    double px = (P(1, 0, 0) - P(-1, 0, 0)) / (2.0 * h);
+    double py = (P(0, 1, 0) - P(0, -1, 0)) / (2.0 * h);
+    double pz = (P(0, 0, 1) - P(0, 0, -1)) / (2.0 * h);
+    double pxx = (P(1, 0, 0) - 2.0 * p0 + P(-1, 0, 0)) / (h * h);
+    double pyy = (P(0, 1, 0) - 2.0 * p0 + P(0, -1, 0)) / (h * h);
+    double pzz = (P(0, 0, 1) - 2.0 * p0 + P(0, 0, -1)) / (h * h);
+    double pxy = (P(1, 1, 0) - P(1, -1, 0) - P(-1, 1, 0) + P(-1, -1, 0)) / (4.0 * h * h);
+    double pxz = (P(1, 0, 1) - P(1, 0, -1) - P(-1, 0, 1) + P(-1, 0, -1)) / (4.0 * h * h);
+    double pyz = (P(0, 1, 1) - P(0, 1, -1) - P(0, -1, 1) + P(0, -1, -1)) / (4.0 * h * h);
+#undef P
+    double g2 = px * px + py * py + pz * pz;
+    double g = sqrt(g2);
+    if (g < 1e-12)
+        return 0.0;
+    double num = (pyy + pzz) * px * px + (pxx + pzz) * py * py + (pxx + pyy) * pz * pz
+               - 2.0 * px * py * pxy - 2.0 * px * pz * pxz - 2.0 * py * pz * pyz;
+    return -num / (g2 * g);
+}
+
+/* A cell is interface-adjacent when one of its in-domain neighbours is on the
+ * other side. */
+static int interface_adjacent(int n, const double *phi, int i, int j, int k)
+{
+    int s = is_plus(phi[ix(n, i, j, k)]);
+    if (i > 0 && is_plus(phi[ix(n, i - 1, j, k)]) != s) return 1;
+    if (i < n - 1 && is_plus(phi[ix(n, i + 1, j, k)]) != s) return 1;
+    if (j > 0 && is_plus(phi[ix(n, i, j - 1, k)]) != s) return 1;
+    if (j < n - 1 && is_plus(phi[ix(n, i, j + 1, k)]) != s) return 1;
+    if (k > 0 && is_plus(phi[ix(n, i, j, k - 1)]) != s) return 1;
+    if (k < n - 1 && is_plus(phi[ix(n, i, j, k + 1)]) != s) return 1;
+    return 0;
+}
+
+/* kappa at every interface-adjacent cell, 0 elsewhere. */
+int orc_curvature(int n, const double *phi, double *kappa)
+{
+    if (n < 2 || !phi || !kappa)
+        return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i)
+                kappa[ix(n, i, j, k)] =
+                    interface_adjacent(n, phi, i, j, k) ? curvature_at(n, phi, i, j, k) : 0.0;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Jump term of the right-hand side                                          */
+/* ------------------------------------------------------------------------ */
+
+/* For every face crossed by the interface, between a (low) and b (high):
+ *   theta  = |phi_a| / (|phi_a| + |phi_b|)     (interface position measured from a)
+ *   J      = sigma * ((1-theta) kappa_a + theta kappa_b)   (kappa interpolated to it)
+ *   beta^  = the ghost-fluid face coefficient,
+ * and the face adds s * beta^ * J / h^2 to each of its two cells, s = +1 for the
+ * cell on the "-" side and -1 for the cell on the "+" side.  This moves the jump of
+ * [p] = p+ - p- = J out of the stencil: A p = f + jterm.
+ * kappa: per-cell curvature (orc_curvature's output, or any override field). */
+int orc_jump(int n, const double *phi, const double *kappa, double rho_neg, double rho_pos,
+             double sigma, double *jterm)
+{
+    if (n < 1 || !phi || !kappa || !jterm)
+        return ORC_EINVAL;
+    double inv_h2 = (double)n * (double)n;
+    memset(jterm, 0, sizeof(double) * (size_t)n * n * n);
+    for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    int ia = i - (d == 0), ja = j - (d == 1), ka = k - (d == 2);
+                    if (ia < 0 || ja < 0 || ka < 0)
+                        continue;
+                    size_t a = ix(n, ia, ja, ka), b = ix(n, i, j, k);
+                    if (is_plus(phi[a]) == is_plus(phi[b]))
+                        continue;
+                    double theta = crossing_theta(phi[a], phi[b]);
+                    double J = sigma * ((1.0 - theta) * kappa[a] + theta * kappa[b]);
+                    double bh = face_beta(phi[a], phi[b], rho_neg, rho_pos);
+                    double s_a = is_plus(phi[a]) ? -1.0 : 1.0;
+                    jterm[a] += s_a * bh * J * inv_h2;
+                    jterm[b] -= s_a * bh * J * inv_h2;
+                }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand side b = f + jterm, projected to zero mean                     */
+/* ------------------------------------------------------------------------ */
+
+/* Neumaier-compensated sum. */
+static double csum(const double *v, size_t m)
+{
+    double s = 0.0, c = 0.0;
+    for (size_t q = 0; q < m; ++q) {
+        double t = s + v[q];
+        if (fabs(s) >= fabs(v[q]))
+            c += (s - t) + v[q];
+        else
+            c += (v[q] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* b = f + jterm (jterm may be NULL), then b -= mean(b).  Returns the removed mean
+ * through *mean_out (the compatibility defect of the Neumann problem). */
+int orc_rhs(int n, const double *f, const double *jterm, double *b, double *mean_out)
+{
+    if (n < 1 || !f || !b)
+        return ORC_EINVAL;
+    size_t m = (size_t)n * n * n;
+    for (size_t q = 0; q < m; ++q)
+        b[q] = f[q] + (jterm ? jterm[q] : 0.0);
+    double mean = csum(b, m) / (double)m;
+    for (size_t q = 0; q < m; ++q)
+        b[q] -= mean;
+    if (mean_out)
+        *mean_out = mean;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The operator                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* y = A x,  (A x)_c = sum_faces beta_f (x_nb - x_c) / h^2, no flux through walls. */
+void orc_apply(int n, const double *bx, const double *by, const double *bz,
+               const double *x, double *y)
+{
+    double inv_h2 = (double)n * (double)n;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t c = ix(n, i, j, k);
+                double s = 0.0;
+                if (i > 0) s += bx[c] * (x[ix(n, i - 1, j, k)] - x[c]);
+                if (i < n - 1) s += bx[ix(n, i + 1, j, k)] * (x[ix(n, i + 1, j, k)] - x[c]);
+                if (j > 0) s += by[c] * (x[ix(n, i, j - 1, k)] - x[c]);
+                if (j < n - 1) s += by[ix(n, i, j + 1, k)] * (x[ix(n, i, j + 1, k)] - x[c]);
+                if (k > 0) s += bz[c] * (x[ix(n, i, j, k - 1)] - x[c]);
+                if (k < n - 1) s += bz[ix(n, i, j, k + 1)] * (x[ix(n, i, j, k + 1)] - x[c]);
+                y[c] = s * inv_h2;
+            }
+}
+
+static double dot(const double *a, const double *b, size_t m)
+{
+    long double s = 0.0L;
+    for (size_t q = 0; q < m; ++q)
+        s += (long double)a[q] * (long double)b[q];
+    return (double)s;
+}
+
+static double nrm2(const double *a, size_t m) { return sqrt(dot(a, a, m)); }
+
+static void remove_mean(double *v, size_t m)
+{
+    double mean = csum(v, m) / (double)m;
+    for (size_t q = 0; q < m; ++q)
+        v[q] -= mean;
+}
+
+/* ||b - A x||_2 / ||b||_2 (0 if b == 0). */
+double orc_rel_residual(int n, const double *bx, const double *by, const double *bz,
+                        const double *b, const double *x)
+{
+    size_t m = (size_t)n * n * n;
+    double *r = (double *)malloc(sizeof(double) * m);
+    if (!r)
+        return NAN;
+    orc_apply(n, bx, by, bz, x, r);
+    for (size_t q = 0; q < m; ++q)
+        r[q] = b[q] - r[q];
+    double bn = nrm2(b, m);
+    double rn = nrm2(r, m);
+    free(r);
+    return bn > 0.0 ? rn / bn : rn;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct solve on small grids: Cholesky of (-A + 11^T/m)                    */
+/* ------------------------------------------------------------------------ */
+
+/* Dense (-A + J/m) in row-major order, J the all-ones matrix; SPD because the
+ * constants (A's null space) get eigenvalue 1 and everything else is -A's. */
+static void dense_regularised(int n, const double *bx, const double *by, const double *bz,
+                              double *M)
+{
+    size_t m = (size_t)n * n * n;
+    double *e = (double *)calloc(m, sizeof(double));
+    double *col = (double *)malloc(sizeof(double) * m);
+    for (size_t c = 0; c < m; ++c) {
+        e[c] = 1.0;
+        orc_apply(n, bx, by, bz, e, col);
+        e[c] = 0.0;
+        for (size_t r = 0; r < m; ++r)
+            M[r * m + c] = -col[r] + 1.0 / (double)m;
+    }
+    free(e);
+    free(col);
+}
+
+/* In-place Cholesky M = L L^T (lower triangle).  Returns 0 or the failing pivot+1. */
+static size_t cholesky(double *M, size_t m)
+{
+    for (size_t j = 0; j < m; ++j) {
+        double d = M[j * m + j];
+        for (size_t q = 0; q < j; ++q)
+            d -= M[j * m + q] * M[j * m + q];
+        if (!(d > 0.0))
+            return j + 1;
+        double l = sqrt(d);
+        M[j * m + j] = l;
+        for (size_t r = j + 1; r < m; ++r) {
+            double s = M[r * m + j];
+            for (size_t q = 0; q < j; ++q)
+                s -= M[r * m + q] * M[j * m + q];
+            M[r * m + j] = s / l;
+        }
+    }
+    return 0;
+}
+
+static void cholesky_solve(const double *L, size_t m, double *v)
+{
+    for (size_t r = 0; r < m; ++r) {
+        double s = v[r];
+        for (size_t q = 0; q < r; ++q)
+            s -= L[r * m + q] * v[q];
+        v[r] = s / L[r * m + r];
+    }
+    for (size_t r = m; r-- > 0;) {
+        double s = v[r];
+        for (size_t q = r + 1; q < m; ++q)
+            s -= L[q * m + r] * v[q];
+        v[r] = s / L[r * m + r];
+    }
+}
+
+/* Unique zero-mean p with A p = b, for zero-mean b; n^3 <= 4096. */
+int orc_solve_dense(int n, const double *bx, const double *by, const double *bz,
+                    const double *b, double *p)
+{
+    if (n < 1 || n > 16)
+        return ORC_EINVAL;
+    size_t m = (size_t)n * n * n;
+    double *M = (double *)malloc(sizeof(double) * m * m);
+    if (!M)
+        return ORC_ENOMEM;
+    dense_regularised(n, bx, by, bz, M);
+    if (cholesky(M, m)) {
+        free(M);
+        return ORC_EBREAKDOWN;
+    }
+    for (size_t q = 0; q < m; ++q)
+        p[q] = -b[q];
+    cholesky_solve(M, m, p);
+    free(M);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometric multigrid V-cycle (the preconditioner's reference definition)   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Levels: n_0 = n; while n_l is even and n_l > 4, n_{l+1} = n_l / 2.  Level l has
+ * h_l = 1/n_l and face coefficients averaged from level l-1: a coarse face is the
+ * union of 2x2 fine faces on the same plane, and its coefficient is their mean.
+ * Restriction: mean of the 8 children.  Prolongation: each child gets its parent's
+ * value (piecewise constant).  Smoother: red-black Gauss-Seidel, red = (i+j+k) even,
+ *   x_c <- (sum_f beta_f x_nb - h^2 b_c) / sum_f beta_f.
+ * V(l, b): x = 0; nu times (red, black); r = b - A x; x += P V(l+1, R r);
+ *          nu times (black, red); return x.
+ * Coarsest level: x = (-A + 11^T/m)^{-1} (-b).
+ */
+
+typedef struct {
+    int n;
+    double *bx, *by, *bz;
+} orc_level;
+
+typedef struct {
+    int nlev, nu;
+    orc_level lev[16];
+    double *Lc; /* Cholesky factor of the coarsest regularised operator */
+    double *work[16][3];
+} orc_mg;
+
+static int level_count(int n)
+{
+    int L = 1;
+    while (n % 2 == 0 && n > 4 && L < 16) {
+        n /= 2;
+        ++L;
+    }
+    return L;
+}
+
+/* Coarse face coefficients from fine ones (mean of the 4 fine faces on the plane). */
+void orc_coarsen_faces(int nf, const double *fx, const double *fy, const double *fz,
+                       double *cx, double *cy, double *cz)
+{
+    int nc = nf / 2;
+    for (int K = 0; K < nc; ++K)
+        for (int J = 0; J < nc; ++J)
+            for (int I = 0; I < nc; ++I) {
+                size_t C = ix(nc, I, J, K);
+                double sx = 0.0, sy = 0.0, sz = 0.0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        sx += fx[ix(nf, 2 * I, 2 * J + a, 2 * K + b)];
+                        sy += fy[ix(nf, 2 * I + a, 2 * J, 2 * K + b)];
+                        sz += fz[ix(nf, 2 * I + a, 2 * J + b, 2 * K)];
+                    }
+                cx[C] = 0.25 * sx;
+                cy[C] = 0.25 * sy;
+                cz[C] = 0.25 * sz;
+            }
+}
+
+/* Update all cells of one colour (colour = (i+j+k) mod 2) in place. */
+void orc_gs_colour(int n, const double *bx, const double *by, const double *bz,
+                   const double *b, double *x, int colour)
+{
+    double h2 = 1.0 / ((double)n * (double)n);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                if (((i + j + k) & 1) != colour)
+                    continue;
+                size_t c = ix(n, i, j, k);
+                double num = 0.0, den = 0.0;
+                if (i > 0) { num += bx[c] * x[ix(n, i - 1, j, k)]; den += bx[c]; }
+                if (i < n - 1) { double w = bx[ix(n, i + 1, j, k)]; num += w * x[ix(n, i + 1, j, k)]; den += w; }
+                if (j > 0) { num += by[c] * x[ix(n, i, j - 1, k)]; den += by[c]; }
+                if (j < n - 1) { double w = by[ix(n, i, j + 1, k)]; num += w * x[ix(n, i, j + 1, k)]; den += w; }
+                if (k > 0) { num += bz[c] * x[ix(n, i, j, k - 1)]; den += bz[c]; }
+                if (k < n - 1) { double w = bz[ix(n, i, j, k + 1)]; num += w * x[ix(n, i, j, k + 1)]; den += w; }
+                x[c] = (num - h2 * b[c]) / den;
+            }
+}
+
+void orc_restrict(int nf, const double *rf, double *bc)
+{
+    int nc = nf / 2;
+    for (int K = 0; K < nc; ++K)
+        for (int J = 0; J < nc; ++J)
+            for (int I = 0; I < nc; ++I) {
+                double s = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a)
+                            s += rf[ix(nf, 2 * I + a, 2 * J + b, 2 * K + c)];
+                bc[ix(nc, I, J, K)] = 0.125 * s;
+            }
+}
+
+void orc_prolong_add(int nf, const double *ec, double *xf)
+{
+    int nc = nf / 2;
+    for (int k = 0; k < nf; ++k)
+        for (int j = 0; j < nf; ++j)
+            for (int i = 0; i < nf; ++i)
+                xf[ix(nf, i, j, k)] += ec[ix(nc, i / 2, j / 2, k / 2)];
+}
+
+void orc_mg_destroy(orc_mg *mg)
+{
+    if (!mg)
+        return;
+    for (int l = 1; l < mg->nlev; ++l) {
+        free(mg->lev[l].bx);
+        free(mg->lev[l].by);
+        free(mg->lev[l].bz);
+    }
+    for (int l = 0; l < mg->nlev; ++l)
+        for (int q = 0; q < 3; ++q)
+            free(mg->work[l][q]);
+    free(mg->Lc);
+    free(mg);
+}
+
+/* Builds the hierarchy.  Level 0 borrows the caller's face arrays. */
+orc_mg *orc_mg_create(int n, const double *bx, const double *by, const double *bz, int nu)
+{
+    if (n < 2 || nu < 1)
+        return NULL;
+    orc_mg *mg = (orc_mg *)calloc(1, sizeof(orc_mg));
+    mg->nlev = level_count(n);
+    mg->nu = nu;
+    mg->lev[0].n = n;
+    mg->lev[0].bx = (double *)bx;
+    mg->lev[0].by = (double *)by;
+    mg->lev[0].bz = (double *)bz;
+    for (int l = 1; l < mg->nlev; ++l) {
+        int nc = mg->lev[l - 1].n / 2;
+        size_t mc = (size_t)nc * nc * nc;
+        mg->lev[l].n = nc;
+        mg->lev[l].bx = (double *)malloc(sizeof(double) * mc);
+        mg->lev[l].by = (double *)malloc(sizeof(double) * mc);
+        mg->lev[l].bz = (double *)malloc(sizeof(double) * mc);
+        orc_coarsen_faces(mg->lev[l - 1].n, mg->lev[l - 1].bx, mg->lev[l - 1].by,
+                          mg->lev[l - 1].bz, mg->lev[l].bx, mg->lev[l].by, mg->lev[l].bz);
+    }
+    for (int l = 0; l < mg->nlev; ++l) {
+        size_t m = (size_t)mg->lev[l].n * mg->lev[l].n * mg->lev[l].n;
+        for (int q = 0; q < 3; ++q)
+            mg->work[l][q] = (double *)calloc(m, sizeof(double));
+    }
+    orc_level *c = &mg->lev[mg->nlev - 1];
+    size_t mc = (size_t)c->n * c->n * c->n;
+    if (mc > 4096) {
+        orc_mg_destroy(mg);
+        return NULL;
+    }
+    mg->Lc = (double *)malloc(sizeof(double) * mc * mc);
+    dense_regularised(c->n, c->bx, c->by, c->bz, mg->Lc);
+    if (cholesky(mg->Lc, mc)) {
+        orc_mg_destroy(mg);
+        return NULL;
+    }
+    return mg;
+}
+
+int orc_mg_levels(const orc_mg *mg) { return mg->nlev; }
+
+/* x = V(l, b) (x is overwritten). */
+static void vcycle(orc_mg *mg, int l, const double *b, double *x)
+{
+    orc_level *L = &mg->lev[l];
+    size_t m = (size_t)L->n * L->n * L->n;
+    if (l == mg->nlev - 1) {
+        for (size_t q = 0; q < m; ++q)
+            x[q] = -b[q];
+        cholesky_solve(mg->Lc, m, x);
+        return;
+    }
+    double *r = mg->work[l][0];
+    double *bc = mg->work[l + 1][1];
+    double *xc = mg->work[l + 1][2];
+    memset(x, 0, sizeof(double) * m);
+    for (int s = 0; s < mg->nu; ++s) {
+        orc_gs_colour(L->n, L->bx, L->by, L->bz, b, x, 0);
+        orc_gs_colour(L->n, L->bx, L->by, L->bz, b, x, 1);
+    }
+    orc_apply(L->n, L->bx, L->by, L->bz, x, r);
+    for (size_t q = 0; q < m; ++q)
+        r[q] = b[q] - r[q];
+    orc_restrict(L->n, r, bc);
+    vcycle(mg, l + 1, bc, xc);
+    orc_prolong_add(L->n, xc, x);
+    for (int s = 0; s < mg->nu; ++s) {
+        orc_gs_colour(L->n, L->bx, L->by, L->bz, b, x, 1);
+        orc_gs_colour(L->n, L->bx, L->by, L->bz, b, x, 0);
+    }
+}
+
+/* z = V(0, r): one V-cycle applied to a level-0 residual. */
+void orc_mg_vcycle(orc_mg *mg, const double *r, double *z) { vcycle(mg, 0, r, z); }
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioned conjugate gradients on -A                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * CG for the SPD (on zero-mean vectors) system (-A) x = -b; written with r = b - A x
+ * and q = A p the signs cancel: alpha = (r.z)/(p.q), r -= alpha q.  z is projected
+ * to zero mean.  Stops when ||r||_2 <= tol ||b||_2 for the recurrence residual, then
+ * recomputes the true residual and continues from it if that one is not below tol.
+ * x holds the initial guess on entry and the zero-mean solution on exit.
+ */
+typedef void (*precond_fn)(void *ctx, const double *r, double *z);
+
+typedef struct {
+    size_t m;
+    const double *diag;
+} jac_ctx;
+
+static void jac_apply(void *ctx, const double *r, double *z)
+{
+    jac_ctx *J = (jac_ctx *)ctx;
+    for (size_t q = 0; q < J->m; ++q)
+        z[q] = r[q] / J->diag[q];
+}
+
+static void mg_apply(void *ctx, const double *r, double *z) { orc_mg_vcycle((orc_mg *)ctx, r, z); }
+
+static int pcg(int n, const double *bx, const double *by, const double *bz, const double *b,
+               double *x, double tol, int max_iter, precond_fn M, void *ctx, int *iters_out,
+               double *relres_out)
+{
+    size_t m = (size_t)n * n * n;
+    double *r = (double *)malloc(sizeof(double) * m);
+    double *z = (double *)malloc(sizeof(double) * m);
+    double *p = (double *)malloc(sizeof(double) * m);
+    double *q = (double *)malloc(sizeof(double) * m);
+    if (!r || !z || !p || !q) {
+        free(r); free(z); free(p); free(q);
+        return ORC_ENOMEM;
+    }
+    double bn = nrm2(b, m);
+    int it = 0, status = ORC_ENOTCONVERGED;
+    double rel = 0.0, best = INFINITY;
+    int stall = 0;
+    if (bn == 0.0) {
+        memset(x, 0, sizeof(double) * m);
+        status = ORC_OK;
+        goto done;
+    }
+    for (;;) { /* restart loop: true residual */
+        orc_apply(n, bx, by, bz, x, r);
+        for (size_t c = 0; c < m; ++c)
+            r[c] = b[c] - r[c];
+        rel = nrm2(r, m) / bn;
+        if (rel <= tol) {
+            status = ORC_OK;
+            break;
+        }
+        if (it >= max_iter)
+            break;
+        if (rel < 0.5 * best) {
+            best = rel;
+            stall = 0;
+        } else if (++stall >= 3) { /* FP64 stagnation: report the level reached */
+            status = ORC_ENOTCONVERGED;
+            break;
+        }
+        M(ctx, r, z);
+        remove_mean(z, m);
+        memcpy(p, z, sizeof(double) * m);
+        double rz = dot(r, z, m);
+        while (it < max_iter) {
+            orc_apply(n, bx, by, bz, p, q);
+            double pq = dot(p, q, m);
+            if (!(pq < 0.0) || !(rz < 0.0)) { /* -A and M must stay positive */
+                status = ORC_EBREAKDOWN;
+                goto done;
+            }
+            double alpha = rz / pq;
+            for (size_t c = 0; c < m; ++c) {
+                x[c] += alpha * p[c];
+                r[c] -= alpha * q[c];
+            }
+            ++it;
+            if (nrm2(r, m) <= tol * bn)
+                break;
+            M(ctx, r, z);
+            remove_mean(z, m);
+            double rz_new = dot(r, z, m);
+            double beta = rz_new / rz;
+            rz = rz_new;
+            for (size_t c = 0; c < m; ++c)
+                p[c] = z[c] + beta * p[c];
+        }
+    }
+done:
+    remove_mean(x, m);
+    if (status != ORC_EBREAKDOWN)
+        rel = orc_rel_residual(n, bx, by, bz, b, x);
+    if (iters_out) *iters_out = it;
+    if (relres_out) *relres_out = rel;
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+int orc_solve_jacobi_pcg(int n, const double *bx, const double *by, const double *bz,
+                         const double *b, double *x, double tol, int max_iter, int *iters,
+                         double *relres)
+{
+    size_t m = (size_t)n * n * n;
+    double *diag = (double *)malloc(sizeof(double) * m);
+    double inv_h2 = (double)n * (double)n;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t c = ix(n, i, j, k);
+                double s = 0.0;
+                if (i > 0) s += bx[c];
+                if (i < n - 1) s += bx[ix(n, i + 1, j, k)];
+                if (j > 0) s += by[c];
+                if (j < n - 1) s += by[ix(n, i, j + 1, k)];
+                if (k > 0) s += bz[c];
+                if (k < n - 1) s += bz[ix(n, i, j, k + 1)];
+                diag[c] = -s * inv_h2;
+            }
+    jac_ctx J = {m, diag};
+    int st = pcg(n, bx, by, bz, b, x, tol, max_iter, jac_apply, &J, iters, relres);
+    free(diag);
+    return st;
+}
+
+int orc_solve_mg_pcg(int n, const double *bx, const double *by, const double *bz,
+                     const double *b, double *x, double tol, int max_iter, int nu, int *iters,
+                     double *relres)
+{
+    orc_mg *mg = orc_mg_create(n, bx, by, bz, nu);
+    if (!mg)
+        return ORC_EINVAL;
+    int st = pcg(n, bx, by, bz, b, x, tol, max_iter, mg_apply, mg, iters, relres);
+    orc_mg_destroy(mg);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole pipeline: phi, f -> faces, kappa, jterm, b, p                       */
+/* ------------------------------------------------------------------------ */
+/* kappa_override: NULL to compute kappa from phi, else a per-cell field used as is. */
+int orc_pipeline(int n, const double *phi, const double *f, double rho_neg, double rho_pos,
+                 double sigma, const double *kappa_override, double *bx, double *by,
+                 double *bz, double *kappa, double *jterm, double *b, double *mean_out)
+{
+    if (n < 2 || !(rho_neg > 0.0) || !(rho_pos > 0.0) || !(sigma >= 0.0) || !isfinite(rho_neg)
+        || !isfinite(rho_pos) || !isfinite(sigma))
+        return ORC_EINVAL;
+    int st = orc_faces(n, phi, rho_neg, rho_pos, bx, by, bz);
+    if (st) return st;
+    if (kappa_override)
+        memcpy(kappa, kappa_override, sizeof(double) * (size_t)n * n * n);
+    else if ((st = orc_curvature(n, phi, kappa)))
+        return st;
+    if ((st = orc_jump(n, phi, kappa, rho_neg, rho_pos, sigma, jterm)))
+        return st;
+    return orc_rhs(n, f, jterm, b, mean_out);
+}
