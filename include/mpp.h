@@ -1,0 +1,159 @@
+/*
+ * mpp.h -- C ABI of the MI355X (gfx950) multiphase pressure-projection solver.
+ *
+ * The library solves the variable-density pressure Poisson equation of a
+ * fractional-step projection method,
+ *
+ *        div( (1/rho) grad p ) = f        on [0,1]^3, homogeneous Neumann walls,
+ *
+ * on a cell-centred n^3 grid.  Flash-X (arXiv 2312.11740) frames this step: Sec. 2
+ * (staggered stencil: pressure, density and the level set at cell centres, vectors
+ * on faces; signed level set phi > 0 in air and < 0 in liquid), Sec. 3 (IncompNS
+ * varDens with density set from the level set by the Multiphase unit, and the
+ * multigrid Poisson solver behind Grid_solvePoisson).  The discrete operator is
+ *
+ *        (A p)_c = sum over the 6 faces f of c of beta_f (p_nb - p_c) / h^2,  h = 1/n,
+ *
+ * with beta_f = 1/rho of the phase when both cells lie on the same side of the
+ * interface, beta_f = 1/(theta rho_a + (1-theta) rho_b) on a face crossed by it
+ * (ghost-fluid coefficient of Liu, Fedkiw & Kang, theta = |phi_a|/(|phi_a|+|phi_b|)),
+ * and 0 through walls.  A cell with phi > 0 is on the "+" side (density rho_pos), a
+ * cell with phi <= 0 on the "-" side (rho_neg).
+ *
+ * The surface-tension jump [p] = p(+) - p(-) = sigma*kappa, kappa = -div(grad phi /
+ * |grad phi|) from central differences of phi, enters the right-hand side
+ * (ghost-fluid method of Kang, Fedkiw & Liu): b = f + jterm, then b -= mean(b).
+ * The solver returns the unique zero-mean p with A p = b to a relative residual
+ * ||b - A p||_2 <= rtol ||b||_2, by conjugate gradients on -A preconditioned with a
+ * geometric multigrid V-cycle.
+ *
+ * Memory and layout.  Every array argument is DEVICE memory on the current HIP
+ * device unless marked "host".  A grid field is n^3 doubles, x fastest: cell (i,j,k)
+ * at offset i + n*(j + n*k).  Batched calls take [batch][n^3] contiguous fields.
+ * The caller owns every array and the workspace; the library never allocates
+ * device memory.  All work is enqueued on `stream` (a hipStream_t, NULL = default
+ * stream); calls return after the results are complete on the stream, except where
+ * stated.  One operator may be used by one call at a time: concurrent calls on the
+ * same operator race on its workspace.
+ *
+ * Errors.  Every call returns MPP_OK or a negative status; no exception crosses the
+ * ABI.  Invalid sizes, null pointers and non-positive or non-finite densities give
+ * MPP_EINVAL before any device work; HIP failures give MPP_EDEVICE.
+ */
+#ifndef MPP_H
+#define MPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPP_OK 0
+#define MPP_EINVAL (-1)         /* invalid argument (size, pointer, density, sigma) */
+#define MPP_ENOMEM (-2)         /* workspace too small */
+#define MPP_EDEVICE (-3)        /* a HIP runtime call failed */
+#define MPP_ENOTCONVERGED (-4)  /* max_iter reached; p holds the last iterate */
+#define MPP_EBREAKDOWN (-5)     /* CG breakdown (non-positive curvature or NaN) */
+
+/* solve modes */
+#define MPP_MODE_FP64 0   /* FP64 throughout */
+#define MPP_MODE_MIXED 1  /* FP64 residual refinement around an FP32 MG-PCG */
+
+/* initial guess */
+#define MPP_GUESS_ZERO 0
+#define MPP_GUESS_GIVEN 1 /* p holds the initial guess on entry */
+
+typedef struct mpp_op_s *mpp_op;
+
+/* Problem shape.  n: cells per side, 2 <= n <= 1024, with n = m * 2^k for some
+ * m <= 10 (the multigrid coarsens while the size is even and above 4; the coarsest
+ * level, at most 10^3 cells, is solved directly).  batch: independent problems of
+ * the same n solved together (>= 1). */
+typedef struct {
+    int32_t n;
+    int32_t batch;
+    uint32_t flags; /* reserved, 0 */
+} mpp_desc;
+
+typedef struct {
+    double rtol;          /* relative residual target, e.g. 1e-10 */
+    int32_t max_iter;     /* CG iterations (all inner iterations in mixed mode) */
+    int32_t mode;         /* MPP_MODE_FP64 or MPP_MODE_MIXED */
+    int32_t guess;        /* MPP_GUESS_ZERO or MPP_GUESS_GIVEN */
+    int32_t nu;           /* pre- and post-smoothing red-black sweeps per level, >= 1 */
+    int32_t check_every;  /* iterations between host polls of convergence, >= 1 */
+    double inner_rtol;    /* mixed mode: inner FP32 solve target (e.g. 1e-5) */
+} mpp_solve_opts;
+
+typedef struct {
+    int32_t status;       /* MPP_OK, MPP_ENOTCONVERGED or MPP_EBREAKDOWN */
+    int32_t iters;        /* CG iterations (sum of inner iterations in mixed mode) */
+    int32_t outer_iters;  /* FP64 refinement steps (mixed mode), else restarts + 1 */
+    int32_t reserved;
+    double rel_resid;     /* final true ||b - A p|| / ||b|| in FP64 */
+    double removed_mean;  /* mean of f + jterm projected out of the right-hand side */
+    double bnorm;         /* ||b||_2 after the projection */
+} mpp_solve_info;
+
+/* Default options: rtol 1e-10, max_iter 500, FP64, zero guess, nu 2, check_every 2,
+ * inner_rtol 1e-5. */
+void mpp_default_opts(mpp_solve_opts *opts);
+
+/* Bytes of device workspace an operator of this shape needs (0 if desc is invalid). */
+size_t mpp_workspace_bytes(const mpp_desc *desc);
+
+/* Build the operator for level set phi (device, [batch][n^3]) and per-problem
+ * densities and surface tension (host arrays of `batch` doubles: rho_neg > 0 for
+ * phi <= 0, rho_pos > 0 for phi > 0, sigma >= 0; all finite).  Computes the face
+ * coefficients, the interface curvature, the jump term and the multigrid hierarchy
+ * (coarse coefficients as means of the fine ones, a dense factor of the coarsest
+ * level) inside `workspace` (device, mpp_workspace_bytes(desc) bytes, 256-byte
+ * aligned, owned by the caller and kept alive until mpp_destroy_operator).  On
+ * success *out receives a handle (host memory owned by the library).  phi is read
+ * during the call only.  The operator is immutable afterwards. */
+int mpp_build_operator(const mpp_desc *desc, const double *phi, const double *rho_neg,
+                       const double *rho_pos, const double *sigma, void *workspace,
+                       size_t workspace_bytes, void *stream, mpp_op *out);
+
+/* y = A x for every problem (device, [batch][n^3]); no jump term.  x and y must not
+ * overlap. */
+int mpp_apply_stencil(mpp_op op, const double *x, double *y, void *stream);
+
+/* Solve A p = f + jterm (mean-projected) for every problem.  f, p: device
+ * [batch][n^3]; p is the initial guess on entry when opts->guess == MPP_GUESS_GIVEN
+ * and the zero-mean solution on exit.  info: host array of `batch` records, filled
+ * on every return that got past argument checks (also MPP_ENOTCONVERGED, where p
+ * holds the last iterate).  Returns the worst status over the batch. */
+int mpp_solve(mpp_op op, const double *f, double *p, const mpp_solve_opts *opts,
+              mpp_solve_info *info, void *stream);
+
+/* The right-hand side the solver uses: b = f + jterm, minus its mean (device
+ * [batch][n^3]).  mean_out: host [batch], may be NULL. */
+int mpp_rhs(mpp_op op, const double *f, double *b, double *mean_out, void *stream);
+
+/* One multigrid V-cycle as a preconditioner: z ~= A^{-1} r with zero initial guess,
+ * nu red-black sweeps before and black-red sweeps after the coarse correction on
+ * every level; FP64.  r, z: device [batch][n^3]. */
+int mpp_vcycle(mpp_op op, const double *r, double *z, int nu, void *stream);
+
+/* Copies of the operator's data for inspection (device destinations, [batch][n^3]
+ * each; any pointer may be NULL): face coefficients of the finest level (low face of
+ * each cell, 0 on walls), curvature (0 away from the interface) and jump term. */
+int mpp_operator_fields(mpp_op op, double *beta_x, double *beta_y, double *beta_z,
+                        double *kappa, double *jterm, void *stream);
+
+/* Number of multigrid levels and the size of each (host array of up to 16). */
+int mpp_levels(mpp_op op, int32_t *nlevels, int32_t *sizes);
+
+/* Releases the handle (not the caller's workspace). */
+void mpp_destroy_operator(mpp_op op);
+
+const char *mpp_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPP_H */

@@ -1,0 +1,262 @@
+"""MI355X (gfx950) multiphase pressure-projection solver.
+
+Python binding of libmpp.so (include/mpp.h).  This layer only marshals arguments:
+PyTorch supplies device memory (the operator workspace and every field) and the HIP
+stream; every step of the computation runs in the library's HIP kernels.  There is
+no CPU fallback: if the library is missing or no GPU is visible, calls raise.
+
+Fields are float64 CUDA tensors of shape (n, n, n) or (batch, n, n, n), contiguous,
+indexed [k, j, i] (x fastest), cell centres at ((i+1/2)/n, (j+1/2)/n, (k+1/2)/n).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpp.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONVERGED, EBREAKDOWN = 0, -1, -2, -3, -4, -5
+MODE_FP64, MODE_MIXED = 0, 1
+GUESS_ZERO, GUESS_GIVEN = 0, 1
+
+EXPORTS = (
+    "mpp_default_opts", "mpp_workspace_bytes", "mpp_build_operator", "mpp_apply_stencil",
+    "mpp_solve", "mpp_rhs", "mpp_vcycle", "mpp_operator_fields", "mpp_levels",
+    "mpp_destroy_operator", "mpp_strerror",
+)
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("batch", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("guess", ctypes.c_int32), ("nu", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("outer_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("removed_mean", ctypes.c_double),
+                ("bnorm", ctypes.c_double)]
+
+
+class MppError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, strerror(status), status))
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libmpp.so and declares its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libmpp.so is not built: run `python -m paper_2312_11740_amd.build` "
+                           "(hipcc --offload-arch=gfx950)")
+    L = ctypes.CDLL(path)
+    P, i32, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.mpp_default_opts.argtypes = [ctypes.POINTER(SolveOpts)]
+    L.mpp_default_opts.restype = None
+    L.mpp_workspace_bytes.argtypes = [ctypes.POINTER(Desc)]
+    L.mpp_workspace_bytes.restype = ctypes.c_size_t
+    L.mpp_build_operator.argtypes = [ctypes.POINTER(Desc), P, P, P, P, P, ctypes.c_size_t, P,
+                                     ctypes.POINTER(P)]
+    L.mpp_apply_stencil.argtypes = [P, P, P, P]
+    L.mpp_solve.argtypes = [P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P]
+    L.mpp_rhs.argtypes = [P, P, P, P, P]
+    L.mpp_vcycle.argtypes = [P, P, P, i32, P]
+    L.mpp_operator_fields.argtypes = [P, P, P, P, P, P, P]
+    L.mpp_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.mpp_destroy_operator.argtypes = [P]
+    L.mpp_destroy_operator.restype = None
+    L.mpp_strerror.argtypes = [i32]
+    L.mpp_strerror.restype = ctypes.c_char_p
+    for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
+                                                 "mpp_strerror", "mpp_workspace_bytes")):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    try:
+        return load_library().mpp_strerror(int(status)).decode()
+    except RuntimeError:
+        return "status %d" % status
+
+
+def workspace_bytes(n: int, batch: int = 1) -> int:
+    d = Desc(n, batch, 0)
+    return int(load_library().mpp_workspace_bytes(ctypes.byref(d)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_field(t, shape, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % what)
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % what)
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError("%s must be contiguous with shape %s, got %s" % (what, tuple(shape),
+                                                                          tuple(t.shape)))
+
+
+@dataclass
+class Info:
+    status: int
+    iters: int
+    outer_iters: int
+    rel_resid: float
+    removed_mean: float
+    bnorm: float
+
+
+class Operator:
+    """A built operator: ghost-fluid faces, curvature, jump term, multigrid hierarchy.
+
+    phi: (n,n,n) or (B,n,n,n) float64 CUDA tensor; rho_neg, rho_pos, sigma: scalars or
+    length-B sequences (density where phi <= 0, where phi > 0, surface tension)."""
+
+    def __init__(self, phi, rho_neg, rho_pos, sigma):
+        torch = _torch()
+        L = load_library()
+        self.batched = phi.dim() == 4
+        if phi.dim() not in (3, 4):
+            raise ValueError("phi must be (n,n,n) or (B,n,n,n)")
+        B = phi.shape[0] if self.batched else 1
+        n = phi.shape[-1]
+        self.n, self.batch = int(n), int(B)
+        self.shape = tuple(phi.shape)
+        _check_field(phi, self.shape, "phi")
+        self.device = phi.device
+
+        def arr(v):
+            vals = list(v) if hasattr(v, "__len__") else [v] * B
+            if len(vals) != B:
+                raise ValueError("need %d values" % B)
+            return (ctypes.c_double * B)(*[float(x) for x in vals])
+
+        self._rn, self._rp, self._sg = arr(rho_neg), arr(rho_pos), arr(sigma)
+        self._desc = Desc(self.n, self.batch, 0)
+        nbytes = int(L.mpp_workspace_bytes(ctypes.byref(self._desc)))
+        if nbytes == 0:
+            raise MppError(EINVAL, "unsupported shape n=%d batch=%d" % (n, B))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        st = L.mpp_build_operator(ctypes.byref(self._desc), ctypes.c_void_p(phi.data_ptr()),
+                                  self._rn, self._rp, self._sg,
+                                  ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  _stream_handle(self.device), ctypes.byref(h))
+        if st != OK:
+            raise MppError(st, "mpp_build_operator")
+        self._h = h
+
+    # -- calls --------------------------------------------------------------------
+    def _new(self):
+        return _torch().empty(self.shape, dtype=_torch().float64, device=self.device)
+
+    def apply(self, x, out=None):
+        _check_field(x, self.shape, "x")
+        y = self._new() if out is None else out
+        _check_field(y, self.shape, "out")
+        st = load_library().mpp_apply_stencil(self._h, ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(y.data_ptr()),
+                                              _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_apply_stencil")
+        return y
+
+    def rhs(self, f):
+        _check_field(f, self.shape, "f")
+        b = self._new()
+        means = (ctypes.c_double * self.batch)()
+        st = load_library().mpp_rhs(self._h, ctypes.c_void_p(f.data_ptr()),
+                                    ctypes.c_void_p(b.data_ptr()), means,
+                                    _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_rhs")
+        return b, list(means)
+
+    def vcycle(self, r, nu=2):
+        _check_field(r, self.shape, "r")
+        z = self._new()
+        st = load_library().mpp_vcycle(self._h, ctypes.c_void_p(r.data_ptr()),
+                                       ctypes.c_void_p(z.data_ptr()), int(nu),
+                                       _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_vcycle")
+        return z
+
+    def fields(self):
+        out = {k: self._new() for k in ("beta_x", "beta_y", "beta_z", "kappa", "jterm")}
+        st = load_library().mpp_operator_fields(
+            self._h, *[ctypes.c_void_p(out[k].data_ptr())
+                       for k in ("beta_x", "beta_y", "beta_z", "kappa", "jterm")],
+            _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_operator_fields")
+        return out
+
+    def levels(self):
+        nl = ctypes.c_int32(0)
+        sizes = (ctypes.c_int32 * 16)()
+        st = load_library().mpp_levels(self._h, ctypes.byref(nl), sizes)
+        if st != OK:
+            raise MppError(st, "mpp_levels")
+        return [sizes[i] for i in range(nl.value)]
+
+    def solve(self, f, p=None, rtol=1e-10, mode="fp64", max_iter=500, nu=2, check_every=2,
+              inner_rtol=1e-5, raise_on_error=True):
+        """Returns (p, [Info per problem]).  p: optional initial guess (overwritten)."""
+        _check_field(f, self.shape, "f")
+        opts = SolveOpts()
+        load_library().mpp_default_opts(ctypes.byref(opts))
+        opts.rtol, opts.max_iter, opts.nu = float(rtol), int(max_iter), int(nu)
+        opts.check_every, opts.inner_rtol = int(check_every), float(inner_rtol)
+        opts.mode = {"fp64": MODE_FP64, "mixed": MODE_MIXED}[mode]
+        if p is None:
+            p = self._new()
+            opts.guess = GUESS_ZERO
+        else:
+            _check_field(p, self.shape, "p")
+            opts.guess = GUESS_GIVEN
+        infos = (SolveInfo * self.batch)()
+        st = load_library().mpp_solve(self._h, ctypes.c_void_p(f.data_ptr()),
+                                      ctypes.c_void_p(p.data_ptr()), ctypes.byref(opts), infos,
+                                      _stream_handle(self.device))
+        out = [Info(q.status, q.iters, q.outer_iters, q.rel_resid, q.removed_mean, q.bnorm)
+               for q in infos]
+        if st != OK and raise_on_error:
+            raise MppError(st, "mpp_solve")
+        return p, out
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            load_library().mpp_destroy_operator(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,710 @@
+// Device kernels of the gfx950 pressure-projection library: operator build,
+// stencil sweeps, grid transfers, coarsest solve and the CG vector updates with
+// deterministic reductions.
+//
+// Layout: a problem's field is n^3 values, x fastest; batched fields are
+// [B][n^3].  Cell kernels run on a (blocks-per-problem, B) grid of kBlock threads,
+// each thread striding over the cells of its problem, so every block belongs to
+// exactly one problem and reductions stay per problem.
+#pragma once
+
+#include "mpp_internal.h"
+
+namespace mpp {
+
+// ------------------------------------------------------------------------------
+// reductions: wave shuffles, one partial per block, last block finishes in a fixed
+// order (no floating-point atomics: bitwise reproducible)
+// ------------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; ++q) s += sh[q];
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ inline double load_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide per-problem sum.  Returns true in thread 0 of the last block of the
+// problem, with the total in *total.
+__device__ inline bool grid_sum(double v, const Ctl& ctl, int b, double* total) {
+  __shared__ double sh[16];
+  __shared__ int last;
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = s;
+    __threadfence();
+    const unsigned prev = atomicAdd(&ctl.counters[b], 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double t = 0.0;
+  for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x)
+    t += load_agent(&ctl.partials[(size_t)b * ctl.pstride + q]);
+  const double tot = block_sum(t, sh);
+  if (threadIdx.x == 0) {
+    ctl.counters[b] = 0;
+    *total = tot;
+    return true;
+  }
+  return false;
+}
+
+// What the last block does with a finished sum.
+enum Epi {
+  E_STORE_MEAN = 0,  // scal[slot] = total / cells
+  E_MEAN,            // scal[S_MEAN] = total / cells
+  E_BB,              // scal[S_BB] = total, scal[S_TOL2] = rtol^2 total
+  E_START,           // scal[S_RR] = total; active = total > tol2 && status OK
+  E_START_REL,       // as E_START with tol2 = rtol^2 total (a solve relative to this rhs)
+  E_RZ,              // beta = total / rz (0 on the first iteration), rz = total
+  E_PQ,              // alpha = rz / total; breakdown check
+  E_RR_ITER,         // rr = total; ++iters; active = rr > tol2 && iters < max
+};
+
+struct EpiArgs {
+  int kind;
+  int slot;
+  double rtol2;
+  double inv_cells;
+  int first;
+  const int* gate;   // E_START_REL: problems whose gate is 0 stay inactive
+};
+
+__device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& e) {
+  double* s = ctl.scal + (size_t)b * kSlots;
+  switch (e.kind) {
+    case E_STORE_MEAN: s[e.slot] = tot * e.inv_cells; break;
+    case E_MEAN: s[S_MEAN] = tot * e.inv_cells; break;
+    case E_BB:
+      s[S_BB] = tot;
+      s[S_TOL2] = e.rtol2 * tot;
+      break;
+    case E_START_REL:
+      s[S_BB] = tot;
+      s[S_TOL2] = e.rtol2 * tot;
+      [[fallthrough]];
+    case E_START:
+      s[S_RR] = tot;
+      ctl.active[b] = (tot > s[S_TOL2] && ctl.status[b] == MPP_OK) ? 1 : 0;
+      if (e.gate && !e.gate[b]) ctl.active[b] = 0;
+      if (!(tot == tot)) { ctl.active[b] = 0; ctl.status[b] = MPP_EBREAKDOWN; }
+      break;
+    case E_RZ: {
+      const double rz_old = s[S_RZ];
+      s[S_BETA] = e.first ? 0.0 : tot / rz_old;
+      s[S_RZ] = tot;
+      // A is negative semidefinite and the V-cycle approximates its inverse, so
+      // r.z < 0 for r != 0; anything else is a breakdown of the preconditioner
+      if (!(tot < 0.0)) { ctl.active[b] = 0; ctl.status[b] = MPP_EBREAKDOWN; }
+      break;
+    }
+    case E_PQ:
+      s[S_PQ] = tot;
+      s[S_ALPHA] = s[S_RZ] / tot;
+      if (!(tot < 0.0)) { ctl.active[b] = 0; ctl.status[b] = MPP_EBREAKDOWN; }
+      break;
+    case E_RR_ITER: {
+      s[S_RR] = tot;
+      const int it = ctl.iters[b] + 1;
+      ctl.iters[b] = it;
+      if (!(tot == tot)) { ctl.active[b] = 0; ctl.status[b] = MPP_EBREAKDOWN; }
+      else if (tot <= s[S_TOL2]) ctl.active[b] = 0;
+      else if (it >= ctl.max_iter) { ctl.active[b] = 0; ctl.status[b] = MPP_ENOTCONVERGED; }
+      break;
+    }
+  }
+}
+
+__device__ inline void reduce_and_finish(double v, const Ctl& ctl, int b, const EpiArgs& e) {
+  double tot;
+  if (grid_sum(v, ctl, b, &tot)) finish(ctl, b, tot, e);
+}
+
+// ------------------------------------------------------------------------------
+// cell indexing and faces
+// ------------------------------------------------------------------------------
+__device__ inline void ijk(int c, int n, int& i, int& j, int& k) {
+  i = c % n;
+  const int t = c / n;
+  j = t % n;
+  k = t / n;
+}
+
+// Coefficients of the six faces -x,+x,-y,+y,-z,+z of cell c (0 through walls).
+template <typename T>
+__device__ inline void cell_faces(const Faces<T>& F, int b, size_t base, int c, int i, int j,
+                                  int k, int n, T w[6]) {
+  const size_t nn = (size_t)n * n;
+  if (F.code) {
+    const unsigned cd = F.code[base + c];
+    const T ir = F.inv_rho[2 * b + ((cd >> 6) & 1u)];
+    w[0] = i > 0 ? ((cd & 1u) ? F.bx[base + c] : ir) : T(0);
+    w[1] = i < n - 1 ? ((cd & 2u) ? F.bx[base + c + 1] : ir) : T(0);
+    w[2] = j > 0 ? ((cd & 4u) ? F.by[base + c] : ir) : T(0);
+    w[3] = j < n - 1 ? ((cd & 8u) ? F.by[base + c + n] : ir) : T(0);
+    w[4] = k > 0 ? ((cd & 16u) ? F.bz[base + c] : ir) : T(0);
+    w[5] = k < n - 1 ? ((cd & 32u) ? F.bz[base + c + nn] : ir) : T(0);
+  } else {
+    w[0] = i > 0 ? F.bx[base + c] : T(0);
+    w[1] = i < n - 1 ? F.bx[base + c + 1] : T(0);
+    w[2] = j > 0 ? F.by[base + c] : T(0);
+    w[3] = j < n - 1 ? F.by[base + c + n] : T(0);
+    w[4] = k > 0 ? F.bz[base + c] : T(0);
+    w[5] = k < n - 1 ? F.bz[base + c + nn] : T(0);
+  }
+}
+
+// (A x)_c = sum_f w_f (x_nb - x_c) / h^2
+template <typename T>
+__device__ inline T stencil_at(const T w[6], const T* x, size_t base, int c, int i, int j, int k,
+                               int n, T inv_h2) {
+  const size_t nn = (size_t)n * n;
+  const T xc = x[base + c];
+  T s = T(0);
+  if (i > 0) s += w[0] * (x[base + c - 1] - xc);
+  if (i < n - 1) s += w[1] * (x[base + c + 1] - xc);
+  if (j > 0) s += w[2] * (x[base + c - n] - xc);
+  if (j < n - 1) s += w[3] * (x[base + c + n] - xc);
+  if (k > 0) s += w[4] * (x[base + c - nn] - xc);
+  if (k < n - 1) s += w[5] * (x[base + c + nn] - xc);
+  return s * inv_h2;
+}
+
+#define CELL_LOOP(cells)                                                     \
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < (int)(cells);      \
+       c += gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------------------------
+// operator build (FP64, no contraction so that the coefficients are the exactly
+// rounded values of their defining expressions)
+// ------------------------------------------------------------------------------
+__device__ inline bool plus_side(double phi) { return phi > 0.0; }
+
+__device__ inline double ghost_fluid_beta(double pa, double pb, double rn, double rp) {
+#pragma clang fp contract(off)
+  const double ra = plus_side(pa) ? rp : rn;
+  const double rb = plus_side(pb) ? rp : rn;
+  if (plus_side(pa) == plus_side(pb)) return 1.0 / ra;
+  const double theta = fabs(pa) / (fabs(pa) + fabs(pb));
+  return 1.0 / (theta * ra + (1.0 - theta) * rb);
+}
+
+__global__ void k_params(const double* rho, double* ir64, float* ir32, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double a = 1.0 / rho[3 * b + 0], c = 1.0 / rho[3 * b + 1];
+  ir64[2 * b + 0] = a;
+  ir64[2 * b + 1] = c;
+  ir32[2 * b + 0] = (float)a;
+  ir32[2 * b + 1] = (float)c;
+}
+
+// Face coefficients (low face of each cell), FP32 copies and the finest-level code.
+__global__ void k_faces(const double* __restrict__ phi, const double* __restrict__ rho, int n,
+                        int cells, uint8_t* __restrict__ code, double* __restrict__ bx,
+                        double* __restrict__ by, double* __restrict__ bz, float* __restrict__ fx,
+                        float* __restrict__ fy, float* __restrict__ fz, int* __restrict__ bad) {
+  const int b = blockIdx.y;
+  const size_t base = (size_t)b * cells;
+  const double rn = rho[3 * b + 0], rp = rho[3 * b + 1];
+  const size_t nn = (size_t)n * n;
+  CELL_LOOP(cells) {
+    int i, j, k;
+    ijk(c, n, i, j, k);
+    const double pc = phi[base + c];
+    if (!isfinite(pc)) atomicOr(bad, 1);
+    const bool s = plus_side(pc);
+    const double vx = i > 0 ? ghost_fluid_beta(phi[base + c - 1], pc, rn, rp) : 0.0;
+    const double vy = j > 0 ? ghost_fluid_beta(phi[base + c - n], pc, rn, rp) : 0.0;
+    const double vz = k > 0 ? ghost_fluid_beta(phi[base + c - nn], pc, rn, rp) : 0.0;
+    bx[base + c] = vx;
+    by[base + c] = vy;
+    bz[base + c] = vz;
+    fx[base + c] = (float)vx;
+    fy[base + c] = (float)vy;
+    fz[base + c] = (float)vz;
+    unsigned cd = s ? 64u : 0u;
+    if (i > 0 && plus_side(phi[base + c - 1]) != s) cd |= 1u;
+    if (i < n - 1 && plus_side(phi[base + c + 1]) != s) cd |= 2u;
+    if (j > 0 && plus_side(phi[base + c - n]) != s) cd |= 4u;
+    if (j < n - 1 && plus_side(phi[base + c + n]) != s) cd |= 8u;
+    if (k > 0 && plus_side(phi[base + c - nn]) != s) cd |= 16u;
+    if (k < n - 1 && plus_side(phi[base + c + nn]) != s) cd |= 32u;
+    code[base + c] = (uint8_t)cd;
+  }
+}
+
+// phi with linear extrapolation beyond the walls, axis by axis (x, then y, then z).
+__device__ inline double phi_ld(const double* phi, size_t base, int n, int i, int j, int k) {
+  return phi[base + (size_t)i + (size_t)n * ((size_t)j + (size_t)n * (size_t)k)];
+}
+__device__ inline double phi_ez(const double* phi, size_t base, int n, int i, int j, int k) {
+  if (k < 0) return 2.0 * phi_ld(phi, base, n, i, j, 0) - phi_ld(phi, base, n, i, j, 1);
+  if (k > n - 1) return 2.0 * phi_ld(phi, base, n, i, j, n - 1) - phi_ld(phi, base, n, i, j, n - 2);
+  return phi_ld(phi, base, n, i, j, k);
+}
+__device__ inline double phi_ey(const double* phi, size_t base, int n, int i, int j, int k) {
+  if (j < 0) return 2.0 * phi_ez(phi, base, n, i, 0, k) - phi_ez(phi, base, n, i, 1, k);
+  if (j > n - 1) return 2.0 * phi_ez(phi, base, n, i, n - 1, k) - phi_ez(phi, base, n, i, n - 2, k);
+  return phi_ez(phi, base, n, i, j, k);
+}
+__device__ inline double phi_ex(const double* phi, size_t base, int n, int i, int j, int k) {
+  if (i < 0) return 2.0 * phi_ey(phi, base, n, 0, j, k) - phi_ey(phi, base, n, 1, j, k);
+  if (i > n - 1) return 2.0 * phi_ey(phi, base, n, n - 1, j, k) - phi_ey(phi, base, n, n - 2, j, k);
+  return phi_ey(phi, base, n, i, j, k);
+}
+
+// Mean curvature -div(grad phi/|grad phi|) from central differences at interface
+// cells (cells with a crossed face), 0 elsewhere.
+__global__ void k_curvature(const double* __restrict__ phi, const uint8_t* __restrict__ code,
+                            int n, int cells, double* __restrict__ kappa) {
+#pragma clang fp contract(off)
+  const int b = blockIdx.y;
+  const size_t base = (size_t)b * cells;
+  const double h = 1.0 / n;
+  CELL_LOOP(cells) {
+    if ((code[base + c] & 63u) == 0) {
+      kappa[base + c] = 0.0;
+      continue;
+    }
+    int i, j, k;
+    ijk(c, n, i, j, k);
+#define P(a, bb, cc) phi_ex(phi, base, n, i + (a), j + (bb), k + (cc))
+    const double p0 = P(0, 0, 0);
+    const double px = (P(1, 0, 0) - P(-1, 0, 0)) / (2.0 * h);
+    const double py = (P(0, 1, 0) - P(0, -1, 0)) / (2.0 * h);
+    const double pz = (P(0, 0, 1) - P(0, 0, -1)) / (2.0 * h);
+    const double pxx = (P(1, 0, 0) - 2.0 * p0 + P(-1, 0, 0)) / (h * h);
+    const double pyy = (P(0, 1, 0) - 2.0 * p0 + P(0, -1, 0)) / (h * h);
+    const double pzz = (P(0, 0, 1) - 2.0 * p0 + P(0, 0, -1)) / (h * h);
+    const double pxy = (P(1, 1, 0) - P(1, -1, 0) - P(-1, 1, 0) + P(-1, -1, 0)) / (4.0 * h * h);
+    const double pxz = (P(1, 0, 1) - P(1, 0, -1) - P(-1, 0, 1) + P(-1, 0, -1)) / (4.0 * h * h);
+    const double pyz = (P(0, 1, 1) - P(0, 1, -1) - P(0, -1, 1) + P(0, -1, -1)) / (4.0 * h * h);
+#undef P
+    const double g2 = px * px + py * py + pz * pz;
+    const double g = sqrt(g2);
+    double kap = 0.0;
+    if (!(g < 1e-12)) {
+      const double num = (pyy + pzz) * px * px + (pxx + pzz) * py * py + (pxx + pyy) * pz * pz -
+                         2.0 * px * py * pxy - 2.0 * px * pz * pxz - 2.0 * py * pz * pyz;
+      kap = -num / (g2 * g);
+    }
+    kappa[base + c] = kap;
+  }
+}
+
+// One crossed face between a (low) and b (high): the term s_a beta^ J / h^2 that
+// the face adds to cell a (and subtracts from cell b).
+__device__ inline double jump_face_term(double pa, double pb, double ka, double kb, double rn,
+                                        double rp, double sigma, double inv_h2) {
+#pragma clang fp contract(off)
+  const double theta = fabs(pa) / (fabs(pa) + fabs(pb));
+  const double J = sigma * ((1.0 - theta) * ka + theta * kb);
+  const double bh = ghost_fluid_beta(pa, pb, rn, rp);
+  const double s_a = plus_side(pa) ? -1.0 : 1.0;
+  return s_a * bh * J * inv_h2;
+}
+
+// jterm_c = sum over the crossed faces of c of the face term (+ for the low cell,
+// - for the high cell), in the order -x, +x, -y, +y, -z, +z.
+__global__ void k_jump(const double* __restrict__ phi, const uint8_t* __restrict__ code,
+                       const double* __restrict__ kappa, const double* __restrict__ rho, int n,
+                       int cells, double* __restrict__ jterm) {
+#pragma clang fp contract(off)
+  const int b = blockIdx.y;
+  const size_t base = (size_t)b * cells;
+  const double rn = rho[3 * b + 0], rp = rho[3 * b + 1], sg = rho[3 * b + 2];
+  const double inv_h2 = (double)n * (double)n;
+  const size_t nn = (size_t)n * n;
+  CELL_LOOP(cells) {
+    const unsigned cd = code[base + c];
+    double acc = 0.0;
+    if (cd & 63u) {
+      const size_t cc = base + c;
+      const double pc = phi[cc], kc = kappa[cc];
+      const size_t off[3] = {1, (size_t)n, nn};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (cd & (1u << (2 * d))) {
+          const size_t a = cc - off[d];
+          acc -= jump_face_term(phi[a], pc, kappa[a], kc, rn, rp, sg, inv_h2);
+        }
+        if (cd & (2u << (2 * d))) {
+          const size_t bq = cc + off[d];
+          acc += jump_face_term(pc, phi[bq], kc, kappa[bq], rn, rp, sg, inv_h2);
+        }
+      }
+    }
+    jterm[base + c] = acc;
+  }
+}
+
+// Coarse face = mean of the 2x2 fine faces on the same plane (FP64 and FP32 copy).
+__global__ void k_coarsen_faces(const double* __restrict__ fx, const double* __restrict__ fy,
+                                const double* __restrict__ fz, int nf, double* __restrict__ cx,
+                                double* __restrict__ cy, double* __restrict__ cz,
+                                float* __restrict__ gx, float* __restrict__ gy,
+                                float* __restrict__ gz) {
+#pragma clang fp contract(off)
+  const int b = blockIdx.y;
+  const int nc = nf / 2;
+  const int cells_c = nc * nc * nc;
+  const size_t bf = (size_t)b * nf * nf * nf, bc = (size_t)b * cells_c;
+  CELL_LOOP(cells_c) {
+    int I, J, K;
+    ijk(c, nc, I, J, K);
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int e = 0; e < 2; ++e) {
+        sx += fx[bf + (size_t)(2 * I) + (size_t)nf * ((size_t)(2 * J + a) + (size_t)nf * (2 * K + e))];
+        sy += fy[bf + (size_t)(2 * I + a) + (size_t)nf * ((size_t)(2 * J) + (size_t)nf * (2 * K + e))];
+        sz += fz[bf + (size_t)(2 * I + a) + (size_t)nf * ((size_t)(2 * J + e) + (size_t)nf * (2 * K))];
+      }
+    const double vx = 0.25 * sx, vy = 0.25 * sy, vz = 0.25 * sz;
+    cx[bc + c] = vx;
+    cy[bc + c] = vy;
+    cz[bc + c] = vz;
+    gx[bc + c] = (float)vx;
+    gy[bc + c] = (float)vy;
+    gz[bc + c] = (float)vz;
+  }
+}
+
+// Coarsest level: dense M = -A + 11^T/m, Cholesky M = L L^T, then M^{-1} column by
+// column.  One block per problem; work is [B][m][m] scratch.
+__global__ void k_coarse_factor(const double* __restrict__ cx, const double* __restrict__ cy,
+                                const double* __restrict__ cz, int n, double* __restrict__ work,
+                                double* __restrict__ inv) {
+  const int b = blockIdx.x;
+  const int m = n * n * n;
+  const size_t bm = (size_t)b * m * m, bc = (size_t)b * m;
+  double* M = work + bm;
+  double* X = inv + bm;
+  const double inv_h2 = (double)n * (double)n, jm = 1.0 / m;
+  for (size_t q = threadIdx.x; q < (size_t)m * m; q += blockDim.x) M[q] = jm;
+  __syncthreads();
+  for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    int i, j, k;
+    ijk(c, n, i, j, k);
+    const bool in[6] = {i > 0, i < n - 1, j > 0, j < n - 1, k > 0, k < n - 1};
+    const int nb[6] = {c - 1, c + 1, c - n, c + n, c - n * n, c + n * n};
+    const int fc[6] = {c, c + 1, c, c + n, c, c + n * n};
+    const double* arr[6] = {cx, cx, cy, cy, cz, cz};
+    double d = 0.0;
+    for (int f = 0; f < 6; ++f)
+      if (in[f]) {
+        const double w = arr[f][bc + fc[f]];
+        M[(size_t)c * m + nb[f]] -= w * inv_h2;
+        d += w;
+      }
+    M[(size_t)c * m + c] += d * inv_h2;
+  }
+  __syncthreads();
+  // left-looking Cholesky, lower triangle of M
+  __shared__ double piv;
+  for (int j = 0; j < m; ++j) {
+    if (threadIdx.x == 0) {
+      double d = M[(size_t)j * m + j];
+      for (int q = 0; q < j; ++q) d -= M[(size_t)j * m + q] * M[(size_t)j * m + q];
+      piv = sqrt(d);
+      M[(size_t)j * m + j] = piv;
+    }
+    __syncthreads();
+    for (int r = j + 1 + threadIdx.x; r < m; r += blockDim.x) {
+      double s = M[(size_t)r * m + j];
+      for (int q = 0; q < j; ++q) s -= M[(size_t)r * m + q] * M[(size_t)j * m + q];
+      M[(size_t)r * m + j] = s / piv;
+    }
+    __syncthreads();
+  }
+  // columns of the inverse: L y = e_col, L^T x = y
+  for (int col = threadIdx.x; col < m; col += blockDim.x) {
+    double* x = X + (size_t)col * m;
+    for (int r = 0; r < m; ++r) {
+      double s = (r == col) ? 1.0 : 0.0;
+      for (int q = 0; q < r; ++q) s -= M[(size_t)r * m + q] * x[q];
+      x[r] = s / M[(size_t)r * m + r];
+    }
+    for (int r = m - 1; r >= 0; --r) {
+      double s = x[r];
+      for (int q = r + 1; q < m; ++q) s -= M[(size_t)q * m + r] * x[q];
+      x[r] = s / M[(size_t)r * m + r];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------
+// right-hand side
+// ------------------------------------------------------------------------------
+__global__ void k_rhs_sum(const double* __restrict__ f, const double* __restrict__ jterm,
+                          double* __restrict__ b, int cells, Ctl ctl, EpiArgs e) {
+  const int pb = blockIdx.y;
+  const size_t base = (size_t)pb * cells;
+  double acc = 0.0;
+  CELL_LOOP(cells) {
+    const double v = f[base + c] + jterm[base + c];
+    b[base + c] = v;
+    acc += v;
+  }
+  reduce_and_finish(acc, ctl, pb, e);
+}
+
+// v -= scal[S_MEAN]; optional sum of squares into an epilogue
+__global__ void k_sub_mean_sq(double* __restrict__ v, int cells, Ctl ctl, EpiArgs e, int slot,
+                              int want_sq) {
+  const int pb = blockIdx.y;
+  const size_t base = (size_t)pb * cells;
+  const double mean = ctl.scal[(size_t)pb * kSlots + slot];
+  double acc = 0.0;
+  CELL_LOOP(cells) {
+    const double x = v[base + c] - mean;
+    v[base + c] = x;
+    acc += x * x;
+  }
+  if (want_sq) reduce_and_finish(acc, ctl, pb, e);
+}
+
+template <typename T>
+__global__ void k_sum(const T* __restrict__ v, int cells, Ctl ctl, EpiArgs e) {
+  const int pb = blockIdx.y;
+  const size_t base = (size_t)pb * cells;
+  double acc = 0.0;
+  CELL_LOOP(cells) acc += (double)v[base + c];
+  reduce_and_finish(acc, ctl, pb, e);
+}
+
+// ------------------------------------------------------------------------------
+// stencil kernels
+// ------------------------------------------------------------------------------
+template <typename T, bool DOT>
+__global__ void k_apply(Faces<T> F, int n, int cells, const T* __restrict__ x, T* __restrict__ y,
+                        Ctl ctl, EpiArgs e, const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const size_t base = (size_t)b * cells;
+  const T inv_h2 = (T)((double)n * (double)n);
+  double acc = 0.0;
+  CELL_LOOP(cells) {
+    int i, j, k;
+    ijk(c, n, i, j, k);
+    T w[6];
+    cell_faces(F, b, base, c, i, j, k, n, w);
+    const T yc = stencil_at(w, x, base, c, i, j, k, n, inv_h2);
+    y[base + c] = yc;
+    if (DOT) acc += (double)x[base + c] * (double)yc;
+  }
+  if (DOT) reduce_and_finish(acc, ctl, b, e);
+}
+
+// r = rhs - A x, with ||r||^2 into the epilogue; xzero: treat x as 0 (r = rhs)
+template <typename T>
+__global__ void k_residual(Faces<T> F, int n, int cells, const T* __restrict__ rhs,
+                           const T* __restrict__ x, T* __restrict__ r, Ctl ctl, EpiArgs e,
+                           int xzero) {
+  const int b = blockIdx.y;
+  const size_t base = (size_t)b * cells;
+  const T inv_h2 = (T)((double)n * (double)n);
+  double acc = 0.0;
+  CELL_LOOP(cells) {
+    T rc;
+    if (xzero) {
+      rc = rhs[base + c];
+    } else {
+      int i, j, k;
+      ijk(c, n, i, j, k);
+      T w[6];
+      cell_faces(F, b, base, c, i, j, k, n, w);
+      rc = rhs[base + c] - stencil_at(w, x, base, c, i, j, k, n, inv_h2);
+    }
+    r[base + c] = rc;
+    acc += (double)rc * (double)rc;
+  }
+  reduce_and_finish(acc, ctl, b, e);
+}
+
+// Red-black Gauss-Seidel update of one colour, in place:
+//   x_c <- (sum_f w_f x_nb - h^2 b_c) / sum_f w_f,   colour = (i+j+k) mod 2.
+// from_zero: x is taken as 0 on entry; cells of the other colour are set to 0.
+template <typename T>
+__global__ void k_smooth(Faces<T> F, int n, int cells, const T* __restrict__ rhs,
+                         T* __restrict__ x, int colour, int from_zero,
+                         const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const size_t base = (size_t)b * cells;
+  const size_t nn = (size_t)n * n;
+  const T h2 = (T)(1.0 / ((double)n * (double)n));
+  CELL_LOOP(cells) {
+    int i, j, k;
+    ijk(c, n, i, j, k);
+    if (((i + j + k) & 1) != colour) {
+      if (from_zero) x[base + c] = T(0);
+      continue;
+    }
+    T w[6];
+    cell_faces(F, b, base, c, i, j, k, n, w);
+    T num = T(0), den = T(0);
+    if (!from_zero) {
+      if (i > 0) num += w[0] * x[base + c - 1];
+      if (i < n - 1) num += w[1] * x[base + c + 1];
+      if (j > 0) num += w[2] * x[base + c - n];
+      if (j < n - 1) num += w[3] * x[base + c + n];
+      if (k > 0) num += w[4] * x[base + c - nn];
+      if (k < n - 1) num += w[5] * x[base + c + nn];
+    }
+    den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
+    x[base + c] = (num - h2 * rhs[base + c]) / den;
+  }
+}
+
+// Coarse right-hand side: mean over the 8 children of the fine residual b - A x.
+template <typename T>
+__global__ void k_resid_restrict(Faces<T> F, int nf, const T* __restrict__ bf,
+                                 const T* __restrict__ xf, T* __restrict__ bcv,
+                                 const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int nc = nf / 2;
+  const int cells_c = nc * nc * nc;
+  const int cells_f = nf * nf * nf;
+  const size_t base = (size_t)b * cells_f, basec = (size_t)b * cells_c;
+  const T inv_h2 = (T)((double)nf * (double)nf);
+  CELL_LOOP(cells_c) {
+    int I, J, K;
+    ijk(c, nc, I, J, K);
+    T s = T(0);
+    for (int e = 0; e < 2; ++e)
+      for (int d = 0; d < 2; ++d)
+        for (int a = 0; a < 2; ++a) {
+          const int i = 2 * I + a, j = 2 * J + d, k = 2 * K + e;
+          const int cf = i + nf * (j + nf * k);
+          T w[6];
+          cell_faces(F, b, base, cf, i, j, k, nf, w);
+          s += bf[base + cf] - stencil_at(w, xf, base, cf, i, j, k, nf, inv_h2);
+        }
+    bcv[basec + c] = s * T(0.125);
+  }
+}
+
+// x_f += x_c[parent]
+template <typename T>
+__global__ void k_prolong_add(int nf, const T* __restrict__ xc, T* __restrict__ xf,
+                              const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int nc = nf / 2;
+  const int cells_f = nf * nf * nf;
+  const size_t base = (size_t)b * cells_f, basec = (size_t)b * nc * nc * nc;
+  CELL_LOOP(cells_f) {
+    int i, j, k;
+    ijk(c, nf, i, j, k);
+    xf[base + c] += xc[basec + (i >> 1) + nc * ((j >> 1) + nc * (k >> 1))];
+  }
+}
+
+// Coarsest level: x = M^{-1} (-b) with the FP64 inverse; one block per problem.
+template <typename T>
+__global__ void k_coarse_solve(const double* __restrict__ inv, int m, const T* __restrict__ bcv,
+                               T* __restrict__ x, const int* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  __shared__ double sb[kMaxCoarse];
+  for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)bcv[(size_t)b * m + q];
+  __syncthreads();
+  const double* Mi = inv + (size_t)b * m * m;
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < m; ++q) s += Mi[(size_t)q * m + r] * sb[q];
+    x[(size_t)b * m + r] = (T)s;
+  }
+}
+
+// ------------------------------------------------------------------------------
+// CG vector updates
+// ------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_dot(const T* __restrict__ a, const T* __restrict__ bv, int cells, Ctl ctl,
+                      EpiArgs e, const int* __restrict__ active) {
+  const int pb = blockIdx.y;
+  if (active && !active[pb]) return;
+  const size_t base = (size_t)pb * cells;
+  double acc = 0.0;
+  CELL_LOOP(cells) acc += (double)a[base + c] * (double)bv[base + c];
+  reduce_and_finish(acc, ctl, pb, e);
+}
+
+// p = z + beta p   (first: p = z)
+template <typename T>
+__global__ void k_update_p(const T* __restrict__ z, T* __restrict__ p, int cells, Ctl ctl,
+                           int first) {
+  const int pb = blockIdx.y;
+  if (!ctl.active[pb]) return;
+  const size_t base = (size_t)pb * cells;
+  const T beta = (T)ctl.scal[(size_t)pb * kSlots + S_BETA];
+  CELL_LOOP(cells) p[base + c] = first ? z[base + c] : z[base + c] + beta * p[base + c];
+}
+
+// x += alpha p, r -= alpha q, ||r||^2 into the iteration epilogue
+template <typename T>
+__global__ void k_update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                            const T* __restrict__ q, int cells, Ctl ctl, EpiArgs e) {
+  const int pb = blockIdx.y;
+  if (!ctl.active[pb]) return;
+  const size_t base = (size_t)pb * cells;
+  const T alpha = (T)ctl.scal[(size_t)pb * kSlots + S_ALPHA];
+  double acc = 0.0;
+  CELL_LOOP(cells) {
+    x[base + c] += alpha * p[base + c];
+    const T rc = r[base + c] - alpha * q[base + c];
+    r[base + c] = rc;
+    acc += (double)rc * (double)rc;
+  }
+  reduce_and_finish(acc, ctl, pb, e);
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ v, int cells, T val) {
+  const size_t base = (size_t)blockIdx.y * cells;
+  CELL_LOOP(cells) v[base + c] = val;
+}
+
+// mixed mode: r32 = r64 / ||r64|| (scale from the outer control block)
+__global__ void k_scale_down(const double* __restrict__ r, float* __restrict__ r32, int cells,
+                             const double* __restrict__ oscal, const int* __restrict__ oactive) {
+  const int pb = blockIdx.y;
+  if (!oactive[pb]) return;
+  const size_t base = (size_t)pb * cells;
+  const double inv = 1.0 / sqrt(oscal[(size_t)pb * kSlots + S_RR]);
+  CELL_LOOP(cells) r32[base + c] = (float)(r[base + c] * inv);
+}
+
+// mixed mode: x64 += ||r64|| d32
+__global__ void k_correct(double* __restrict__ x, const float* __restrict__ d, int cells,
+                          const double* __restrict__ oscal, const int* __restrict__ oactive) {
+  const int pb = blockIdx.y;
+  if (!oactive[pb]) return;
+  const size_t base = (size_t)pb * cells;
+  const double s = sqrt(oscal[(size_t)pb * kSlots + S_RR]);
+  CELL_LOOP(cells) x[base + c] += s * (double)d[base + c];
+}
+
+}  // namespace mpp

@@ -1,0 +1,103 @@
+// Internal declarations of the gfx950 pressure-projection library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mpp.h"
+
+namespace mpp {
+
+constexpr int kMaxLevels = 16;
+constexpr int kBlock = 256;           // threads per block of the cell kernels
+constexpr int kMaxCoarse = 1000;      // cells of the coarsest level (direct solve)
+
+// per-problem scalar slots of a solve (doubles)
+enum Slot {
+  S_MEAN = 0,   // mean projected out of f + jterm
+  S_BB,         // ||b||^2
+  S_TOL2,       // rtol^2 * ||b||^2: convergence threshold on ||r||^2
+  S_RR,         // ||r||^2 of the recurrence (or of the true residual after a restart)
+  S_RZ,         // r.z of the current iteration
+  S_BETA,       // rz_new / rz_old
+  S_PQ,         // p.q
+  S_ALPHA,      // rz / pq
+  S_SCALE,      // mixed mode: ||r|| of the outer residual that scaled the inner rhs
+  S_SUM,        // scratch sum (means)
+  kSlots = 16
+};
+
+// Convergence bookkeeping shared by the kernels of one PCG run (device pointers).
+struct Ctl {
+  double* scal;         // [B][kSlots]
+  int* active;          // [B] 1 while the problem iterates
+  int* iters;           // [B] iterations done
+  int* status;          // [B] MPP_OK / MPP_ENOTCONVERGED / MPP_EBREAKDOWN
+  double* partials;     // [B][pstride] block partial sums
+  unsigned* counters;   // [B] arrival counters of the last-block reductions (kept 0)
+  int pstride;
+  int max_iter;
+};
+
+// Face coefficients of one level, in precision T.  On the finest level `code`
+// holds per cell: bits 0..5 set when the -x,+x,-y,+y,-z,+z face is crossed by the
+// interface (its coefficient is read from bx/by/bz), bit 6 set on the "+" side; all
+// other faces take 1/rho of the cell's side from inv_rho[2*b + side].  Coarse levels
+// have code == nullptr and read every face from the arrays.
+template <typename T>
+struct Faces {
+  const uint8_t* code;
+  const T* bx;
+  const T* by;
+  const T* bz;
+  const T* inv_rho;     // [B][2]
+};
+
+struct Level {
+  int n = 0;
+  size_t cells = 0;         // n^3 per problem
+  uint8_t* code = nullptr;  // level 0 only
+  double* f64[3] = {nullptr, nullptr, nullptr};
+  float* f32[3] = {nullptr, nullptr, nullptr};
+  // V-cycle right-hand side and correction of this level (levels >= 1)
+  double* b64 = nullptr;
+  double* x64 = nullptr;
+  float* b32 = nullptr;
+  float* x32 = nullptr;
+  int bpp = 1;              // blocks per problem of the cell kernels on this level
+};
+
+}  // namespace mpp
+
+struct mpp_op_s {
+  int n = 0, batch = 0, nlev = 0;
+  uint32_t flags = 0;
+  mpp::Level lev[mpp::kMaxLevels];
+  size_t cells = 0;
+  int coarse_m = 0;
+  double* coarse_inv = nullptr;   // [B][m][m] inverse of (-A_c + 11^T/m)
+  double* coarse_work = nullptr;  // [B][m][m] factorisation scratch
+  double* rho = nullptr;          // [B][3]: rho_neg, rho_pos, sigma
+  double* inv_rho64 = nullptr;    // [B][2]
+  float* inv_rho32 = nullptr;     // [B][2]
+  double* kappa = nullptr;        // [B][cells]
+  double* jterm = nullptr;        // [B][cells]
+  // FP64 PCG vectors
+  double *b = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  // FP32 inner vectors (mixed mode)
+  float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+  // control
+  mpp::Ctl outer{}, inner{};
+  double* partials = nullptr;
+  unsigned* counters = nullptr;
+  int pstride = 0;
+  // host mirrors for polling
+  int* h_active = nullptr;
+  int* h_iters = nullptr;
+  int* h_status = nullptr;
+  double* h_scal = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};

@@ -1,0 +1,84 @@
+"""The C-ABI library: loads, exports what include/mpp.h declares, validates
+arguments on the host (no GPU calls are made by these tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2312_11740_amd as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mpp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_exports():
+    assert declared_functions() == sorted(M.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = M.load_library()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("n,batch,ok", [
+    (0, 1, False), (1, 1, False), (2, 1, True), (3, 1, True), (8, 1, True), (11, 1, False),
+    (20, 1, True), (36, 1, True), (44, 1, False), (256, 1, True), (1024, 1, True),
+    (2048, 1, False), (64, 0, False), (64, 64, True), (64, 70000, False)])
+def test_workspace_bytes_validates_shapes(n, batch, ok):
+    nb = M.workspace_bytes(n, batch)
+    assert (nb > 0) == ok
+    if ok:
+        assert nb >= 6 * 8 * n ** 3 * batch
+
+
+def test_workspace_grows_with_batch():
+    assert M.workspace_bytes(32, 4) > 3 * M.workspace_bytes(32, 1)
+
+
+def test_build_rejects_bad_arguments_before_device_work():
+    L = M.load_library()
+    d = M.Desc(16, 1, 0)
+    h = ctypes.c_void_p()
+    one = (ctypes.c_double * 1)(1.0)
+    neg = (ctypes.c_double * 1)(-1.0)
+    nan = (ctypes.c_double * 1)(float("nan"))
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    nbytes = M.workspace_bytes(16)
+    # null phi
+    assert L.mpp_build_operator(ctypes.byref(d), None, one, one, one, fake, nbytes, None,
+                                ctypes.byref(h)) == M.EINVAL
+    # non-positive or non-finite density, negative sigma
+    for rn, rp, sg in ((neg, one, one), (one, nan, one), (one, one, neg)):
+        assert L.mpp_build_operator(ctypes.byref(d), fake, rn, rp, sg, fake, nbytes, None,
+                                    ctypes.byref(h)) == M.EINVAL
+    # workspace too small
+    assert L.mpp_build_operator(ctypes.byref(d), fake, one, one, one, fake, 100, None,
+                                ctypes.byref(h)) == M.ENOMEM
+    # bad shape
+    bad = M.Desc(11, 1, 0)
+    assert L.mpp_build_operator(ctypes.byref(bad), fake, one, one, one, fake, nbytes, None,
+                                ctypes.byref(h)) == M.EINVAL
+    assert h.value is None
+
+
+def test_calls_on_null_operator():
+    L = M.load_library()
+    assert L.mpp_apply_stencil(None, None, None, None) == M.EINVAL
+    assert L.mpp_solve(None, None, None, None, None, None) == M.EINVAL
+    assert L.mpp_vcycle(None, None, None, 2, None) == M.EINVAL
+    L.mpp_destroy_operator(None)
+
+
+def test_default_opts_and_strerror():
+    L = M.load_library()
+    o = M.SolveOpts()
+    L.mpp_default_opts(ctypes.byref(o))
+    assert o.rtol == 1e-10 and o.mode == M.MODE_FP64 and o.nu == 2
+    assert M.strerror(M.ENOTCONVERGED) == "not converged within max_iter"
