@@ -1,0 +1,268 @@
+#!/usr/bin/env python
+"""Benchmark of the pressure-projection solve on one MI355X.
+
+Workload: the 256^3 rising-bubble sequence (radius 0.1 starting at (0.5, 0.5, 0.2),
++0.004 in z per step, density ratio 1000, sigma = 0.01, Neumann walls, one seeded
+uniform right-hand side per step).  One step = one projection solve: build the
+operator for that step's level set and solve to a relative residual of 1e-10,
+warm-started from the previous step's pressure.  Inputs (phi_t, f_t) for every
+step are resident in HBM before the timed region.
+
+Two methods run on the same steps:
+  plain  -- FP64 multigrid-preconditioned CG (the baseline),
+  mixed  -- FP32 multigrid-preconditioned CG inside FP64 residual refinement.
+The headline value is the faster method's mean time per step (ms, lower is better);
+the other is reported beside it.
+
+Also reported: the dominant kernel's achieved HBM bandwidth (algorithmic bytes per
+launch / mean launch time from HIP events in a profiled repeat of the timed steps),
+and the CPU oracle timed on the host cores on a bounded sample (one full-size solve).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2312_11740_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    rec = t.get(kernel)
+    if not rec or rec.get("src_sha") != kernel_sources_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup):
+    """warmup + steps projection solves, each warm-started from the previous step;
+    returns (mean ms per timed step, infos of the timed steps)."""
+    p = torch.zeros_like(fs[0])
+    infos = []
+    t0 = None
+    op = M.Operator(phis[0], prm["rho_neg"], prm["rho_pos"], prm["sigma"], workspace=ws)
+    for t in range(warmup + steps):
+        if t == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        op.update(phis[t], prm["rho_neg"], prm["rho_pos"], prm["sigma"])
+        p, info = op.solve(fs[t], p=p, rtol=prm["rtol"], mode=mode, nu=nu)
+        if t >= warmup:
+            infos.append(info[0])
+    torch.cuda.synchronize()
+    op.close()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return ms, infos
+
+
+def run_profiled(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup):
+    p = torch.zeros_like(fs[0])
+    stats = {}
+    op = M.Operator(phis[0], prm["rho_neg"], prm["rho_pos"], prm["sigma"], workspace=ws)
+    for t in range(warmup + steps):
+        op.update(phis[t], prm["rho_neg"], prm["rho_pos"], prm["sigma"])
+        if t >= warmup:
+            op.profile_start()
+        p, info = op.solve(fs[t], p=p, rtol=prm["rtol"], mode=mode, nu=nu)
+        if t >= warmup:
+            for k, v in op.profile_stop().items():
+                s = stats.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))
+                for f in ("launches", "ms", "bytes"):
+                    s[f] += v[f]
+    torch.cuda.synchronize()
+    op.close()
+    return stats
+
+
+def cpu_baseline(prob, p_gpu):
+    """The FP64 CPU oracle (as it stands) on one full-size step: assemble + MG-PCG to
+    1e-10 on the host cores.  Returns the record and the GPU-vs-oracle error."""
+    import numpy as np
+    import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    d = O.pipeline(prob.phi, prob.f, prob.rho_neg, prob.rho_pos, prob.sigma)
+    po, oi = O.solve_mg_pcg(d["faces"], d["b"], tol=1e-10)
+    sec = time.perf_counter() - t0
+    err = None
+    rr = None
+    if p_gpu is not None:
+        err = float(np.linalg.norm(p_gpu - po) / np.linalg.norm(po))
+        rr = float(O.rel_residual(d["faces"], d["b"], p_gpu))
+    rec = {"value": round(sec * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+           "sample": "one 256^3 step (t=0) of the same sequence, zero start, assemble + "
+                     "FP64 MG-PCG (nu=2) to 1e-10 (%d iterations)" % oi["iters"]}
+    return rec, err, rr
+
+
+def copy_calibration(torch, nbytes):
+    """A plain device copy of known size, for scaling HBM counters."""
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                      "ms": dt * 1e3, "GBps": 2 * n * 8 / dt / 1e9}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--nu", type=int, default=2)
+    ap.add_argument("--methods", default="plain,mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device copy of this many bytes (counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested); run with --gpus 1" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2312_11740_amd as M
+    from paper_2312_11740_amd import problems as G
+
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration)
+        return
+
+    dev = torch.device("cuda:0")
+    n, K, W = args.n, args.steps, args.warmup
+    prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01, rtol=1e-10)
+    log("generating %d steps of the %d^3 rising-bubble sequence" % (K + W, n))
+    probs = [G.rising_bubble_problem(t, n=n) for t in range(K + W)]
+    phis = [torch.from_numpy(q.phi).to(dev) for q in probs]
+    fs = [torch.from_numpy(q.f).to(dev) for q in probs]
+    ws = torch.empty(M.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    results = {}
+    for meth in args.methods.split(","):
+        mode = {"plain": "fp64", "mixed": "mixed"}[meth]
+        ms, infos = run_sequence(M, torch, ws, phis, fs, prm, mode, args.nu, K, W)
+        worst = max(i.rel_resid for i in infos)
+        ok = all(i.status == M.OK for i in infos) and worst <= prm["rtol"]
+        results[meth] = dict(ms=ms, iters=[i.iters for i in infos],
+                             outer=[i.outer_iters for i in infos], max_rel_resid=worst, ok=ok)
+        log("%s: %.2f ms/step iters %s max rel resid %.2e ok=%s"
+            % (meth, ms, results[meth]["iters"], worst, ok))
+
+    best = min((m for m in results if results[m]["ok"]), key=lambda m: results[m]["ms"],
+               default=None)
+    if best is None:
+        best = min(results, key=lambda m: results[m]["ms"])
+    plain_ms = results.get("plain", {}).get("ms")
+
+    roofline = None
+    kernels = None
+    if not args.no_profile:
+        mode = {"plain": "fp64", "mixed": "mixed"}[best]
+        stats = run_profiled(M, torch, ws, phis, fs, prm, mode, args.nu, K, W)
+        kernels = {k: dict(launches=v["launches"], mean_us=1e3 * v["ms"] / v["launches"],
+                           GBps=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["bytes"] else None,
+                           share=None)
+                   for k, v in stats.items()}
+        total = sum(v["ms"] for v in stats.values())
+        for k in kernels:
+            kernels[k]["share"] = round(stats[k]["ms"] / total, 3)
+        dom = max((k for k in stats if stats[k]["bytes"] > 0), key=lambda k: stats[k]["ms"])
+        v = stats[dom]
+        per_launch = v["bytes"] / v["launches"]
+        achieved = per_launch / (v["ms"] * 1e-3 / v["launches"]) / 1e9
+        kname = "%s/%s" % (dom, "f64" if best == "plain" else "f32")
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(kname), "kernel": kname,
+                    "alg_bytes_per_launch": per_launch,
+                    "mean_launch_us": round(1e3 * v["ms"] / v["launches"], 2)}
+        log("kernels:", json.dumps(kernels))
+
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on step 0 (full size)")
+        op = M.Operator(phis[0], prm["rho_neg"], prm["rho_pos"], prm["sigma"], workspace=ws)
+        p0, _ = op.solve(fs[0], rtol=prm["rtol"], mode="fp64" if best == "plain" else "mixed",
+                         nu=args.nu)
+        p0h = p0.cpu().numpy()
+        op.close()
+        cpu, err, rr = cpu_baseline(probs[0], p0h)
+        log("cpu baseline %s, gpu err vs oracle %.3e, oracle-computed residual %.3e"
+            % (cpu, err, rr))
+
+    value = results[best]["ms"]
+    line = {
+        "metric": "time to 1e-10 rel. residual, 256^3 rho-ratio 1000 (learned+mixed vs plain); "
+                  "HBM GB/s",
+        "value": round(value, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(value, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if best == "plain" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "rising bubble %d^3, density ratio 1000, sigma 0.01, one "
+                               "projection solve (operator build + MG-PCG to 1e-10, warm "
+                               "start) per step" % n,
+                   "n": n, "method": best, "nu": args.nu},
+        "methods": {m: {"ms_per_step": round(r["ms"], 3), "iters": r["iters"],
+                        "outer": r["outer"], "max_rel_resid": r["max_rel_resid"]}
+                    for m, r in results.items()},
+        "speedup_vs_plain_fp64": (round(plain_ms / value, 3) if plain_ms else None),
+        "err_vs_oracle_step0": err,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

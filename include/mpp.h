@@ -74,8 +74,12 @@ typedef struct mpp_op_s *mpp_op;
 typedef struct {
     int32_t n;
     int32_t batch;
-    uint32_t flags; /* reserved, 0 */
+    uint32_t flags; /* 0 or MPP_FLAG_NO_GRAPHS */
 } mpp_desc;
+
+/* desc.flags: launch every kernel directly instead of replaying captured HIP graphs
+ * of the CG iterations (same results; for debugging and profiling). */
+#define MPP_FLAG_NO_GRAPHS 1u
 
 typedef struct {
     double rtol;          /* relative residual target, e.g. 1e-10 */
@@ -117,8 +121,14 @@ int mpp_build_operator(const mpp_desc *desc, const double *phi, const double *rh
                        const double *rho_pos, const double *sigma, void *workspace,
                        size_t workspace_bytes, void *stream, mpp_op *out);
 
+/* Rebuilds an operator in place for a new level set and new constants (same shape,
+ * same workspace), e.g. once per time step of a projection method.  Arguments as
+ * for mpp_build_operator.  Keeps the operator's captured launch graphs valid. */
+int mpp_update_operator(mpp_op op, const double *phi, const double *rho_neg,
+                        const double *rho_pos, const double *sigma, void *stream);
+
 /* y = A x for every problem (device, [batch][n^3]); no jump term.  x and y must not
- * overlap. */
+ * overlap.  Asynchronous: returns once the work is enqueued on the stream. */
 int mpp_apply_stencil(mpp_op op, const double *x, double *y, void *stream);
 
 /* Solve A p = f + jterm (mean-projected) for every problem.  f, p: device
@@ -130,12 +140,12 @@ int mpp_solve(mpp_op op, const double *f, double *p, const mpp_solve_opts *opts,
               mpp_solve_info *info, void *stream);
 
 /* The right-hand side the solver uses: b = f + jterm, minus its mean (device
- * [batch][n^3]).  mean_out: host [batch], may be NULL. */
+ * [batch][n^3]).  mean_out: host [batch], may be NULL (then asynchronous). */
 int mpp_rhs(mpp_op op, const double *f, double *b, double *mean_out, void *stream);
 
 /* One multigrid V-cycle as a preconditioner: z ~= A^{-1} r with zero initial guess,
  * nu red-black sweeps before and black-red sweeps after the coarse correction on
- * every level; FP64.  r, z: device [batch][n^3]. */
+ * every level; FP64.  r, z: device [batch][n^3].  Asynchronous. */
 int mpp_vcycle(mpp_op op, const double *r, double *z, int nu, void *stream);
 
 /* Copies of the operator's data for inspection (device destinations, [batch][n^3]
@@ -146,6 +156,24 @@ int mpp_operator_fields(mpp_op op, double *beta_x, double *beta_y, double *beta_
 
 /* Number of multigrid levels and the size of each (host array of up to 16). */
 int mpp_levels(mpp_op op, int32_t *nlevels, int32_t *sizes);
+
+/* Kernel timing.  Between mpp_profile_start and mpp_profile_stop every launch on the
+ * finest level made by calls on this operator is bracketed by HIP events on the
+ * call's stream (the levels below the finest are timed as one record per V-cycle).
+ * stop waits for the events and returns, per kernel, the launch count, the summed
+ * event time and the summed algorithmic bytes (each array the kernel must read or
+ * write counted once; see the kernel descriptions in the library).  stats: host
+ * array of max_stats records; *n_stats receives the number filled. */
+typedef struct {
+    char name[32];
+    int32_t launches;
+    int32_t reserved;
+    double total_ms;
+    double bytes;
+} mpp_kernel_stat;
+
+int mpp_profile_start(mpp_op op);
+int mpp_profile_stop(mpp_op op, mpp_kernel_stat *stats, int32_t max_stats, int32_t *n_stats);
 
 /* Releases the handle (not the caller's workspace). */
 void mpp_destroy_operator(mpp_op op);

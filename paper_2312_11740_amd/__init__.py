@@ -24,8 +24,10 @@ GUESS_ZERO, GUESS_GIVEN = 0, 1
 EXPORTS = (
     "mpp_default_opts", "mpp_workspace_bytes", "mpp_build_operator", "mpp_apply_stencil",
     "mpp_solve", "mpp_rhs", "mpp_vcycle", "mpp_operator_fields", "mpp_levels",
-    "mpp_destroy_operator", "mpp_strerror",
+    "mpp_destroy_operator", "mpp_strerror", "mpp_profile_start", "mpp_profile_stop",
+    "mpp_update_operator",
 )
+FLAG_NO_GRAPHS = 1
 
 
 class Desc(ctypes.Structure):
@@ -43,6 +45,12 @@ class SolveInfo(ctypes.Structure):
                 ("outer_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("rel_resid", ctypes.c_double), ("removed_mean", ctypes.c_double),
                 ("bnorm", ctypes.c_double)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class MppError(RuntimeError):
@@ -70,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     L.mpp_workspace_bytes.restype = ctypes.c_size_t
     L.mpp_build_operator.argtypes = [ctypes.POINTER(Desc), P, P, P, P, P, ctypes.c_size_t, P,
                                      ctypes.POINTER(P)]
+    L.mpp_update_operator.argtypes = [P, P, P, P, P, P]
     L.mpp_apply_stencil.argtypes = [P, P, P, P]
     L.mpp_solve.argtypes = [P, P, P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo), P]
     L.mpp_rhs.argtypes = [P, P, P, P, P]
@@ -78,6 +87,9 @@ def load_library(path: str = LIB_PATH):
     L.mpp_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.mpp_destroy_operator.argtypes = [P]
     L.mpp_destroy_operator.restype = None
+    L.mpp_profile_start.argtypes = [P]
+    L.mpp_profile_stop.argtypes = [P, ctypes.POINTER(KernelStat), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
     L.mpp_strerror.argtypes = [i32]
     L.mpp_strerror.restype = ctypes.c_char_p
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
@@ -136,7 +148,7 @@ class Operator:
     phi: (n,n,n) or (B,n,n,n) float64 CUDA tensor; rho_neg, rho_pos, sigma: scalars or
     length-B sequences (density where phi <= 0, where phi > 0, surface tension)."""
 
-    def __init__(self, phi, rho_neg, rho_pos, sigma):
+    def __init__(self, phi, rho_neg, rho_pos, sigma, workspace=None, graphs=True):
         torch = _torch()
         L = load_library()
         self.batched = phi.dim() == 4
@@ -156,11 +168,15 @@ class Operator:
             return (ctypes.c_double * B)(*[float(x) for x in vals])
 
         self._rn, self._rp, self._sg = arr(rho_neg), arr(rho_pos), arr(sigma)
-        self._desc = Desc(self.n, self.batch, 0)
+        self._desc = Desc(self.n, self.batch, 0 if graphs else FLAG_NO_GRAPHS)
         nbytes = int(L.mpp_workspace_bytes(ctypes.byref(self._desc)))
         if nbytes == 0:
             raise MppError(EINVAL, "unsupported shape n=%d batch=%d" % (n, B))
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        elif workspace.dtype != torch.uint8 or workspace.numel() < nbytes or not workspace.is_cuda:
+            raise ValueError("workspace must be a CUDA uint8 tensor of >= %d bytes" % nbytes)
+        self.workspace = workspace
         h = ctypes.c_void_p()
         st = L.mpp_build_operator(ctypes.byref(self._desc), ctypes.c_void_p(phi.data_ptr()),
                                   self._rn, self._rp, self._sg,
@@ -169,6 +185,22 @@ class Operator:
         if st != OK:
             raise MppError(st, "mpp_build_operator")
         self._h = h
+
+    def update(self, phi, rho_neg, rho_pos, sigma):
+        """Rebuilds the operator in place for a new level set and constants."""
+        _check_field(phi, self.shape, "phi")
+        B = self.batch
+
+        def arr(v):
+            vals = list(v) if hasattr(v, "__len__") else [v] * B
+            return (ctypes.c_double * B)(*[float(x) for x in vals])
+
+        self._rn, self._rp, self._sg = arr(rho_neg), arr(rho_pos), arr(sigma)
+        st = load_library().mpp_update_operator(self._h, ctypes.c_void_p(phi.data_ptr()),
+                                                self._rn, self._rp, self._sg,
+                                                _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_update_operator")
 
     # -- calls --------------------------------------------------------------------
     def _new(self):
@@ -248,6 +280,22 @@ class Operator:
         if st != OK and raise_on_error:
             raise MppError(st, "mpp_solve")
         return p, out
+
+    def profile_start(self):
+        st = load_library().mpp_profile_start(self._h)
+        if st != OK:
+            raise MppError(st, "mpp_profile_start")
+
+    def profile_stop(self):
+        """Per-kernel launches, event time (ms) and algorithmic bytes since profile_start."""
+        stats = (KernelStat * 32)()
+        cnt = ctypes.c_int32(0)
+        st = load_library().mpp_profile_stop(self._h, stats, 32, ctypes.byref(cnt))
+        if st != OK:
+            raise MppError(st, "mpp_profile_stop")
+        return {stats[i].name.decode(): dict(launches=stats[i].launches, ms=stats[i].total_ms,
+                                             bytes=stats[i].bytes)
+                for i in range(cnt.value)}
 
     def close(self):
         h = getattr(self, "_h", None)

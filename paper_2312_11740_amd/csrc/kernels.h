@@ -12,6 +12,12 @@
 
 namespace mpp {
 
+// Workgroup barrier that waits for LDS traffic only: global loads issued before it
+// stay in flight (the compiler still waits for them before their values are used).
+__device__ inline void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // ------------------------------------------------------------------------------
 // reductions: wave shuffles, one partial per block, last block finishes in a fixed
 // order (no floating-point atomics: bitwise reproducible)
@@ -37,35 +43,13 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;
 }
 
-__device__ inline double load_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide per-problem sum.  Returns true in thread 0 of the last block of the
-// problem, with the total in *total.
-__device__ inline bool grid_sum(double v, const Ctl& ctl, int b, double* total) {
+// Per-problem sums without atomics: every block of a producer kernel stores its
+// partial sum; a separate one-block-per-problem kernel (k_finish) adds the partials
+// in a fixed order and runs the epilogue, so results are bitwise reproducible.
+__device__ inline void block_partial(double v, const Ctl& ctl, int b) {
   __shared__ double sh[16];
-  __shared__ int last;
   const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) {
-    ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = s;
-    __threadfence();
-    const unsigned prev = atomicAdd(&ctl.counters[b], 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  double t = 0.0;
-  for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x)
-    t += load_agent(&ctl.partials[(size_t)b * ctl.pstride + q]);
-  const double tot = block_sum(t, sh);
-  if (threadIdx.x == 0) {
-    ctl.counters[b] = 0;
-    *total = tot;
-    return true;
-  }
-  return false;
+  if (threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = s;
 }
 
 // What the last block does with a finished sum.
@@ -82,6 +66,7 @@ enum Epi {
 
 struct EpiArgs {
   int kind;
+  int only_active;   // skip problems whose active flag is 0 (their partials are stale)
   int slot;
   double rtol2;
   double inv_cells;
@@ -134,9 +119,24 @@ __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& 
   }
 }
 
-__device__ inline void reduce_and_finish(double v, const Ctl& ctl, int b, const EpiArgs& e) {
-  double tot;
-  if (grid_sum(v, ctl, b, &tot)) finish(ctl, b, tot, e);
+__global__ void __launch_bounds__(1024) k_finish(Ctl ctl, int nparts, EpiArgs e) {
+  const int b = blockIdx.x;
+  if (e.only_active && !ctl.active[b]) return;
+  __shared__ double sh[16];
+  const double* P = ctl.partials + (size_t)b * ctl.pstride;
+  // four independent loads in flight per thread, fixed order of the sums
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+  const int st = blockDim.x;
+  int q = threadIdx.x;
+  for (; q + 3 * st < nparts; q += 4 * st) {
+    t0 += P[q];
+    t1 += P[q + st];
+    t2 += P[q + 2 * st];
+    t3 += P[q + 3 * st];
+  }
+  for (; q < nparts; q += st) t0 += P[q];
+  const double tot = block_sum((t0 + t1) + (t2 + t3), sh);
+  if (threadIdx.x == 0) finish(ctl, b, tot, e);
 }
 
 // ------------------------------------------------------------------------------
@@ -150,11 +150,11 @@ __device__ inline void ijk(int c, int n, int& i, int& j, int& k) {
 }
 
 // Coefficients of the six faces -x,+x,-y,+y,-z,+z of cell c (0 through walls).
-template <typename T>
+template <typename T, bool FINE>
 __device__ inline void cell_faces(const Faces<T>& F, int b, size_t base, int c, int i, int j,
                                   int k, int n, T w[6]) {
   const size_t nn = (size_t)n * n;
-  if (F.code) {
+  if (FINE) {
     const unsigned cd = F.code[base + c];
     const T ir = F.inv_rho[2 * b + ((cd >> 6) & 1u)];
     w[0] = i > 0 ? ((cd & 1u) ? F.bx[base + c] : ir) : T(0);
@@ -465,7 +465,7 @@ __global__ void k_rhs_sum(const double* __restrict__ f, const double* __restrict
     b[base + c] = v;
     acc += v;
   }
-  reduce_and_finish(acc, ctl, pb, e);
+  block_partial(acc, ctl, pb);
 }
 
 // v -= scal[S_MEAN]; optional sum of squares into an epilogue
@@ -480,7 +480,7 @@ __global__ void k_sub_mean_sq(double* __restrict__ v, int cells, Ctl ctl, EpiArg
     v[base + c] = x;
     acc += x * x;
   }
-  if (want_sq) reduce_and_finish(acc, ctl, pb, e);
+  if (want_sq) block_partial(acc, ctl, pb);
 }
 
 template <typename T>
@@ -489,155 +489,12 @@ __global__ void k_sum(const T* __restrict__ v, int cells, Ctl ctl, EpiArgs e) {
   const size_t base = (size_t)pb * cells;
   double acc = 0.0;
   CELL_LOOP(cells) acc += (double)v[base + c];
-  reduce_and_finish(acc, ctl, pb, e);
+  block_partial(acc, ctl, pb);
 }
 
 // ------------------------------------------------------------------------------
 // stencil kernels
 // ------------------------------------------------------------------------------
-template <typename T, bool DOT>
-__global__ void k_apply(Faces<T> F, int n, int cells, const T* __restrict__ x, T* __restrict__ y,
-                        Ctl ctl, EpiArgs e, const int* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const size_t base = (size_t)b * cells;
-  const T inv_h2 = (T)((double)n * (double)n);
-  double acc = 0.0;
-  CELL_LOOP(cells) {
-    int i, j, k;
-    ijk(c, n, i, j, k);
-    T w[6];
-    cell_faces(F, b, base, c, i, j, k, n, w);
-    const T yc = stencil_at(w, x, base, c, i, j, k, n, inv_h2);
-    y[base + c] = yc;
-    if (DOT) acc += (double)x[base + c] * (double)yc;
-  }
-  if (DOT) reduce_and_finish(acc, ctl, b, e);
-}
-
-// r = rhs - A x, with ||r||^2 into the epilogue; xzero: treat x as 0 (r = rhs)
-template <typename T>
-__global__ void k_residual(Faces<T> F, int n, int cells, const T* __restrict__ rhs,
-                           const T* __restrict__ x, T* __restrict__ r, Ctl ctl, EpiArgs e,
-                           int xzero) {
-  const int b = blockIdx.y;
-  const size_t base = (size_t)b * cells;
-  const T inv_h2 = (T)((double)n * (double)n);
-  double acc = 0.0;
-  CELL_LOOP(cells) {
-    T rc;
-    if (xzero) {
-      rc = rhs[base + c];
-    } else {
-      int i, j, k;
-      ijk(c, n, i, j, k);
-      T w[6];
-      cell_faces(F, b, base, c, i, j, k, n, w);
-      rc = rhs[base + c] - stencil_at(w, x, base, c, i, j, k, n, inv_h2);
-    }
-    r[base + c] = rc;
-    acc += (double)rc * (double)rc;
-  }
-  reduce_and_finish(acc, ctl, b, e);
-}
-
-// Red-black Gauss-Seidel update of one colour, in place:
-//   x_c <- (sum_f w_f x_nb - h^2 b_c) / sum_f w_f,   colour = (i+j+k) mod 2.
-// from_zero: x is taken as 0 on entry; cells of the other colour are set to 0.
-template <typename T>
-__global__ void k_smooth(Faces<T> F, int n, int cells, const T* __restrict__ rhs,
-                         T* __restrict__ x, int colour, int from_zero,
-                         const int* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const size_t base = (size_t)b * cells;
-  const size_t nn = (size_t)n * n;
-  const T h2 = (T)(1.0 / ((double)n * (double)n));
-  CELL_LOOP(cells) {
-    int i, j, k;
-    ijk(c, n, i, j, k);
-    if (((i + j + k) & 1) != colour) {
-      if (from_zero) x[base + c] = T(0);
-      continue;
-    }
-    T w[6];
-    cell_faces(F, b, base, c, i, j, k, n, w);
-    T num = T(0), den = T(0);
-    if (!from_zero) {
-      if (i > 0) num += w[0] * x[base + c - 1];
-      if (i < n - 1) num += w[1] * x[base + c + 1];
-      if (j > 0) num += w[2] * x[base + c - n];
-      if (j < n - 1) num += w[3] * x[base + c + n];
-      if (k > 0) num += w[4] * x[base + c - nn];
-      if (k < n - 1) num += w[5] * x[base + c + nn];
-    }
-    den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
-    x[base + c] = (num - h2 * rhs[base + c]) / den;
-  }
-}
-
-// Coarse right-hand side: mean over the 8 children of the fine residual b - A x.
-template <typename T>
-__global__ void k_resid_restrict(Faces<T> F, int nf, const T* __restrict__ bf,
-                                 const T* __restrict__ xf, T* __restrict__ bcv,
-                                 const int* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const int nc = nf / 2;
-  const int cells_c = nc * nc * nc;
-  const int cells_f = nf * nf * nf;
-  const size_t base = (size_t)b * cells_f, basec = (size_t)b * cells_c;
-  const T inv_h2 = (T)((double)nf * (double)nf);
-  CELL_LOOP(cells_c) {
-    int I, J, K;
-    ijk(c, nc, I, J, K);
-    T s = T(0);
-    for (int e = 0; e < 2; ++e)
-      for (int d = 0; d < 2; ++d)
-        for (int a = 0; a < 2; ++a) {
-          const int i = 2 * I + a, j = 2 * J + d, k = 2 * K + e;
-          const int cf = i + nf * (j + nf * k);
-          T w[6];
-          cell_faces(F, b, base, cf, i, j, k, nf, w);
-          s += bf[base + cf] - stencil_at(w, xf, base, cf, i, j, k, nf, inv_h2);
-        }
-    bcv[basec + c] = s * T(0.125);
-  }
-}
-
-// x_f += x_c[parent]
-template <typename T>
-__global__ void k_prolong_add(int nf, const T* __restrict__ xc, T* __restrict__ xf,
-                              const int* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
-  const int nc = nf / 2;
-  const int cells_f = nf * nf * nf;
-  const size_t base = (size_t)b * cells_f, basec = (size_t)b * nc * nc * nc;
-  CELL_LOOP(cells_f) {
-    int i, j, k;
-    ijk(c, nf, i, j, k);
-    xf[base + c] += xc[basec + (i >> 1) + nc * ((j >> 1) + nc * (k >> 1))];
-  }
-}
-
-// Coarsest level: x = M^{-1} (-b) with the FP64 inverse; one block per problem.
-template <typename T>
-__global__ void k_coarse_solve(const double* __restrict__ inv, int m, const T* __restrict__ bcv,
-                               T* __restrict__ x, const int* __restrict__ active) {
-  const int b = blockIdx.x;
-  if (active && !active[b]) return;
-  __shared__ double sb[kMaxCoarse];
-  for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)bcv[(size_t)b * m + q];
-  __syncthreads();
-  const double* Mi = inv + (size_t)b * m * m;
-  for (int r = threadIdx.x; r < m; r += blockDim.x) {
-    double s = 0.0;
-    for (int q = 0; q < m; ++q) s += Mi[(size_t)q * m + r] * sb[q];
-    x[(size_t)b * m + r] = (T)s;
-  }
-}
-
 // ------------------------------------------------------------------------------
 // CG vector updates
 // ------------------------------------------------------------------------------
@@ -649,7 +506,7 @@ __global__ void k_dot(const T* __restrict__ a, const T* __restrict__ bv, int cel
   const size_t base = (size_t)pb * cells;
   double acc = 0.0;
   CELL_LOOP(cells) acc += (double)a[base + c] * (double)bv[base + c];
-  reduce_and_finish(acc, ctl, pb, e);
+  block_partial(acc, ctl, pb);
 }
 
 // p = z + beta p   (first: p = z)
@@ -678,7 +535,7 @@ __global__ void k_update_xr(T* __restrict__ x, T* __restrict__ r, const T* __res
     r[base + c] = rc;
     acc += (double)rc * (double)rc;
   }
-  reduce_and_finish(acc, ctl, pb, e);
+  block_partial(acc, ctl, pb);
 }
 
 template <typename T>
@@ -705,6 +562,153 @@ __global__ void k_correct(double* __restrict__ x, const float* __restrict__ d, i
   const size_t base = (size_t)pb * cells;
   const double s = sqrt(oscal[(size_t)pb * kSlots + S_RR]);
   CELL_LOOP(cells) x[base + c] += s * (double)d[base + c];
+}
+
+}  // namespace mpp
+
+namespace mpp {
+
+// ------------------------------------------------------------------------------
+// the bottom of the V-cycle in one launch: levels with at most kSmallCells cells per
+// problem are smoothed, restricted, solved and prolonged by a single workgroup per
+// problem, in global memory (L2-resident at these sizes), with barriers between
+// phases.  Same operations, in the same order, as the per-level kernels.
+// ------------------------------------------------------------------------------
+constexpr int kSmallCells = 4096;   // 16^3
+constexpr int kSmallBlock = 1024;
+
+template <typename T>
+struct SmallLevel {
+  int n;
+  const T* bx;
+  const T* by;
+  const T* bz;
+  T* b;
+  T* x;
+};
+
+template <typename T>
+struct SmallCycle {
+  int nlev;                        // levels in the sub-cycle (the last one is solved directly)
+  SmallLevel<T> lv[kMaxLevels];
+  const double* inv;               // [B][m][m]
+  int m;
+  int nu;
+};
+
+template <typename T>
+__device__ inline void small_faces(const SmallLevel<T>& L, size_t base, int c, int i, int j, int k,
+                                   T w[6]) {
+  const int n = L.n, nn = n * n;
+  w[0] = i > 0 ? L.bx[base + c] : T(0);
+  w[1] = i < n - 1 ? L.bx[base + c + 1] : T(0);
+  w[2] = j > 0 ? L.by[base + c] : T(0);
+  w[3] = j < n - 1 ? L.by[base + c + n] : T(0);
+  w[4] = k > 0 ? L.bz[base + c] : T(0);
+  w[5] = k < n - 1 ? L.bz[base + c + nn] : T(0);
+}
+
+template <typename T>
+__device__ void small_smooth(const SmallLevel<T>& L, size_t base, int colour, int from_zero) {
+  const int n = L.n, cells = n * n * n, nn = n * n;
+  const T h2 = (T)(1.0 / ((double)n * (double)n));
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+    int i, j, k;
+    ijk(c, n, i, j, k);
+    if (((i + j + k) & 1) != colour) {
+      if (from_zero) L.x[base + c] = T(0);
+      continue;
+    }
+    T w[6];
+    small_faces(L, base, c, i, j, k, w);
+    T num = T(0);
+    if (!from_zero) {
+      if (i > 0) num += w[0] * L.x[base + c - 1];
+      if (i < n - 1) num += w[1] * L.x[base + c + 1];
+      if (j > 0) num += w[2] * L.x[base + c - n];
+      if (j < n - 1) num += w[3] * L.x[base + c + n];
+      if (k > 0) num += w[4] * L.x[base + c - nn];
+      if (k < n - 1) num += w[5] * L.x[base + c + nn];
+    }
+    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
+    L.x[base + c] = (num - h2 * L.b[base + c]) / den;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void small_resid_restrict(const SmallLevel<T>& F, size_t basef, const SmallLevel<T>& C,
+                                     size_t basec) {
+  const int nf = F.n, nc = C.n, cells_c = nc * nc * nc;
+  const T inv_h2 = (T)((double)nf * (double)nf);
+  for (int c = threadIdx.x; c < cells_c; c += blockDim.x) {
+    int I, J, K;
+    ijk(c, nc, I, J, K);
+    T s = T(0);
+    for (int e = 0; e < 2; ++e)
+      for (int d = 0; d < 2; ++d)
+        for (int a = 0; a < 2; ++a) {
+          const int i = 2 * I + a, j = 2 * J + d, k = 2 * K + e;
+          const int cf = i + nf * (j + nf * k);
+          T w[6];
+          small_faces(F, basef, cf, i, j, k, w);
+          s += F.b[basef + cf] - stencil_at(w, F.x, basef, cf, i, j, k, nf, inv_h2);
+        }
+    C.b[basec + c] = s * T(0.125);
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void small_prolong(const SmallLevel<T>& F, size_t basef, const SmallLevel<T>& C,
+                              size_t basec) {
+  const int nf = F.n, nc = C.n, cells_f = nf * nf * nf;
+  for (int c = threadIdx.x; c < cells_f; c += blockDim.x) {
+    int i, j, k;
+    ijk(c, nf, i, j, k);
+    F.x[basef + c] += C.x[basec + (i >> 1) + nc * ((j >> 1) + nc * (k >> 1))];
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSmallBlock) k_small_cycle(SmallCycle<T> S,
+                                                             const int* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  size_t base[kMaxLevels];
+  for (int l = 0; l < S.nlev; ++l) base[l] = (size_t)b * S.lv[l].n * S.lv[l].n * S.lv[l].n;
+  for (int l = 0; l + 1 < S.nlev; ++l) {
+    small_smooth(S.lv[l], base[l], 0, 1);
+    small_smooth(S.lv[l], base[l], 1, 0);
+    for (int q = 1; q < S.nu; ++q) {
+      small_smooth(S.lv[l], base[l], 0, 0);
+      small_smooth(S.lv[l], base[l], 1, 0);
+    }
+    small_resid_restrict(S.lv[l], base[l], S.lv[l + 1], base[l + 1]);
+  }
+  {
+    // coarsest: x = M^{-1} (-b), FP64
+    const SmallLevel<T>& L = S.lv[S.nlev - 1];
+    __shared__ double sb[kMaxCoarse];
+    const int m = S.m;
+    for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)L.b[(size_t)b * m + q];
+    __syncthreads();
+    const double* Mi = S.inv + (size_t)b * m * m;
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+      double s = 0.0;
+      for (int q = 0; q < m; ++q) s += Mi[(size_t)q * m + r] * sb[q];
+      L.x[(size_t)b * m + r] = (T)s;
+    }
+    __syncthreads();
+  }
+  for (int l = S.nlev - 2; l >= 0; --l) {
+    small_prolong(S.lv[l], base[l], S.lv[l + 1], base[l + 1]);
+    for (int q = 0; q < S.nu; ++q) {
+      small_smooth(S.lv[l], base[l], 1, 0);
+      small_smooth(S.lv[l], base[l], 0, 0);
+    }
+  }
 }
 
 }  // namespace mpp

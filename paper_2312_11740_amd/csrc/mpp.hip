@@ -16,6 +16,8 @@
 #include <vector>
 
 #include "kernels.h"
+#include "rbgs.h"
+#include "stencil.h"
 
 using namespace mpp;
 
@@ -43,7 +45,8 @@ int level_sizes(int n, int* sizes) {
 }
 
 bool desc_ok(const mpp_desc* d) {
-  if (!d || d->n < 2 || d->n > 1024 || d->batch < 1 || d->batch > 65535 || d->flags != 0)
+  if (!d || d->n < 2 || d->n > 1024 || d->batch < 1 || d->batch > 65535 ||
+      (d->flags & ~(uint32_t)MPP_FLAG_NO_GRAPHS) != 0)
     return false;
   int sizes[kMaxLevels];
   const int L = level_sizes(d->n, sizes);
@@ -96,8 +99,10 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     if (l > 0) {
       lv.b64 = cv.take<double>(cl);
       lv.x64 = cv.take<double>(cl);
+      lv.t64 = cv.take<double>(cl);
       lv.b32 = cv.take<float>(cl);
       lv.x32 = cv.take<float>(cl);
+      lv.t32 = cv.take<float>(cl);
     }
   }
   const int m = sizes[L - 1] * sizes[L - 1] * sizes[L - 1];
@@ -109,6 +114,7 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
   op->inv_rho32 = cv.take<float>((size_t)B * 2);
   op->kappa = cv.take<double>(C);
   op->jterm = cv.take<double>(C);
+  op->x = cv.take<double>(C);
   op->b = cv.take<double>(C);
   op->r = cv.take<double>(C);
   op->z = cv.take<double>(C);
@@ -119,6 +125,8 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
   op->p32 = cv.take<float>(C);
   op->q32 = cv.take<float>(C);
   op->d32 = cv.take<float>(C);
+  for (int l = 0; l < L; ++l) op->pstride = std::max(op->pstride, rb_grid(rb_tiles(sizes[l], B)));
+  op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
   op->partials = cv.take<double>((size_t)B * op->pstride);
   op->counters = cv.take<unsigned>((size_t)B);
   for (Ctl* c : {&op->outer, &op->inner}) {
@@ -151,6 +159,9 @@ template <typename T> T* lvl_b(Level& L);
 template <typename T> T* lvl_x(Level& L);
 template <> double* lvl_b<double>(Level& L) { return L.b64; }
 template <> double* lvl_x<double>(Level& L) { return L.x64; }
+template <typename T> T* lvl_t(Level& L);
+template <> double* lvl_t<double>(Level& L) { return L.t64; }
+template <> float* lvl_t<float>(Level& L) { return L.t32; }
 template <> float* lvl_b<float>(Level& L) { return L.b32; }
 template <> float* lvl_x<float>(Level& L) { return L.x32; }
 
@@ -159,96 +170,348 @@ inline dim3 grid_of(const Level& lv, int B) { return dim3(lv.bpp, B); }
 EpiArgs epi(int kind) {
   EpiArgs e{};
   e.kind = kind;
+  e.only_active = (kind == E_RZ || kind == E_PQ || kind == E_RR_ITER) ? 1 : 0;
   return e;
 }
+
+// Adds the block partials of the preceding producer launch per problem and runs the
+// epilogue (one block per problem).
+void finish_sums(mpp_op_s* op, const Ctl& ctl, const EpiArgs& e, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, dim3(op->batch), dim3(1024), 0, s, ctl, nparts, e);
+  ck_launch();
+}
+
+// ------------------------------------------------------------------------------
+// finest-level streaming kernels (grid = XCD-ordered tiles of 64 x 4 columns)
+// ------------------------------------------------------------------------------
+// y = A x on the finest level, with x.y block partials when dot; returns the number
+// of partials written (0 without dot).
+template <typename T>
+int launch_apply(const mpp_op_s* op, Faces<T> F, const T* x, T* y, const Ctl& ctl, int dot,
+                 const int* active, hipStream_t s) {
+  const int n = op->lev[0].n;
+  const StTiles tl = st_tiles(n, kStKZ);
+  const dim3 grid(st_grid(tl), op->batch);
+  hipLaunchKernelGGL((k_stencil_z<T, 0>), grid, dim3(kStThreads), 0, s, F, n, tl, kStKZ, x,
+                     (const T*)nullptr, y, ctl, dot, 0, active);
+  return dot ? (int)grid.x : 0;
+}
+
+// r = rhs - A x (x = 0 when xzero) with ||r||^2 block partials; returns their number.
+template <typename T>
+int launch_residual(const mpp_op_s* op, Faces<T> F, const T* rhs, const T* x, T* r,
+                    const Ctl& ctl, int xzero, hipStream_t s) {
+  const int n = op->lev[0].n;
+  const StTiles tl = st_tiles(n, kStKZ);
+  const dim3 grid(st_grid(tl), op->batch);
+  hipLaunchKernelGGL((k_stencil_z<T, 1>), grid, dim3(kStThreads), 0, s, F, n, tl, kStKZ, x, rhs,
+                     r, ctl, 1, xzero, (const int*)nullptr);
+  return (int)grid.x;
+}
+
+// coarse rhs of level l+1 from the residual of level l
+template <typename T>
+void launch_resid_restrict(const mpp_op_s* op, int l, Faces<T> F, const T* rhs, const T* x, T* bc,
+                           const int* active, hipStream_t s) {
+  const int n = op->lev[l].n;
+  const StTiles tl = st_tiles(n, kStKZ);
+  const dim3 grid(st_grid(tl), op->batch);
+  if (l == 0)
+    hipLaunchKernelGGL((k_resid_restrict_z<T, true>), grid, dim3(kStThreads), 0, s, F, n, tl,
+                       kStKZ, rhs, x, bc, active);
+  else
+    hipLaunchKernelGGL((k_resid_restrict_z<T, false>), grid, dim3(kStThreads), 0, s, F, n, tl,
+                       kStKZ, rhs, x, bc, active);
+}
+
+// ------------------------------------------------------------------------------
+// profiler: HIP events around launches
+// ------------------------------------------------------------------------------
+const char* kKernelNames[kKernelIds] = {
+    "apply_dot", "residual", "smooth_colour", "resid_restrict", "prolong_add",  "dot",
+    "update_p",  "update_xr", "coarse_vcycle", "apply",        "rb_sweep_zero", "rb_sweep",
+    "rb_sweep_prolong"};
+
+hipEvent_t prof_event(Prof& P) {
+  if (P.used == P.pool.size()) {
+    hipEvent_t e;
+    ck(hipEventCreate(&e));
+    P.pool.push_back(e);
+  }
+  return P.pool[P.used++];
+}
+
+// Folds finished records into the totals (the stream must be synchronised).
+void prof_collect(Prof& P) {
+  for (const ProfRec& r : P.recs) {
+    float ms = 0.f;
+    ck(hipEventElapsedTime(&ms, r.a, r.b));
+    P.ms[r.kid] += ms;
+    P.bytes[r.kid] += r.bytes;
+    P.launches[r.kid] += 1;
+  }
+  P.recs.clear();
+  P.used = 0;
+}
+
+template <class F>
+void timed(mpp_op_s* op, int kid, double bytes, hipStream_t s, F&& launch) {
+  Prof& P = op->prof;
+  if (!P.on) {
+    launch();
+    return;
+  }
+  hipEvent_t a = prof_event(P), b = prof_event(P);
+  ck(hipEventRecord(a, s));
+  launch();
+  ck(hipEventRecord(b, s));
+  P.recs.push_back(ProfRec{kid, a, b, bytes});
+}
+
+// Algorithmic bytes of one launch on the finest level: every array the kernel must
+// touch, once; S = bytes per value, per cell of every problem.
+double alg_bytes(const mpp_op_s* op, int kid, size_t S) {
+  const double cells = (double)op->cells * op->batch;
+  const double s = (double)S;
+  switch (kid) {
+    case K_APPLY_DOT: case K_APPLY: return cells * (2 * s + 1);   // x, y, code
+    case K_RESIDUAL: return cells * (3 * s + 1);                  // b, x, r, code
+    case K_SMOOTH: return cells * (2.5 * s + 1);                  // x, b, half of x, code
+    case K_RESID_RESTRICT: return cells * (2 * s + s / 8 + 1);    // b, x, coarse b, code
+    case K_PROLONG: return cells * (2 * s + s / 8);               // x (r+w), coarse x
+    case K_DOT: return cells * 2 * s;
+    case K_UPDATE_P: return cells * 3 * s;
+    case K_UPDATE_XR: return cells * 6 * s;
+    case K_RB_ZERO: return cells * (2 * s + 1);                   // b, code, out
+    case K_RB: return cells * (3 * s + 1);                        // x_in, b, code, out
+    case K_RB_PROLONG: return cells * (3 * s + s / 8 + 1);        // + coarse correction
+    default: return 0.0;
+  }
+}
+
+template <typename T> const T* lvl_f(const Level& L, int a);
+template <> const double* lvl_f<double>(const Level& L, int a) { return L.f64[a]; }
+template <> const float* lvl_f<float>(const Level& L, int a) { return L.f32[a]; }
 
 // ------------------------------------------------------------------------------
 // V-cycle: z ~= A^{-1} r, zero initial guess
 // ------------------------------------------------------------------------------
+template <typename T> T* level0_tmp(mpp_op_s* op);
+template <> double* level0_tmp<double>(mpp_op_s* op) { return op->q; }
+template <> float* level0_tmp<float>(mpp_op_s* op) { return op->q32; }
+
 template <typename T>
-void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, hipStream_t s) {
+void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, hipStream_t s,
+            const Ctl* dctl = nullptr, int* dot_parts = nullptr);
+
+// A level with fused sweeps: 2 nu out-of-place sweeps alternate between x and a
+// scratch array so that the last one lands in x; the prolongation is folded into the
+// first post-smoothing sweep and r.z (b.x) into the last one when dot_parts is given.
+template <typename T>
+void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active,
+                  hipStream_t s, const Ctl* dctl, int* dot_parts) {
   Level& L = op->lev[l];
-  const int B = op->batch;
-  if (l == op->nlev - 1) {
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(B), dim3(kBlock), 0, s, op->coarse_inv,
-                       op->coarse_m, rhs, x, active);
-    ck_launch();
-    return;
-  }
+  Level& Lc = op->lev[l + 1];
+  const int B = op->batch, n = L.n;
   const Faces<T> F = faces_of<T>(op, l);
-  const dim3 g = grid_of(L, B);
-  const int n = L.n, cells = (int)L.cells;
-  auto smooth = [&](int colour, int from_zero) {
-    hipLaunchKernelGGL(k_smooth<T>, g, dim3(kBlock), 0, s, F, n, cells, rhs, x, colour,
-                       from_zero, active);
+  T* tmp = l == 0 ? level0_tmp<T>(op) : lvl_t<T>(L);
+  const RbTiles tl = rb_tiles(n, B);
+  const dim3 grid(rb_grid(tl), B);
+  const Ctl ctl = dctl ? *dctl : op->outer;
+  const bool fine = l == 0;
+  auto dst = [&](int sw) { return ((2 * nu - 1 - sw) % 2 == 0) ? x : tmp; };
+  auto launch = [&](int sw, const T* in, int c1, int mode, int dot) {
+#define MPP_RB(MD, FN)                                                                           \
+  hipLaunchKernelGGL((k_rb_sweep<T, MD, FN>), grid, dim3(kRbThreads), 0, s, F, n, tl, rhs, in,    \
+                     (const T*)(MD == 2 ? lvl_x<T>(Lc) : nullptr), dst(sw), c1, ctl, dot, active)
+    if (fine) {
+      if (mode == 1) MPP_RB(1, true); else if (mode == 2) MPP_RB(2, true); else MPP_RB(0, true);
+    } else {
+      if (mode == 1) MPP_RB(1, false); else if (mode == 2) MPP_RB(2, false); else MPP_RB(0, false);
+    }
+#undef MPP_RB
+  };
+  auto sweep = [&](int sw, const T* in, int c1, int mode, int dot) {
+    const int kid = mode == 1 ? K_RB_ZERO : (mode == 2 ? K_RB_PROLONG : K_RB);
+    if (fine)
+      timed(op, kid, alg_bytes(op, kid, sizeof(T)), s, [&] { launch(sw, in, c1, mode, dot); });
+    else
+      launch(sw, in, c1, mode, dot);
     ck_launch();
   };
-  smooth(0, 1);
-  smooth(1, 0);
-  for (int q = 1; q < nu; ++q) {
-    smooth(0, 0);
-    smooth(1, 0);
-  }
-  Level& Lc = op->lev[l + 1];
-  hipLaunchKernelGGL(k_resid_restrict<T>, grid_of(Lc, B), dim3(kBlock), 0, s, F, n, rhs, x,
-                     lvl_b<T>(Lc), active);
+  sweep(0, nullptr, 0, 1, 0);
+  for (int q = 1; q < nu; ++q) sweep(q, dst(q - 1), 0, 0, 0);
+  const T* xpre = dst(nu - 1);
+  auto restrict_ = [&] { launch_resid_restrict<T>(op, l, F, rhs, xpre, lvl_b<T>(Lc), active, s); };
+  if (fine)
+    timed(op, K_RESID_RESTRICT, alg_bytes(op, K_RESID_RESTRICT, sizeof(T)), s, restrict_);
+  else
+    restrict_();
   ck_launch();
-  vcycle<T>(op, l + 1, lvl_b<T>(Lc), lvl_x<T>(Lc), nu, active, s);
-  hipLaunchKernelGGL(k_prolong_add<T>, g, dim3(kBlock), 0, s, n, lvl_x<T>(Lc), x, active);
-  ck_launch();
-  for (int q = 0; q < nu; ++q) {
-    smooth(1, 0);
-    smooth(0, 0);
+  if (fine)
+    timed(op, K_COARSE_VCYCLE, 0.0, s,
+          [&] { vcycle<T>(op, 1, lvl_b<T>(Lc), lvl_x<T>(Lc), nu, active, s); });
+  else
+    vcycle<T>(op, l + 1, lvl_b<T>(Lc), lvl_x<T>(Lc), nu, active, s);
+  const int want = dot_parts ? 1 : 0;
+  sweep(nu, xpre, 1, 2, (nu == 1) ? want : 0);
+  for (int q = nu + 1; q < 2 * nu; ++q) sweep(q, dst(q - 1), 1, 0, (q == 2 * nu - 1) ? want : 0);
+  if (dot_parts) *dot_parts = grid.x;
+}
+
+template <typename T>
+void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, hipStream_t s,
+            const Ctl* dctl, int* dot_parts) {
+  Level& L = op->lev[l];
+  const int B = op->batch;
+  if (dot_parts) *dot_parts = 0;
+  if (l < op->nlev - 1 && L.cells > (size_t)kSmallCells) {
+    vcycle_fused<T>(op, l, rhs, x, nu, active, s, l == 0 ? dctl : nullptr,
+                    l == 0 ? dot_parts : nullptr);
+    return;
   }
+  // this level and everything below: one workgroup per problem, one launch
+  SmallCycle<T> S{};
+  S.nlev = op->nlev - l;
+  for (int q = 0; q < S.nlev; ++q) {
+    Level& Lq = op->lev[l + q];
+    S.lv[q] = SmallLevel<T>{Lq.n, lvl_f<T>(Lq, 0), lvl_f<T>(Lq, 1), lvl_f<T>(Lq, 2),
+                            q == 0 ? const_cast<T*>(rhs) : lvl_b<T>(Lq), q == 0 ? x : lvl_x<T>(Lq)};
+  }
+  S.inv = op->coarse_inv;
+  S.m = op->coarse_m;
+  S.nu = nu;
+  hipLaunchKernelGGL(k_small_cycle<T>, dim3(B), dim3(kSmallBlock), 0, s, S, active);
+  ck_launch();
 }
 
 bool any_active(mpp_op_s* op, const Ctl& ctl, hipStream_t s) {
   ck(hipMemcpyAsync(op->h_active, ctl.active, sizeof(int) * op->batch, hipMemcpyDeviceToHost, s));
   ck(hipStreamSynchronize(s));
+  if (op->prof.on) prof_collect(op->prof);
   for (int b = 0; b < op->batch; ++b)
     if (op->h_active[b]) return true;
   return false;
 }
 
 // ------------------------------------------------------------------------------
+// launch graphs: a block of CG iterations is captured once per operator and
+// argument set and replayed (no memset nodes: every buffer a replay relies on is
+// written by kernels)
+// ------------------------------------------------------------------------------
+template <class F>
+void run_graph(mpp_op_s* op, const GraphKey& key, hipStream_t s, F&& enqueue) {
+  for (GraphEntry& g : op->graphs)
+    if (g.key == key) {
+      ck(hipGraphLaunch(g.exec, s));
+      return;
+    }
+  if (!op->cap_stream) ck(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  ck(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue(op->cap_stream);
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(op->cap_stream, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  ck(hipStreamEndCapture(op->cap_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    throw HipError{e};
+  }
+  op->graphs.push_back(GraphEntry{key, graph, exec});
+  ck(hipGraphLaunch(exec, s));
+}
+
+// ------------------------------------------------------------------------------
 // Preconditioned CG on -A for every problem whose ctl.active flag is set by the
 // start epilogue.  Uses ctl.scal[S_TOL2] as the per-problem target on ||r||^2.
 // ------------------------------------------------------------------------------
+// z = V(r) and the r.z epilogue (the dot is folded into the last sweep when the
+// finest level uses the fused sweeps)
+template <typename T>
+void vcycle_dot(mpp_op_s* op, Ctl& ctl, const T* r, T* z, int nu, const EpiArgs& erz,
+                hipStream_t s) {
+  const Level& L0 = op->lev[0];
+  int parts = 0;
+  vcycle<T>(op, 0, r, z, nu, ctl.active, s, &ctl, &parts);
+  if (parts == 0) {
+    timed(op, K_DOT, alg_bytes(op, K_DOT, sizeof(T)), s, [&] {
+      hipLaunchKernelGGL(k_dot<T>, grid_of(L0, op->batch), dim3(kBlock), 0, s, r, z,
+                         (int)L0.cells, ctl, erz, ctl.active);
+    });
+    ck_launch();
+    parts = L0.bpp;
+  }
+  finish_sums(op, ctl, erz, parts, s);
+}
+
+template <typename T>
+void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu, int iters,
+                    hipStream_t s) {
+  Level& L0 = op->lev[0];
+  const dim3 g = grid_of(L0, op->batch);
+  const Faces<T> F = faces_of<T>(op, 0);
+  const int cells = (int)L0.cells;
+  const EpiArgs erz = epi(E_RZ), epq = epi(E_PQ), err = epi(E_RR_ITER);
+  for (int it = 0; it < iters; ++it) {
+    int parts = 0;
+    timed(op, K_APPLY_DOT, alg_bytes(op, K_APPLY_DOT, sizeof(T)), s,
+          [&] { parts = launch_apply<T>(op, F, p, q, ctl, 1, ctl.active, s); });
+    ck_launch();
+    finish_sums(op, ctl, epq, parts, s);
+    timed(op, K_UPDATE_XR, alg_bytes(op, K_UPDATE_XR, sizeof(T)), s, [&] {
+      hipLaunchKernelGGL(k_update_xr<T>, g, dim3(kBlock), 0, s, x, r, p, q, cells, ctl, err);
+    });
+    ck_launch();
+    finish_sums(op, ctl, err, L0.bpp, s);
+    vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
+    timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
+      hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 0);
+    });
+    ck_launch();
+  }
+}
+
 template <typename T>
 void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int nu,
          int check_every, int xzero, const EpiArgs& start, hipStream_t s) {
   Level& L0 = op->lev[0];
-  const int B = op->batch;
-  const dim3 g = grid_of(L0, B);
+  const dim3 g = grid_of(L0, op->batch);
   const Faces<T> F = faces_of<T>(op, 0);
-  const int n = L0.n, cells = (int)L0.cells;
-  hipLaunchKernelGGL(k_residual<T>, g, dim3(kBlock), 0, s, F, n, cells, rhs, x, r, ctl, start,
-                     xzero);
+  const int cells = (int)L0.cells;
+  int parts = 0;
+  timed(op, K_RESIDUAL, alg_bytes(op, K_RESIDUAL, sizeof(T)), s,
+        [&] { parts = launch_residual<T>(op, F, rhs, x, r, ctl, xzero, s); });
   ck_launch();
+  finish_sums(op, ctl, start, parts, s);
   if (!any_active(op, ctl, s)) return;
-  EpiArgs erz = epi(E_RZ), epq = epi(E_PQ), err = epi(E_RR_ITER);
+  EpiArgs erz = epi(E_RZ);
   erz.first = 1;
-  vcycle<T>(op, 0, r, z, nu, ctl.active, s);
-  hipLaunchKernelGGL(k_dot<T>, g, dim3(kBlock), 0, s, r, z, cells, ctl, erz, ctl.active);
+  vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
+  timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
+    hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 1);
+  });
   ck_launch();
-  hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 1);
-  ck_launch();
-  erz.first = 0;
-  const int cap = ctl.max_iter + check_every + 1;
-  for (int it = 0; it < cap; ++it) {
-    hipLaunchKernelGGL((k_apply<T, true>), g, dim3(kBlock), 0, s, F, n, cells, p, q, ctl, epq,
-                       ctl.active);
-    ck_launch();
-    hipLaunchKernelGGL(k_update_xr<T>, g, dim3(kBlock), 0, s, x, r, p, q, cells, ctl, err);
-    ck_launch();
-    if ((it + 1) % check_every == 0 && !any_active(op, ctl, s)) return;
-    vcycle<T>(op, 0, r, z, nu, ctl.active, s);
-    hipLaunchKernelGGL(k_dot<T>, g, dim3(kBlock), 0, s, r, z, cells, ctl, erz, ctl.active);
-    ck_launch();
-    hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 0);
-    ck_launch();
+  // iterations in blocks of check_every; the kernels themselves stop working on a
+  // problem once it has converged, so a block may overrun the last useful iteration
+  const bool graphs = op->use_graphs && !op->prof.on;
+  const GraphKey key{(int)sizeof(T), nu, check_every, ctl.max_iter,
+                     {(const void*)ctl.scal, x, r, z, p, q}};
+  for (int done = 0; done <= ctl.max_iter; done += check_every) {
+    if (graphs)
+      run_graph(op, key, s, [&](hipStream_t cs) {
+        pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, cs);
+      });
+    else
+      pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, s);
+    if (!any_active(op, ctl, s)) return;
   }
-  any_active(op, ctl, s);
 }
 
 void reset_ctl(mpp_op_s* op, Ctl& ctl, int max_iter, hipStream_t s) {
@@ -270,11 +533,13 @@ void make_rhs(mpp_op_s* op, Ctl& ctl, const double* f, double* out, hipStream_t 
   em.inv_cells = 1.0 / (double)L0.cells;
   hipLaunchKernelGGL(k_rhs_sum, g, dim3(kBlock), 0, s, f, op->jterm, out, cells, ctl, em);
   ck_launch();
+  finish_sums(op, ctl, em, L0.bpp, s);
   EpiArgs eb = epi(E_BB);
   eb.rtol2 = rtol * rtol;
   hipLaunchKernelGGL(k_sub_mean_sq, g, dim3(kBlock), 0, s, out, cells, ctl, eb, (int)S_MEAN,
                      want_bb ? 1 : 0);
   ck_launch();
+  if (want_bb) finish_sums(op, ctl, eb, L0.bpp, s);
 }
 
 // x -= mean(x)
@@ -287,6 +552,7 @@ void remove_mean(mpp_op_s* op, Ctl& ctl, double* x, hipStream_t s) {
   e.inv_cells = 1.0 / (double)L0.cells;
   hipLaunchKernelGGL(k_sum<double>, g, dim3(kBlock), 0, s, x, cells, ctl, e);
   ck_launch();
+  finish_sums(op, ctl, e, L0.bpp, s);
   hipLaunchKernelGGL(k_sub_mean_sq, g, dim3(kBlock), 0, s, x, cells, ctl, e, (int)S_SUM, 0);
   ck_launch();
 }
@@ -345,95 +611,179 @@ const char* mpp_strerror(int st) {
   }
 }
 
-int mpp_build_operator(const mpp_desc* desc, const double* phi, const double* rho_neg,
-                       const double* rho_pos, const double* sigma, void* workspace,
-                       size_t workspace_bytes, void* stream, mpp_op* out) {
-  if (out) *out = nullptr;
-  if (!desc_ok(desc) || !phi || !rho_neg || !rho_pos || !sigma || !workspace || !out)
-    return MPP_EINVAL;
-  const int B = desc->batch;
-  std::vector<double> host(3 * (size_t)B);
+}  // extern "C"
+
+namespace {
+
+// Validates the per-problem constants into a host array [B][3].
+bool read_params(int B, const double* rho_neg, const double* rho_pos, const double* sigma,
+                 std::vector<double>& host) {
+  if (!rho_neg || !rho_pos || !sigma) return false;
+  host.assign(3 * (size_t)B, 0.0);
   for (int b = 0; b < B; ++b) {
     const double rn = rho_neg[b], rp = rho_pos[b], sg = sigma[b];
     if (!(rn > 0.0) || !(rp > 0.0) || !std::isfinite(rn) || !std::isfinite(rp) ||
         !(sg >= 0.0) || !std::isfinite(sg))
-      return MPP_EINVAL;
+      return false;
     host[3 * b + 0] = rn;
     host[3 * b + 1] = rp;
     host[3 * b + 2] = sg;
   }
+  return true;
+}
+
+// Faces, curvature, jump term and the multigrid hierarchy for level set phi, in the
+// operator's workspace.  Returns MPP_EINVAL for a non-finite phi.
+int build_into(mpp_op_s* op, const double* phi, const std::vector<double>& host, hipStream_t s) {
+  const int B = op->batch;
+  ck(hipMemcpyAsync(op->rho, host.data(), sizeof(double) * 3 * B, hipMemcpyHostToDevice, s));
+  // the outer status array doubles as the non-finite flag during the build
+  ck(hipMemsetAsync(op->outer.status, 0, sizeof(int) * B, s));
+  hipLaunchKernelGGL(k_params, dim3((B + 255) / 256), dim3(256), 0, s, op->rho, op->inv_rho64,
+                     op->inv_rho32, B);
+  ck_launch();
+  Level& L0 = op->lev[0];
+  const int n = op->n, cells = (int)L0.cells;
+  const dim3 g = grid_of(L0, B);
+  hipLaunchKernelGGL(k_faces, g, dim3(kBlock), 0, s, phi, op->rho, n, cells, L0.code, L0.f64[0],
+                     L0.f64[1], L0.f64[2], L0.f32[0], L0.f32[1], L0.f32[2], op->outer.status);
+  ck_launch();
+  hipLaunchKernelGGL(k_curvature, g, dim3(kBlock), 0, s, phi, L0.code, n, cells, op->kappa);
+  ck_launch();
+  hipLaunchKernelGGL(k_jump, g, dim3(kBlock), 0, s, phi, L0.code, op->kappa, op->rho, n, cells,
+                     op->jterm);
+  ck_launch();
+  for (int l = 1; l < op->nlev; ++l) {
+    Level& Lf = op->lev[l - 1];
+    Level& Lc = op->lev[l];
+    hipLaunchKernelGGL(k_coarsen_faces, grid_of(Lc, B), dim3(kBlock), 0, s, Lf.f64[0], Lf.f64[1],
+                       Lf.f64[2], Lf.n, Lc.f64[0], Lc.f64[1], Lc.f64[2], Lc.f32[0], Lc.f32[1],
+                       Lc.f32[2]);
+    ck_launch();
+  }
+  const Level& Lc = op->lev[op->nlev - 1];
+  hipLaunchKernelGGL(k_coarse_factor, dim3(B), dim3(kBlock), 0, s, Lc.f64[0], Lc.f64[1],
+                     Lc.f64[2], Lc.n, op->coarse_work, op->coarse_inv);
+  ck_launch();
+  ck(hipMemcpyAsync(op->h_status, op->outer.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+  ck(hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b)
+    if (op->h_status[b]) return MPP_EINVAL;
+  return MPP_OK;
+}
+
+void free_op(mpp_op_s* op) {
+  for (GraphEntry& g : op->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
+  for (hipEvent_t e : op->prof.pool) (void)hipEventDestroy(e);
+  delete[] op->h_active;
+  delete[] op->h_iters;
+  delete[] op->h_status;
+  delete[] op->h_scal;
+  delete op;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpp_build_operator(const mpp_desc* desc, const double* phi, const double* rho_neg,
+                       const double* rho_pos, const double* sigma, void* workspace,
+                       size_t workspace_bytes, void* stream, mpp_op* out) {
+  if (out) *out = nullptr;
+  if (!desc_ok(desc) || !phi || !workspace || !out) return MPP_EINVAL;
+  const int B = desc->batch;
+  std::vector<double> host;
+  if (!read_params(B, rho_neg, rho_pos, sigma, host)) return MPP_EINVAL;
+  mpp_op_s tmp;
+  const size_t need = layout(&tmp, desc, nullptr);
+  if (workspace_bytes < need) return MPP_ENOMEM;
   mpp_op_s* op = new (std::nothrow) mpp_op_s();
   if (!op) return MPP_ENOMEM;
   char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
-  const size_t need = layout(op, desc, nullptr);
-  if (workspace_bytes < need) {
-    delete op;
-    return MPP_ENOMEM;
-  }
   layout(op, desc, base);
+  op->flags = desc->flags;
+  op->use_graphs = (desc->flags & MPP_FLAG_NO_GRAPHS) == 0;
   op->ws = workspace;
   op->ws_bytes = workspace_bytes;
   op->h_active = new int[B];
   op->h_iters = new int[B];
   op->h_status = new int[B];
   op->h_scal = new double[(size_t)B * kSlots];
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int st;
   try {
-    ck(hipMemcpyAsync(op->rho, host.data(), sizeof(double) * 3 * B, hipMemcpyHostToDevice, s));
-    ck(hipMemsetAsync(op->counters, 0, sizeof(unsigned) * B, s));
-    // a scratch int for the non-finite flag: reuse the outer status array
-    ck(hipMemsetAsync(op->outer.status, 0, sizeof(int) * B, s));
-    hipLaunchKernelGGL(k_params, dim3((B + 255) / 256), dim3(256), 0, s, op->rho, op->inv_rho64,
-                       op->inv_rho32, B);
-    ck_launch();
-    Level& L0 = op->lev[0];
-    const int n = op->n, cells = (int)L0.cells;
-    const dim3 g = grid_of(L0, B);
-    hipLaunchKernelGGL(k_faces, g, dim3(kBlock), 0, s, phi, op->rho, n, cells, L0.code,
-                       L0.f64[0], L0.f64[1], L0.f64[2], L0.f32[0], L0.f32[1], L0.f32[2],
-                       op->outer.status);
-    ck_launch();
-    hipLaunchKernelGGL(k_curvature, g, dim3(kBlock), 0, s, phi, L0.code, n, cells, op->kappa);
-    ck_launch();
-    hipLaunchKernelGGL(k_jump, g, dim3(kBlock), 0, s, phi, L0.code, op->kappa, op->rho, n, cells,
-                       op->jterm);
-    ck_launch();
-    for (int l = 1; l < op->nlev; ++l) {
-      Level& Lf = op->lev[l - 1];
-      Level& Lc = op->lev[l];
-      hipLaunchKernelGGL(k_coarsen_faces, grid_of(Lc, B), dim3(kBlock), 0, s, Lf.f64[0],
-                         Lf.f64[1], Lf.f64[2], Lf.n, Lc.f64[0], Lc.f64[1], Lc.f64[2], Lc.f32[0],
-                         Lc.f32[1], Lc.f32[2]);
-      ck_launch();
-    }
-    const Level& Lc = op->lev[op->nlev - 1];
-    hipLaunchKernelGGL(k_coarse_factor, dim3(B), dim3(kBlock), 0, s, Lc.f64[0], Lc.f64[1],
-                       Lc.f64[2], Lc.n, op->coarse_work, op->coarse_inv);
-    ck_launch();
-    ck(hipMemcpyAsync(op->h_status, op->outer.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    ck(hipStreamSynchronize(s));
+    st = build_into(op, phi, host, reinterpret_cast<hipStream_t>(stream));
   } catch (HipError& e) {
-    delete[] op->h_active; delete[] op->h_iters; delete[] op->h_status; delete[] op->h_scal;
-    delete op;
+    st = status_of(e.e);
+  }
+  if (st != MPP_OK) {
+    free_op(op);
+    return st;
+  }
+  *out = op;
+  return MPP_OK;
+}
+
+int mpp_update_operator(mpp_op op, const double* phi, const double* rho_neg,
+                        const double* rho_pos, const double* sigma, void* stream) {
+  if (!op || !phi) return MPP_EINVAL;
+  std::vector<double> host;
+  if (!read_params(op->batch, rho_neg, rho_pos, sigma, host)) return MPP_EINVAL;
+  try {
+    return build_into(op, phi, host, reinterpret_cast<hipStream_t>(stream));
+  } catch (HipError& e) {
     return status_of(e.e);
   }
-  for (int b = 0; b < B; ++b)
-    if (op->h_status[b]) {
-      delete[] op->h_active; delete[] op->h_iters; delete[] op->h_status; delete[] op->h_scal;
-      delete op;
-      return MPP_EINVAL;  // non-finite phi
+}
+
+int mpp_profile_start(mpp_op op) {
+  if (!op) return MPP_EINVAL;
+  Prof& P = op->prof;
+  P.on = true;
+  P.recs.clear();
+  P.used = 0;
+  for (int k = 0; k < kKernelIds; ++k) {
+    P.ms[k] = 0.0;
+    P.bytes[k] = 0.0;
+    P.launches[k] = 0;
+  }
+  return MPP_OK;
+}
+
+int mpp_profile_stop(mpp_op op, mpp_kernel_stat* stats, int32_t max_stats, int32_t* n_stats) {
+  if (!op || (max_stats > 0 && !stats)) return MPP_EINVAL;
+  Prof& P = op->prof;
+  try {
+    for (const ProfRec& r : P.recs) ck(hipEventSynchronize(r.b));
+    prof_collect(P);
+  } catch (HipError& e) {
+    P.on = false;
+    return status_of(e.e);
+  }
+  P.on = false;
+  int cnt = 0;
+  for (int k = 0; k < kKernelIds; ++k) {
+    if (P.launches[k] == 0) continue;
+    if (cnt < max_stats) {
+      mpp_kernel_stat& st = stats[cnt];
+      std::memset(&st, 0, sizeof(st));
+      std::snprintf(st.name, sizeof(st.name), "%s", kKernelNames[k]);
+      st.launches = (int32_t)P.launches[k];
+      st.total_ms = P.ms[k];
+      st.bytes = P.bytes[k];
     }
-  *out = op;
+    ++cnt;
+  }
+  if (n_stats) *n_stats = std::min(cnt, (int)std::max(max_stats, 0));
   return MPP_OK;
 }
 
 void mpp_destroy_operator(mpp_op op) {
   if (!op) return;
-  delete[] op->h_active;
-  delete[] op->h_iters;
-  delete[] op->h_status;
-  delete[] op->h_scal;
-  delete op;
+  free_op(op);
 }
 
 int mpp_levels(mpp_op op, int32_t* nlevels, int32_t* sizes) {
@@ -448,10 +798,9 @@ int mpp_apply_stencil(mpp_op op, const double* x, double* y, void* stream) {
   if (!op || !x || !y || x == y) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   try {
-    const Level& L0 = op->lev[0];
-    hipLaunchKernelGGL((k_apply<double, false>), grid_of(L0, op->batch), dim3(kBlock), 0, s,
-                       faces_of<double>(op, 0), L0.n, (int)L0.cells, x, y, op->outer, epi(0),
-                       (const int*)nullptr);
+    timed(op, K_APPLY, alg_bytes(op, K_APPLY, sizeof(double)), s, [&] {
+      launch_apply<double>(op, faces_of<double>(op, 0), x, y, op->outer, 0, nullptr, s);
+    });
     ck_launch();
   } catch (HipError& e) {
     return status_of(e.e);
@@ -524,17 +873,23 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
     Ctl& oc = op->outer;
     reset_ctl(op, oc, o.max_iter, s);
     make_rhs(op, oc, f, op->b, s, o.rtol, true);
+    // the iterate lives in the workspace (captured launch graphs refer to it); the
+    // caller's p is copied in and out
+    double* const user_p = p;
+    p = op->x;
     if (o.guess == MPP_GUESS_ZERO) {
       hipLaunchKernelGGL(k_fill<double>, g, dim3(kBlock), 0, s, p, cells, 0.0);
       ck_launch();
+    } else {
+      ck(hipMemcpyAsync(p, user_p, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
     }
     EpiArgs start = epi(E_START);
     if (o.mode == MPP_MODE_FP64) {
       for (int restart = 0; restart < 4; ++restart) {
         pcg<double>(op, oc, op->b, p, op->r, op->z, op->p, op->q, o.nu, o.check_every, 0, start, s);
         // true residual; re-arms the problems that are not there yet
-        hipLaunchKernelGGL(k_residual<double>, g, dim3(kBlock), 0, s, faces_of<double>(op, 0),
-                           L0.n, cells, op->b, p, op->r, oc, start, 0);
+        finish_sums(op, oc, start,
+                    launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
         ck_launch();
         for (int b = 0; b < B; ++b) outer_count[b] += 1;
         if (!any_active(op, oc, s)) break;
@@ -545,13 +900,13 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
       EpiArgs istart = epi(E_START_REL);
       istart.rtol2 = o.inner_rtol * o.inner_rtol;
       istart.gate = oc.active;
-      bool settled = false;
+      bool settled = false, converged = false;
       for (int outer = 0; outer < 40 && !settled; ++outer) {
-        hipLaunchKernelGGL(k_residual<double>, g, dim3(kBlock), 0, s, faces_of<double>(op, 0),
-                           L0.n, cells, op->b, p, op->r, oc, start, 0);
+        finish_sums(op, oc, start,
+                    launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
         ck_launch();
         if (!any_active(op, oc, s)) {
-          settled = true;
+          settled = converged = true;
           break;
         }
         for (int b = 0; b < B; ++b) outer_count[b] += op->h_active[b];
@@ -570,12 +925,14 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
         for (int b = 0; b < B; ++b)
           if (op->h_status[b] != MPP_OK) settled = true;
       }
-      // final true residual of the returned iterate
-      hipLaunchKernelGGL(k_residual<double>, g, dim3(kBlock), 0, s, faces_of<double>(op, 0),
-                         L0.n, cells, op->b, p, op->r, oc, start, 0);
-      ck_launch();
+      if (!converged) {   // true residual of the returned iterate
+        finish_sums(op, oc, start,
+                    launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
+        ck_launch();
+      }
     }
     remove_mean(op, oc, p, s);
+    ck(hipMemcpyAsync(user_p, p, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
     ck(hipMemcpyAsync(op->h_scal, oc.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
     ck(hipMemcpyAsync(op->h_status, oc.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     ck(hipMemcpyAsync(op->h_iters, (o.mode == MPP_MODE_FP64 ? oc.iters : op->inner.iters),

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "mpp.h"
 
@@ -64,14 +65,73 @@ struct Level {
   // V-cycle right-hand side and correction of this level (levels >= 1)
   double* b64 = nullptr;
   double* x64 = nullptr;
+  double* t64 = nullptr;    // scratch for the out-of-place sweeps
   float* b32 = nullptr;
   float* x32 = nullptr;
+  float* t32 = nullptr;
   int bpp = 1;              // blocks per problem of the cell kernels on this level
+};
+
+// Kernel classes timed by the profiler.
+enum KernelId {
+  K_APPLY_DOT = 0,   // q = A p and p.q
+  K_RESIDUAL,        // r = b - A x and ||r||^2
+  K_SMOOTH,          // one colour of red-black Gauss-Seidel, in place
+  K_RESID_RESTRICT,  // coarse rhs = mean over children of b - A x
+  K_PROLONG,         // x += parent value
+  K_DOT,             // r.z
+  K_UPDATE_P,        // p = z + beta p
+  K_UPDATE_XR,       // x += alpha p, r -= alpha q, ||r||^2
+  K_COARSE_VCYCLE,   // all levels below the finest, one record per V-cycle
+  K_APPLY,           // y = A x
+  K_RB_ZERO,         // fused red-black sweep from a zero iterate (finest level)
+  K_RB,              // fused red-black sweep
+  K_RB_PROLONG,      // fused red-black sweep after adding the coarse correction
+  kKernelIds
+};
+
+struct ProfRec {
+  int kid;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<ProfRec> recs;
+  double ms[kKernelIds] = {};
+  double bytes[kKernelIds] = {};
+  long launches[kKernelIds] = {};
+};
+
+// A captured block of CG iterations and what it was captured for.
+struct GraphKey {
+  int tsize, nu, iters, max_iter;
+  const void* ptr[6];
+  bool operator==(const GraphKey& o) const {
+    if (tsize != o.tsize || nu != o.nu || iters != o.iters || max_iter != o.max_iter) return false;
+    for (int q = 0; q < 6; ++q)
+      if (ptr[q] != o.ptr[q]) return false;
+    return true;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
 };
 
 }  // namespace mpp
 
 struct mpp_op_s {
+  mpp::Prof prof;
+  bool use_graphs = true;
+  std::vector<mpp::GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
+  double* x = nullptr;              // FP64 iterate (the caller's p is copied in and out)
   int n = 0, batch = 0, nlev = 0;
   uint32_t flags = 0;
   mpp::Level lev[mpp::kMaxLevels];

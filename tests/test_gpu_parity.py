@@ -270,3 +270,49 @@ def test_rising_bubble_256_full_size(mode):
     e = rel2(ph, po)
     print("err vs oracle %.3e" % e, flush=True)
     assert e <= 1e-8
+
+
+# ---------------------------------------------------------------------------------
+# launch graphs and in-place rebuilds
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_graph_replays_match_direct_launches(mode):
+    pr = G.many_bubbles_problem(n=64, count=5, seed=8)
+    phi, f = to_dev(pr.phi), to_dev(pr.f)
+    direct = M.Operator(phi, pr.rho_neg, pr.rho_pos, pr.sigma, graphs=False)
+    pd, idd = direct.solve(f, mode=mode, check_every=3)
+    ref = to_host(pd)
+    graphed = M.Operator(phi, pr.rho_neg, pr.rho_pos, pr.sigma)
+    for rep in range(4):
+        # eager work and synchronisation between the replays
+        y = direct.apply(pd)
+        torch.cuda.synchronize()
+        pg, ig = graphed.solve(f, mode=mode, check_every=3)
+        assert ig[0].iters == idd[0].iters
+        assert np.array_equal(to_host(pg), ref), rep
+
+
+def test_update_operator_equals_fresh_build():
+    n = 32
+    a = G.rising_bubble_problem(0, n=n)
+    b = G.rising_bubble_problem(30, n=n)
+    op = M.Operator(to_dev(a.phi), a.rho_neg, a.rho_pos, a.sigma)
+    op.solve(to_dev(a.f))
+    op.update(to_dev(b.phi), b.rho_neg, b.rho_pos, b.sigma)
+    p1, i1 = op.solve(to_dev(b.f))
+    fresh = M.Operator(to_dev(b.phi), b.rho_neg, b.rho_pos, b.sigma)
+    p2, i2 = fresh.solve(to_dev(b.f))
+    assert np.array_equal(to_host(p1), to_host(p2))
+    f1, f2 = op.fields(), fresh.fields()
+    for k in f1:
+        assert torch.equal(f1[k], f2[k]), k
+
+
+def test_profiler_reports_kernels():
+    pr = G.rising_bubble_problem(0, n=64)
+    op = M.Operator(to_dev(pr.phi), pr.rho_neg, pr.rho_pos, pr.sigma)
+    op.profile_start()
+    p, infos = op.solve(to_dev(pr.f))
+    st = op.profile_stop()
+    assert st["apply_dot"]["launches"] == infos[0].iters or st["apply_dot"]["launches"] >= infos[0].iters
+    assert all(v["ms"] > 0 for v in st.values())
