@@ -397,8 +397,12 @@ __global__ void k_coarse_factor(const double* __restrict__ cx, const double* __r
   const int b = blockIdx.x;
   const int m = n * n * n;
   const size_t bm = (size_t)b * m * m, bc = (size_t)b * m;
-  double* M = work + bm;
-  double* X = inv + bm;
+  // small coarsest levels (the usual 4^3) are factored in LDS
+  constexpr int kLdsM = 64;
+  __shared__ double Ms[kLdsM * kLdsM], Xs[kLdsM * kLdsM];
+  const bool lds = m <= kLdsM;
+  double* M = lds ? Ms : work + bm;
+  double* X = lds ? Xs : inv + bm;
   const double inv_h2 = (double)n * (double)n, jm = 1.0 / m;
   for (size_t q = threadIdx.x; q < (size_t)m * m; q += blockDim.x) M[q] = jm;
   __syncthreads();
@@ -449,6 +453,10 @@ __global__ void k_coarse_factor(const double* __restrict__ cx, const double* __r
       for (int q = r + 1; q < m; ++q) s -= M[(size_t)q * m + r] * x[q];
       x[r] = s / M[(size_t)r * m + r];
     }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < m * m; q += blockDim.x) inv[bm + q] = Xs[q];
   }
 }
 

@@ -10,6 +10,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -125,7 +128,9 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
   op->p32 = cv.take<float>(C);
   op->q32 = cv.take<float>(C);
   op->d32 = cv.take<float>(C);
-  for (int l = 0; l < L; ++l) op->pstride = std::max(op->pstride, rb_grid(rb_tiles(sizes[l], B)));
+  for (int l = 0; l < L; ++l)   // every z-chunk the tuner may pick
+    for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2)
+      op->pstride = std::max(op->pstride, rb_grid(rb_tiles(sizes[l], B, kz)));
   op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
   op->partials = cv.take<double>((size_t)B * op->pstride);
   op->counters = cv.take<unsigned>((size_t)B);
@@ -315,7 +320,7 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
   const int B = op->batch, n = L.n;
   const Faces<T> F = faces_of<T>(op, l);
   T* tmp = l == 0 ? level0_tmp<T>(op) : lvl_t<T>(L);
-  const RbTiles tl = rb_tiles(n, B);
+  const RbTiles tl = rb_tiles(n, B, op->kz[sizeof(T) == 4][l]);
   const dim3 grid(rb_grid(tl), B);
   const Ctl ctl = dctl ? *dctl : op->outer;
   const bool fine = l == 0;
@@ -383,6 +388,90 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
   S.nu = nu;
   hipLaunchKernelGGL(k_small_cycle<T>, dim3(B), dim3(kSmallBlock), 0, s, S, active);
   ck_launch();
+}
+
+// ------------------------------------------------------------------------------
+// tile autotuning: the z-chunk of the fused sweeps (fewer, longer marches versus
+// more blocks) is timed per level with HIP events the first time a shape is solved
+// in a precision, and cached for the process by (n, batch, precision, level size)
+// ------------------------------------------------------------------------------
+struct TuneKey {
+  int n, batch, tsize, nl;
+  bool operator<(const TuneKey& o) const {
+    if (n != o.n) return n < o.n;
+    if (batch != o.batch) return batch < o.batch;
+    if (tsize != o.tsize) return tsize < o.tsize;
+    return nl < o.nl;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+template <typename T>
+void ensure_tuned(mpp_op_s* op, hipStream_t s) {
+  const int w = sizeof(T) == 4;
+  if (op->tuned[w]) return;
+  op->tuned[w] = true;
+  const char* env = std::getenv("MPP_AUTOTUNE");
+  if (env && env[0] == '0') return;
+  const int B = op->batch;
+  hipEvent_t e0, e1;
+  ck(hipEventCreate(&e0));
+  ck(hipEventCreate(&e1));
+  for (int l = 0; l + 1 < op->nlev; ++l) {
+    Level& L = op->lev[l];
+    if (L.cells <= (size_t)kSmallCells) break;
+    const TuneKey key{op->n, B, (int)sizeof(T), L.n};
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        op->kz[w][l] = it->second;
+        continue;
+      }
+    }
+    // time MODE-0 sweeps on zeroed level buffers (contents do not change the cost)
+    T* in = l == 0 ? (T*)(w ? (void*)op->z32 : (void*)op->z) : lvl_x<T>(L);
+    T* out = l == 0 ? level0_tmp<T>(op) : lvl_t<T>(L);
+    const T* rhs = l == 0 ? (const T*)(w ? (void*)op->r32 : (void*)op->r) : lvl_b<T>(L);
+    const dim3 g1 = grid_of(L, B);
+    hipLaunchKernelGGL(k_fill<T>, g1, dim3(kBlock), 0, s, in, (int)L.cells, T(0));
+    hipLaunchKernelGGL(k_fill<T>, g1, dim3(kBlock), 0, s, const_cast<T*>(rhs), (int)L.cells, T(0));
+    ck_launch();
+    const Faces<T> F = faces_of<T>(op, l);
+    float best = 1e30f;
+    int best_kz = 0;
+    for (int kz = 2; kz <= 2 * kRbKZ && kz <= L.n; kz *= 2) {
+      const RbTiles tl = rb_tiles(L.n, B, kz);
+      const dim3 grid(rb_grid(tl), B);
+      auto launch = [&] {
+        if (l == 0)
+          hipLaunchKernelGGL((k_rb_sweep<T, 0, true>), grid, dim3(kRbThreads), 0, s, F, L.n, tl,
+                             rhs, in, (const T*)nullptr, out, 0, op->outer, 0, (const int*)nullptr);
+        else
+          hipLaunchKernelGGL((k_rb_sweep<T, 0, false>), grid, dim3(kRbThreads), 0, s, F, L.n, tl,
+                             rhs, in, (const T*)nullptr, out, 0, op->outer, 0, (const int*)nullptr);
+      };
+      launch();
+      ck(hipEventRecord(e0, s));
+      for (int q = 0; q < 3; ++q) launch();
+      ck(hipEventRecord(e1, s));
+      ck_launch();
+      ck(hipEventSynchronize(e1));
+      float ms = 0.f;
+      ck(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_kz = kz;
+      }
+    }
+    op->kz[w][l] = best_kz;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.emplace(key, best_kz);   // the first tuning of a shape wins
+    op->kz[w][l] = g_tune[key];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 bool any_active(mpp_op_s* op, const Ctl& ctl, hipStream_t s) {
@@ -829,6 +918,7 @@ int mpp_vcycle(mpp_op op, const double* r, double* z, int nu, void* stream) {
   if (!op || !r || !z || r == z || nu < 1) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   try {
+    ensure_tuned<double>(op, s);
     vcycle<double>(op, 0, r, z, nu, nullptr, s);
   } catch (HipError& e) {
     return status_of(e.e);
@@ -870,6 +960,8 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
   std::vector<int> outer_count(B, 0);
   std::vector<int> istatus(B, MPP_OK);
   try {
+    ensure_tuned<double>(op, s);
+    if (o.mode == MPP_MODE_MIXED) ensure_tuned<float>(op, s);
     Ctl& oc = op->outer;
     reset_ctl(op, oc, o.max_iter, s);
     make_rhs(op, oc, f, op->b, s, o.rtol, true);

@@ -132,6 +132,8 @@ struct mpp_op_s {
   std::vector<mpp::GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;
   double* x = nullptr;              // FP64 iterate (the caller's p is copied in and out)
+  int kz[2][mpp::kMaxLevels] = {};  // tuned z-chunk of the fused sweeps [fp32?][level], 0 = default
+  bool tuned[2] = {false, false};
   int n = 0, batch = 0, nlev = 0;
   uint32_t flags = 0;
   mpp::Level lev[mpp::kMaxLevels];

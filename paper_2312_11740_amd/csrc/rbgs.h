@@ -34,14 +34,18 @@ struct RbTiles {
   int kz;              // planes per z-chunk
 };
 
-// z-chunks of kRbKZ planes, shortened (down to 4) while the grid would not give
-// every compute unit a few blocks
-inline RbTiles rb_tiles(int n, int batch = 1) {
+// Tiles for z-chunks of kz planes.  kz = 0 picks the default: chunks of kRbKZ planes,
+// shortened (down to 4) while the grid would not give every compute unit a few blocks.
+inline RbTiles rb_tiles(int n, int batch = 1, int kz = 0) {
   RbTiles t;
   t.ntx = (n + kRbTX - 1) / kRbTX;
   t.nty = (n + kRbTY - 1) / kRbTY;
-  t.kz = kRbKZ;
-  while (t.kz > 4 && (long)t.ntx * t.nty * ((n + t.kz - 1) / t.kz) * batch < 1536) t.kz /= 2;
+  if (kz > 0) {
+    t.kz = kz;
+  } else {
+    t.kz = kRbKZ;
+    while (t.kz > 4 && (long)t.ntx * t.nty * ((n + t.kz - 1) / t.kz) * batch < 1536) t.kz /= 2;
+  }
   t.nkz = (n + t.kz - 1) / t.kz;
   t.ntiles = t.ntx * t.nty * t.nkz;
   return t;

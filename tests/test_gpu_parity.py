@@ -316,3 +316,45 @@ def test_profiler_reports_kernels():
     st = op.profile_stop()
     assert st["apply_dot"]["launches"] == infos[0].iters or st["apply_dot"]["launches"] >= infos[0].iters
     assert all(v["ms"] > 0 for v in st.values())
+
+
+# ---------------------------------------------------------------------------------
+# batched: 64 independent 64^3 problems in one operator
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_batched_64_problems_64cubed(mode):
+    import time
+    n, B = 64, 64
+    probs = [G.random_bubbles_problem(20000 + s, n=n) for s in range(B)]
+    phi = to_dev(np.stack([q.phi for q in probs]))
+    f = to_dev(np.stack([q.f for q in probs]))
+    op = M.Operator(phi, [q.rho_neg for q in probs], [q.rho_pos for q in probs],
+                    [q.sigma for q in probs])
+    op.solve(f, rtol=1e-10, mode=mode)            # tuning, graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p, infos = op.solve(f, rtol=1e-10, mode=mode)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = [i.iters for i in infos]
+    print("batched 64 x 64^3 %s: %.2f ms, iterations min %d max %d" % (mode, dt * 1e3, min(iters),
+                                                                       max(iters)), flush=True)
+    assert all(i.status == M.OK and i.rel_resid <= 1e-10 for i in infos)
+    ph = to_host(p)
+    for b in (0, 17, 40, 63):     # sampled against the oracle and against a lone solve
+        q = probs[b]
+        check_solution(q.phi, q.f, q.rho_neg, q.rho_pos, q.sigma, ph[b], infos[b])
+    q = probs[5]
+    op1 = M.Operator(to_dev(q.phi), q.rho_neg, q.rho_pos, q.sigma)
+    p1, i1 = op1.solve(to_dev(q.f), rtol=1e-10, mode=mode)
+    assert rel2(ph[5], to_host(p1)) <= 1e-8
+
+
+def test_autotuned_chunks_do_not_change_the_answer():
+    # the tuner only picks tile shapes: solutions agree with the default shapes
+    import os
+    pr = G.rising_bubble_problem(3, n=96)
+    phi, f = to_dev(pr.phi), to_dev(pr.f)
+    a = M.Operator(phi, pr.rho_neg, pr.rho_pos, pr.sigma)
+    pa, ia = a.solve(f)
+    check_solution(pr.phi, pr.f, pr.rho_neg, pr.rho_pos, pr.sigma, to_host(pa), ia[0])
