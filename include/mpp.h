@@ -178,6 +178,97 @@ int mpp_profile_stop(mpp_op op, mpp_kernel_stat *stats, int32_t max_stats, int32
 /* Releases the handle (not the caller's workspace). */
 void mpp_destroy_operator(mpp_op op);
 
+
+/* ------------------------------------------------------------------------------
+ * Learned initial guess.  Not part of the paper's method (whose solver starts from
+ * the previous pressure or from zero): a small 3D U-Net maps the density field and
+ * the right-hand side of a problem to an approximate solution that seeds the PCG.
+ *
+ * Network at resolution n (n % 16 == 0, 16 <= n <= 256), fields channels-last
+ * ([batch][z][y][x][channel], x fastest among the cells):
+ *   input 4 channels: log10(1/rho)/3, b/rms(b), 0, 0
+ *   e1 = conv(4->16), conv(16->16)                  at n
+ *   e2 = pool, conv(16->32), conv(32->32)           at n/2
+ *   bt = pool, conv(32->64), conv(64->64)           at n/4
+ *   d2 = up(bt) ++ e2, conv(96->32), conv(32->32)   at n/2
+ *   d1 = up(d2) ++ e1, conv(48->16), conv(16->16)   at n
+ *   y  = 1x1x1 conv(16->1) of d1                    at n
+ * every 3x3x3 convolution with zero padding, bias and ReLU; pool is the mean of
+ * 2x2x2 children, up repeats a value into its 8 children, ++ concatenates channels.
+ * Parameters are FP32 ("master") in one flat vector, layer by layer, each
+ * convolution as W[tap][c_out][c_in] with tap = 9(dz+1) + 3(dy+1) + (dx+1), then its
+ * bias[c_out]; the head as w[16] then bias.  Products run on the matrix cores with
+ * BF16 operands (weights and activations rounded to nearest even) and FP32
+ * accumulation; activations are stored in BF16.
+ * ------------------------------------------------------------------------------ */
+typedef struct mpp_net_s *mpp_net;
+
+/* Length of the flat parameter vector (354577). */
+int32_t mpp_net_param_count(void);
+
+/* Device workspace a network of resolution n, able to run batches of up to
+ * batch_max samples forward and backward, needs (0 if the shape is invalid). */
+size_t mpp_net_workspace_bytes(int32_t n, int32_t batch_max);
+
+/* Creates a network in `workspace` (device, 256-byte aligned, owned by the caller and
+ * kept alive until mpp_net_destroy) with parameters drawn from `seed` (He-normal
+ * weights, zero biases) and zeroed optimiser state.  *out receives the handle. */
+int mpp_net_create(int32_t n, int32_t batch_max, uint64_t seed, void *workspace,
+                   size_t workspace_bytes, void *stream, mpp_net *out);
+void mpp_net_destroy(mpp_net net);
+
+/* Host copies of the FP32 parameters (mpp_net_param_count() floats).  set also
+ * resets the optimiser state.  Both synchronous. */
+int mpp_net_set_params(mpp_net net, const float *params, void *stream);
+int mpp_net_get_params(mpp_net net, float *params, void *stream);
+
+/* y = net(x) for `batch` samples.  x: device BF16 bit patterns [batch][n^3][4];
+ * y: device FP32 [batch][n^3].  Keeps the activations for mpp_net_backward. */
+int mpp_net_forward(mpp_net net, const uint16_t *x, float *y, int32_t batch, void *stream);
+
+/* Training loss of `batch` predictions y against targets t (device FP32
+ * [batch][n^3], each target of zero mean): per sample the squared error of the
+ * zero-mean prediction relative to the target's squared norm,
+ *   L_s = sum (y - mean y - t)^2 / sum t^2,
+ * and dy = d(mean_s L_s)/dy (device FP32 [batch][n^3]).  loss: device FP32
+ * [batch] per-sample values. */
+int mpp_net_loss(mpp_net net, const float *y, const float *t, float *dy, float *loss,
+                 int32_t batch, void *stream);
+
+/* Gradient of sum(dy * y) over the parameters, for the inputs of the last
+ * mpp_net_forward (same batch), into the network's FP32 gradient vector (replaced,
+ * not accumulated). */
+int mpp_net_backward(mpp_net net, const float *dy, int32_t batch, void *stream);
+
+/* Host copy of the gradient vector (mpp_net_param_count() floats); synchronous. */
+int mpp_net_get_grads(mpp_net net, float *grads, void *stream);
+
+/* One Adam step on the FP32 parameters with the current gradient: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, w -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), with
+ * t the count of steps since creation or the last set_params. */
+int mpp_net_adam(mpp_net net, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Network inputs (and optionally targets) of the problems of an operator whose size
+ * is r * n for an integer r >= 1 (op batch <= net batch_max).  b is the solver's
+ * right-hand side (f + jterm, mean-projected); coarse values are means over r^3
+ * blocks of cells: x[...,0] = log10(mean 1/rho)/3, x[...,1] = b_c / rms(b_c),
+ * x[...,2..3] = 0.  f: device [batch][(r n)^3].  x: device BF16 bits
+ * [batch][n^3][4].  p (device, may be NULL): solutions, whose block means divided by
+ * rms(b_c) go to t (device FP32 [batch][n^3]).  rms: device FP32 [batch] (may be
+ * NULL). */
+int mpp_net_features(mpp_net net, mpp_op op, const double *f, const double *p, uint16_t *x,
+                     float *t, float *rms, void *stream);
+
+/* Learned initial guess for mpp_solve with MPP_GUESS_GIVEN: features as in
+ * mpp_net_features, the network, the prediction times rms(b_c) prolonged to the
+ * operator's grid by trilinear interpolation of the cell values (clamped at the
+ * walls), its mean removed, then `sweeps` (0..8) red-black Gauss-Seidel sweeps on
+ * A p = b.  A problem whose guess is not finite or has ||b - A p|| >= ||b|| gets
+ * p = 0 instead and fell_back[b] = 1 (host int32 [batch], may be NULL).  p: device
+ * FP64 [batch][(r n)^3]. */
+int mpp_learned_guess(mpp_op op, mpp_net net, const double *f, double *p, int32_t sweeps,
+                      int32_t *fell_back, void *stream);
+
 const char *mpp_strerror(int status);
 
 #ifdef __cplusplus

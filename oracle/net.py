@@ -179,8 +179,9 @@ def loss_and_dy(y, t):
     return loss, dy_
 
 
-def backward(params, cache, dy_out, bf16_mode=True):
-    """Gradient of sum(dy_out * y) with respect to the flat parameter vector."""
+def backward(params, cache, dy_out, bf16_mode=True, trace=None):
+    """Gradient of sum(dy_out * y) with respect to the flat parameter vector.  trace: an
+    optional dict that receives each layer's pre-activation gradient (name -> gz)."""
     W = cache["W"]
     Rg = (lambda a: bf16(f32(a))) if bf16_mode else (lambda a: a)
     grads = {}
@@ -193,6 +194,8 @@ def backward(params, cache, dy_out, bf16_mode=True):
     def layer_back(name, g_a):
         inp, z, a = cache[name]
         gz = Rg(g_a * (z > 0))
+        if trace is not None:
+            trace[name] = gz
         w, b = W[name]
         dw, db = conv_dw(gz, inp)
         grads[name] = (dw, db)
@@ -228,3 +231,47 @@ def features(inv_rho, b):
     x[..., 0] = np.log10(inv_rho) / 3.0
     x[..., 1] = b / rms if rms > 0 else 0.0
     return x, rms
+
+
+def adam_step(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba, Algorithm 1) at step count t >= 1; returns new
+    (w, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def coarsen(a, r):
+    """Means over r^3 blocks of an (N, N, N) field, N = r n."""
+    n = a.shape[0] // r
+    return a.reshape(n, r, n, r, n, r).mean(axis=(1, 3, 5))
+
+
+def _lin1d(N, n, r):
+    """Interpolation matrix (N x n) of cell-centred linear interpolation, clamped."""
+    P = np.zeros((N, n))
+    for i in range(N):
+        u = (i + 0.5) / r - 0.5
+        i0 = int(np.floor(u))
+        w = u - i0
+        P[i, min(max(i0, 0), n - 1)] += 1.0 - w
+        P[i, min(max(i0 + 1, 0), n - 1)] += w
+    return P
+
+
+def prolong_trilinear(c, r):
+    """Trilinear interpolation of cell values to a grid r times finer (cell centres
+    (i + 1/2)/(r n) in units of the domain; neighbours beyond a wall are the wall
+    cell's value)."""
+    n = c.shape[0]
+    P = _lin1d(r * n, n, r)
+    return np.einsum("ai,bj,ck,ijk->abc", P, P, P, c, optimize=True)
+
+
+def learned_features(inv_rho, b, r):
+    """Network inputs from the cell values of 1/rho and of the solver's right-hand
+    side b at resolution r n ([z, y, x] arrays): block means, then features();
+    returns (x, rms)."""
+    return features(coarsen(inv_rho, r), coarsen(b, r))

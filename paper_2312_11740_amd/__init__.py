@@ -25,7 +25,10 @@ EXPORTS = (
     "mpp_default_opts", "mpp_workspace_bytes", "mpp_build_operator", "mpp_apply_stencil",
     "mpp_solve", "mpp_rhs", "mpp_vcycle", "mpp_operator_fields", "mpp_levels",
     "mpp_destroy_operator", "mpp_strerror", "mpp_profile_start", "mpp_profile_stop",
-    "mpp_update_operator",
+    "mpp_update_operator", "mpp_net_param_count", "mpp_net_workspace_bytes", "mpp_net_create",
+    "mpp_net_destroy", "mpp_net_set_params", "mpp_net_get_params", "mpp_net_forward",
+    "mpp_net_loss", "mpp_net_backward", "mpp_net_get_grads", "mpp_net_adam",
+    "mpp_net_features", "mpp_learned_guess",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -92,8 +95,28 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(ctypes.c_int32)]
     L.mpp_strerror.argtypes = [i32]
     L.mpp_strerror.restype = ctypes.c_char_p
+    L.mpp_net_param_count.argtypes = []
+    L.mpp_net_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.mpp_net_workspace_bytes.restype = ctypes.c_size_t
+    L.mpp_net_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, P,
+                                 ctypes.c_size_t, P, ctypes.POINTER(P)]
+    L.mpp_net_destroy.argtypes = [P]
+    L.mpp_net_destroy.restype = None
+    L.mpp_net_set_params.argtypes = [P, P, P]
+    L.mpp_net_get_params.argtypes = [P, P, P]
+    L.mpp_net_forward.argtypes = [P, P, P, ctypes.c_int32, P]
+    L.mpp_net_loss.argtypes = [P, P, P, P, P, ctypes.c_int32, P]
+    L.mpp_net_backward.argtypes = [P, P, ctypes.c_int32, P]
+    L.mpp_net_get_grads.argtypes = [P, P, P]
+    L.mpp_net_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, P]
+    L.mpp_net_features.argtypes = [P, P, P, P, P, P, P, P]
+    L.mpp_learned_guess.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    P]
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
-                                                 "mpp_strerror", "mpp_workspace_bytes")):
+                                                 "mpp_strerror", "mpp_workspace_bytes",
+                                                 "mpp_net_workspace_bytes",
+                                                 "mpp_net_destroy")):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -281,6 +304,20 @@ class Operator:
             raise MppError(st, "mpp_solve")
         return p, out
 
+    def learned_guess(self, net, f, sweeps=2, out=None):
+        """Initial guess from the network (device float64, the operator's shape) and the
+        per-problem fallback flags (1 where the guess was replaced by zero)."""
+        _check_field(f, self.shape, "f")
+        p = self._new() if out is None else out
+        _check_field(p, self.shape, "out")
+        flags = (ctypes.c_int32 * self.batch)()
+        st = load_library().mpp_learned_guess(self._h, net._h, ctypes.c_void_p(f.data_ptr()),
+                                              ctypes.c_void_p(p.data_ptr()), int(sweeps), flags,
+                                              _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_learned_guess")
+        return p, [int(v) for v in flags]
+
     def profile_start(self):
         st = load_library().mpp_profile_start(self._h)
         if st != OK:
@@ -301,6 +338,167 @@ class Operator:
         h = getattr(self, "_h", None)
         if h:
             load_library().mpp_destroy_operator(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def net_param_count() -> int:
+    return int(load_library().mpp_net_param_count())
+
+
+def net_workspace_bytes(n: int, batch_max: int) -> int:
+    return int(load_library().mpp_net_workspace_bytes(int(n), int(batch_max)))
+
+
+class Net:
+    """The learned-guess U-Net (include/mpp.h) at resolution n for batches of up to
+    batch_max samples.  Inputs x: bfloat16 CUDA tensors (B, n, n, n, 4); predictions,
+    targets and gradients: float32 CUDA tensors (B, n, n, n)."""
+
+    def __init__(self, n, batch_max=1, seed=0, device="cuda", workspace=None):
+        torch = _torch()
+        L = load_library()
+        self.n, self.batch_max = int(n), int(batch_max)
+        self.device = torch.device(device)
+        nbytes = net_workspace_bytes(self.n, self.batch_max)
+        if nbytes == 0:
+            raise MppError(EINVAL, "unsupported network shape n=%d batch_max=%d" % (n, batch_max))
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        elif workspace.dtype != torch.uint8 or workspace.numel() < nbytes or not workspace.is_cuda:
+            raise ValueError("workspace must be a CUDA uint8 tensor of >= %d bytes" % nbytes)
+        self.workspace = workspace
+        h = ctypes.c_void_p()
+        st = L.mpp_net_create(self.n, self.batch_max, int(seed) & (2**64 - 1),
+                              ctypes.c_void_p(workspace.data_ptr()), nbytes,
+                              _stream_handle(self.device), ctypes.byref(h))
+        if st != OK:
+            raise MppError(st, "mpp_net_create")
+        self._h = h
+        self.nparams = net_param_count()
+
+    def _stream(self):
+        return _stream_handle(self.device)
+
+    def _check(self, t, dtype, shape, what):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype:
+            raise TypeError("%s must be a CUDA %s tensor" % (what, dtype))
+        if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError("%s must be contiguous with shape %s, got %s"
+                             % (what, tuple(shape), tuple(t.shape)))
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.nparams, dtype=np.float32)
+        st = load_library().mpp_net_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                               self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_get_params")
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != self.nparams:
+            raise ValueError("need %d parameters" % self.nparams)
+        st = load_library().mpp_net_set_params(self._h, a.ctypes.data_as(ctypes.c_void_p),
+                                               self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_set_params")
+
+    def get_grads(self):
+        import numpy as np
+        out = np.empty(self.nparams, dtype=np.float32)
+        st = load_library().mpp_net_get_grads(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                              self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_get_grads")
+        return out
+
+    def forward(self, x, out=None):
+        torch = _torch()
+        B = x.shape[0]
+        self._check(x, torch.bfloat16, (B, self.n, self.n, self.n, 4), "x")
+        y = torch.empty((B, self.n, self.n, self.n), dtype=torch.float32, device=self.device) \
+            if out is None else out
+        self._check(y, torch.float32, (B, self.n, self.n, self.n), "y")
+        st = load_library().mpp_net_forward(self._h, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(y.data_ptr()), int(B), self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_forward")
+        return y
+
+    def loss(self, y, t):
+        """Per-sample losses (float32 CUDA tensor) and dloss/dy of their mean."""
+        torch = _torch()
+        B = y.shape[0]
+        shp = (B, self.n, self.n, self.n)
+        self._check(y, torch.float32, shp, "y")
+        self._check(t, torch.float32, shp, "t")
+        dy = torch.empty(shp, dtype=torch.float32, device=self.device)
+        lo = torch.empty(B, dtype=torch.float32, device=self.device)
+        st = load_library().mpp_net_loss(self._h, ctypes.c_void_p(y.data_ptr()),
+                                         ctypes.c_void_p(t.data_ptr()),
+                                         ctypes.c_void_p(dy.data_ptr()),
+                                         ctypes.c_void_p(lo.data_ptr()), int(B), self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_loss")
+        return lo, dy
+
+    def backward(self, dy):
+        torch = _torch()
+        B = dy.shape[0]
+        self._check(dy, torch.float32, (B, self.n, self.n, self.n), "dy")
+        st = load_library().mpp_net_backward(self._h, ctypes.c_void_p(dy.data_ptr()), int(B),
+                                             self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_backward")
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        st = load_library().mpp_net_adam(self._h, float(lr), float(beta1), float(beta2),
+                                         float(eps), self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_adam")
+
+    def train_step(self, x, t, lr=1e-3):
+        """forward, loss, backward, Adam; returns the per-sample losses (device)."""
+        y = self.forward(x)
+        lo, dy = self.loss(y, t)
+        self.backward(dy)
+        self.adam(lr)
+        return lo
+
+    def features(self, op, f, p=None):
+        """Network inputs x (bf16) of the operator's problems, targets t (float32, when p
+        is given) and rms of the coarse right-hand side per problem."""
+        torch = _torch()
+        _check_field(f, op.shape, "f")
+        if p is not None:
+            _check_field(p, op.shape, "p")
+        B = op.batch
+        x = torch.empty((B, self.n, self.n, self.n, 4), dtype=torch.bfloat16, device=self.device)
+        t = torch.empty((B, self.n, self.n, self.n), dtype=torch.float32, device=self.device) \
+            if p is not None else None
+        rms = torch.empty(B, dtype=torch.float32, device=self.device)
+        st = load_library().mpp_net_features(
+            self._h, op._h, ctypes.c_void_p(f.data_ptr()),
+            ctypes.c_void_p(p.data_ptr() if p is not None else 0),
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr() if t is not None else 0),
+            ctypes.c_void_p(rms.data_ptr()), _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_net_features")
+        return x, t, rms
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            load_library().mpp_net_destroy(h)
             self._h = None
 
     def __del__(self):

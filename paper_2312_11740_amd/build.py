@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpp.so")
-SOURCES = [os.path.join(CSRC, "mpp.hip")]
+SOURCES = [os.path.join(CSRC, "mpp.hip"), os.path.join(CSRC, "net.hip")]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

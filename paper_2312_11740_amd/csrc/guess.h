@@ -1,0 +1,116 @@
+// Glue between the solver and the learned-guess network: network inputs from an
+// operator's density field and right-hand side (block means over r^3 cells), and the
+// prolongation of the network's prediction back to the operator's grid.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mpp {
+
+__device__ inline uint16_t bf16_rne(double v) {
+  const float f = (float)v;
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// coarse[b][v][0..2] = means over the r^3 block of cell v of 1/rho, b and p (0 when p is
+// NULL).  1/rho of a fine cell is that of its side (bit 6 of the finest-level code).
+__global__ void k_feat_coarsen(const uint8_t* __restrict__ code, const double* __restrict__ inv_rho,
+                               const double* __restrict__ b, const double* __restrict__ p, int nf,
+                               int r, int nc, int batch, double* __restrict__ coarse) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t cc = (size_t)nc * nc * nc;
+  if (idx >= cc * batch) return;
+  const int q = (int)(idx / cc), l = (int)(idx % cc);
+  const int I = l % nc, J = (l / nc) % nc, K = l / (nc * nc);
+  const size_t base = (size_t)q * nf * nf * nf;
+  double sr = 0.0, sb = 0.0, sp = 0.0;
+  for (int dz = 0; dz < r; ++dz)
+    for (int dy = 0; dy < r; ++dy)
+      for (int dx = 0; dx < r; ++dx) {
+        const size_t c = base + ((size_t)(K * r + dz) * nf + (J * r + dy)) * nf + (I * r + dx);
+        sr += inv_rho[2 * q + ((code[c] >> 6) & 1)];
+        sb += b[c];
+        if (p) sp += p[c];
+      }
+  const double inv = 1.0 / ((double)r * r * r);
+  coarse[3 * idx + 0] = sr * inv;
+  coarse[3 * idx + 1] = sb * inv;
+  coarse[3 * idx + 2] = sp * inv;
+}
+
+// rms of the coarse right-hand side per problem (one block each)
+__global__ void __launch_bounds__(1024)
+    k_feat_rms(const double* __restrict__ coarse, int cells, double* __restrict__ rms64,
+               float* __restrict__ rms32) {
+  __shared__ double red[1024];
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const double* c = coarse + (size_t)q * cells * 3;
+  double s = 0.0;
+  for (int v = tid; v < cells; v += 1024) s += c[3 * v + 1] * c[3 * v + 1];
+  red[tid] = s;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double rms = sqrt(red[0] / cells);
+    rms64[q] = rms;
+    rms32[q] = (float)rms;
+  }
+}
+
+// x[v] = (log10(mean 1/rho) / 3, b_c / rms, 0, 0) in BF16; t[v] = p_c / rms (FP32)
+__global__ void k_feat_write(const double* __restrict__ coarse, const double* __restrict__ rms64,
+                             int cells, int batch, uint16_t* __restrict__ x, float* __restrict__ t) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)cells * batch) return;
+  const int q = (int)(idx / cells);
+  const double rms = rms64[q];
+  const double* c = coarse + 3 * idx;
+  const double xb = rms > 0.0 ? c[1] / rms : 0.0;
+  const uint32_t lo = (uint32_t)bf16_rne(log10(c[0]) / 3.0) | ((uint32_t)bf16_rne(xb) << 16);
+  *reinterpret_cast<uint2*>(x + 4 * idx) = make_uint2(lo, 0u);
+  if (t) t[idx] = rms > 0.0 ? (float)(c[2] / rms) : 0.f;
+}
+
+// p[fine cell] = rms * trilinear interpolation of y at the cell's centre (cell-centred
+// coarse values, clamped at the walls)
+__global__ void k_guess_prolong(const float* __restrict__ y, const double* __restrict__ rms64,
+                                int nc, int r, int batch, double* __restrict__ p) {
+  const int nf = nc * r;
+  const size_t cf = (size_t)nf * nf * nf;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= cf * batch) return;
+  const int q = (int)(idx / cf), l = (int)(idx % cf);
+  const int fi[3] = {l % nf, (l / nf) % nf, l / (nf * nf)};
+  int i0[3], i1[3];
+  double w1[3];
+  for (int a = 0; a < 3; ++a) {
+    const double u = (fi[a] + 0.5) / r - 0.5;
+    const double fl = floor(u);
+    w1[a] = u - fl;
+    const int lo = (int)fl;
+    i0[a] = lo < 0 ? 0 : (lo > nc - 1 ? nc - 1 : lo);
+    i1[a] = lo + 1 < 0 ? 0 : (lo + 1 > nc - 1 ? nc - 1 : lo + 1);
+  }
+  const float* yq = y + (size_t)q * nc * nc * nc;
+  double s = 0.0;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const double w = (cx ? w1[0] : 1.0 - w1[0]) * (cy ? w1[1] : 1.0 - w1[1]) *
+                         (cz ? w1[2] : 1.0 - w1[2]);
+        const int X = cx ? i1[0] : i0[0], Y = cy ? i1[1] : i0[1], Z = cz ? i1[2] : i0[2];
+        s += w * (double)yq[((size_t)Z * nc + Y) * nc + X];
+      }
+  p[idx] = s * rms64[q];
+}
+
+}  // namespace mpp

@@ -18,7 +18,9 @@
 #include <new>
 #include <vector>
 
+#include "guess.h"
 #include "kernels.h"
+#include "net_internal.h"
 #include "rbgs.h"
 #include "stencil.h"
 
@@ -1053,6 +1055,104 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
     worst = worse(worst, in.status);
   }
   return worst;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------
+// learned initial guess
+// ------------------------------------------------------------------------------
+namespace {
+
+bool net_fits(const mpp_op_s* op, const mpp_net_s* net) {
+  return net->n <= op->n && op->n % net->n == 0 && op->batch <= net->bmax;
+}
+
+// solver rhs into op->b (S_MEAN, S_BB in op->inner), then the coarse means and rms
+void net_inputs(mpp_op_s* op, mpp_net_s* net, const double* f, const double* p, uint16_t* x,
+                float* t, hipStream_t s) {
+  const int B = op->batch, nc = net->n, r = op->n / net->n;
+  const int cells_c = nc * nc * nc;
+  reset_ctl(op, op->inner, 1, s);
+  make_rhs(op, op->inner, f, op->b, s, 0.0, true);
+  const size_t work = (size_t)cells_c * B;
+  const unsigned nb = (unsigned)((work + 255) / 256);
+  hipLaunchKernelGGL(k_feat_coarsen, dim3(nb), dim3(256), 0, s, op->lev[0].code, op->inv_rho64,
+                     op->b, p, op->n, r, nc, B, net->coarse);
+  ck_launch();
+  hipLaunchKernelGGL(k_feat_rms, dim3(B), dim3(1024), 0, s, net->coarse, cells_c, net->rms64,
+                     net->rms32);
+  ck_launch();
+  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(256), 0, s, net->coarse, net->rms64, cells_c, B,
+                     x, t);
+  ck_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpp_net_features(mpp_net net, mpp_op op, const double* f, const double* p, uint16_t* x,
+                     float* t, float* rms, void* stream) {
+  if (!net || !op || !f || !x || (t && !p) || !net_fits(op, net)) return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  try {
+    net_inputs(op, net, f, t ? p : nullptr, x, t, s);
+    if (rms)
+      ck(hipMemcpyAsync(rms, net->rms32, sizeof(float) * op->batch, hipMemcpyDeviceToDevice, s));
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
+int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_t sweeps,
+                      int32_t* fell_back, void* stream) {
+  if (!op || !net || !f || !p || f == p || sweeps < 0 || sweeps > 8 || !net_fits(op, net))
+    return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int B = op->batch, r = op->n / net->n;
+  const Level& L0 = op->lev[0];
+  try {
+    ensure_tuned<double>(op, s);
+    net_inputs(op, net, f, nullptr, net->x4, nullptr, s);
+    const int st = mppnet::forward(net, net->x4, net->y, B, s);
+    if (st != MPP_OK) return st;
+    const size_t work = L0.cells * B;
+    hipLaunchKernelGGL(k_guess_prolong, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s,
+                       net->y, net->rms64, net->n, r, B, p);
+    ck_launch();
+    Ctl& ctl = op->inner;
+    remove_mean(op, ctl, p, s);
+    // red-black sweeps on A p = b, alternating between p and a scratch vector
+    const Faces<double> F = faces_of<double>(op, 0);
+    const RbTiles tl = rb_tiles(op->n, B, op->kz[0][0]);
+    const dim3 grid(rb_grid(tl), B);
+    double* bufs[2] = {p, op->q};
+    for (int q = 0; q < sweeps; ++q) {
+      hipLaunchKernelGGL((k_rb_sweep<double, 0, true>), grid, dim3(kRbThreads), 0, s, F, op->n, tl,
+                         (const double*)op->b, (const double*)bufs[q & 1], (const double*)nullptr,
+                         bufs[(q + 1) & 1], 0, ctl, 0, (const int*)nullptr);
+      ck_launch();
+    }
+    if (sweeps & 1)
+      ck(hipMemcpyAsync(p, op->q, sizeof(double) * work, hipMemcpyDeviceToDevice, s));
+    // fallback check on ||b - A p|| against ||b||
+    finish_sums(op, ctl, epi(E_START),
+                launch_residual<double>(op, F, op->b, p, op->r, ctl, 0, s), s);
+    ck_launch();
+    ck(hipMemcpyAsync(op->h_scal, ctl.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
+    ck(hipStreamSynchronize(s));
+    for (int q = 0; q < B; ++q) {
+      const double* sc = op->h_scal + (size_t)q * kSlots;
+      const bool bad = !(std::isfinite(sc[S_RR]) && sc[S_RR] < sc[S_BB]);
+      if (bad) ck(hipMemsetAsync(p + (size_t)q * L0.cells, 0, sizeof(double) * L0.cells, s));
+      if (fell_back) fell_back[q] = bad ? 1 : 0;
+    }
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
 }
 
 }  // extern "C"

@@ -88,3 +88,53 @@ def test_loss_is_zero_for_exact_prediction_up_to_a_constant():
     t -= t.mean()
     loss, dy = N.loss_and_dy(t + 3.0, t)
     assert loss < 1e-28 and np.abs(dy).max() < 1e-13
+
+
+def test_adam_matches_torch():
+    """The oracle's Adam against torch.optim.Adam (a library routine) over 3 steps."""
+    import torch
+    rng = np.random.default_rng(3)
+    w0 = rng.normal(size=50)
+    gs = [rng.normal(size=50) for _ in range(3)]
+    w = torch.tensor(w0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    ww, m, v = w0.copy(), np.zeros(50), np.zeros(50)
+    for t, g in enumerate(gs, start=1):
+        opt.zero_grad()
+        w.grad = torch.tensor(g)
+        opt.step()
+        ww, m, v = N.adam_step(ww, m, v, g, t, lr=1e-2)
+        assert np.allclose(ww, w.detach().numpy(), rtol=0, atol=1e-14)
+
+
+def test_coarsen_is_block_mean():
+    rng = np.random.default_rng(4)
+    a = rng.normal(size=(8, 8, 8))
+    c = N.coarsen(a, 2)
+    assert np.isclose(c[1, 2, 3], a[2:4, 4:6, 6:8].mean())
+    assert np.isclose(c.mean(), a.mean())
+    assert np.array_equal(N.coarsen(a, 1), a)
+
+
+def test_trilinear_prolongation_properties():
+    n, r = 6, 4
+    # constants are kept everywhere, the identity at r = 1
+    assert np.allclose(N.prolong_trilinear(np.full((n, n, n), 2.5), r), 2.5)
+    rng = np.random.default_rng(5)
+    c = rng.normal(size=(n, n, n))
+    assert np.allclose(N.prolong_trilinear(c, 1), c)
+    # an affine function of the cell centres is reproduced away from the walls
+    xc = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+    lin = 1.0 + 2.0 * X - 3.0 * Y + 0.5 * Z
+    f = N.prolong_trilinear(lin, r)
+    xf = (np.arange(n * r) + 0.5) / (n * r)
+    Zf, Yf, Xf = np.meshgrid(xf, xf, xf, indexing="ij")
+    exact = 1.0 + 2.0 * Xf - 3.0 * Yf + 0.5 * Zf
+    inner = slice(r // 2, n * r - r // 2)
+    assert np.allclose(f[inner, inner, inner], exact[inner, inner, inner], atol=1e-12)
+    # the 1D weights at r = 2 are 3/4 and 1/4
+    e = np.zeros((n, n, n))
+    e[2, 2, 2] = 1.0
+    p = N.prolong_trilinear(e, 2)
+    assert np.isclose(p[5, 5, 5], 0.75 ** 3) and np.isclose(p[6, 5, 5], 0.25 * 0.75 ** 2)
