@@ -88,7 +88,9 @@ typedef struct {
     int32_t guess;        /* MPP_GUESS_ZERO or MPP_GUESS_GIVEN */
     int32_t nu;           /* pre- and post-smoothing red-black sweeps per level, >= 1 */
     int32_t check_every;  /* iterations between host polls of convergence, >= 1 */
-    double inner_rtol;    /* mixed mode: inner FP32 solve target (e.g. 1e-5) */
+    double inner_rtol;    /* mixed mode: tightest inner FP32 target (e.g. 1e-5); each
+                           * refinement step asks only for the reduction it still
+                           * needs, between inner_rtol and 1/2 */
 } mpp_solve_opts;
 
 typedef struct {
@@ -212,7 +214,8 @@ size_t mpp_net_workspace_bytes(int32_t n, int32_t batch_max);
 
 /* Creates a network in `workspace` (device, 256-byte aligned, owned by the caller and
  * kept alive until mpp_net_destroy) with parameters drawn from `seed` (He-normal
- * weights, zero biases) and zeroed optimiser state.  *out receives the handle. */
+ * convolution weights, zero biases, a zero head) and zeroed optimiser state.  *out
+ * receives the handle. */
 int mpp_net_create(int32_t n, int32_t batch_max, uint64_t seed, void *workspace,
                    size_t workspace_bytes, void *stream, mpp_net *out);
 void mpp_net_destroy(mpp_net net);
@@ -253,19 +256,20 @@ int mpp_net_adam(mpp_net net, float lr, float beta1, float beta2, float eps, voi
  * right-hand side (f + jterm, mean-projected); coarse values are means over r^3
  * blocks of cells: x[...,0] = log10(mean 1/rho)/3, x[...,1] = b_c / rms(b_c),
  * x[...,2..3] = 0.  f: device [batch][(r n)^3].  x: device BF16 bits
- * [batch][n^3][4].  p (device, may be NULL): solutions, whose block means divided by
- * rms(b_c) go to t (device FP32 [batch][n^3]).  rms: device FP32 [batch] (may be
- * NULL). */
+ * [batch][n^3][4].  p (device, may be NULL): solutions, whose block means scaled by
+ * n^2 / rms(b_c) (p is of the order of h^2 b, h = 1/n) go to t (device FP32
+ * [batch][n^3]).  rms: device FP32 [batch] (may be NULL). */
 int mpp_net_features(mpp_net net, mpp_op op, const double *f, const double *p, uint16_t *x,
                      float *t, float *rms, void *stream);
 
 /* Learned initial guess for mpp_solve with MPP_GUESS_GIVEN: features as in
- * mpp_net_features, the network, the prediction times rms(b_c) prolonged to the
+ * mpp_net_features, the network, the prediction times rms(b_c) / n^2 prolonged to the
  * operator's grid by trilinear interpolation of the cell values (clamped at the
- * walls), its mean removed, then `sweeps` (0..8) red-black Gauss-Seidel sweeps on
- * A p = b.  A problem whose guess is not finite or has ||b - A p|| >= ||b|| gets
- * p = 0 instead and fell_back[b] = 1 (host int32 [batch], may be NULL).  p: device
- * FP64 [batch][(r n)^3]. */
+ * walls), its mean removed, scaled by (p.b) / (p.Ap) (the multiple of the prediction
+ * closest to the solution in the energy norm, so never farther than zero), then
+ * `sweeps` (0..8) red-black Gauss-Seidel sweeps on A p = b.  A problem whose guess is
+ * not finite or has ||b - A p|| >= ||b|| gets p = 0 instead and fell_back[b] = 1 (host
+ * int32 [batch], may be NULL).  p: device FP64 [batch][(r n)^3]. */
 int mpp_learned_guess(mpp_op op, mpp_net net, const double *f, double *p, int32_t sweeps,
                       int32_t *fell_back, void *stream);
 

@@ -16,6 +16,8 @@ from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpp.so")
+# parameters of the learned-guess network trained on 64^3 problems (train.py)
+TRAINED_WEIGHTS = os.path.join(HERE, "weights", "unet64.f32")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONVERGED, EBREAKDOWN = 0, -1, -2, -3, -4, -5
 MODE_FP64, MODE_MIXED = 0, 1
@@ -411,6 +413,14 @@ class Net:
                                                self._stream())
         if st != OK:
             raise MppError(st, "mpp_net_set_params")
+
+    def load(self, path):
+        """Parameters from a raw little-endian FP32 file (as train.py writes them)."""
+        import numpy as np
+        self.set_params(np.fromfile(path, dtype="<f4"))
+
+    def save(self, path):
+        self.get_params().astype("<f4").tofile(path)
 
     def get_grads(self):
         import numpy as np

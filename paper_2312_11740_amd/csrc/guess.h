@@ -66,9 +66,11 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-// x[v] = (log10(mean 1/rho) / 3, b_c / rms, 0, 0) in BF16; t[v] = p_c / rms (FP32)
+// x[v] = (log10(mean 1/rho) / 3, b_c / rms, 0, 0) in BF16; t[v] = p_c / (rms h^2) (FP32),
+// h = 1 / nc the spacing of the coarse grid (p ~ h^2 b for the discrete operator)
 __global__ void k_feat_write(const double* __restrict__ coarse, const double* __restrict__ rms64,
-                             int cells, int batch, uint16_t* __restrict__ x, float* __restrict__ t) {
+                             int nc, int batch, uint16_t* __restrict__ x, float* __restrict__ t) {
+  const int cells = nc * nc * nc;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)cells * batch) return;
   const int q = (int)(idx / cells);
@@ -77,11 +79,11 @@ __global__ void k_feat_write(const double* __restrict__ coarse, const double* __
   const double xb = rms > 0.0 ? c[1] / rms : 0.0;
   const uint32_t lo = (uint32_t)bf16_rne(log10(c[0]) / 3.0) | ((uint32_t)bf16_rne(xb) << 16);
   *reinterpret_cast<uint2*>(x + 4 * idx) = make_uint2(lo, 0u);
-  if (t) t[idx] = rms > 0.0 ? (float)(c[2] / rms) : 0.f;
+  if (t) t[idx] = rms > 0.0 ? (float)(c[2] * ((double)nc * nc) / rms) : 0.f;
 }
 
-// p[fine cell] = rms * trilinear interpolation of y at the cell's centre (cell-centred
-// coarse values, clamped at the walls)
+// p[fine cell] = rms h^2 * trilinear interpolation of y at the cell's centre (cell-centred
+// coarse values, clamped at the walls; h = 1 / nc)
 __global__ void k_guess_prolong(const float* __restrict__ y, const double* __restrict__ rms64,
                                 int nc, int r, int batch, double* __restrict__ p) {
   const int nf = nc * r;
@@ -110,7 +112,20 @@ __global__ void k_guess_prolong(const float* __restrict__ y, const double* __res
         const int X = cx ? i1[0] : i0[0], Y = cy ? i1[1] : i0[1], Z = cz ? i1[2] : i0[2];
         s += w * (double)yq[((size_t)Z * nc + Y) * nc + X];
       }
-  p[idx] = s * rms64[q];
+  p[idx] = s * rms64[q] / ((double)nc * nc);
+}
+
+// p *= alpha with alpha = (p.b) / (p.Ap) from the slots (0 when p.Ap is 0 or either
+// dot is not finite): the multiple of p closest to the solution in the energy norm
+__global__ void k_energy_scale(double* __restrict__ p, int cells, const double* __restrict__ scal,
+                               int slot_pb, int slot_pap, int slots) {
+  const int q = blockIdx.y;
+  const double* sc = scal + (size_t)q * slots;
+  const double pb = sc[slot_pb], pap = sc[slot_pap];
+  const double a = (pap != 0.0 && isfinite(pb) && isfinite(pap)) ? pb / pap : 0.0;
+  double* pq = p + (size_t)q * cells;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x)
+    pq[c] *= a;
 }
 
 }  // namespace mpp

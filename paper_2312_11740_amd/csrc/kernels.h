@@ -72,6 +72,10 @@ struct EpiArgs {
   double inv_cells;
   int first;
   const int* gate;   // E_START_REL: problems whose gate is 0 stay inactive
+  // E_START_REL of an inner solve in residual refinement: the outer solve's slots
+  // and its target; the inner target is relaxed to what the outer step still needs
+  const double* outer_scal;
+  double outer_rtol;
 };
 
 __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& e) {
@@ -83,9 +87,19 @@ __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& 
       s[S_BB] = tot;
       s[S_TOL2] = e.rtol2 * tot;
       break;
-    case E_START_REL:
+    case E_START_REL: {
       s[S_BB] = tot;
-      s[S_TOL2] = e.rtol2 * tot;
+      double rel2 = e.rtol2;
+      if (e.outer_scal) {
+        // the refinement step only has to bring ||r|| below outer_rtol ||b||: ask the
+        // inner solve for that reduction with a factor 2 margin, never for less than
+        // halving the residual, never for more than rtol2
+        const double* os = e.outer_scal + (size_t)b * kSlots;
+        const double need2 = 0.25 * e.outer_rtol * e.outer_rtol * os[S_BB] / os[S_RR];
+        rel2 = fmin(0.25, fmax(rel2, need2));
+      }
+      s[S_TOL2] = rel2 * tot;
+    }
       [[fallthrough]];
     case E_START:
       s[S_RR] = tot;

@@ -994,6 +994,8 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
       EpiArgs istart = epi(E_START_REL);
       istart.rtol2 = o.inner_rtol * o.inner_rtol;
       istart.gate = oc.active;
+      istart.outer_scal = oc.scal;
+      istart.outer_rtol = o.rtol;
       bool settled = false, converged = false;
       for (int outer = 0; outer < 40 && !settled; ++outer) {
         finish_sums(op, oc, start,
@@ -1083,8 +1085,8 @@ void net_inputs(mpp_op_s* op, mpp_net_s* net, const double* f, const double* p, 
   hipLaunchKernelGGL(k_feat_rms, dim3(B), dim3(1024), 0, s, net->coarse, cells_c, net->rms64,
                      net->rms32);
   ck_launch();
-  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(256), 0, s, net->coarse, net->rms64, cells_c, B,
-                     x, t);
+  hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(256), 0, s, net->coarse, net->rms64, nc, B, x,
+                     t);
   ck_launch();
 }
 
@@ -1124,8 +1126,24 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
     ck_launch();
     Ctl& ctl = op->inner;
     remove_mean(op, ctl, p, s);
-    // red-black sweeps on A p = b, alternating between p and a scratch vector
+    // scale along p to the energy-norm optimum: alpha = (p.b) / (p.Ap)
     const Faces<double> F = faces_of<double>(op, 0);
+    const dim3 g = grid_of(L0, B);
+    EpiArgs e1 = epi(E_STORE_MEAN);
+    e1.slot = S_RZ;
+    e1.inv_cells = 1.0;
+    hipLaunchKernelGGL(k_dot<double>, g, dim3(kBlock), 0, s, (const double*)p, (const double*)op->b,
+                       (int)L0.cells, ctl, e1, (const int*)nullptr);
+    ck_launch();
+    finish_sums(op, ctl, e1, L0.bpp, s);
+    EpiArgs e2 = e1;
+    e2.slot = S_PQ;
+    finish_sums(op, ctl, e2, launch_apply<double>(op, F, p, op->q, ctl, 1, nullptr, s), s);
+    ck_launch();
+    hipLaunchKernelGGL(k_energy_scale, g, dim3(kBlock), 0, s, p, (int)L0.cells, ctl.scal,
+                       (int)S_RZ, (int)S_PQ, (int)kSlots);
+    ck_launch();
+    // red-black sweeps on A p = b, alternating between p and a scratch vector
     const RbTiles tl = rb_tiles(op->n, B, op->kz[0][0]);
     const dim3 grid(rb_grid(tl), B);
     double* bufs[2] = {p, op->q};

@@ -300,7 +300,7 @@ void backward(mpp_net_s* net, const float* dy, int batch, hipStream_t s) {
   conv_wgrad(net, 0, net->g0b, batch, s);
 }
 
-// He-normal weights (std sqrt(2 / fan_in)), zero biases; head std sqrt(1 / 16).
+// He-normal weights (std sqrt(2 / fan_in)), zero biases, zero head.
 // Normal deviates by Box-Muller over a splitmix64 stream.
 void init_params(mpp_net_s* net, uint64_t seed, std::vector<float>& h) {
   h.assign(net->nparams, 0.f);
@@ -321,7 +321,8 @@ void init_params(mpp_net_s* net, uint64_t seed, std::vector<float>& h) {
     const size_t cnt = (size_t)27 * kSpec[l].co * kSpec[l].ci;
     for (size_t i = 0; i < cnt; ++i) h[net->off_w[l] + i] = (float)(sd * normal());
   }
-  for (int c = 0; c < kHeadCI; ++c) h[net->off_head + c] = (float)(std::sqrt(1.0 / kHeadCI) * normal());
+  // the head starts at zero: the first prediction is 0 (relative loss 1) instead of a
+  // random field many times the target's size
 }
 
 int set_params_impl(mpp_net_s* net, const float* params, hipStream_t s) {

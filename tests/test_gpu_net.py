@@ -282,7 +282,7 @@ def test_features_and_targets_match_oracle(nf, nn):
         xr = N.bf16(x_ref)
         # one BF16 ulp at most (the GPU's b differs from the oracle's by rounding)
         assert np.all(np.abs(x[b] - xr) <= 2.0 ** -8 * np.abs(xr) + 1e-30)
-        t_ref = N.coarsen(p_ref[b], r) / rms_ref
+        t_ref = N.coarsen(p_ref[b], r) * nn ** 2 / rms_ref
         assert rel2(t[b], t_ref) <= 1e-6
 
 
@@ -292,8 +292,11 @@ def oracle_guess(params, phi, f, rn, rp, sg, r, sweeps):
     inv_rho = np.where(phi > 0, 1.0 / rp, 1.0 / rn)
     x, rms = N.learned_features(inv_rho, d["b"], r)
     y, _ = N.forward(params, x, bf16_mode=True)
-    p = N.prolong_trilinear(y * rms, r)
+    nc = phi.shape[0] // r
+    p = N.prolong_trilinear(y * rms / nc ** 2, r)
     p -= p.mean()
+    # the multiple of p closest to the solution in the energy norm
+    p *= np.dot(p.ravel(), d["b"].ravel()) / np.dot(p.ravel(), O.apply(d["faces"], p).ravel())
     for _ in range(sweeps):
         p = O.gs_colour(d["faces"], d["b"], p, 0)
         p = O.gs_colour(d["faces"], d["b"], p, 1)
@@ -308,7 +311,6 @@ def test_learned_guess_matches_oracle(sweeps):
     phi, f, rn, rp, sg = problem_batch(nf, seeds)
     params = sparse_params(12)
     P = N.unpack(params)
-    P["head"][0][:] *= 2.0 ** -8   # a small prediction keeps ||b - A p|| below ||b||
     op = M.Operator(to_dev(phi), rn, rp, sg)
     net = make_net(nn, len(seeds), params)
     p, fell = op.learned_guess(net, to_dev(f), sweeps=sweeps)
@@ -316,7 +318,9 @@ def test_learned_guess_matches_oracle(sweeps):
     for b in range(len(seeds)):
         p_ref, res, _ = oracle_guess(params, phi[b], f[b], rn[b], rp[b], sg[b], nf // nn, sweeps)
         print("sample %d: oracle residual %.3f, fell back %d" % (b, res, fell[b]), flush=True)
-        if res >= 1.0:
+        if abs(res - 1.0) < 1e-6:   # on the fallback threshold: either outcome is right
+            assert fell[b] == 1 and np.all(p[b] == 0.0) or rel2(p[b], p_ref) <= 1e-3
+        elif res > 1.0:
             assert fell[b] == 1 and np.all(p[b] == 0.0)
         else:
             assert fell[b] == 0
