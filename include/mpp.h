@@ -88,6 +88,7 @@ typedef struct {
     int32_t guess;        /* MPP_GUESS_ZERO or MPP_GUESS_GIVEN */
     int32_t nu;           /* pre- and post-smoothing red-black sweeps per level, >= 1 */
     int32_t check_every;  /* iterations between host polls of convergence, >= 1 */
+    int32_t nu_coarse;    /* sweeps on the levels below the finest (0: nu) */
     double inner_rtol;    /* mixed mode: tightest inner FP32 target (e.g. 1e-5); each
                            * refinement step asks only for the reduction it still
                            * needs, between inner_rtol and 1/2 */
@@ -104,7 +105,7 @@ typedef struct {
 } mpp_solve_info;
 
 /* Default options: rtol 1e-10, max_iter 500, FP64, zero guess, nu 2, check_every 2,
- * inner_rtol 1e-5. */
+ * nu_coarse 0 (as nu), inner_rtol 1e-5. */
 void mpp_default_opts(mpp_solve_opts *opts);
 
 /* Bytes of device workspace an operator of this shape needs (0 if desc is invalid). */

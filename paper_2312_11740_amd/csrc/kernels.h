@@ -403,9 +403,10 @@ __global__ void k_coarsen_faces(const double* __restrict__ fx, const double* __r
   }
 }
 
-// Coarsest level: dense M = -A + 11^T/m, Cholesky M = L L^T, then M^{-1} column by
-// column.  One block per problem; work is [B][m][m] scratch.
-__global__ void k_coarse_factor(const double* __restrict__ cx, const double* __restrict__ cy,
+// Coarsest level: dense M = -A + 11^T/m and its inverse.  One block per problem; up to
+// 64 cells by Gauss-Jordan elimination in LDS, above that by a Cholesky factor M = L L^T
+// in the [B][m][m] scratch `work` and M^{-1} column by column.
+__global__ void __launch_bounds__(1024) k_coarse_factor(const double* __restrict__ cx, const double* __restrict__ cy,
                                 const double* __restrict__ cz, int n, double* __restrict__ work,
                                 double* __restrict__ inv) {
   const int b = blockIdx.x;
@@ -437,6 +438,29 @@ __global__ void k_coarse_factor(const double* __restrict__ cx, const double* __r
     M[(size_t)c * m + c] += d * inv_h2;
   }
   __syncthreads();
+  if (lds) {
+    // Gauss-Jordan on [M | I] in LDS, every thread on every pivot (M is symmetric
+    // positive definite: no pivoting needed)
+    __shared__ double fac[kLdsM];
+    for (int q = threadIdx.x; q < m * m; q += blockDim.x) X[q] = (q / m == q % m) ? 1.0 : 0.0;
+    // thread t owns column t % (2m) of [M | I] and rows t / (2m), + rows_step, ...
+    const int tw = 2 * m, col = threadIdx.x % tw, row0 = threadIdx.x / tw;
+    const int rows_step = blockDim.x / tw;
+    const bool has_col = (int)threadIdx.x < rows_step * tw;
+    double* cp = col < m ? M + col : X + (col - m);   // this column, stride m
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+      // reads of pivot row and column before the barrier, writes after it
+      const double pinv = 1.0 / M[(size_t)k * m + k];
+      if ((int)threadIdx.x < m) fac[threadIdx.x] = M[(size_t)threadIdx.x * m + k];
+      const double pk = has_col ? cp[(size_t)k * m] * pinv : 0.0;   // pivot row, scaled
+      __syncthreads();
+      if (has_col)
+        for (int i = row0; i < m; i += rows_step)
+          cp[(size_t)i * m] = i == k ? pk : cp[(size_t)i * m] - fac[i] * pk;
+      __syncthreads();
+    }
+  } else {
   // left-looking Cholesky, lower triangle of M
   __shared__ double piv;
   for (int j = 0; j < m; ++j) {
@@ -454,19 +478,22 @@ __global__ void k_coarse_factor(const double* __restrict__ cx, const double* __r
     }
     __syncthreads();
   }
-  // columns of the inverse: L y = e_col, L^T x = y
+  // columns of the inverse: L y = e_col, L^T x = y.  Column col is kept at stride m
+  // (X[r m + col]) so that the lanes of a wave touch consecutive words; M^{-1} is
+  // symmetric, so this is also its row-major layout.
   for (int col = threadIdx.x; col < m; col += blockDim.x) {
-    double* x = X + (size_t)col * m;
+    double* x = X + col;
     for (int r = 0; r < m; ++r) {
       double s = (r == col) ? 1.0 : 0.0;
-      for (int q = 0; q < r; ++q) s -= M[(size_t)r * m + q] * x[q];
-      x[r] = s / M[(size_t)r * m + r];
+      for (int q = 0; q < r; ++q) s -= M[(size_t)r * m + q] * x[(size_t)q * m];
+      x[(size_t)r * m] = s / M[(size_t)r * m + r];
     }
     for (int r = m - 1; r >= 0; --r) {
-      double s = x[r];
-      for (int q = r + 1; q < m; ++q) s -= M[(size_t)q * m + r] * x[q];
-      x[r] = s / M[(size_t)r * m + r];
+      double s = x[(size_t)r * m];
+      for (int q = r + 1; q < m; ++q) s -= M[(size_t)q * m + r] * x[(size_t)q * m];
+      x[(size_t)r * m] = s / M[(size_t)r * m + r];
     }
+  }
   }
   if (lds) {
     __syncthreads();
@@ -632,15 +659,19 @@ __device__ inline void small_faces(const SmallLevel<T>& L, size_t base, int c, i
 
 template <typename T>
 __device__ void small_smooth(const SmallLevel<T>& L, size_t base, int colour, int from_zero) {
-  const int n = L.n, cells = n * n * n, nn = n * n;
+  const int n = L.n, cells = n * n * n, nn = n * n, nh = n >> 1;
   const T h2 = (T)(1.0 / ((double)n * (double)n));
-  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
-    int i, j, k;
-    ijk(c, n, i, j, k);
-    if (((i + j + k) & 1) != colour) {
-      if (from_zero) L.x[base + c] = T(0);
-      continue;
+  if (from_zero)   // the other colour starts at zero
+    for (int q = threadIdx.x; q < cells / 2; q += blockDim.x) {
+      const int j = (q / nh) % n, k = q / (nh * n);
+      const int i = 2 * (q % nh) + ((colour + j + k + 1) & 1);
+      L.x[base + i + n * (j + n * k)] = T(0);
     }
+  // only the cells of this colour (n is even: half of every x-row)
+  for (int q = threadIdx.x; q < cells / 2; q += blockDim.x) {
+    const int j = (q / nh) % n, k = q / (nh * n);
+    const int i = 2 * (q % nh) + ((colour + j + k) & 1);
+    const int c = i + n * (j + n * k);
     T w[6];
     small_faces(L, base, c, i, j, k, w);
     T num = T(0);
@@ -714,13 +745,14 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_cycle(SmallCycle<T> S,
     const SmallLevel<T>& L = S.lv[S.nlev - 1];
     __shared__ double sb[kMaxCoarse];
     const int m = S.m;
-    for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)L.b[(size_t)b * m + q];
+    const size_t bl = base[S.nlev - 1];
+    for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)L.b[bl + q];
     __syncthreads();
     const double* Mi = S.inv + (size_t)b * m * m;
     for (int r = threadIdx.x; r < m; r += blockDim.x) {
       double s = 0.0;
       for (int q = 0; q < m; ++q) s += Mi[(size_t)q * m + r] * sb[q];
-      L.x[(size_t)b * m + r] = (T)s;
+      L.x[bl + r] = (T)s;
     }
     __syncthreads();
   }

@@ -357,9 +357,9 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
   ck_launch();
   if (fine)
     timed(op, K_COARSE_VCYCLE, 0.0, s,
-          [&] { vcycle<T>(op, 1, lvl_b<T>(Lc), lvl_x<T>(Lc), nu, active, s); });
+          [&] { vcycle<T>(op, 1, lvl_b<T>(Lc), lvl_x<T>(Lc), op->nu_c, active, s); });
   else
-    vcycle<T>(op, l + 1, lvl_b<T>(Lc), lvl_x<T>(Lc), nu, active, s);
+    vcycle<T>(op, l + 1, lvl_b<T>(Lc), lvl_x<T>(Lc), op->nu_c, active, s);
   const int want = dot_parts ? 1 : 0;
   sweep(nu, xpre, 1, 2, (nu == 1) ? want : 0);
   for (int q = nu + 1; q < 2 * nu; ++q) sweep(q, dst(q - 1), 1, 0, (q == 2 * nu - 1) ? want : 0);
@@ -387,7 +387,7 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
   }
   S.inv = op->coarse_inv;
   S.m = op->coarse_m;
-  S.nu = nu;
+  S.nu = l == 0 ? nu : op->nu_c;
   hipLaunchKernelGGL(k_small_cycle<T>, dim3(B), dim3(kSmallBlock), 0, s, S, active);
   ck_launch();
 }
@@ -592,7 +592,7 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
   // iterations in blocks of check_every; the kernels themselves stop working on a
   // problem once it has converged, so a block may overrun the last useful iteration
   const bool graphs = op->use_graphs && !op->prof.on;
-  const GraphKey key{(int)sizeof(T), nu, check_every, ctl.max_iter,
+  const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter,
                      {(const void*)ctl.scal, x, r, z, p, q}};
   for (int done = 0; done <= ctl.max_iter; done += check_every) {
     if (graphs)
@@ -680,6 +680,7 @@ void mpp_default_opts(mpp_solve_opts* o) {
   o->mode = MPP_MODE_FP64;
   o->guess = MPP_GUESS_ZERO;
   o->nu = 2;
+  o->nu_coarse = 0;
   o->check_every = 2;
   o->inner_rtol = 1e-5;
 }
@@ -753,7 +754,7 @@ int build_into(mpp_op_s* op, const double* phi, const std::vector<double>& host,
     ck_launch();
   }
   const Level& Lc = op->lev[op->nlev - 1];
-  hipLaunchKernelGGL(k_coarse_factor, dim3(B), dim3(kBlock), 0, s, Lc.f64[0], Lc.f64[1],
+  hipLaunchKernelGGL(k_coarse_factor, dim3(B), dim3(1024), 0, s, Lc.f64[0], Lc.f64[1],
                      Lc.f64[2], Lc.n, op->coarse_work, op->coarse_inv);
   ck_launch();
   ck(hipMemcpyAsync(op->h_status, op->outer.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
@@ -921,6 +922,7 @@ int mpp_vcycle(mpp_op op, const double* r, double* z, int nu, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   try {
     ensure_tuned<double>(op, s);
+    op->nu_c = nu;
     vcycle<double>(op, 0, r, z, nu, nullptr, s);
   } catch (HipError& e) {
     return status_of(e.e);
@@ -949,7 +951,7 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
               mpp_solve_info* info, void* stream) {
   if (!op || !f || !p || !opts || !info || f == p) return MPP_EINVAL;
   const mpp_solve_opts& o = *opts;
-  if (!(o.rtol > 0.0) || o.max_iter < 1 || o.nu < 1 || o.check_every < 1 ||
+  if (!(o.rtol > 0.0) || o.max_iter < 1 || o.nu < 1 || o.check_every < 1 || o.nu_coarse < 0 ||
       (o.mode != MPP_MODE_FP64 && o.mode != MPP_MODE_MIXED) ||
       (o.guess != MPP_GUESS_ZERO && o.guess != MPP_GUESS_GIVEN))
     return MPP_EINVAL;
@@ -964,6 +966,7 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
   try {
     ensure_tuned<double>(op, s);
     if (o.mode == MPP_MODE_MIXED) ensure_tuned<float>(op, s);
+    op->nu_c = o.nu_coarse > 0 ? o.nu_coarse : o.nu;
     Ctl& oc = op->outer;
     reset_ctl(op, oc, o.max_iter, s);
     make_rhs(op, oc, f, op->b, s, o.rtol, true);

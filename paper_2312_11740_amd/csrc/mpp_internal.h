@@ -108,10 +108,12 @@ struct Prof {
 
 // A captured block of CG iterations and what it was captured for.
 struct GraphKey {
-  int tsize, nu, iters, max_iter;
+  int tsize, nu, nu_c, iters, max_iter;
   const void* ptr[6];
   bool operator==(const GraphKey& o) const {
-    if (tsize != o.tsize || nu != o.nu || iters != o.iters || max_iter != o.max_iter) return false;
+    if (tsize != o.tsize || nu != o.nu || nu_c != o.nu_c || iters != o.iters ||
+        max_iter != o.max_iter)
+      return false;
     for (int q = 0; q < 6; ++q)
       if (ptr[q] != o.ptr[q]) return false;
     return true;
@@ -134,6 +136,7 @@ struct mpp_op_s {
   double* x = nullptr;              // FP64 iterate (the caller's p is copied in and out)
   int kz[2][mpp::kMaxLevels] = {};  // tuned z-chunk of the fused sweeps [fp32?][level], 0 = default
   bool tuned[2] = {false, false};
+  int nu_c = 2;                     // sweeps per level below the finest
   int n = 0, batch = 0, nlev = 0;
   uint32_t flags = 0;
   mpp::Level lev[mpp::kMaxLevels];
