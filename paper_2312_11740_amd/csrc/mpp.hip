@@ -22,6 +22,7 @@
 #include "kernels.h"
 #include "net_internal.h"
 #include "rbgs.h"
+#include "rbgs3d.h"
 #include "stencil.h"
 
 using namespace mpp;
@@ -130,9 +131,11 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
   op->p32 = cv.take<float>(C);
   op->q32 = cv.take<float>(C);
   op->d32 = cv.take<float>(C);
-  for (int l = 0; l < L; ++l)   // every z-chunk the tuner may pick
+  for (int l = 0; l < L; ++l) {   // every sweep kernel the tuner may pick
     for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2)
       op->pstride = std::max(op->pstride, rb_grid(rb_tiles(sizes[l], B, kz)));
+    op->pstride = std::max(op->pstride, grid3(tiles3(sizes[l])));
+  }
   op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
   op->partials = cv.take<double>((size_t)B * op->pstride);
   op->counters = cv.take<unsigned>((size_t)B);
@@ -311,6 +314,28 @@ template <typename T>
 void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, hipStream_t s,
             const Ctl* dctl = nullptr, int* dot_parts = nullptr);
 
+// One fused sweep on level l with the kernel the tuner picked for it: kz > 0 the
+// z-marching kernel with chunks of kz planes (0: its default), kz < 0 the 3D-tile
+// kernel.  Returns the grid size (the number of dot partials).
+template <typename T, int MODE, bool FINE>
+int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs, const T* in,
+              const T* ec, T* out, int c1, const Ctl& ctl, int dot, const int* active,
+              hipStream_t s) {
+  const int n = op->lev[l].n, B = op->batch;
+  if (kz < 0) {
+    const Tiles3 t3 = tiles3(n);
+    const dim3 grid(grid3(t3), B);
+    hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE>), grid, dim3(k3Threads), 0, s, F, n, t3, rhs,
+                       in, ec, out, c1, ctl, dot, active);
+    return (int)grid.x;
+  }
+  const RbTiles tl = rb_tiles(n, B, kz);
+  const dim3 grid(rb_grid(tl), B);
+  hipLaunchKernelGGL((k_rb_sweep<T, MODE, FINE>), grid, dim3(kRbThreads), 0, s, F, n, tl, rhs, in,
+                     ec, out, c1, ctl, dot, active);
+  return (int)grid.x;
+}
+
 // A level with fused sweeps: 2 nu out-of-place sweeps alternate between x and a
 // scratch array so that the last one lands in x; the prolongation is folded into the
 // first post-smoothing sweep and r.z (b.x) into the last one when dot_parts is given.
@@ -319,18 +344,17 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
                   hipStream_t s, const Ctl* dctl, int* dot_parts) {
   Level& L = op->lev[l];
   Level& Lc = op->lev[l + 1];
-  const int B = op->batch, n = L.n;
   const Faces<T> F = faces_of<T>(op, l);
   T* tmp = l == 0 ? level0_tmp<T>(op) : lvl_t<T>(L);
-  const RbTiles tl = rb_tiles(n, B, op->kz[sizeof(T) == 4][l]);
-  const dim3 grid(rb_grid(tl), B);
+  const int kz = op->kz[sizeof(T) == 4][l];
   const Ctl ctl = dctl ? *dctl : op->outer;
   const bool fine = l == 0;
+  int nparts = 0;
   auto dst = [&](int sw) { return ((2 * nu - 1 - sw) % 2 == 0) ? x : tmp; };
   auto launch = [&](int sw, const T* in, int c1, int mode, int dot) {
-#define MPP_RB(MD, FN)                                                                           \
-  hipLaunchKernelGGL((k_rb_sweep<T, MD, FN>), grid, dim3(kRbThreads), 0, s, F, n, tl, rhs, in,    \
-                     (const T*)(MD == 2 ? lvl_x<T>(Lc) : nullptr), dst(sw), c1, ctl, dot, active)
+    const T* ecv = lvl_x<T>(Lc);
+#define MPP_RB(MD, FN) \
+  nparts = launch_rb<T, MD, FN>(op, l, kz, F, rhs, in, ecv, dst(sw), c1, ctl, dot, active, s)
     if (fine) {
       if (mode == 1) MPP_RB(1, true); else if (mode == 2) MPP_RB(2, true); else MPP_RB(0, true);
     } else {
@@ -363,7 +387,7 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
   const int want = dot_parts ? 1 : 0;
   sweep(nu, xpre, 1, 2, (nu == 1) ? want : 0);
   for (int q = nu + 1; q < 2 * nu; ++q) sweep(q, dst(q - 1), 1, 0, (q == 2 * nu - 1) ? want : 0);
-  if (dot_parts) *dot_parts = grid.x;
+  if (dot_parts) *dot_parts = nparts;
 }
 
 template <typename T>
@@ -393,9 +417,10 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
 }
 
 // ------------------------------------------------------------------------------
-// tile autotuning: the z-chunk of the fused sweeps (fewer, longer marches versus
-// more blocks) is timed per level with HIP events the first time a shape is solved
-// in a precision, and cached for the process by (n, batch, precision, level size)
+// tile autotuning: the sweep kernel of each level (z-marching with a z-chunk of 2 .. 32
+// planes, or 3D tiles loaded at once) is timed with HIP events the first time a shape
+// is solved in a precision, and cached for the process by (n, batch, precision, level
+// size)
 // ------------------------------------------------------------------------------
 struct TuneKey {
   int n, batch, tsize, nl;
@@ -416,6 +441,12 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
   op->tuned[w] = true;
   const char* env = std::getenv("MPP_AUTOTUNE");
   if (env && env[0] == '0') return;
+  // MPP_SWEEP=march or =tile fixes the sweep kernel of every level (no timing)
+  const char* force = std::getenv("MPP_SWEEP");
+  if (force && (std::strcmp(force, "march") == 0 || std::strcmp(force, "tile") == 0)) {
+    for (int l = 0; l < op->nlev; ++l) op->kz[w][l] = force[0] == 't' ? -1 : 0;
+    return;
+  }
   const int B = op->batch;
   hipEvent_t e0, e1;
   ck(hipEventCreate(&e0));
@@ -443,16 +474,18 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     const Faces<T> F = faces_of<T>(op, l);
     float best = 1e30f;
     int best_kz = 0;
-    for (int kz = 2; kz <= 2 * kRbKZ && kz <= L.n; kz *= 2) {
-      const RbTiles tl = rb_tiles(L.n, B, kz);
-      const dim3 grid(rb_grid(tl), B);
+    // candidates: the z-marching kernel with chunks of 2 .. 32 planes, the 3D-tile kernel
+    std::vector<int> cands;
+    for (int kz = 2; kz <= 2 * kRbKZ && kz <= L.n; kz *= 2) cands.push_back(kz);
+    cands.push_back(-1);
+    for (int kz : cands) {
       auto launch = [&] {
         if (l == 0)
-          hipLaunchKernelGGL((k_rb_sweep<T, 0, true>), grid, dim3(kRbThreads), 0, s, F, L.n, tl,
-                             rhs, in, (const T*)nullptr, out, 0, op->outer, 0, (const int*)nullptr);
+          launch_rb<T, 0, true>(op, l, kz, F, rhs, in, (const T*)nullptr, out, 0, op->outer, 0,
+                                (const int*)nullptr, s);
         else
-          hipLaunchKernelGGL((k_rb_sweep<T, 0, false>), grid, dim3(kRbThreads), 0, s, F, L.n, tl,
-                             rhs, in, (const T*)nullptr, out, 0, op->outer, 0, (const int*)nullptr);
+          launch_rb<T, 0, false>(op, l, kz, F, rhs, in, (const T*)nullptr, out, 0, op->outer, 0,
+                                 (const int*)nullptr, s);
       };
       launch();
       ck(hipEventRecord(e0, s));
@@ -1147,13 +1180,11 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
                        (int)S_RZ, (int)S_PQ, (int)kSlots);
     ck_launch();
     // red-black sweeps on A p = b, alternating between p and a scratch vector
-    const RbTiles tl = rb_tiles(op->n, B, op->kz[0][0]);
-    const dim3 grid(rb_grid(tl), B);
     double* bufs[2] = {p, op->q};
     for (int q = 0; q < sweeps; ++q) {
-      hipLaunchKernelGGL((k_rb_sweep<double, 0, true>), grid, dim3(kRbThreads), 0, s, F, op->n, tl,
-                         (const double*)op->b, (const double*)bufs[q & 1], (const double*)nullptr,
-                         bufs[(q + 1) & 1], 0, ctl, 0, (const int*)nullptr);
+      launch_rb<double, 0, true>(op, 0, op->kz[0][0], F, (const double*)op->b,
+                                 (const double*)bufs[q & 1], (const double*)nullptr,
+                                 bufs[(q + 1) & 1], 0, ctl, 0, (const int*)nullptr, s);
       ck_launch();
     }
     if (sweeps & 1)

@@ -1,0 +1,207 @@
+// Red-black Gauss-Seidel sweep, one pass over memory, on 3D tiles loaded at once.
+//
+// Same semantics as the z-marching sweep (two one-colour half sweeps, out of place):
+//   x1  = x_in with every c1 cell set to (sum_f w_f x_in[nb] - h^2 b) / sum_f w_f,
+//   out = x1  with every c2 cell set to (sum_f w_f x1[nb]  - h^2 b) / sum_f w_f.
+// A block owns a 32 x 8 x 8 tile.  It issues every load of its inputs together
+// (x_in on the tile and a two-cell ring, b and the finest-level code on the tile and a
+// one-cell ring), so each block has ~40 KB in flight instead of one plane; then the
+// c1 values on tile + ring, a barrier, the c2 values on the tile.  The ring reads of
+// neighbouring tiles hit L2 (tiles are handed out in x-fastest order per XCD).
+#pragma once
+
+#include "rbgs.h"
+
+namespace mpp {
+
+constexpr int k3X = 32, k3Y = 8, k3Z = 8;
+constexpr int k3Threads = 512;
+constexpr int k3XX = k3X + 4, k3XY = k3Y + 4, k3XZ = k3Z + 4;   // x_in tile, 2-cell ring
+constexpr int k3BX = k3X + 2, k3BY = k3Y + 2, k3BZ = k3Z + 2;   // b / c1 tile, 1-cell ring
+constexpr int k3NX = k3XX * k3XY * k3XZ;
+constexpr int k3NB = k3BX * k3BY * k3BZ;
+
+struct Tiles3 {
+  int tx, ty, tz, ntiles;
+};
+
+inline Tiles3 tiles3(int n) {
+  Tiles3 t;
+  t.tx = (n + k3X - 1) / k3X;
+  t.ty = (n + k3Y - 1) / k3Y;
+  t.tz = (n + k3Z - 1) / k3Z;
+  t.ntiles = t.tx * t.ty * t.tz;
+  return t;
+}
+
+inline int grid3(const Tiles3& t) { return 8 * ((t.ntiles + 7) / 8); }
+
+template <typename T>
+struct Lds3 {
+  T x[k3NX];
+  T c1[k3NB];
+  T b[k3NB];
+  uint8_t code[k3NB];
+};
+
+template <typename T, int MODE, bool FINE>
+__global__ void __launch_bounds__(k3Threads)
+    k_rb_sweep3d(Faces<T> F, int n, Tiles3 tl, const T* __restrict__ rhs,
+                 const T* __restrict__ xin, const T* __restrict__ ec, T* __restrict__ xout,
+                 int c1, Ctl ctl, int dot, const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int tile = xcd_tile(blockIdx.x, tl.ntiles);
+  if (tile < 0) {
+    if (dot && threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = 0.0;
+    return;
+  }
+  __shared__ Lds3<T> S;
+  const int tid = threadIdx.x;
+  const int i0 = (tile % tl.tx) * k3X;
+  const int j0 = ((tile / tl.tx) % tl.ty) * k3Y;
+  const int k0 = (tile / (tl.tx * tl.ty)) * k3Z;
+  const size_t nn = (size_t)n * n;
+  const size_t base = (size_t)b * nn * n;
+  const int nc = n >> 1;
+  const size_t basec = (size_t)b * (size_t)nc * nc * nc;
+  const T h2 = (T)(1.0 / ((double)n * (double)n));
+  const T ir0 = FINE ? F.inv_rho[2 * b] : T(0), ir1 = FINE ? F.inv_rho[2 * b + 1] : T(0);
+  const T hr0 = FINE ? h2 / ir0 : T(0), hr1 = FINE ? h2 / ir1 : T(0);
+
+  // ---- every load of the block at once ----
+  constexpr int PX = (k3NX + k3Threads - 1) / k3Threads;
+  constexpr int PB = (k3NB + k3Threads - 1) / k3Threads;
+  if (MODE != 1) {
+    T rx[PX];
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + u * k3Threads;
+      const int i = i0 - 2 + e % k3XX, j = j0 - 2 + (e / k3XX) % k3XY, k = k0 - 2 + e / (k3XX * k3XY);
+      T v = T(0);
+      if (e < k3NX && i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) {
+        v = xin[base + (size_t)k * nn + (size_t)j * n + i];
+        if (MODE == 2) v += ec[basec + ((size_t)(k >> 1) * nc + (j >> 1)) * nc + (i >> 1)];
+      }
+      rx[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + u * k3Threads;
+      if (e < k3NX) S.x[e] = rx[u];
+    }
+  }
+  {
+    T rb[PB];
+    uint8_t rc[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int e = tid + u * k3Threads;
+      const int i = i0 - 1 + e % k3BX, j = j0 - 1 + (e / k3BX) % k3BY, k = k0 - 1 + e / (k3BX * k3BY);
+      T v = T(0);
+      uint8_t cd = 0;
+      if (e < k3NB && i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n) {
+        const size_t c = base + (size_t)k * nn + (size_t)j * n + i;
+        v = rhs[c];
+        if (FINE) cd = F.code[c];
+      }
+      rb[u] = v;
+      rc[u] = cd;
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int e = tid + u * k3Threads;
+      if (e < k3NB) {
+        S.b[e] = rb[u];
+        if (FINE) S.code[e] = rc[u];
+      }
+    }
+  }
+  lds_barrier();
+
+  // Gauss-Seidel update of one cell from its six neighbour values (walls masked);
+  // nb = false when every neighbour value is zero (first colour of a sweep from zero)
+  auto update = [&](bool nb, unsigned cd, size_t cell, int i, int j, int k, T xw, T xe, T xs,
+                    T xn, T xd, T xu, T bb) -> T {
+    const bool wl = i > 0, wr = i < n - 1, ws = j > 0, wn = j < n - 1, wd = k > 0, wu = k < n - 1;
+    if (FINE && (cd & 63u) == 0u) {
+      T sum = T(0);
+      if (nb) {
+        sum = (wl ? xw : T(0)) + (wr ? xe : T(0));
+        sum += (ws ? xs : T(0)) + (wn ? xn : T(0));
+        sum += (wd ? xd : T(0)) + (wu ? xu : T(0));
+      }
+      const int cnt = (int)wl + (int)wr + (int)ws + (int)wn + (int)wd + (int)wu;
+      const T inv = cnt == 6 ? T(1) / T(6) : (cnt == 5 ? T(1) / T(5) : (cnt == 4 ? T(0.25) : T(1) / T(3)));
+      const T hr = (cd & 64u) ? hr1 : hr0;
+      return (sum - hr * bb) * inv;
+    }
+    T w[6];
+    sweep_faces<T, FINE>(F, cell, cd, i, j, k, n, nn, ir0, ir1, w);
+    T num = T(0);
+    if (nb) {
+      if (wl) num += w[0] * xw;
+      if (wr) num += w[1] * xe;
+      if (ws) num += w[2] * xs;
+      if (wn) num += w[3] * xn;
+      if (wd) num += w[4] * xd;
+      if (wu) num += w[5] * xu;
+    }
+    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
+    return (num - h2 * bb) / den;
+  };
+
+  // ---- c1 values on the tile and its one-cell ring (17 per ring row) ----
+  constexpr int kRowC1 = k3BX / 2;
+  constexpr int kNC1 = kRowC1 * k3BY * k3BZ;
+  for (int q = tid; q < kNC1; q += k3Threads) {
+    const int row = q / kRowC1;
+    const int ey = row % k3BY, ez = row / k3BY;
+    const int j = j0 - 1 + ey, k = k0 - 1 + ez;
+    const int par = ((c1 - (i0 - 1) - j - k) % 2 + 2) % 2;
+    const int ex = 2 * (q % kRowC1) + par;
+    const int i = i0 - 1 + ex;
+    if (i < 0 || i >= n || j < 0 || j >= n || k < 0 || k >= n) continue;
+    const int lb = (ez * k3BY + ey) * k3BX + ex;
+    const int lx = ((ez + 1) * k3XY + ey + 1) * k3XX + ex + 1;
+    T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
+    if (MODE != 1) {
+      xw = S.x[lx - 1];
+      xe = S.x[lx + 1];
+      xs = S.x[lx - k3XX];
+      xn = S.x[lx + k3XX];
+      xd = S.x[lx - k3XX * k3XY];
+      xu = S.x[lx + k3XX * k3XY];
+    }
+    const unsigned cd = FINE ? S.code[lb] : 0u;
+    S.c1[lb] = update(MODE != 1, cd, base + (size_t)k * nn + (size_t)j * n + i, i, j, k, xw, xe,
+                      xs, xn, xd, xu, S.b[lb]);
+  }
+  lds_barrier();
+
+  // ---- c2 values (and the c1 copies) on the tile ----
+  double acc = 0.0;
+  constexpr int kCells = k3X * k3Y * k3Z;
+  for (int t = tid; t < kCells; t += k3Threads) {
+    const int tx = t % k3X, ty = (t / k3X) % k3Y, tz = t / (k3X * k3Y);
+    const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+    if (i >= n || j >= n || k >= n) continue;
+    const int q = ((tz + 1) * k3BY + ty + 1) * k3BX + tx + 1;
+    const size_t cell = base + (size_t)k * nn + (size_t)j * n + i;
+    const T bb = S.b[q];
+    T out;
+    if (((i + j + k) & 1) == c1) {
+      out = S.c1[q];
+    } else {
+      // c1 entries outside the domain were never written: the wall masks skip them
+      const unsigned cd = FINE ? S.code[q] : 0u;
+      out = update(true, cd, cell, i, j, k, S.c1[q - 1], S.c1[q + 1], S.c1[q - k3BX],
+                   S.c1[q + k3BX], S.c1[q - k3BX * k3BY], S.c1[q + k3BX * k3BY], bb);
+    }
+    xout[cell] = out;
+    if (dot) acc += (double)bb * (double)out;
+  }
+  if (dot) block_partial(acc, ctl, b);
+}
+
+}  // namespace mpp
