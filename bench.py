@@ -8,9 +8,10 @@ operator for that step's level set and solve to a relative residual of 1e-10,
 warm-started from the previous step's pressure.  Inputs (phi_t, f_t) for every
 step are resident in HBM before the timed region.
 
-Three methods run on the same steps:
+Four methods run on the same steps:
   plain   -- FP64 multigrid-preconditioned CG warm-started from the previous step's
              pressure (the baseline),
+  plain0  -- the same from a zero initial guess,
   mixed   -- FP32 multigrid-preconditioned CG inside FP64 residual refinement, warm
              started likewise,
   learned -- mixed, started from the learned guess: the U-Net trained on 64^3 problems
@@ -69,10 +70,10 @@ def measured_traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
-def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None):
+def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None, zero=False):
     """warmup + steps projection solves, each warm-started from the previous step (or,
-    with a network, from the learned guess); returns (mean ms per timed step, infos of
-    the timed steps, learned-guess fallbacks)."""
+    with a network, from the learned guess; with zero, from zero); returns (mean ms per
+    timed step, infos of the timed steps, learned-guess fallbacks)."""
     p = torch.zeros_like(fs[0])
     infos = []
     fallbacks = 0
@@ -87,7 +88,7 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None)
             p, fell = op.learned_guess(net, fs[t], sweeps=2, out=p)
             if t >= warmup:
                 fallbacks += sum(fell)
-        p, info = op.solve(fs[t], p=p, rtol=prm["rtol"], mode=mode, nu=nu)
+        p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu)
         if t >= warmup:
             infos.append(info[0])
     torch.cuda.synchronize()
@@ -196,6 +197,64 @@ def batched64(M, G, torch, args):
                       "methods": res}), flush=True)
 
 
+def cpu_baseline_single(pr, solutions, rtol):
+    """The CPU leg of a single-problem workload: the oracle (assemble + its FP64 MG-PCG to
+    1e-13) timed on the host cores, and each GPU method's error against its solution."""
+    import oracle as O
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    po, _, oi = O.solve(pr.phi, pr.f, pr.rho_neg, pr.rho_pos, pr.sigma, tol=1e-13)
+    sec = time.perf_counter() - t0
+    errs = {m: float(np.linalg.norm(ph - po) / np.linalg.norm(po)) for m, ph in solutions.items()}
+    rec = {"value": round(sec * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+           "sample": "the whole problem: assemble + FP64 MG-PCG (nu=2) to 1e-13 (%d iterations)"
+                     % oi["iters"]}
+    return rec, errs
+
+
+def single_problem(M, G, torch, args, which):
+    """One of the fixed single-problem configurations, plain vs mixed, zero start:
+    single32 -- one sphere r 0.25 at the centre, rho 1 inside / 10 outside, sigma 0,
+                manufactured right-hand side, 32^3;
+    bubbles128 -- 20 bubbles (seed 1, r in [0.04, 0.12]), ratio 1000, sigma 0.01, 128^3.
+    Time per solve (operator built once, outside the timed region), iterations and the
+    error against the oracle's solution."""
+    dev = torch.device("cuda:0")
+    pr = G.single_bubble_problem(32) if which == "single32" else G.many_bubbles_problem()
+    rtol = 1e-10 if which == "single32" else 2e-11
+    phi = torch.from_numpy(pr.phi).to(dev)
+    f = torch.from_numpy(pr.f).to(dev)
+    op = M.Operator(phi, pr.rho_neg, pr.rho_pos, pr.sigma)
+    res, sols = {}, {}
+    for meth, mode in (("plain", "fp64"), ("mixed", "mixed")):
+        for _ in range(args.warmup):
+            op.solve(f, rtol=rtol, mode=mode, nu=args.nu)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            p, infos = op.solve(f, rtol=rtol, mode=mode, nu=args.nu)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        sols[meth] = p.cpu().numpy()
+        res[meth] = {"ms_per_solve": round(ms, 3), "iters": infos[0].iters,
+                     "outer": infos[0].outer_iters, "rel_resid": infos[0].rel_resid,
+                     "ok": infos[0].status == M.OK}
+        log(meth, res[meth])
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, errs = cpu_baseline_single(pr, sols, rtol)
+        for m in res:
+            res[m]["err_vs_oracle"] = errs[m]
+        log("cpu baseline", cpu, errs)
+    best = min(res, key=lambda m: res[m]["ms_per_solve"])
+    print(json.dumps({"metric": "time per solve to %g rel. residual" % rtol,
+                      "value": res[best]["ms_per_solve"], "unit": "ms",
+                      "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "data": "synthetic",
+                      "config": {"workload": which, "method": best},
+                      "methods": res, "cpu_baseline": cpu}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,11 +262,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--nu", type=int, default=2)
-    ap.add_argument("--methods", default="plain,mixed,learned")
+    ap.add_argument("--methods", default="plain,plain0,mixed,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", default="rising256", choices=["rising256", "batched64"],
-                    help="rising256: the 256^3 sequence (default); batched64: 64 x 64^3")
+    ap.add_argument("--workload", default="rising256",
+                    choices=["rising256", "batched64", "single32", "bubbles128"],
+                    help="rising256: the 256^3 sequence (default); batched64: 64 x 64^3; "
+                         "single32 / bubbles128: one fixed problem, plain vs mixed")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter scaling)")
     args = ap.parse_args()
@@ -230,6 +291,9 @@ def main():
     if args.workload == "batched64":
         batched64(M, G, torch, args)
         return
+    if args.workload in ("single32", "bubbles128"):
+        single_problem(M, G, torch, args, args.workload)
+        return
     n, K, W = args.n, args.steps, args.warmup
     prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01, rtol=1e-10)
     log("generating %d steps of the %d^3 rising-bubble sequence" % (K + W, n))
@@ -239,7 +303,7 @@ def main():
     ws = torch.empty(M.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    MODES = {"plain": "fp64", "mixed": "mixed", "learned": "mixed"}
+    MODES = {"plain": "fp64", "plain0": "fp64", "mixed": "mixed", "learned": "mixed"}
     net = None
     if "learned" in args.methods.split(","):
         net = M.Net(64, 1, device=dev)
@@ -248,7 +312,7 @@ def main():
     for meth in args.methods.split(","):
         mode = MODES[meth]
         ms, infos, fb = run_sequence(M, torch, ws, phis, fs, prm, mode, args.nu, K, W,
-                                     net if meth == "learned" else None)
+                                     net if meth == "learned" else None, zero=meth == "plain0")
         worst = max(i.rel_resid for i in infos)
         ok = all(i.status == M.OK for i in infos) and worst <= prm["rtol"]
         results[meth] = dict(ms=ms, iters=[i.iters for i in infos],
@@ -283,7 +347,7 @@ def main():
         v = stats[dom]
         per_launch = v["bytes"] / v["launches"]
         achieved = per_launch / (v["ms"] * 1e-3 / v["launches"]) / 1e9
-        kname = "%s/%s" % (dom, "f64" if best == "plain" else "f32")
+        kname = "%s/%s" % (dom, "f64" if MODES[best] == "fp64" else "f32")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(kname), "kernel": kname,
@@ -319,7 +383,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"plain": "f64", "mixed": "f32+f64", "learned": "bf16+f32+f64"}[best],
+        "dtype": {"plain": "f64", "plain0": "f64", "mixed": "f32+f64",
+                  "learned": "bf16+f32+f64"}[best],
         "data": "synthetic",
         "config": {"workload": "rising bubble %d^3, density ratio 1000, sigma 0.01, one "
                                "projection solve (operator build + MG-PCG to 1e-10, warm "
@@ -333,6 +398,9 @@ def main():
                         "ok": r["ok"], "guess_fallbacks": r["fallbacks"]}
                     for m, r in results.items()},
         "speedup_vs_plain_fp64": (round(plain_ms / value, 3) if plain_ms else None),
+        "speedup_vs_best_plain": (round(min(results[m]["ms"] for m in ("plain", "plain0")
+                                            if m in results) / value, 3)
+                                  if ("plain" in results or "plain0" in results) else None),
         "err_vs_oracle_step0": err,
         "roofline": roofline,
         "kernels": kernels,
