@@ -53,6 +53,8 @@ def lib():
         L.orc_solve_jacobi_pcg.argtypes = [i, P, P, P, P, P, d, i, P, P]
         L.orc_solve_mg_pcg.argtypes = [i, P, P, P, P, P, d, i, i, P, P]
         L.orc_pipeline.argtypes = [i, P, P, d, d, d, P, P, P, P, P, P, P, P]
+        L.orc_divergence.argtypes = [i, P, P, P, d, P]
+        L.orc_project.argtypes = [i, P, P, P, d, d, d, d, P, P, P]
         L.orc_gs_colour.argtypes = [i, P, P, P, P, P, i]
         L.orc_gs_colour.restype = None
         L.orc_restrict.argtypes = [i, P, P]
@@ -170,6 +172,23 @@ def solve_mg_pcg(fc, b, tol=1e-13, max_iter=1000, nu=2, x0=None):
     st = lib().orc_solve_mg_pcg(_n(b), _p(bx), _p(by), _p(bz), _p(b), _p(x), tol, max_iter, nu,
                                 ctypes.byref(it), ctypes.byref(rr))
     return x, dict(status=st, iters=it.value, rel_residual=rr.value)
+
+
+def divergence(u, dt):
+    """u = (ux, uy, uz) low-face velocities -> f = div(u)/dt at the cell centres."""
+    ux, uy, uz = (_c(a) for a in u)
+    f = np.empty_like(ux)
+    _check(lib().orc_divergence(_n(ux), _p(ux), _p(uy), _p(uz), float(dt), _p(f)), "divergence")
+    return f
+
+
+def project(phi, kappa, p, rho_neg, rho_pos, sigma, dt, u):
+    """u - dt beta grad p with the jump-corrected gradient (returns new arrays)."""
+    phi, kappa, p = _c(phi), _c(kappa), _c(p)
+    ux, uy, uz = (_c(a).copy() for a in u)
+    _check(lib().orc_project(_n(phi), _p(phi), _p(kappa), _p(p), float(rho_neg), float(rho_pos),
+                             float(sigma), float(dt), _p(ux), _p(uy), _p(uz)), "project")
+    return ux, uy, uz
 
 
 def pipeline(phi, f, rho_neg, rho_pos, sigma, kappa_override=None):

@@ -740,6 +740,73 @@ int orc_solve_mg_pcg(int n, const double *bx, const double *by, const double *bz
 }
 
 /* ------------------------------------------------------------------------ */
+/* The projection around the solve (Sec. 2, fractional step on the staggered  */
+/* grid): f = div(u*)/dt on the cell centres, then u = u* - dt beta grad p on  */
+/* the faces, with the same jump-corrected gradient the right-hand side uses   */
+/* ------------------------------------------------------------------------ */
+
+/* Face velocities use the low-face layout of the coefficients: ux[i,j,k] is the
+ * x-velocity on the face between (i-1,j,k) and (i,j,k); ux[0,j,k] is the wall (and
+ * is read as 0, whatever it holds); high wall faces are implicit zeros.
+ * f[c] = (sum over the three axes of (u on the high face - u on the low face) / h) / dt. */
+int orc_divergence(int n, const double *ux, const double *uy, const double *uz, double dt,
+                   double *f)
+{
+    if (n < 1 || !ux || !uy || !uz || !f || !(dt > 0.0))
+        return ORC_EINVAL;
+    double inv_h = (double)n;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t c = ix(n, i, j, k);
+                double xl = i > 0 ? ux[c] : 0.0, xh = i < n - 1 ? ux[ix(n, i + 1, j, k)] : 0.0;
+                double yl = j > 0 ? uy[c] : 0.0, yh = j < n - 1 ? uy[ix(n, i, j + 1, k)] : 0.0;
+                double zl = k > 0 ? uz[c] : 0.0, zh = k < n - 1 ? uz[ix(n, i, j, k + 1)] : 0.0;
+                f[c] = (((xh - xl) + (yh - yl)) + (zh - zl)) * inv_h / dt;
+            }
+    return ORC_OK;
+}
+
+/* u_f -= dt * beta^_f * (p_b - p_a - d_f J_f) / h on every interior face between a
+ * (low) and b (high): J_f = sigma ((1-theta) kappa_a + theta kappa_b) and d_f = +1
+ * when a is on the "-" side and b on the "+" side, -1 for the opposite crossing, 0
+ * on same-side faces.  That is the gradient of p with b's value carried across the
+ * interface to a's side (p+ - p- = J), the same flux whose jump part the jump term
+ * moves to the right-hand side, so div(u) = div(u*) - dt (A p - jterm).  Wall faces
+ * are set to 0. */
+int orc_project(int n, const double *phi, const double *kappa, const double *p, double rho_neg,
+                double rho_pos, double sigma, double dt, double *ux, double *uy, double *uz)
+{
+    if (n < 1 || !phi || !kappa || !p || !ux || !uy || !uz || !(dt > 0.0))
+        return ORC_EINVAL;
+    double inv_h = (double)n;
+    double *u[3] = {ux, uy, uz};
+    for (int d = 0; d < 3; ++d)
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    size_t b = ix(n, i, j, k);
+                    int ia = i - (d == 0), ja = j - (d == 1), ka = k - (d == 2);
+                    if (ia < 0 || ja < 0 || ka < 0) {
+                        u[d][b] = 0.0;
+                        continue;
+                    }
+                    size_t a = ix(n, ia, ja, ka);
+                    double beta = face_beta(phi[a], phi[b], rho_neg, rho_pos);
+                    double jump = 0.0;
+                    if (is_plus(phi[a]) != is_plus(phi[b])) {
+                        double theta = crossing_theta(phi[a], phi[b]);
+                        double J = sigma * ((1.0 - theta) * kappa[a] + theta * kappa[b]);
+                        jump = is_plus(phi[a]) ? -J : J;
+                    }
+                    u[d][b] -= dt * beta * ((p[b] - p[a]) - jump) * inv_h;
+                }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole pipeline: phi, f -> faces, kappa, jterm, b, p                       */
 /* ------------------------------------------------------------------------ */
 /* kappa_override: NULL to compute kappa from phi, else a per-cell field used as is. */
