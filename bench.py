@@ -70,7 +70,8 @@ def measured_traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
-def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None, zero=False):
+def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None, zero=False,
+                 guess_sweeps=2):
     """warmup + steps projection solves, each warm-started from the previous step (or,
     with a network, from the learned guess; with zero, from zero); returns (mean ms per
     timed step, infos of the timed steps, learned-guess fallbacks)."""
@@ -85,7 +86,7 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
             t0 = time.perf_counter()
         op.update(phis[t], prm["rho_neg"], prm["rho_pos"], prm["sigma"])
         if net is not None:
-            p, fell = op.learned_guess(net, fs[t], sweeps=2, out=p)
+            p, fell = op.learned_guess(net, fs[t], sweeps=guess_sweeps, out=p)
             if t >= warmup:
                 fallbacks += sum(fell)
         p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu)
@@ -255,6 +256,70 @@ def single_problem(M, G, torch, args, which):
                       "methods": res, "cpu_baseline": cpu}), flush=True)
 
 
+def projection256(M, G, torch, args):
+    """The projection step around the solve on the 256^3 rising-bubble sequence: f =
+    div(u*)/dt from seeded face velocities, the mixed solve warm-started from the
+    previous step, the jump-consistent correction.  Time per step and the HIP-event time
+    of the divergence and correction kernels against the HBM roofline."""
+    dev = torch.device("cuda:0")
+    n, K, W = 256, args.steps, args.warmup
+    prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01)
+    dt = 1e-3
+    probs = [G.rising_bubble_problem(t, n=n) for t in range(K + W)]
+    phis = [torch.from_numpy(q.phi).to(dev) for q in probs]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(50000)
+    us = []
+    for _ in range(K + W):
+        u = [torch.randn((n, n, n), dtype=torch.float64, device=dev, generator=gen)
+             for _ in range(3)]
+        u[0][:, :, 0] = 0.0
+        u[1][:, 0, :] = 0.0
+        u[2][0, :, :] = 0.0
+        us.append(u)
+    op = M.Operator(phis[0], **prm)
+    p = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    f = torch.empty_like(p)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_div, t_proj = [], []
+    for t in range(K + W):
+        if t == W:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        op.update(phis[t], **prm)
+        ev[0].record()
+        op.divergence(us[t], dt, out=f)
+        ev[1].record()
+        p, info = op.solve(f, p=p, rtol=1e-10, mode="mixed", nu=args.nu)
+        ev[2].record()
+        op.project(phis[t], p, dt, us[t])
+        ev[3].record()
+        if t >= W:
+            torch.cuda.synchronize()
+            t_div.append(ev[0].elapsed_time(ev[1]))
+            t_proj.append(ev[2].elapsed_time(ev[3]))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    # divergence left after the last step relative to div(u*)/dt (still in f)
+    ratio = float(torch.linalg.vector_norm(op.divergence(us[-1], dt)) /
+                  torch.linalg.vector_norm(f))
+    cells = n ** 3
+    div_ms, proj_ms = float(np.mean(t_div)), float(np.mean(t_proj))
+    div_bytes, proj_bytes = 32.0 * cells, 64.0 * cells
+    rec = {"metric": "time per projection step (divergence + mixed solve + correction), 256^3",
+           "value": round(ms, 3), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "steps": K, "warmup": W, "data": "synthetic",
+           "config": {"workload": "projection256", "dt": dt},
+           "kernels": {"divergence": {"ms": round(div_ms, 4),
+                                      "GBps": round(div_bytes / (div_ms * 1e-3) / 1e9, 1),
+                                      "alg_bytes": div_bytes},
+                       "project": {"ms": round(proj_ms, 4),
+                                   "GBps": round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1),
+                                   "alg_bytes": proj_bytes}},
+           "iters_last": info[0].iters, "div_ratio_last": ratio}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,9 +329,12 @@ def main():
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--methods", default="plain,plain0,mixed,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--guess-sweeps", type=int, default=2,
+                    help="red-black sweeps applied to the learned guess")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", default="rising256",
-                    choices=["rising256", "batched64", "single32", "bubbles128"],
+                    choices=["rising256", "batched64", "single32", "bubbles128",
+                             "projection256"],
                     help="rising256: the 256^3 sequence (default); batched64: 64 x 64^3; "
                          "single32 / bubbles128: one fixed problem, plain vs mixed")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -294,6 +362,9 @@ def main():
     if args.workload in ("single32", "bubbles128"):
         single_problem(M, G, torch, args, args.workload)
         return
+    if args.workload == "projection256":
+        projection256(M, G, torch, args)
+        return
     n, K, W = args.n, args.steps, args.warmup
     prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01, rtol=1e-10)
     log("generating %d steps of the %d^3 rising-bubble sequence" % (K + W, n))
@@ -312,7 +383,8 @@ def main():
     for meth in args.methods.split(","):
         mode = MODES[meth]
         ms, infos, fb = run_sequence(M, torch, ws, phis, fs, prm, mode, args.nu, K, W,
-                                     net if meth == "learned" else None, zero=meth == "plain0")
+                                     net if meth == "learned" else None, zero=meth == "plain0",
+                                     guess_sweeps=args.guess_sweeps)
         worst = max(i.rel_resid for i in infos)
         ok = all(i.status == M.OK for i in infos) and worst <= prm["rtol"]
         results[meth] = dict(ms=ms, iters=[i.iters for i in infos],

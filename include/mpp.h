@@ -183,6 +183,32 @@ void mpp_destroy_operator(mpp_op op);
 
 
 /* ------------------------------------------------------------------------------
+ * The projection around the solve (the fractional step of the paper's Sec. 2 on the
+ * staggered grid).  Face velocities are device [batch][n^3] arrays in the low-face
+ * layout of the coefficients: ux[i,j,k] on the face between cells (i-1,j,k) and
+ * (i,j,k); ux[0,j,k] is the wall face (read as 0; written as 0 by mpp_project); high
+ * wall faces are implicit zeros.
+ * ------------------------------------------------------------------------------ */
+
+/* f = div(u)/dt at the cell centres: (sum over the axes of (u on the high face - u on
+ * the low face) / h) / dt, h = 1/n.  f: device [batch][n^3].  dt > 0 and finite.
+ * Asynchronous. */
+int mpp_divergence(mpp_op op, const double *ux, const double *uy, const double *uz, double dt,
+                   double *f, void *stream);
+
+/* u = u - dt beta^ grad p on every interior face, with the gradient corrected by the
+ * surface-tension jump: (p_b - p_a - d J) / h between the lower cell a and the upper
+ * cell b, J = sigma ((1-theta) kappa_a + theta kappa_b) the jump at the face's crossing
+ * and d = +1 when a is on the phi <= 0 side and b on the phi > 0 side, -1 for the
+ * opposite crossing, 0 on faces the interface does not cross; beta^ the operator's
+ * face coefficient.  This is the flux whose jump part the operator moved into its
+ * right-hand side, so with p the solution for f = div(u*)/dt the result is discretely
+ * divergence-free.  phi: the device level set the operator was built from; p: device
+ * [batch][n^3]; ux, uy, uz updated in place.  Asynchronous. */
+int mpp_project(mpp_op op, const double *phi, const double *p, double dt, double *ux,
+                double *uy, double *uz, void *stream);
+
+/* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from
  * the previous pressure or from zero): a small 3D U-Net maps the density field and
  * the right-hand side of a problem to an approximate solution that seeds the PCG.

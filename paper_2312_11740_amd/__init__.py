@@ -30,7 +30,7 @@ EXPORTS = (
     "mpp_update_operator", "mpp_net_param_count", "mpp_net_workspace_bytes", "mpp_net_create",
     "mpp_net_destroy", "mpp_net_set_params", "mpp_net_get_params", "mpp_net_forward",
     "mpp_net_loss", "mpp_net_backward", "mpp_net_get_grads", "mpp_net_adam",
-    "mpp_net_features", "mpp_learned_guess",
+    "mpp_net_features", "mpp_learned_guess", "mpp_divergence", "mpp_project",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH):
     L.mpp_net_features.argtypes = [P, P, P, P, P, P, P, P]
     L.mpp_learned_guess.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     P]
+    L.mpp_divergence.argtypes = [P, P, P, P, d, P, P]
+    L.mpp_project.argtypes = [P, P, P, d, P, P, P, P]
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
                                                  "mpp_strerror", "mpp_workspace_bytes",
                                                  "mpp_net_workspace_bytes",
@@ -306,6 +308,33 @@ class Operator:
         if st != OK and raise_on_error:
             raise MppError(st, "mpp_solve")
         return p, out
+
+    def divergence(self, u, dt, out=None):
+        """f = div(u)/dt of the low-face velocities u = (ux, uy, uz)."""
+        for name, a in zip(("ux", "uy", "uz"), u):
+            _check_field(a, self.shape, name)
+        f = self._new() if out is None else out
+        _check_field(f, self.shape, "out")
+        st = load_library().mpp_divergence(self._h, *[ctypes.c_void_p(a.data_ptr()) for a in u],
+                                           float(dt), ctypes.c_void_p(f.data_ptr()),
+                                           _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_divergence")
+        return f
+
+    def project(self, phi, p, dt, u):
+        """u -= dt beta grad p (jump-corrected), in place; returns u."""
+        _check_field(phi, self.shape, "phi")
+        _check_field(p, self.shape, "p")
+        for name, a in zip(("ux", "uy", "uz"), u):
+            _check_field(a, self.shape, name)
+        st = load_library().mpp_project(self._h, ctypes.c_void_p(phi.data_ptr()),
+                                        ctypes.c_void_p(p.data_ptr()), float(dt),
+                                        *[ctypes.c_void_p(a.data_ptr()) for a in u],
+                                        _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_project")
+        return u
 
     def learned_guess(self, net, f, sweeps=2, out=None):
         """Initial guess from the network (device float64, the operator's shape) and the

@@ -21,6 +21,7 @@
 #include "guess.h"
 #include "kernels.h"
 #include "net_internal.h"
+#include "project.h"
 #include "rbgs.h"
 #include "rbgs3d.h"
 #include "stencil.h"
@@ -1201,6 +1202,44 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
       if (bad) ck(hipMemsetAsync(p + (size_t)q * L0.cells, 0, sizeof(double) * L0.cells, s));
       if (fell_back) fell_back[q] = bad ? 1 : 0;
     }
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------
+// the projection around the solve
+// ------------------------------------------------------------------------------
+extern "C" {
+
+int mpp_divergence(mpp_op op, const double* ux, const double* uy, const double* uz, double dt,
+                   double* f, void* stream) {
+  if (!op || !ux || !uy || !uz || !f || !(dt > 0.0) || !std::isfinite(dt)) return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Level& L0 = op->lev[0];
+  try {
+    hipLaunchKernelGGL(k_divergence, grid_of(L0, op->batch), dim3(kBlock), 0, s, ux, uy, uz, op->n,
+                       (int)L0.cells, dt, f);
+    ck_launch();
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
+int mpp_project(mpp_op op, const double* phi, const double* p, double dt, double* ux, double* uy,
+                double* uz, void* stream) {
+  if (!op || !phi || !p || !ux || !uy || !uz || !(dt > 0.0) || !std::isfinite(dt))
+    return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Level& L0 = op->lev[0];
+  try {
+    hipLaunchKernelGGL(k_project, grid_of(L0, op->batch), dim3(kBlock), 0, s, phi, op->kappa, p,
+                       op->rho, op->n, (int)L0.cells, dt, ux, uy, uz);
+    ck_launch();
   } catch (HipError& e) {
     return status_of(e.e);
   }

@@ -1,0 +1,110 @@
+"""The projection around the solve on the GPU (through the C ABI) against the oracle,
+and the discrete divergence-free property of the corrected velocity."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2312_11740_amd import problems as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2312_11740_amd as M  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def faces(shape, seed):
+    rng = np.random.default_rng(seed)
+    u = [rng.standard_normal(shape) for _ in range(3)]
+    u[0][..., :, :, 0] = 0.0
+    u[1][..., :, 0, :] = 0.0
+    u[2][..., 0, :, :] = 0.0
+    return u
+
+
+def case(n, seed):
+    pr = G.random_bubbles_problem(seed, n=n)
+    return pr.phi, pr.rho_neg, pr.rho_pos, pr.sigma
+
+
+@pytest.mark.parametrize("n", [24, 40])
+def test_divergence_matches_oracle(n):
+    phi, rn, rp, sg = case(n, 1)
+    op = M.Operator(to_dev(phi), rn, rp, sg)
+    u = faces((n, n, n), 2)
+    f = to_host(op.divergence([to_dev(a) for a in u], dt=0.05))
+    fo = O.divergence(u, 0.05)
+    assert np.array_equal(f, fo)
+
+
+@pytest.mark.parametrize("n", [24, 40])
+def test_project_matches_oracle(n):
+    phi, rn, rp, sg = case(n, 3)
+    d = O.pipeline(phi, np.zeros((n, n, n)), rn, rp, sg)
+    op = M.Operator(to_dev(phi), rn, rp, sg)
+    p = np.random.default_rng(4).standard_normal((n, n, n))
+    u = faces((n, n, n), 5)
+    ud = [to_dev(a) for a in u]
+    op.project(to_dev(phi), to_dev(p), 0.05, ud)
+    uo = O.project(phi, d["kappa"], p, rn, rp, sg, 0.05, u)
+    for a, b in zip(ud, uo):
+        a = to_host(a)
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_projection_batched_equals_single():
+    n = 24
+    cases = [case(n, s) for s in (7, 8)]
+    phi = np.stack([c[0] for c in cases])
+    op = M.Operator(to_dev(phi), [c[1] for c in cases], [c[2] for c in cases],
+                    [c[3] for c in cases])
+    u = faces((2, n, n, n), 9)
+    p = np.random.default_rng(10).standard_normal((2, n, n, n))
+    ud = [to_dev(a) for a in u]
+    f = to_host(op.divergence(ud, 0.1))
+    op.project(to_dev(phi), to_dev(p), 0.1, ud)
+    for b in range(2):
+        opb = M.Operator(to_dev(phi[b]), cases[b][1], cases[b][2], cases[b][3])
+        ub = [to_dev(a[b]) for a in u]
+        assert np.array_equal(to_host(opb.divergence(ub, 0.1)), f[b])
+        opb.project(to_dev(phi[b]), to_dev(p[b]), 0.1, ub)
+        for a, c in zip(ub, ud):
+            assert np.array_equal(to_host(a), to_host(c)[b])
+
+
+@pytest.mark.parametrize("n,mode", [(64, "fp64"), (64, "mixed"), (256, "mixed")])
+def test_projection_step_is_divergence_free(n, mode):
+    """f = div(u*)/dt, solve, correct: the corrected velocity's divergence is at the
+    solve's relative residual (the rising-bubble geometry at 256^3, the bench's)."""
+    if n == 256:
+        pr = G.rising_bubble_problem(0, n=256)
+        phi, rn, rp, sg = pr.phi, pr.rho_neg, pr.rho_pos, pr.sigma
+    else:
+        phi, rn, rp, sg = case(n, 11)
+    dt = 1e-3
+    phid = to_dev(phi)
+    op = M.Operator(phid, rn, rp, sg)
+    ud = [to_dev(a) for a in faces((n, n, n), 12)]
+    f = op.divergence(ud, dt)
+    p, info = op.solve(f, rtol=1e-10, mode=mode)
+    assert info[0].status == M.OK
+    op.project(phid, p, dt, ud)
+    div = op.divergence(ud, dt)
+    ratio = float(torch.linalg.vector_norm(div) / torch.linalg.vector_norm(f))
+    # div(u) = -(A p - b) (b = f + jterm, mean-free): bounded by the residual target
+    # measured against ||b||, which the jump term makes larger than ||f||
+    b, _ = op.rhs(f)
+    bound = 1.5e-10 * float(torch.linalg.vector_norm(b) / torch.linalg.vector_norm(f))
+    print("n=%d %s: ||div u|| / ||div u*|| = %.3e (bound %.3e)" % (n, mode, ratio, bound),
+          flush=True)
+    assert ratio <= max(bound, 1e-12)
