@@ -71,7 +71,7 @@ def measured_traffic(kernel):
 
 
 def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None, zero=False,
-                 guess_sweeps=2):
+                 guess_sweeps=2, check_every=2):
     """warmup + steps projection solves, each warm-started from the previous step (or,
     with a network, from the learned guess; with zero, from zero); returns (mean ms per
     timed step, infos of the timed steps, learned-guess fallbacks)."""
@@ -89,7 +89,8 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
             p, fell = op.learned_guess(net, fs[t], sweeps=guess_sweeps, out=p)
             if t >= warmup:
                 fallbacks += sum(fell)
-        p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu)
+        p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu,
+                           check_every=check_every)
         if t >= warmup:
             infos.append(info[0])
     torch.cuda.synchronize()
@@ -331,6 +332,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--guess-sweeps", type=int, default=2,
                     help="red-black sweeps applied to the learned guess")
+    ap.add_argument("--check-every", type=int, default=2,
+                    help="CG iterations between host polls of convergence")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", default="rising256",
                     choices=["rising256", "batched64", "single32", "bubbles128",
@@ -384,7 +387,8 @@ def main():
         mode = MODES[meth]
         ms, infos, fb = run_sequence(M, torch, ws, phis, fs, prm, mode, args.nu, K, W,
                                      net if meth == "learned" else None, zero=meth == "plain0",
-                                     guess_sweeps=args.guess_sweeps)
+                                     guess_sweeps=args.guess_sweeps,
+                                     check_every=args.check_every)
         worst = max(i.rel_resid for i in infos)
         ok = all(i.status == M.OK for i in infos) and worst <= prm["rtol"]
         results[meth] = dict(ms=ms, iters=[i.iters for i in infos],

@@ -87,7 +87,8 @@ size_t net_layout(mpp_net_s* net, int n, int bmax, char* base) {
   net->gp2 = cv.take<uint16_t>(c2 * 32);
   size_t most = 0;
   for (int l = 0; l < kLayers; ++l) most = std::max(most, (size_t)kSpec[l].co * kpad(kSpec[l].cip));
-  net->part_floats = most * kMaxParts;
+  // a layer's partials: batch x chunks <= max(kMaxParts, batch) (conv_wgrad)
+  net->part_floats = most * (size_t)std::max(kMaxParts, bmax);
   net->part = cv.take<float>(net->part_floats);
   net->cpart_floats = (size_t)kMaxChanParts * 64;
   net->cpart = cv.take<float>(net->cpart_floats);
@@ -191,6 +192,7 @@ void conv_wgrad(mpp_net_s* net, int l, const uint16_t* gz, int batch, hipStream_
   const int kp = kpad(L.cip);
   const int cols_per_block = 16 * kWgNT * (kNetThreads / 64);
   const int yblocks = (kp + cols_per_block - 1) / cols_per_block;
+  // batch * chunks partials, at most max(kMaxParts, batch) (the buffer's size)
   int chunks = std::max(1, std::min(kMaxParts / batch, (2048 + batch * yblocks - 1) / (batch * yblocks)));
   int chunk_len = ((cells + chunks - 1) / chunks + 31) / 32 * 32;
   chunks = (cells + chunk_len - 1) / chunk_len;
