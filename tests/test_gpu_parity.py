@@ -379,3 +379,43 @@ def test_sweep_kernels_agree(mode, monkeypatch):
     assert np.array_equal(out["march"][0], out["tile"][0])
     assert rel2(out["tile"][1], out["march"][1]) <= 1e-12
     assert abs(out["march"][2] - out["tile"][2]) <= 1
+
+
+@pytest.mark.parametrize("sign", [-1.0, 1.0])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_without_interface(sign, mode):
+    """One phase everywhere (phi of one sign, sigma > 0 has no interface to act on): the
+    constant-coefficient problem, on either side of the tie-break."""
+    n = 24
+    phi = sign * (1.0 + np.random.default_rng(30).random((n, n, n)))
+    f = np.random.default_rng(31).uniform(-1, 1, (n, n, n))
+    op = M.Operator(to_dev(phi), 1e-3, 1.0, 0.01)
+    p, infos = op.solve(to_dev(f), rtol=1e-10, mode=mode)
+    check_solution(phi, f, 1e-3, 1.0, 0.01, to_host(p), infos[0])
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_solve_bubbles_cut_by_the_walls(mode):
+    """Interfaces that meet the walls: curvature there reads phi extrapolated past the wall."""
+    n = 32
+    phi = G.bubble_phi(n, [(0.0, 0.5, 0.5), (0.7, 1.0, 0.3), (0.5, 0.5, 1.0)], [0.3, 0.25, 0.2])
+    f = np.random.default_rng(32).uniform(-1, 1, (n, n, n))
+    op = M.Operator(to_dev(phi), 1e-3, 1.0, 0.01)
+    p, infos = op.solve(to_dev(f), rtol=1e-11, mode=mode)
+    check_solution(phi, f, 1e-3, 1.0, 0.01, to_host(p), infos[0], rtol=1e-11)
+
+
+def test_solve_wide_batch_small_problems():
+    """128 problems of 32^3 in one operator (grid.y = 128), sampled ones against the oracle."""
+    n, B = 32, 128
+    probs = [G.random_bubbles_problem(500 + s, n=n) for s in range(B)]
+    phi = np.stack([q.phi for q in probs])
+    f = np.stack([q.f for q in probs])
+    op = M.Operator(to_dev(phi), [q.rho_neg for q in probs], [q.rho_pos for q in probs],
+                    [q.sigma for q in probs])
+    p, infos = op.solve(to_dev(f), rtol=1e-10, mode="mixed")
+    ph = to_host(p)
+    assert all(i.status == M.OK and i.rel_resid <= 1e-10 for i in infos)
+    for b in (0, 37, 127):
+        q = probs[b]
+        check_solution(q.phi, q.f, q.rho_neg, q.rho_pos, q.sigma, ph[b], infos[b])
