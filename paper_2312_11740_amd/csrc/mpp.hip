@@ -24,6 +24,7 @@
 #include "project.h"
 #include "rbgs.h"
 #include "rbgs3d.h"
+#include "rbpair.h"
 #include "stencil.h"
 
 using namespace mpp;
@@ -136,6 +137,8 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2)
       op->pstride = std::max(op->pstride, rb_grid(rb_tiles(sizes[l], B, kz)));
     op->pstride = std::max(op->pstride, grid3(tiles3(sizes[l])));
+    for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2)
+      op->pstride = std::max(op->pstride, rb_grid(pr_tiles<64>(sizes[l], kz)));
   }
   op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
   op->partials = cv.take<double>((size_t)B * op->pstride);
@@ -316,13 +319,26 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
             const Ctl* dctl = nullptr, int* dot_parts = nullptr);
 
 // One fused sweep on level l with the kernel the tuner picked for it: kz > 0 the
-// z-marching kernel with chunks of kz planes (0: its default), kz < 0 the 3D-tile
-// kernel.  Returns the grid size (the number of dot partials).
+// z-marching kernel with chunks of kz planes (0: its default), kz = -1 the 3D-tile
+// kernel, kz <= -2 the pair-per-thread kernel with chunks of -kz planes (finest level,
+// even n).  Returns the grid size (the number of dot partials).
 template <typename T, int MODE, bool FINE>
 int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs, const T* in,
               const T* ec, T* out, int c1, const Ctl& ctl, int dot, const int* active,
               hipStream_t s) {
   const int n = op->lev[l].n, B = op->batch;
+  if (kz <= -2) {
+    if constexpr (FINE) {
+      if (n % 2 == 0) {
+        const RbTiles tl = pr_tiles<64>(n, -kz);
+        const dim3 grid(rb_grid(tl), B);
+        hipLaunchKernelGGL((k_rb_pair<T, MODE, 64>), grid, dim3(kPrThreads), 0, s, F, n, tl, rhs,
+                           in, ec, out, c1, ctl, dot, active);
+        return (int)grid.x;
+      }
+    }
+    throw HipError{hipErrorInvalidValue};   // the pair kernel only runs on an even finest level
+  }
   if (kz < 0) {
     const Tiles3 t3 = tiles3(n);
     const dim3 grid(grid3(t3), B);
@@ -442,10 +458,13 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
   op->tuned[w] = true;
   const char* env = std::getenv("MPP_AUTOTUNE");
   if (env && env[0] == '0') return;
-  // MPP_SWEEP=march or =tile fixes the sweep kernel of every level (no timing)
+  // MPP_SWEEP=march, =tile or =pair fixes the sweep kernel of every level (no timing;
+  // pair: the pair kernel with 16-plane chunks on an even finest level, z-marching below)
   const char* force = std::getenv("MPP_SWEEP");
-  if (force && (std::strcmp(force, "march") == 0 || std::strcmp(force, "tile") == 0)) {
+  if (force && (std::strcmp(force, "march") == 0 || std::strcmp(force, "tile") == 0 ||
+                std::strcmp(force, "pair") == 0)) {
     for (int l = 0; l < op->nlev; ++l) op->kz[w][l] = force[0] == 't' ? -1 : 0;
+    if (force[0] == 'p' && op->lev[0].n % 2 == 0) op->kz[w][0] = -16;
     return;
   }
   const int B = op->batch;
@@ -475,10 +494,13 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     const Faces<T> F = faces_of<T>(op, l);
     float best = 1e30f;
     int best_kz = 0;
-    // candidates: the z-marching kernel with chunks of 2 .. 32 planes, the 3D-tile kernel
+    // candidates: the z-marching kernel with chunks of 2 .. 32 planes, the 3D-tile kernel,
+    // on an even finest level the pair kernel with chunks of 4 .. 32 planes
     std::vector<int> cands;
     for (int kz = 2; kz <= 2 * kRbKZ && kz <= L.n; kz *= 2) cands.push_back(kz);
     cands.push_back(-1);
+    if (l == 0 && L.n % 2 == 0)
+      for (int kz = 4; kz <= 2 * kRbKZ && kz <= L.n; kz *= 2) cands.push_back(-kz);
     for (int kz : cands) {
       auto launch = [&] {
         if (l == 0)
