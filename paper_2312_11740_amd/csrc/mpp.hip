@@ -138,7 +138,7 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
       op->pstride = std::max(op->pstride, rb_grid(rb_tiles(sizes[l], B, kz)));
     op->pstride = std::max(op->pstride, grid3(tiles3(sizes[l])));
     for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2)
-      op->pstride = std::max(op->pstride, rb_grid(pr_tiles<64>(sizes[l], kz)));
+      op->pstride = std::max(op->pstride, rb_grid(pr_tiles(sizes[l], kz)));
   }
   op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
   op->partials = cv.take<double>((size_t)B * op->pstride);
@@ -330,9 +330,9 @@ int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs
   if (kz <= -2) {
     if constexpr (FINE) {
       if (n % 2 == 0) {
-        const RbTiles tl = pr_tiles<64>(n, -kz);
+        const RbTiles tl = pr_tiles(n, -kz);
         const dim3 grid(rb_grid(tl), B);
-        hipLaunchKernelGGL((k_rb_pair<T, MODE, 64>), grid, dim3(kPrThreads), 0, s, F, n, tl, rhs,
+        hipLaunchKernelGGL((k_rb_pair<T, MODE>), grid, dim3(kPrThreads), 0, s, F, n, tl, rhs,
                            in, ec, out, c1, ctl, dot, active);
         return (int)grid.x;
       }
@@ -458,13 +458,17 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
   op->tuned[w] = true;
   const char* env = std::getenv("MPP_AUTOTUNE");
   if (env && env[0] == '0') return;
-  // MPP_SWEEP=march, =tile or =pair fixes the sweep kernel of every level (no timing;
-  // pair: the pair kernel with 16-plane chunks on an even finest level, z-marching below)
+  // MPP_SWEEP=march, =tile or =pair[K] fixes the sweep kernel of every level (no timing;
+  // pair: the pair kernel with K-plane chunks (default 16) on an even finest level,
+  // z-marching below)
   const char* force = std::getenv("MPP_SWEEP");
   if (force && (std::strcmp(force, "march") == 0 || std::strcmp(force, "tile") == 0 ||
-                std::strcmp(force, "pair") == 0)) {
+                std::strncmp(force, "pair", 4) == 0)) {
     for (int l = 0; l < op->nlev; ++l) op->kz[w][l] = force[0] == 't' ? -1 : 0;
-    if (force[0] == 'p' && op->lev[0].n % 2 == 0) op->kz[w][0] = -16;
+    if (force[0] == 'p' && op->lev[0].n % 2 == 0) {
+      const int kz = std::atoi(force + 4);
+      op->kz[w][0] = -(kz >= 2 && kz <= 2 * kRbKZ ? kz : 16);
+    }
     return;
   }
   const int B = op->batch;

@@ -3,16 +3,20 @@
 // Same semantics as the other fused sweeps (two one-colour half sweeps, out of place):
 //   x1  = x_in with every c1 cell set to (sum_f w_f x_in[nb] - h^2 b) / sum_f w_f,
 //   out = x1  with every c2 cell set to (sum_f w_f x1[nb]  - h^2 b) / sum_f w_f.
-// A block owns a column of TX x TY cells (TX = 2 PW) and marches up a chunk of planes
-// like the z-marching kernel, but a thread owns two cells along x, one of each colour:
-// with one wave per row (PW = 64) the colour of the first cell of every pair in a wave
-// is the same, so neither colour phase diverges and every lane does useful work in
-// both.  Each thread keeps b, the interface code and its own c1 value in registers
-// between the phases; only x_in (tile + 2-cell ring) and the c1 values (tile + 1-cell
-// ring) go through LDS.  Cells outside the domain hold zero in both LDS tiles, so the
-// constant-coefficient update needs no wall masks: the neighbour sum is taken as is
-// and divided by the number of interior faces.  Pairs are loaded and stored as one
-// 8- or 16-byte access; the grid size must be even.
+// A block owns a column of 128 x 8 cells and marches up a chunk of planes like the
+// z-marching kernel, but each wave owns one row and each lane two cells of it along x,
+// one of each colour.  The colour of a lane's first cell is then the same across the
+// wave, so neither colour phase diverges, every lane works in both, and the choice of
+// cell, neighbour array and LDS row is wave-uniform (scalar registers and branches).
+// Each thread keeps b, the interface codes and its own c1 value in registers between
+// the phases; x_in (tile + 2-cell ring) and the c1 values (tile + 1-cell ring) go
+// through LDS, split by the parity of the column so that a wave reads consecutive
+// words.  Cells outside the domain hold zero in both tiles, so the constant-
+// coefficient update needs no wall masks: the six neighbour values are summed as they
+// are and divided by the number of interior faces.  Loads and stores are raw buffer
+// accesses: an offset past the end of the plane reads zero and drops the store, which
+// covers cells and planes outside the domain without branches.  The grid size must be
+// even (a pair never straddles the domain's edge).
 #pragma once
 
 #include "rbgs.h"
@@ -31,37 +35,19 @@ struct PairOf<double> {
 };
 
 constexpr int kPrThreads = 512;
-constexpr int kPrWaves = kPrThreads / 64;
-constexpr int kPrRing0 = 320;   // first thread of the c1-ring items (waves 5..7)
+constexpr int kPrTX = 128, kPrTY = 8;   // cells of a tile along x and y
 
-template <int PW>
-struct PrShape {
-  static constexpr int TX = 2 * PW;               // cells along x
-  static constexpr int TY = kPrWaves * (64 / PW); // rows
-  static constexpr int XW = TX + 4, XH = TY + 4;  // x_in tile with a 2-cell ring
-  static constexpr int CW = TX + 2, CH = TY + 2;  // c1 tile with a 1-cell ring
-  static constexpr int NX = XW * XH, NC = CW * CH;
-  static constexpr int XE = 4 * PW + 2 * XH;      // pairs of the x_in ring
-  static constexpr int RE = 2 * PW + TY;          // c1 cells of the ring
-  static_assert(XE <= kPrThreads && RE <= kPrThreads - kPrRing0, "ring items per thread");
-};
-
-template <int PW>
 inline RbTiles pr_tiles(int n, int kz) {
   RbTiles t;
-  t.ntx = (n + PrShape<PW>::TX - 1) / PrShape<PW>::TX;
-  t.nty = (n + PrShape<PW>::TY - 1) / PrShape<PW>::TY;
+  t.ntx = (n + kPrTX - 1) / kPrTX;
+  t.nty = (n + kPrTY - 1) / kPrTY;
   t.kz = kz;
   t.nkz = (n + kz - 1) / kz;
   t.ntiles = t.ntx * t.nty * t.nkz;
   return t;
 }
 
-// Buffer resource of one plane of an array (stride 0, num_records bytes): raw buffer
-// accesses at offsets >= num_records read zero and drop stores, which handles cells
-// outside the domain (offset kOob) and planes outside the domain (num_records = 0)
-// without branches.
-constexpr unsigned kOob = 0x80000000u;
+constexpr unsigned kOob = 0x80000000u;   // a buffer offset past the end of any plane
 
 __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
@@ -87,34 +73,33 @@ template <>
 __device__ inline double2 buf_ld_pair<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
-template <typename T>
-__device__ inline void buf_st_pair(typename PairOf<T>::V v, __amdgpu_buffer_rsrc_t r, unsigned off);
-template <>
-__device__ inline void buf_st_pair<float>(float2 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
-                                        off, 0, 0);
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ inline void buf_st_pair(float2 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
-template <>
-__device__ inline void buf_st_pair<double>(double2 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b128(
-      __builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, off, 0, 0);
+__device__ inline void buf_st_pair(double2 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
 }
 
-// FP32: 64 VGPRs so that four blocks (32 waves) share a compute unit; FP64 is held to
-// two blocks by its LDS tiles anyway
+// FP32: at most 80 VGPRs, three blocks per compute unit; FP64: two (its LDS tiles)
 template <typename T>
 struct PrWaves {
   static constexpr int value = sizeof(T) == 4 ? 6 : 4;
 };
 
-template <typename T, int MODE, int PW>
+
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     k_rb_pair(Faces<T> F, int n, RbTiles tl, const T* __restrict__ rhs, const T* __restrict__ xin,
               const T* __restrict__ ec, T* __restrict__ xout, int c1, Ctl ctl, int dot,
               const int* __restrict__ active) {
-  using Sh = PrShape<PW>;
   using V = typename PairOf<T>::V;
-  constexpr int TX = Sh::TX, TY = Sh::TY, XW = Sh::XW, CW = Sh::CW;
+  constexpr int TX = kPrTX, TY = kPrTY;
+  constexpr int XH = TY + 4, CH = TY + 2;   // rows of the x_in and c1 tiles
+  constexpr int XP = TX / 2 + 2;            // pairs per tile row (columns i0 - 2 .. i0 + TX + 1)
+  constexpr int XPL = XH * XP, CPL = CH * XP;   // one parity of one plane
+  constexpr int XSL = 2 * XPL, CSL = 2 * CPL;   // one plane (slot)
   constexpr unsigned TS = sizeof(T);
   const int b = blockIdx.y;
   if (active && !active[b]) return;
@@ -123,11 +108,11 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     if (dot && threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = 0.0;
     return;
   }
-  __shared__ __align__(16) T sx[3][Sh::NX];
-  __shared__ __align__(16) T sc[3][Sh::NC];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // x_in and c1 tiles, three planes each: [slot][parity][row][pair]
+  __shared__ __align__(16) T sx[3 * XSL];
+  __shared__ __align__(16) T sc[3 * CSL];
+  const int p = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int i0 = (tile % tl.ntx) * TX;
   const int j0 = ((tile / tl.ntx) % tl.nty) * TY;
   const int k0 = (tile / (tl.ntx * tl.nty)) * tl.kz;
@@ -142,111 +127,93 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   const T ir0 = F.inv_rho[2 * b], ir1 = F.inv_rho[2 * b + 1];
   const T hr0 = h2 / ir0, hr1 = h2 / ir1;
   const T inv6 = T(1) / T(6), inv5 = T(1) / T(5), inv4 = T(1) / T(4), inv3 = T(1) / T(3);
+  auto inv_of = [&](int walls) {
+    return walls <= 0 ? inv6 : (walls == 1 ? inv5 : (walls == 2 ? inv4 : inv3));
+  };
   const V vzero = {T(0), T(0)};
 
-  // ---- the thread's own pair: cells (i, j) and (i + 1, j) ----
-  const int pp = lane % PW;
-  const int jj = wave * (64 / PW) + lane / PW;
-  const int i = i0 + 2 * pp, j = j0 + jj;
-  const bool own_ok = i < n && j < n;
-  const unsigned own_b = own_ok ? (unsigned)(i + n * j) * TS : kOob;   // byte offset in a plane
-  const unsigned own_eb = own_ok ? (unsigned)((i >> 1) + nc * (j >> 1)) * TS : kOob;
-  const int own_x = (jj + 2) * XW + 2 * pp + 2;   // first cell in the x_in tile
-  const int own_c = (jj + 1) * CW + 2 * pp + 1;   // first cell in the c1 tile
-  const int wj = (j == 0) + (j == n - 1);
-  const int wx0 = (i == 0) + wj, wx1 = (i + 1 == n - 1) + wj;   // walls in x and y
+  // ---- the lane's pair of columns (i, i + 1) and its wave's row j ----
+  const int i = i0 + 2 * p;
+  const int j = j0 + w;
+  const bool col_ok = i < n;
+  const bool wx0 = i == 0, wx1 = i + 1 == n - 1;   // x walls of the two cells
+  const unsigned own_b = col_ok && j < n ? (unsigned)(i + n * j) * TS : kOob;
+  const unsigned own_eb = col_ok && j < n ? (unsigned)((i >> 1) + nc * (j >> 1)) * TS : kOob;
 
-  // ---- one pair of the x_in ring (threads below XE; the others read nothing) ----
+  // ---- a second x_in pair: ring rows j0 - 2, j0 - 1, j0 + TY, j0 + TY + 1 (waves 0..3)
+  //      or the ring columns i0 - 2 / i0 + TX of the 12 tile rows (wave 4, lanes 0..23)
+  int xr_row = 0, xr_pair = 0;
   unsigned xr_b = kOob, xr_eb = kOob;
-  int xr_l = 0;
-  const bool xr_item = tid < Sh::XE;
-  if (xr_item) {
-    int xrow, xcol;
-    if (tid < 4 * PW) {
-      const int r = tid / PW;
-      xrow = r < 2 ? r : TY + r;
-      xcol = 2 * (tid % PW) + 2;
+  if (w < 5) {
+    int gi;
+    bool item = true;
+    if (w < 4) {
+      xr_row = w < 2 ? w : TY + w;
+      xr_pair = p + 1;
+      gi = i;
     } else {
-      const int q = tid - 4 * PW;
-      xrow = q >> 1;
-      xcol = (q & 1) ? TX + 2 : 0;
+      item = p < 2 * XH;
+      xr_row = item ? p >> 1 : 0;
+      xr_pair = (p & 1) ? XP - 1 : 0;
+      gi = (p & 1) ? i0 + TX : i0 - 2;
     }
-    const int gi = i0 - 2 + xcol, gj = j0 - 2 + xrow;
-    if (gi >= 0 && gi < n && gj >= 0 && gj < n) {
+    const int gj = j0 - 2 + xr_row;
+    if (item && gi >= 0 && gi < n && gj >= 0 && gj < n) {
       xr_b = (unsigned)(gi + n * gj) * TS;
       xr_eb = (unsigned)((gi >> 1) + nc * (gj >> 1)) * TS;
     }
-    xr_l = xrow * XW + xcol;
+  }
+  // ---- c1 ring: rows j0 - 1 (wave 5) and j0 + TY (wave 6) over the tile's pairs; the
+  //      column cells i0 - 1 / i0 + TX of the tile rows (wave 7, lanes 0..TY-1; of the
+  //      two, the one of colour c1 on the plane)
+  const int rrow = w == 5 ? -1 : TY;    // waves 5 and 6: offset of the ring row from j0
+  const int rj = j0 + rrow;
+  unsigned rb0 = kOob, rb1 = kOob;      // waves 5, 6: the pair; wave 7: the two cells
+  bool rok0 = false, rok1 = false;
+  const int cj = j0 + p;                // wave 7: the row of the lane's column cells
+  if (w == 5 || w == 6) {
+    rok0 = rok1 = col_ok && rj >= 0 && rj < n;
+    if (rok0) rb0 = (unsigned)(i + n * rj) * TS;
+  } else if (w == 7 && p < TY) {
+    rok0 = i0 >= 1 && cj < n;
+    rok1 = i0 + TX < n && cj < n;
+    if (rok0) rb0 = (unsigned)(i0 - 1 + n * cj) * TS;
+    if (rok1) rb1 = (unsigned)(i0 + TX + n * cj) * TS;
   }
 
-  // ---- one c1 cell of the ring (threads kPrRing0 .. kPrRing0 + RE - 1): rows j0 - 1
-  //      and j0 + TY over the tile's pairs (one pair loaded, o picks the cell), or the
-  //      cells i0 - 1 and i0 + TX of a tile row (both loaded, o picks the one of colour
-  //      c1 on the plane); o = (r_oadd + L) & 1
-  const int rq = tid - kPrRing0;
-  const bool r_item = rq >= 0 && rq < Sh::RE;
-  int r_oadd = 0, r_step = 1, r_i = 0, r_j = 0, r_c = 0, r_x = 0;
-  bool r_ok0 = false, r_ok1 = false;
-  unsigned r_b0 = kOob, r_b1 = kOob;   // byte offsets of the first and second value
-  if (r_item) {
-    if (rq < 2 * PW) {
-      const int row = rq < PW ? -1 : TY;
-      const int q2 = 2 * (rq % PW);
-      r_j = j0 + row;
-      r_i = i0 + q2;
-      r_ok0 = r_ok1 = r_j >= 0 && r_j < n && r_i < n;
-      r_oadd = c1 + r_j;
-      r_step = 1;
-      r_c = (row + 1) * CW + q2 + 1;
-      r_x = (row + 2) * XW + q2 + 2;
-      if (r_ok0) {
-        r_b0 = (unsigned)(r_i + n * r_j) * TS;
-        r_b1 = r_b0 + TS;
-      }
-    } else {
-      const int row = rq - 2 * PW;
-      r_j = j0 + row;
-      r_i = i0 - 1;
-      r_ok0 = i0 >= 1 && r_j < n;
-      r_ok1 = i0 + TX < n && r_j < n;
-      r_oadd = c1 + 1 + r_j;
-      r_step = TX + 1;
-      r_c = (row + 1) * CW;
-      r_x = (row + 2) * XW + 1;
-      if (r_ok0) r_b0 = (unsigned)(i0 - 1 + n * r_j) * TS;
-      if (r_ok1) r_b1 = (unsigned)(i0 + TX + n * r_j) * TS;
-    }
-  }
-  const int rwj = (r_j == 0) + (r_j == n - 1);
-
-  // ---- loads: every thread issues the same instructions in every step (absent values
-  //      read zero), results are consumed a step later, nothing is combined on arrival
   struct XLoad {
-    V a, r;     // own pair, ring pair
-    T ea, er;   // coarse corrections of the two (MODE 2)
+    V a, r;     // own pair, second pair
+    T ea, er;   // their coarse corrections (MODE 2)
   };
   struct BLoad {
-    V bo;              // b of the own pair
-    unsigned co;       // its two code bytes
-    T rb0, rb1;        // b of the ring cell(s)
-    unsigned rc0, rc1; // their code bytes
+    V bo, br;                // b of the own pair, of the ring pair or the two column cells
+    unsigned co, cr0, cr1;   // code bytes: own pair (16 bits), ring pair / column cells
   };
-  auto issue_x = [&](int Lx, bool live, XLoad& d) {
+  // every wave issues the same loads in every step (a plane outside the domain or past
+  // the chunk has a zero-size resource); results are consumed a step later.  Plane
+  // addresses advance by one plane per step (no multiplies in the loop).
+  const unsigned code_bytes = (unsigned)nn;
+  const char* xq = reinterpret_cast<const char*>(xin + base) + (ptrdiff_t)(k0 - 2) * plane_bytes;
+  const char* bq = reinterpret_cast<const char*>(rhs + base) + (ptrdiff_t)(k0 - 1) * plane_bytes;
+  const char* cq = reinterpret_cast<const char*>(F.code + base) + (ptrdiff_t)(k0 - 1) * code_bytes;
+  char* oq = reinterpret_cast<char*>(xout + base) + (ptrdiff_t)(k0 - 2) * plane_bytes;
+  const char* eb = reinterpret_cast<const char*>(ec + basec);
+  auto issue_x = [&](int Lx, bool live, XLoad& d) {   // x_in of plane Lx at xq
     if (MODE == 1) return;
     const bool pl = live && Lx >= 0 && Lx < n;
-    const int Lc = pl ? Lx : 0;
-    const auto rx = plane_rsrc(xin + base + (size_t)Lc * nn, pl ? plane_bytes : 0u);
+    const auto rx = plane_rsrc(xq, pl ? plane_bytes : 0u);
     d.a = buf_ld_pair<T>(rx, own_b);
-    d.r = buf_ld_pair<T>(rx, xr_b);
+    if (w < 5) d.r = buf_ld_pair<T>(rx, xr_b);
     if (MODE == 2) {
-      const auto re = plane_rsrc(ec + basec + (size_t)(Lc >> 1) * ncc, pl ? cplane_bytes : 0u);
+      const auto re = plane_rsrc(eb + (ptrdiff_t)(pl ? Lx >> 1 : 0) * cplane_bytes,
+                                 pl ? cplane_bytes : 0u);
       d.ea = buf_ld<T>(re, own_eb);
-      d.er = buf_ld<T>(re, xr_eb);
+      if (w < 5) d.er = buf_ld<T>(re, xr_eb);
     }
   };
-  auto commit_x = [&](int Lx, const XLoad& d) {
+  auto commit_x = [&](int xs, const XLoad& d) {   // into the x_in slot at element xs
     if (MODE == 1) return;
-    T* dst = sx[(Lx + 3) % 3];
+    T* dst = sx + xs;
     V a = d.a, r = d.r;
     if (MODE == 2) {
       a.x += d.ea;
@@ -254,108 +221,175 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
       r.x += d.er;
       r.y += d.er;
     }
-    *reinterpret_cast<V*>(dst + own_x) = a;
-    if (xr_item) *reinterpret_cast<V*>(dst + xr_l) = r;
+    dst[(w + 2) * XP + p + 1] = a.x;
+    dst[XPL + (w + 2) * XP + p + 1] = a.y;
+    if (w < 4 || (w == 4 && p < 2 * XH)) {
+      dst[xr_row * XP + xr_pair] = r.x;
+      dst[XPL + xr_row * XP + xr_pair] = r.y;
+    }
   };
-  auto issue_b = [&](int Lb, bool live, BLoad& d) {
+  auto issue_b = [&](int Lb, bool live, BLoad& d) {   // b and codes of plane Lb at bq, cq
     const bool pl = live && Lb >= 0 && Lb < n;
-    const int Lc = pl ? Lb : 0;
-    const auto rbr = plane_rsrc(rhs + base + (size_t)Lc * nn, pl ? plane_bytes : 0u);
-    const auto rcr = plane_rsrc(F.code + base + (size_t)Lc * nn, pl ? (unsigned)nn : 0u);
+    const auto rbr = plane_rsrc(bq, pl ? plane_bytes : 0u);
+    const auto rcr = plane_rsrc(cq, pl ? code_bytes : 0u);
     d.bo = buf_ld_pair<T>(rbr, own_b);
     d.co = __builtin_amdgcn_raw_buffer_load_b16(rcr, own_b / TS, 0, 0);
-    d.rb0 = buf_ld<T>(rbr, r_b0);
-    d.rb1 = buf_ld<T>(rbr, r_b1);
-    d.rc0 = __builtin_amdgcn_raw_buffer_load_b8(rcr, r_b0 / TS, 0, 0);
-    d.rc1 = __builtin_amdgcn_raw_buffer_load_b8(rcr, r_b1 / TS, 0, 0);
+    if (w == 5 || w == 6) {
+      d.br = buf_ld_pair<T>(rbr, rb0);
+      d.cr0 = __builtin_amdgcn_raw_buffer_load_b16(rcr, rb0 / TS, 0, 0);
+    } else if (w == 7) {
+      d.br.x = buf_ld<T>(rbr, rb0);
+      d.br.y = buf_ld<T>(rbr, rb1);
+      d.cr0 = __builtin_amdgcn_raw_buffer_load_b8(rcr, rb0 / TS, 0, 0);
+      d.cr1 = __builtin_amdgcn_raw_buffer_load_b8(rcr, rb1 / TS, 0, 0);
+    }
   };
 
-  // Gauss-Seidel value of cell (ic, jc, kc) from its six neighbour values (zero outside
-  // the domain); walls = number of its faces on the domain boundary
-  auto relax = [&](unsigned cd, int ic, int jc, int kc, int walls, T xw, T xe, T xs, T xn, T xd,
-                   T xu, T bb) -> T {
-    if ((cd & 63u) == 0u) {
-      const T sum = ((xw + xe) + (xs + xn)) + (xd + xu);
-      const T inv = walls == 0 ? inv6 : (walls == 1 ? inv5 : (walls == 2 ? inv4 : inv3));
-      const T hr = (cd & 64u) ? hr1 : hr0;
-      return (sum - hr * bb) * inv;
-    }
-    T w[6];
-    const size_t cell = base + (size_t)kc * nn + (size_t)jc * n + ic;
-    sweep_faces<T, true>(F, cell, cd, ic, jc, kc, n, nn, ir0, ir1, w);
+  // Gauss-Seidel value of a cell with a crossed face (coefficients from the arrays);
+  // pb = index of the cell's plane, off = its offset in the plane
+  auto relax_coded = [&](unsigned cd, size_t pb, unsigned off, int ic, int jc, int kc, T xw, T xe,
+                         T xs, T xn, T xd, T xu, T bb) -> T {
+    T wf[6];
+    sweep_faces<T, true>(F, pb + off, cd, ic, jc, kc, n, nn, ir0, ir1, wf);
     T num = T(0);
-    num += w[0] * xw;
-    num += w[1] * xe;
-    num += w[2] * xs;
-    num += w[3] * xn;
-    num += w[4] * xd;
-    num += w[5] * xu;
-    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
+    num += wf[0] * xw;
+    num += wf[1] * xe;
+    num += wf[2] * xs;
+    num += wf[3] * xn;
+    num += wf[4] * xd;
+    num += wf[5] * xu;
+    const T den = wf[0] + wf[1] + wf[2] + wf[3] + wf[4] + wf[5];
     return (num - h2 * bb) / den;
   };
-
-  // c1 value of one cell on plane L (LDS indices cx in the x_in tile, cc in the c1
-  // tile), zero when the cell is outside the domain
-  auto c1_cell = [&](bool ok, int L, int ic, int jc, int walls, int cx, int cc, T bb,
-                     unsigned cd) -> T {
-    T v = T(0);
-    if (ok) {
-      const T* xl = sx[(L + 3) % 3];
-      T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
-      if (MODE != 1) {
-        xw = xl[cx - 1];
-        xe = xl[cx + 1];
-        xs = xl[cx - XW];
-        xn = xl[cx + XW];
-        xd = sx[(L + 2) % 3][cx];
-        xu = sx[(L + 4) % 3][cx];
-      }
-      v = relax(cd, ic, jc, L, walls + (L == 0) + (L == n - 1), xw, xe, xs, xn, xd, xu, bb);
+  // Gauss-Seidel value from the six neighbour values (zero outside the domain); inv =
+  // 1 / (number of interior faces) for a cell without a crossed face
+  auto relax = [&](unsigned cd, size_t pb, unsigned off, int ic, int jc, int kc, T inv, T xw, T xe,
+                   T xs, T xn, T xd, T xu, T bb) -> T {
+    const T sum = ((xw + xe) + (xs + xn)) + (xd + xu);
+    const T hr = (cd & 64u) ? hr1 : hr0;
+    T v = (sum - hr * bb) * inv;
+    const bool crossed = (cd & 63u) != 0u;
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(crossed) != 0, 0)) {
+      if (crossed) v = relax_coded(cd, pb, off, ic, jc, kc, xw, xe, xs, xn, xd, xu, bb);
     }
-    sc[(L + 3) % 3][cc] = v;
     return v;
   };
 
+  // 1 / (interior faces) of the lane's two cells on its row, without and with a z wall
+  const int wy = (j == 0) + (j == n - 1);
+  const T in0 = inv_of(wy + wx0), in1 = inv_of(wy + wx1);
+  const T iz0 = inv_of(wy + wx0 + 1), iz1 = inv_of(wy + wx1 + 1);
+  const unsigned own_off = (unsigned)(i + n * j);   // cell offset in a plane (crossed path)
+
   XLoad xl = {vzero, vzero, T(0), T(0)};
-  BLoad bn = {vzero, 0u, T(0), T(0), 0u, 0u}, bc = bn, bp = bn;
+  BLoad bn = {vzero, vzero, 0u, 0u, 0u};
+  V bprev = vzero;       // b of the own pair on plane L - 1
+  unsigned cprev = 0u;   // its codes
   T c1own = T(0), c1prev = T(0);
   double acc = 0.0;
+  // LDS slots (element offsets) of planes L - 1, L, L + 1 for the first step L = k0 - 1
+  int xm = ((k0 + 1) % 3) * XSL, xl0 = ((k0 + 2) % 3) * XSL, xp = (k0 % 3) * XSL;
+  int cm = ((k0 + 1) % 3) * CSL, cl0 = ((k0 + 2) % 3) * CSL, cp = (k0 % 3) * CSL;
+  size_t pbL = base + (size_t)(k0 - 1) * nn;   // index of plane L's first cell
 
   // prologue: x_in of planes k0 - 2 and k0 - 1 into LDS, x_in of k0 and b of k0 - 1 in
   // flight
   if (MODE != 1) {
-    XLoad x0 = xl, x1 = xl;
-    issue_x(k0 - 2, true, x0);
-    issue_x(k0 - 1, true, x1);
-    commit_x(k0 - 2, x0);
-    commit_x(k0 - 1, x1);
+    XLoad xa = xl, xc = xl;
+    issue_x(k0 - 2, true, xa);
+    xq += plane_bytes;
+    issue_x(k0 - 1, true, xc);
+    xq += plane_bytes;
+    commit_x(xm, xa);
+    commit_x(xl0, xc);
   }
   issue_x(k0, true, xl);
+  xq += plane_bytes;
   issue_b(k0 - 1, true, bn);
+  bq += plane_bytes;
+  cq += code_bytes;
 
   for (int L = k0 - 1; L <= k1; ++L) {
-    commit_x(L + 1, xl);
-    bp = bc;
-    bc = bn;
-    // the last step loads nothing (zero-size resources) but issues the same instructions
+    commit_x(xp, xl);   // x_in of plane L + 1
+    const BLoad cur = bn;
     issue_x(L + 2, L < k1, xl);
     issue_b(L + 1, L < k1, bn);
+    xq += plane_bytes;
+    bq += plane_bytes;
+    cq += code_bytes;
     lds_barrier();
 
-    // ---- c1 values of plane L: the own pair's c1 cell, then one ring cell ----
+    // ---- c1 values of plane L: the wave's row, then the ring ----
     const bool pl = L >= 0 && L < n;
+    const bool zwL = L == 0 || L == n - 1;
     {
-      const int o = (c1 + j + L) & 1;
-      c1own = c1_cell(pl && own_ok, L, i + o, j, o ? wx1 : wx0, own_x + o, own_c + o,
-                      o ? bc.bo.y : bc.bo.x, (bc.co >> (8 * o)) & 255u);
+      const int o = (c1 + j + L) & 1;   // wave-uniform: which cell of the pair
+      T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
+      if (MODE != 1) {
+        const T* xo = sx + xl0 + (1 - o) * XPL + (w + 2) * XP + p + o;   // other parity, west
+        xw = xo[0];
+        xe = xo[1];
+        const T* xs0 = sx + xl0 + o * XPL + (w + 2) * XP + p + 1;
+        xs = xs0[-XP];
+        xn = xs0[XP];
+        xd = sx[xm + o * XPL + (w + 2) * XP + p + 1];
+        xu = sx[xp + o * XPL + (w + 2) * XP + p + 1];
+      }
+      const T inv = o ? (zwL ? iz1 : in1) : (zwL ? iz0 : in0);
+      const T bb = o ? cur.bo.y : cur.bo.x;
+      const unsigned cd = (cur.co >> (8 * o)) & 255u;
+      T v = relax(cd, pbL, own_off + o, i + o, j, L, inv, xw, xe, xs, xn, xd, xu, bb);
+      v = pl && col_ok && j < n ? v : T(0);
+      sc[cl0 + o * CPL + (w + 1) * XP + p + 1] = v;
+      c1own = v;
     }
-    if (r_item) {
-      const int o = (r_oadd + L) & 1;
-      const int ic = r_i + o * r_step;
-      const bool ok = pl && (o ? r_ok1 : r_ok0);
-      const int walls = (ic == 0) + (ic == n - 1) + rwj;
-      c1_cell(ok, L, ic, r_j, walls, r_x + o * r_step, r_c + o * r_step, o ? bc.rb1 : bc.rb0,
-              o ? bc.rc1 : bc.rc0);
+    if (w >= 5) {
+      // ring rows j0 - 1 and j0 + TY (waves 5, 6) over the tile's pairs, or the column
+      // cells i0 - 1 / i0 + TX (wave 7, lanes 0 .. TY - 1): the cell of colour c1
+      int o, ic, jc, par, pr, xr, cr;
+      T bb;
+      unsigned cd;
+      bool ok;
+      if (w < 7) {
+        o = (c1 + rj + L) & 1;
+        ic = i + o;
+        jc = rj;
+        par = o;
+        pr = p + 1;
+        xr = rrow + 2;
+        cr = rrow + 1;
+        bb = o ? cur.br.y : cur.br.x;
+        cd = (cur.cr0 >> (8 * o)) & 255u;
+        ok = rok0;
+      } else {
+        o = (c1 + 1 + cj + L) & 1;
+        ic = o ? i0 + TX : i0 - 1;
+        jc = cj;
+        par = o ? 0 : 1;
+        pr = o ? XP - 1 : 0;
+        xr = p + 2;
+        cr = p + 1;
+        bb = o ? cur.br.y : cur.br.x;
+        cd = o ? cur.cr1 : cur.cr0;
+        ok = p < TY && (o ? rok1 : rok0);
+      }
+      T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
+      if (MODE != 1 && (w < 7 || p < TY)) {
+        // west and east: the other parity, pairs pr - 1 + par and pr + par
+        const T* xo = sx + xl0 + (1 - par) * XPL + xr * XP + pr - 1 + par;
+        xw = xo[0];
+        xe = xo[1];
+        const T* xs0 = sx + xl0 + par * XPL + xr * XP + pr;
+        xs = xs0[-XP];
+        xn = xs0[XP];
+        xd = sx[xm + par * XPL + xr * XP + pr];
+        xu = sx[xp + par * XPL + xr * XP + pr];
+      }
+      const int walls = (ic == 0) + (ic == n - 1) + (jc == 0) + (jc == n - 1) + zwL;
+      T v = relax(ok ? cd : 0u, pbL, (unsigned)(ic + n * jc), ic, jc, L, inv_of(walls), xw, xe, xs,
+                  xn, xd, xu, bb);
+      v = pl && ok ? v : T(0);
+      if (w < 7 || p < TY) sc[cl0 + par * CPL + cr * XP + pr] = v;
     }
     lds_barrier();
 
@@ -364,24 +398,40 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const int k = L - 1;
     const bool kin = k >= k0 && k < k1;
     {
-      const int o2 = ((c1 + j + k) & 1) ^ 1;
-      const int kk = kin ? k : k0;
-      const T* cl = sc[(kk + 3) % 3];
-      const int q = own_c + o2;
-      const T xw = o2 ? c1prev : cl[q - 1];
-      const T xe = o2 ? cl[q + 1] : c1prev;
-      const T bb = o2 ? bp.bo.y : bp.bo.x;
-      const unsigned cd = kin ? (bp.co >> (8 * o2)) & 255u : 0u;
-      const T v2 = relax(cd, i + o2, j, kk, (o2 ? wx1 : wx0) + (kk == 0) + (kk == n - 1), xw, xe,
-                         cl[q - CW], cl[q + CW], sc[(kk + 2) % 3][q], sc[(kk + 4) % 3][q], bb);
+      const int o2 = ((c1 + j + k) & 1) ^ 1;   // wave-uniform: the c2 cell of the pair
+      const bool zwk = k == 0 || k == n - 1;
+      // slot(k) = cm, slot(k - 1) = cp, slot(k + 1) = cl0
+      const T* cl = sc + cm + o2 * CPL + (w + 1) * XP + p + 1;
+      // the c1 neighbour along x that is not the lane's own c1 cell
+      const T xo = sc[cm + (1 - o2) * CPL + (w + 1) * XP + p + 2 * o2];
+      const T xw = o2 ? c1prev : xo;
+      const T xe = o2 ? xo : c1prev;
+      const T inv = o2 ? (zwk ? iz1 : in1) : (zwk ? iz0 : in0);
+      const T bb = o2 ? bprev.y : bprev.x;
+      const unsigned cd = kin ? (cprev >> (8 * o2)) & 255u : 0u;
+      const T v2 = relax(cd, pbL - nn, own_off + o2, i + o2, j, k, inv, xw, xe, cl[-XP], cl[XP],
+                         sc[cp + o2 * CPL + (w + 1) * XP + p + 1],
+                         sc[cl0 + o2 * CPL + (w + 1) * XP + p + 1], bb);
       V out;
       out.x = o2 ? c1prev : v2;
       out.y = o2 ? v2 : c1prev;
-      buf_st_pair<T>(out, plane_rsrc(xout + base + (size_t)kk * nn, kin ? plane_bytes : 0u), own_b);
+      buf_st_pair(out, plane_rsrc(oq, kin ? plane_bytes : 0u), own_b);
       // b reads zero outside the domain, so those lanes add nothing
-      if (dot && kin) acc += (double)bp.bo.x * (double)out.x + (double)bp.bo.y * (double)out.y;
+      if (dot && kin) acc += (double)bprev.x * (double)out.x + (double)bprev.y * (double)out.y;
     }
+    bprev = cur.bo;
+    cprev = cur.co;
     c1prev = c1own;
+    oq += plane_bytes;
+    pbL += nn;
+    // rotate: L - 1 <- L, L <- L + 1, L + 1 <- L + 2
+    const int tx = xm, tc = cm;
+    xm = xl0;
+    xl0 = xp;
+    xp = tx;
+    cm = cl0;
+    cl0 = cp;
+    cp = tc;
   }
   if (dot) block_partial(acc, ctl, b);
 }
