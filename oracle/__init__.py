@@ -55,6 +55,8 @@ def lib():
         L.orc_pipeline.argtypes = [i, P, P, d, d, d, P, P, P, P, P, P, P, P]
         L.orc_divergence.argtypes = [i, P, P, P, d, P]
         L.orc_project.argtypes = [i, P, P, P, d, d, d, d, P, P, P]
+        L.orc_ls_advect.argtypes = [i, P, P, P, P, d, P]
+        L.orc_ls_reinit.argtypes = [i, P, P, i, d, P]
         L.orc_gs_colour.argtypes = [i, P, P, P, P, P, i]
         L.orc_gs_colour.restype = None
         L.orc_restrict.argtypes = [i, P, P]
@@ -189,6 +191,25 @@ def project(phi, kappa, p, rho_neg, rho_pos, sigma, dt, u):
     _check(lib().orc_project(_n(phi), _p(phi), _p(kappa), _p(p), float(rho_neg), float(rho_pos),
                              float(sigma), float(dt), _p(ux), _p(uy), _p(uz)), "project")
     return ux, uy, uz
+
+
+def ls_advect(phi, u, dt):
+    """One upwind advection step of the level set by the face velocities u = (ux, uy, uz)."""
+    phi = _c(phi)
+    ux, uy, uz = (_c(a) for a in u)
+    out = np.empty_like(phi)
+    _check(lib().orc_ls_advect(_n(phi), _p(phi), _p(ux), _p(uy), _p(uz), float(dt), _p(out)),
+           "ls_advect")
+    return out
+
+
+def ls_reinit(phi0, phi, iters, dtau):
+    """iters re-distancing steps of size dtau from phi, signs from phi0."""
+    phi0, phi = _c(phi0), _c(phi)
+    out = np.empty_like(phi)
+    _check(lib().orc_ls_reinit(_n(phi), _p(phi0), _p(phi), int(iters), float(dtau), _p(out)),
+           "ls_reinit")
+    return out
 
 
 def pipeline(phi, f, rho_neg, rho_pos, sigma, kappa_override=None):

@@ -807,6 +807,115 @@ int orc_project(int n, const double *phi, const double *kappa, const double *p, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Level set: advection by the face velocities and re-distancing             */
+/* ------------------------------------------------------------------------ */
+/* The level-set unit (Sec. 3, Multiphase / StencilsLevelSet) moves phi with the flow
+ * and keeps it a signed distance; the paper names the operations but gives no scheme.
+ * Readings (stated, not the paper's):
+ *   - advection: phi_t + u . grad phi = 0, one forward-Euler step, first-order upwind
+ *     differences, the cell-centre velocity the mean of the cell's two faces along each
+ *     axis (wall faces 0), one-sided differences across a wall taken as 0 (phi
+ *     extended by its boundary value);
+ *   - re-distancing: pseudo-time steps of phi_tau + S(phi0) (|grad phi| - 1) = 0 with
+ *     S(phi0) = phi0 / sqrt(phi0^2 + h^2) (Sussman, Smereka & Osher, J. Comput. Phys.
+ *     114, 1994) and the first-order Godunov upwind |grad phi| (Rouy & Tourin), forward
+ *     Euler, the same wall rule. */
+
+/* out = phi - dt * (ax + ay + az), a_d = u_d * (backward difference if u_d > 0, else
+ * forward difference) along axis d, u_d the cell-centre velocity. */
+int orc_ls_advect(int n, const double *phi, const double *ux, const double *uy,
+                  const double *uz, double dt, double *out)
+{
+    if (n < 2 || !phi || !ux || !uy || !uz || !out || !(dt > 0.0))
+        return ORC_EINVAL;
+    double inv_h = (double)n;
+    const double *u[3] = {ux, uy, uz};
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int ijk3[3] = {i, j, k};
+                size_t c = ix(n, i, j, k);
+                double a[3];
+                for (int d = 0; d < 3; ++d) {
+                    int q = ijk3[d];
+                    size_t step = d == 0 ? 1 : (d == 1 ? (size_t)n : (size_t)n * n);
+                    double ulo = q > 0 ? u[d][c] : 0.0;
+                    double uhi = q < n - 1 ? u[d][c + step] : 0.0;
+                    double uc = 0.5 * (ulo + uhi);
+                    double back = q > 0 ? (phi[c] - phi[c - step]) * inv_h : 0.0;
+                    double fwd = q < n - 1 ? (phi[c + step] - phi[c]) * inv_h : 0.0;
+                    a[d] = uc > 0.0 ? uc * back : uc * fwd;
+                }
+                out[c] = phi[c] - dt * ((a[0] + a[1]) + a[2]);
+            }
+    return ORC_OK;
+}
+
+/* Godunov |grad phi| at cell c for the sign s of phi0 (s > 0: max over the axes of
+ * max(back+^2, fwd-^2); s < 0: max(back-^2, fwd+^2)), summed over the axes. */
+static double godunov_grad(int n, const double *phi, int i, int j, int k, double s)
+{
+    double inv_h = (double)n;
+    size_t c = ix(n, i, j, k);
+    int ijk3[3] = {i, j, k};
+    double g2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        int q = ijk3[d];
+        size_t step = d == 0 ? 1 : (d == 1 ? (size_t)n : (size_t)n * n);
+        double back = q > 0 ? (phi[c] - phi[c - step]) * inv_h : 0.0;
+        double fwd = q < n - 1 ? (phi[c + step] - phi[c]) * inv_h : 0.0;
+        double t1, t2;
+        if (s > 0.0) {
+            t1 = back > 0.0 ? back : 0.0;
+            t2 = fwd < 0.0 ? fwd : 0.0;
+        } else {
+            t1 = back < 0.0 ? back : 0.0;
+            t2 = fwd > 0.0 ? fwd : 0.0;
+        }
+        double a = t1 * t1, b = t2 * t2;
+        g2 += a > b ? a : b;
+    }
+    return sqrt(g2);
+}
+
+/* iters pseudo-time steps of size dtau from phi (phi0 fixes the smoothed sign);
+ * every step reads the previous iterate only.  out may alias phi. */
+int orc_ls_reinit(int n, const double *phi0, const double *phi, int iters, double dtau,
+                  double *out)
+{
+    if (n < 2 || !phi0 || !phi || !out || iters < 0 || !(dtau > 0.0))
+        return ORC_EINVAL;
+    size_t m = (size_t)n * n * n;
+    double h = 1.0 / (double)n;
+    double *cur = malloc(m * sizeof(double)), *nxt = malloc(m * sizeof(double));
+    if (!cur || !nxt) {
+        free(cur);
+        free(nxt);
+        return ORC_ENOMEM;
+    }
+    memcpy(cur, phi, m * sizeof(double));
+    for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    size_t c = ix(n, i, j, k);
+                    double s = phi0[c] / sqrt(phi0[c] * phi0[c] + h * h);
+                    double g = godunov_grad(n, cur, i, j, k, s);
+                    nxt[c] = cur[c] - dtau * s * (g - 1.0);
+                }
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    memcpy(out, cur, m * sizeof(double));
+    free(cur);
+    free(nxt);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole pipeline: phi, f -> faces, kappa, jterm, b, p                       */
 /* ------------------------------------------------------------------------ */
 /* kappa_override: NULL to compute kappa from phi, else a per-cell field used as is. */
