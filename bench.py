@@ -321,6 +321,71 @@ def projection256(M, G, torch, args):
     print(json.dumps(rec), flush=True)
 
 
+def flow256(M, G, torch, args):
+    """Whole time steps of a buoyant bubble at 256^3 (density ratio 1000, sigma 0.01):
+    gravity on the vertical faces, operator rebuilt from the moving level set, projection
+    around the mixed solve (warm start), upwind advection of the level set by the new
+    velocity and two re-distancing steps.  Time per step and the HIP-event time of the
+    level-set kernels against the HBM roofline."""
+    dev = torch.device("cuda:0")
+    n, K, W = 256, args.steps, args.warmup
+    prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01)
+    dt, g = 1e-3, 1.0
+    phi = torch.from_numpy(G.bubble_phi(n, [(0.5, 0.5, 0.3)], [0.1])).to(dev)
+    u = [torch.zeros_like(phi) for _ in range(3)]
+    p = torch.zeros_like(phi)
+    op = M.Operator(phi, **prm)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_adv, t_re, iters = [], [], []
+    phi0, work = torch.empty_like(phi), torch.empty_like(phi)
+    zs = torch.from_numpy(((np.arange(n) + 0.5) / n)).to(dev)[:, None, None]
+
+    def centre(ph):
+        m = (ph < 0).double()
+        return float((zs * m).sum() / m.sum())
+
+    for t in range(K + W):
+        if t == W:
+            torch.cuda.synchronize()
+            z0 = centre(phi)
+            t0 = time.perf_counter()
+        u[2][1:, :, :] -= dt * g
+        op.update(phi, **prm)
+        f = op.divergence(u, dt)
+        p, info = op.solve(f, p=p, rtol=1e-10, mode="mixed", nu=args.nu)
+        op.project(phi, p, dt, u)
+        ev[0].record()
+        new = M.ls_advect(phi, u, dt)
+        ev[1].record()
+        phi0.copy_(new)
+        M.ls_reinit(new, 2, phi0=phi0, work=work)
+        ev[2].record()
+        phi = new
+        if t >= W:
+            torch.cuda.synchronize()
+            t_adv.append(ev[0].elapsed_time(ev[1]))
+            t_re.append(ev[1].elapsed_time(ev[2]))
+            iters.append(info[0].iters)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    cells = n ** 3
+    adv_ms, re_ms = float(np.mean(t_adv)), float(np.mean(t_re))
+    adv_bytes, re_bytes = 40.0 * cells, 2 * 24.0 * cells
+    rec = {"metric": "time per buoyant-bubble step (gravity, projection with the mixed solve, "
+                     "level-set advection and re-distancing), 256^3",
+           "value": round(ms, 3), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "steps": K, "warmup": W, "data": "synthetic",
+           "config": {"workload": "flow256", "dt": dt, "g": g},
+           "kernels": {"ls_advect": {"ms": round(adv_ms, 4),
+                                     "GBps": round(adv_bytes / (adv_ms * 1e-3) / 1e9, 1),
+                                     "alg_bytes": adv_bytes},
+                       "ls_reinit_x2": {"ms": round(re_ms, 4),
+                                        "GBps": round(re_bytes / (re_ms * 1e-3) / 1e9, 1),
+                                        "alg_bytes": re_bytes}},
+           "solve_iters": iters, "bubble_rise": centre(phi) - z0}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,7 +402,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", default="rising256",
                     choices=["rising256", "batched64", "single32", "bubbles128",
-                             "projection256"],
+                             "projection256", "flow256"],
                     help="rising256: the 256^3 sequence (default); batched64: 64 x 64^3; "
                          "single32 / bubbles128: one fixed problem, plain vs mixed")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -367,6 +432,9 @@ def main():
         return
     if args.workload == "projection256":
         projection256(M, G, torch, args)
+        return
+    if args.workload == "flow256":
+        flow256(M, G, torch, args)
         return
     n, K, W = args.n, args.steps, args.warmup
     prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01, rtol=1e-10)

@@ -209,6 +209,34 @@ int mpp_project(mpp_op op, const double *phi, const double *p, double dt, double
                 double *uy, double *uz, void *stream);
 
 /* ------------------------------------------------------------------------------
+ * Level set (Sec. 3: the Multiphase unit moves phi with the flow and, through
+ * StencilsLevelSet, keeps it a signed distance).  The paper gives no scheme; this
+ * library uses first-order upwind advection and smoothed-sign Godunov re-distancing,
+ * FP64.  Cell fields are device [batch][n^3] arrays (x fastest); face velocities use
+ * the low-face layout above.  Differences across a wall are 0.  These calls need no
+ * operator.
+ * ------------------------------------------------------------------------------ */
+
+/* One forward-Euler step of phi_t + u . grad phi = 0: phi_out = phi - dt (a_x + a_y +
+ * a_z), a_d = u_d D_d phi with u_d = (u on the low face + u on the high face) / 2 at the
+ * cell centre and D_d the backward difference (phi_c - phi_{c-1}) / h when u_d > 0, the
+ * forward difference (phi_{c+1} - phi_c) / h otherwise.  2 <= n <= 1024, 1 <= batch <=
+ * 65535, dt > 0 and finite, phi_out distinct from phi.  Asynchronous. */
+int mpp_ls_advect(int n, int batch, const double *phi, const double *ux, const double *uy,
+                  const double *uz, double dt, double *phi_out, void *stream);
+
+/* iters pseudo-time steps of size dtau of phi_tau + S (|grad phi| - 1) = 0, each from
+ * the previous iterate: phi <- phi - dtau S (G - 1), S = phi0 / sqrt(phi0^2 + h^2), G =
+ * sqrt(sum over the axes of max(t1^2, t2^2)) with (t1, t2) = (max(back, 0), min(fwd, 0))
+ * where S > 0 and (min(back, 0), max(fwd, 0)) otherwise (Godunov upwinding).  phi0
+ * (fixed signs, usually phi before the first step) is read only; phi is updated in
+ * place; work is a caller-owned device scratch array of the same size.  The three
+ * arrays must be distinct; iters >= 0, dtau > 0 (stable up to h/2 ~ 0.5/n).
+ * Asynchronous. */
+int mpp_ls_reinit(int n, int batch, const double *phi0, double *phi, double *work, int iters,
+                  double dtau, void *stream);
+
+/* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from
  * the previous pressure or from zero): a small 3D U-Net maps the density field and
  * the right-hand side of a problem to an approximate solution that seeds the PCG.

@@ -31,6 +31,7 @@ EXPORTS = (
     "mpp_net_destroy", "mpp_net_set_params", "mpp_net_get_params", "mpp_net_forward",
     "mpp_net_loss", "mpp_net_backward", "mpp_net_get_grads", "mpp_net_adam",
     "mpp_net_features", "mpp_learned_guess", "mpp_divergence", "mpp_project",
+    "mpp_ls_advect", "mpp_ls_reinit",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -117,6 +118,8 @@ def load_library(path: str = LIB_PATH):
                                     P]
     L.mpp_divergence.argtypes = [P, P, P, P, d, P, P]
     L.mpp_project.argtypes = [P, P, P, d, P, P, P, P]
+    L.mpp_ls_advect.argtypes = [i32, i32, P, P, P, P, d, P, P]
+    L.mpp_ls_reinit.argtypes = [i32, i32, P, P, P, i32, d, P]
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
                                                  "mpp_strerror", "mpp_workspace_bytes",
                                                  "mpp_net_workspace_bytes",
@@ -377,6 +380,57 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def _grid_shape(phi):
+    """(n, batch) of a device float64 cell field [n,n,n] or [batch,n,n,n]."""
+    torch = _torch()
+    if not isinstance(phi, torch.Tensor) or not phi.is_cuda or phi.dtype != torch.float64:
+        raise TypeError("phi must be a float64 CUDA (HIP) tensor")
+    if phi.dim() == 3:
+        batch, n = 1, phi.shape[0]
+    elif phi.dim() == 4:
+        batch, n = phi.shape[0], phi.shape[1]
+    else:
+        raise ValueError("phi must have shape [n,n,n] or [batch,n,n,n]")
+    if tuple(phi.shape[-3:]) != (n, n, n) or not phi.is_contiguous():
+        raise ValueError("phi must be contiguous and cubic")
+    return n, batch
+
+
+def ls_advect(phi, u, dt, out=None):
+    """One upwind advection step of the level set phi by the low-face velocities
+    u = (ux, uy, uz) (same shape as phi); returns the new level set."""
+    n, batch = _grid_shape(phi)
+    for name, a in zip(("ux", "uy", "uz"), u):
+        _check_field(a, phi.shape, name)
+    out = _torch().empty_like(phi) if out is None else out
+    _check_field(out, phi.shape, "out")
+    st = load_library().mpp_ls_advect(n, batch, ctypes.c_void_p(phi.data_ptr()),
+                                      *[ctypes.c_void_p(a.data_ptr()) for a in u], float(dt),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(phi.device))
+    if st != OK:
+        raise MppError(st, "mpp_ls_advect")
+    return out
+
+
+def ls_reinit(phi, iters, dtau=None, phi0=None, work=None):
+    """iters re-distancing steps of phi in place (signs from phi0, default a copy of phi;
+    dtau default h/2); returns phi."""
+    torch = _torch()
+    n, batch = _grid_shape(phi)
+    phi0 = phi.clone() if phi0 is None else phi0
+    work = torch.empty_like(phi) if work is None else work
+    _check_field(phi0, phi.shape, "phi0")
+    _check_field(work, phi.shape, "work")
+    dtau = 0.5 / n if dtau is None else dtau
+    st = load_library().mpp_ls_reinit(n, batch, ctypes.c_void_p(phi0.data_ptr()),
+                                      ctypes.c_void_p(phi.data_ptr()),
+                                      ctypes.c_void_p(work.data_ptr()), int(iters), float(dtau),
+                                      _stream_handle(phi.device))
+    if st != OK:
+        raise MppError(st, "mpp_ls_reinit")
+    return phi
 
 
 def net_param_count() -> int:

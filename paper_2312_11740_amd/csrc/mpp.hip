@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "guess.h"
+#include "levelset.h"
 #include "kernels.h"
 #include "net_internal.h"
 #include "project.h"
@@ -1266,6 +1267,50 @@ int mpp_project(mpp_op op, const double* phi, const double* p, double dt, double
     hipLaunchKernelGGL(k_project, grid_of(L0, op->batch), dim3(kBlock), 0, s, phi, op->kappa, p,
                        op->rho, op->n, (int)L0.cells, dt, ux, uy, uz);
     ck_launch();
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
+int mpp_ls_advect(int n, int batch, const double* phi, const double* ux, const double* uy,
+                  const double* uz, double dt, double* phi_out, void* stream) {
+  if (n < 2 || n > 1024 || batch < 1 || batch > 65535 || !phi || !ux || !uy || !uz ||
+      !phi_out || phi_out == phi || !(dt > 0.0) || !std::isfinite(dt))
+    return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int cells = n * n * n;
+  const dim3 grid((cells + kLsBlock - 1) / kLsBlock, batch);
+  try {
+    hipLaunchKernelGGL(k_ls_advect, grid, dim3(kLsBlock), 0, s, phi, ux, uy, uz, n, cells, dt,
+                       phi_out);
+    ck_launch();
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
+int mpp_ls_reinit(int n, int batch, const double* phi0, double* phi, double* work, int iters,
+                  double dtau, void* stream) {
+  if (n < 2 || n > 1024 || batch < 1 || batch > 65535 || !phi0 || !phi || !work || iters < 0 ||
+      phi0 == phi || phi0 == work || phi == work || !(dtau > 0.0) || !std::isfinite(dtau))
+    return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int cells = n * n * n;
+  const dim3 grid((cells + kLsBlock - 1) / kLsBlock, batch);
+  try {
+    double* src = phi;
+    double* dst = work;
+    for (int it = 0; it < iters; ++it) {
+      hipLaunchKernelGGL(k_ls_reinit, grid, dim3(kLsBlock), 0, s, phi0, src, n, cells, dtau, dst);
+      ck_launch();
+      std::swap(src, dst);
+    }
+    if (src != phi) {
+      hipLaunchKernelGGL(k_ls_copy, grid, dim3(kLsBlock), 0, s, src, cells, phi);
+      ck_launch();
+    }
   } catch (HipError& e) {
     return status_of(e.e);
   }

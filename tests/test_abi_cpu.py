@@ -82,3 +82,20 @@ def test_default_opts_and_strerror():
     L.mpp_default_opts(ctypes.byref(o))
     assert o.rtol == 1e-10 and o.mode == M.MODE_FP64 and o.nu == 2
     assert M.strerror(M.ENOTCONVERGED) == "not converged within max_iter"
+
+
+def test_level_set_calls_reject_bad_arguments_before_device_work():
+    L = M.load_library()
+    a, b, c = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3))   # never dereferenced
+    u = [ctypes.c_void_p(0x8000)] * 3
+    assert L.mpp_ls_advect(1, 1, a, *u, 0.1, b, None) == M.EINVAL         # n < 2
+    assert L.mpp_ls_advect(8, 0, a, *u, 0.1, b, None) == M.EINVAL         # batch < 1
+    assert L.mpp_ls_advect(8, 1, a, *u, 0.0, b, None) == M.EINVAL         # dt <= 0
+    assert L.mpp_ls_advect(8, 1, a, *u, float("inf"), b, None) == M.EINVAL
+    assert L.mpp_ls_advect(8, 1, a, *u, 0.1, a, None) == M.EINVAL         # out aliases phi
+    assert L.mpp_ls_advect(8, 1, None, *u, 0.1, b, None) == M.EINVAL
+    assert L.mpp_ls_reinit(8, 1, a, b, c, -1, 0.1, None) == M.EINVAL      # iters < 0
+    assert L.mpp_ls_reinit(8, 1, a, b, c, 3, 0.0, None) == M.EINVAL       # dtau <= 0
+    assert L.mpp_ls_reinit(8, 1, a, a, c, 3, 0.1, None) == M.EINVAL       # phi0 aliases phi
+    assert L.mpp_ls_reinit(8, 1, a, b, b, 3, 0.1, None) == M.EINVAL       # work aliases phi
+    assert L.mpp_ls_reinit(2048, 1, a, b, c, 3, 0.1, None) == M.EINVAL    # n too large
