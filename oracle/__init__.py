@@ -57,6 +57,9 @@ def lib():
         L.orc_project.argtypes = [i, P, P, P, d, d, d, d, P, P, P]
         L.orc_ls_advect.argtypes = [i, P, P, P, P, d, P]
         L.orc_ls_reinit.argtypes = [i, P, P, i, d, P]
+        L.orc_heat_apply.argtypes = [i, P, P, P, d, P, P]
+        L.orc_heat_apply.restype = None
+        L.orc_heat_solve.argtypes = [i, P, P, P, d, P, P, d, i, P, P]
         L.orc_gs_colour.argtypes = [i, P, P, P, P, P, i]
         L.orc_gs_colour.restype = None
         L.orc_restrict.argtypes = [i, P, P]
@@ -210,6 +213,34 @@ def ls_reinit(phi0, phi, iters, dtau):
     _check(lib().orc_ls_reinit(_n(phi), _p(phi0), _p(phi), int(iters), float(dtau), _p(out)),
            "ls_reinit")
     return out
+
+
+def heat_faces(phi, k_neg, k_pos):
+    """Conductivity on the faces: the ghost-fluid face rule with rho = 1/K of each phase
+    (K_neg where phi <= 0, K_pos where phi > 0; the two in series on a crossed face)."""
+    return faces(phi, 1.0 / k_neg, 1.0 / k_pos)
+
+
+def heat_apply(fc, dt, x):
+    """y = x - dt div(K grad x), insulated walls."""
+    bx, by, bz = (_c(a) for a in fc)
+    x = _c(x)
+    y = np.empty_like(x)
+    lib().orc_heat_apply(_n(x), _p(bx), _p(by), _p(bz), float(dt), _p(x), _p(y))
+    return y
+
+
+def heat_step(fc, t_old, dt, src=None, tol=1e-13, max_iter=100000, x0=None):
+    """One backward-Euler diffusion step: solves (I - dt div(K grad)) T = t_old + dt src
+    by conjugate gradients; returns (T, iterations, relative residual)."""
+    bx, by, bz = (_c(a) for a in fc)
+    rhs = _c(t_old).copy() if src is None else _c(t_old) + float(dt) * _c(src)
+    x = np.zeros_like(rhs) if x0 is None else _c(x0).copy()
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    _check(lib().orc_heat_solve(_n(rhs), _p(bx), _p(by), _p(bz), float(dt), _p(rhs), _p(x),
+                                float(tol), int(max_iter), ctypes.byref(it), ctypes.byref(rr)),
+           "heat_solve")
+    return x, it.value, rr.value
 
 
 def pipeline(phi, f, rho_neg, rho_pos, sigma, kappa_override=None):

@@ -916,6 +916,94 @@ int orc_ls_reinit(int n, const double *phi0, const double *phi, int iters, doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* Implicit heat diffusion: the diffusion term of the transport equation of   */
+/* Sec. 2 with a coefficient that changes with the phase (the varDiffusion    */
+/* configuration of HeatAD, Sec. 3), one backward-Euler step                  */
+/*        (I - dt div(K grad)) T_new = T_old + dt f                           */
+/* with insulated walls.  The face arrays carry K on every face; built by the */
+/* face rule above from rho = 1/K of each phase they hold the two             */
+/* conductivities in series, split where the interface crosses the face.      */
+/* ------------------------------------------------------------------------ */
+
+/* y = x - dt (A x) */
+void orc_heat_apply(int n, const double *bx, const double *by, const double *bz, double dt,
+                    const double *x, double *y)
+{
+    size_t m = (size_t)n * n * n;
+    orc_apply(n, bx, by, bz, x, y);
+    for (size_t c = 0; c < m; ++c)
+        y[c] = x[c] - dt * y[c];
+}
+
+static double heat_rel_residual(int n, const double *bx, const double *by, const double *bz,
+                                double dt, const double *rhs, const double *x, double *r)
+{
+    size_t m = (size_t)n * n * n;
+    orc_heat_apply(n, bx, by, bz, dt, x, r);
+    for (size_t c = 0; c < m; ++c)
+        r[c] = rhs[c] - r[c];
+    double bn = nrm2(rhs, m);
+    double rn = nrm2(r, m);
+    return bn > 0.0 ? rn / bn : rn;
+}
+
+/* Conjugate gradients (no preconditioner) on the symmetric positive definite heat
+ * matrix.  x holds the start on entry and the solution on exit; stops once the true
+ * residual satisfies ||rhs - H x|| <= tol ||rhs||. */
+int orc_heat_solve(int n, const double *bx, const double *by, const double *bz, double dt,
+                   const double *rhs, double *x, double tol, int max_iter, int *iters_out,
+                   double *relres_out)
+{
+    if (n < 1 || !bx || !by || !bz || !rhs || !x || !(dt >= 0.0) || !(dt < INFINITY) ||
+        !(tol > 0.0) || max_iter < 1)
+        return ORC_EINVAL;
+    size_t m = (size_t)n * n * n;
+    double *r = (double *)malloc(sizeof(double) * m);
+    double *p = (double *)malloc(sizeof(double) * m);
+    double *q = (double *)malloc(sizeof(double) * m);
+    if (!r || !p || !q) {
+        free(r); free(p); free(q);
+        return ORC_ENOMEM;
+    }
+    double bn = nrm2(rhs, m);
+    int it = 0, status = ORC_ENOTCONVERGED;
+    double rel = heat_rel_residual(n, bx, by, bz, dt, rhs, x, r);
+    while (it < max_iter && rel > tol) {   /* restarts from the true residual */
+        memcpy(p, r, sizeof(double) * m);
+        double rr = dot(r, r, m);
+        while (it < max_iter) {
+            orc_heat_apply(n, bx, by, bz, dt, p, q);
+            double pq = dot(p, q, m);
+            if (!(pq > 0.0)) {
+                status = ORC_EBREAKDOWN;
+                goto done;
+            }
+            double alpha = rr / pq;
+            for (size_t c = 0; c < m; ++c) {
+                x[c] += alpha * p[c];
+                r[c] -= alpha * q[c];
+            }
+            ++it;
+            double rr_new = dot(r, r, m);
+            if (sqrt(rr_new) <= tol * bn)
+                break;
+            double beta = rr_new / rr;
+            rr = rr_new;
+            for (size_t c = 0; c < m; ++c)
+                p[c] = r[c] + beta * p[c];
+        }
+        rel = heat_rel_residual(n, bx, by, bz, dt, rhs, x, r);
+    }
+    if (rel <= tol)
+        status = ORC_OK;
+done:
+    if (iters_out) *iters_out = it;
+    if (relres_out) *relres_out = rel;
+    free(r); free(p); free(q);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole pipeline: phi, f -> faces, kappa, jterm, b, p                       */
 /* ------------------------------------------------------------------------ */
 /* kappa_override: NULL to compute kappa from phi, else a per-cell field used as is. */
