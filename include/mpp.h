@@ -237,6 +237,31 @@ int mpp_ls_reinit(int n, int batch, const double *phi0, double *phi, double *wor
                   double dtau, void *stream);
 
 /* ------------------------------------------------------------------------------
+ * Implicit heat diffusion (the diffusion term of the transport equation of Sec. 2
+ * with a coefficient that changes with the phase: the varDiffusion configuration of
+ * HeatAD, Sec. 3).  One backward-Euler step
+ *        (I - dt div(K grad)) T = T_old + dt f,   insulated walls,
+ * on an operator whose face coefficients are read as conductivities: build it with
+ * rho_neg = 1/K_neg and rho_pos = 1/K_pos (K_neg where phi <= 0); crossed faces then
+ * hold the two conductivities in series, split where the interface crosses the face.
+ * Nothing else of the operator (curvature, jump term, multigrid levels) is used.
+ * ------------------------------------------------------------------------------ */
+
+/* t_old, t: device [batch][n^3]; src: device [batch][n^3] or NULL (no source).  t
+ * holds the initial guess when opts->guess is MPP_GUESS_GIVEN (ignored with
+ * MPP_GUESS_ZERO) and receives T; t may be t_old, src may not be t.  dt >= 0 and
+ * finite.  Solved by conjugate gradients on (dt A - I) T = -(T_old + dt f) with the
+ * inverse diagonal as preconditioner, to ||b - H T|| <= opts->rtol ||b|| in FP64
+ * (H = I - dt div(K grad), b = T_old + dt f); of opts only rtol, max_iter,
+ * check_every and guess are used.  The true residual is checked at the end and CG
+ * restarted from it (up to 4 runs).  info[batch] as for mpp_solve (removed_mean 0,
+ * outer_iters = CG runs).  The matrix's condition number is about 1 + 12 dt K_max /
+ * h^2, so the iterations grow as the square root of that.  Synchronous with respect to
+ * the host.  Returns the worst status of the batch. */
+int mpp_heat_solve(mpp_op op, const double *t_old, const double *src, double dt, double *t,
+                   const mpp_solve_opts *opts, mpp_solve_info *info, void *stream);
+
+/* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from
  * the previous pressure or from zero): a small 3D U-Net maps the density field and
  * the right-hand side of a problem to an approximate solution that seeds the PCG.

@@ -31,7 +31,7 @@ EXPORTS = (
     "mpp_net_destroy", "mpp_net_set_params", "mpp_net_get_params", "mpp_net_forward",
     "mpp_net_loss", "mpp_net_backward", "mpp_net_get_grads", "mpp_net_adam",
     "mpp_net_features", "mpp_learned_guess", "mpp_divergence", "mpp_project",
-    "mpp_ls_advect", "mpp_ls_reinit",
+    "mpp_ls_advect", "mpp_ls_reinit", "mpp_heat_solve",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH):
     L.mpp_project.argtypes = [P, P, P, d, P, P, P, P]
     L.mpp_ls_advect.argtypes = [i32, i32, P, P, P, P, d, P, P]
     L.mpp_ls_reinit.argtypes = [i32, i32, P, P, P, i32, d, P]
+    L.mpp_heat_solve.argtypes = [P, P, P, d, P, ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(SolveInfo), P]
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
                                                  "mpp_strerror", "mpp_workspace_bytes",
                                                  "mpp_net_workspace_bytes",
@@ -311,6 +313,35 @@ class Operator:
         if st != OK and raise_on_error:
             raise MppError(st, "mpp_solve")
         return p, out
+
+    def heat_solve(self, t_old, dt, src=None, t=None, rtol=1e-10, max_iter=2000,
+                   check_every=4, raise_on_error=True):
+        """One backward-Euler diffusion step (I - dt div(K grad)) T = t_old + dt src on
+        this operator's face coefficients, read as conductivities K (build the operator
+        with rho_neg = 1/K_neg, rho_pos = 1/K_pos; sigma plays no part).  t: optional
+        initial guess, overwritten with T (may be t_old).  Returns (T, [Info])."""
+        _check_field(t_old, self.shape, "t_old")
+        if src is not None:
+            _check_field(src, self.shape, "src")
+        opts = SolveOpts()
+        load_library().mpp_default_opts(ctypes.byref(opts))
+        opts.rtol, opts.max_iter, opts.check_every = float(rtol), int(max_iter), int(check_every)
+        if t is None:
+            t = self._new()
+            opts.guess = GUESS_ZERO
+        else:
+            _check_field(t, self.shape, "t")
+            opts.guess = GUESS_GIVEN
+        infos = (SolveInfo * self.batch)()
+        st = load_library().mpp_heat_solve(
+            self._h, ctypes.c_void_p(t_old.data_ptr()),
+            ctypes.c_void_p(src.data_ptr() if src is not None else None), float(dt),
+            ctypes.c_void_p(t.data_ptr()), ctypes.byref(opts), infos, _stream_handle(self.device))
+        out = [Info(q.status, q.iters, q.outer_iters, q.rel_resid, q.removed_mean, q.bnorm)
+               for q in infos]
+        if st != OK and raise_on_error:
+            raise MppError(st, "mpp_heat_solve")
+        return t, out
 
     def divergence(self, u, dt, out=None):
         """f = div(u)/dt of the low-face velocities u = (ux, uy, uz)."""

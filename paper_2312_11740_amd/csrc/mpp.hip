@@ -20,6 +20,7 @@
 
 #include "guess.h"
 #include "levelset.h"
+#include "heat.h"
 #include "kernels.h"
 #include "net_internal.h"
 #include "project.h"
@@ -245,7 +246,7 @@ void launch_resid_restrict(const mpp_op_s* op, int l, Faces<T> F, const T* rhs, 
 const char* kKernelNames[kKernelIds] = {
     "apply_dot", "residual", "smooth_colour", "resid_restrict", "prolong_add",  "dot",
     "update_p",  "update_xr", "coarse_vcycle", "apply",        "rb_sweep_zero", "rb_sweep",
-    "rb_sweep_prolong"};
+    "rb_sweep_prolong", "heat_apply", "heat_residual", "heat_jacobi"};
 
 hipEvent_t prof_event(Prof& P) {
   if (P.used == P.pool.size()) {
@@ -300,6 +301,9 @@ double alg_bytes(const mpp_op_s* op, int kid, size_t S) {
     case K_RB_ZERO: return cells * (2 * s + 1);                   // b, code, out
     case K_RB: return cells * (3 * s + 1);                        // x_in, b, code, out
     case K_RB_PROLONG: return cells * (3 * s + s / 8 + 1);        // + coarse correction
+    case K_HEAT_APPLY: return cells * (2 * s + 1);                // p, q, code
+    case K_HEAT_RESIDUAL: return cells * (3 * s + 1);             // b, x, r, code
+    case K_HEAT_JACOBI: return cells * (2 * s + 1);               // r, z, code
     default: return 0.0;
   }
 }
@@ -727,6 +731,96 @@ int status_of(hipError_t e) {
   return MPP_EDEVICE;
 }
 
+// ------------------------------------------------------------------------------
+// implicit heat diffusion: CG on (dt A - I) with the inverse diagonal as the
+// preconditioner, on the operator's finest-level faces
+// ------------------------------------------------------------------------------
+dim3 heat_grid(const mpp_op_s* op, StTiles& tl) {
+  tl = st_tiles(op->lev[0].n, kStKZ);
+  return dim3(st_grid(tl), op->batch);
+}
+
+int heat_apply(mpp_op_s* op, const double* p, double* q, const Ctl& ctl, hipStream_t s) {
+  StTiles tl;
+  const dim3 grid = heat_grid(op, tl);
+  timed(op, K_HEAT_APPLY, alg_bytes(op, K_HEAT_APPLY, 8), s, [&] {
+    hipLaunchKernelGGL(k_heat_z<0>, grid, dim3(kStThreads), 0, s, faces_of<double>(op, 0),
+                       op->lev[0].n, tl, kStKZ, p, (const double*)nullptr, q, ctl, ctl.active);
+  });
+  ck_launch();
+  return (int)grid.x;
+}
+
+int heat_residual(mpp_op_s* op, const double* b, const double* x, double* r, const Ctl& ctl,
+                  hipStream_t s) {
+  StTiles tl;
+  const dim3 grid = heat_grid(op, tl);
+  timed(op, K_HEAT_RESIDUAL, alg_bytes(op, K_HEAT_RESIDUAL, 8), s, [&] {
+    hipLaunchKernelGGL(k_heat_z<1>, grid, dim3(kStThreads), 0, s, faces_of<double>(op, 0),
+                       op->lev[0].n, tl, kStKZ, x, b, r, ctl, (const int*)nullptr);
+  });
+  ck_launch();
+  return (int)grid.x;
+}
+
+int heat_jacobi(mpp_op_s* op, const double* r, double* z, const Ctl& ctl, hipStream_t s) {
+  StTiles tl;
+  const dim3 grid = heat_grid(op, tl);
+  timed(op, K_HEAT_JACOBI, alg_bytes(op, K_HEAT_JACOBI, 8), s, [&] {
+    hipLaunchKernelGGL(k_heat_jacobi, grid, dim3(kStThreads), 0, s, faces_of<double>(op, 0),
+                       op->lev[0].n, tl, kStKZ, r, z, ctl, ctl.active);
+  });
+  ck_launch();
+  return (int)grid.x;
+}
+
+void heat_iterations(mpp_op_s* op, Ctl& ctl, double* x, int iters, hipStream_t s) {
+  const Level& L0 = op->lev[0];
+  const dim3 g = grid_of(L0, op->batch);
+  const int cells = (int)L0.cells;
+  const EpiArgs erz = epi(E_RZ), epq = epi(E_PQ), err = epi(E_RR_ITER);
+  for (int it = 0; it < iters; ++it) {
+    finish_sums(op, ctl, epq, heat_apply(op, op->p, op->q, ctl, s), s);
+    timed(op, K_UPDATE_XR, alg_bytes(op, K_UPDATE_XR, 8), s, [&] {
+      hipLaunchKernelGGL(k_update_xr<double>, g, dim3(kBlock), 0, s, x, op->r, op->p, op->q,
+                         cells, ctl, err);
+    });
+    ck_launch();
+    finish_sums(op, ctl, err, L0.bpp, s);
+    finish_sums(op, ctl, erz, heat_jacobi(op, op->r, op->z, ctl, s), s);
+    timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, 8), s, [&] {
+      hipLaunchKernelGGL(k_update_p<double>, g, dim3(kBlock), 0, s, op->z, op->p, cells, ctl, 0);
+    });
+    ck_launch();
+  }
+}
+
+// CG from the true residual of x until every problem has converged, broken down or
+// used ctl.max_iter iterations
+void heat_pcg(mpp_op_s* op, Ctl& ctl, double* x, int check_every, hipStream_t s) {
+  const Level& L0 = op->lev[0];
+  const dim3 g = grid_of(L0, op->batch);
+  const int cells = (int)L0.cells;
+  finish_sums(op, ctl, epi(E_START), heat_residual(op, op->b, x, op->r, ctl, s), s);
+  if (!any_active(op, ctl, s)) return;
+  EpiArgs erz = epi(E_RZ);
+  erz.first = 1;
+  finish_sums(op, ctl, erz, heat_jacobi(op, op->r, op->z, ctl, s), s);
+  hipLaunchKernelGGL(k_update_p<double>, g, dim3(kBlock), 0, s, op->z, op->p, cells, ctl, 1);
+  ck_launch();
+  // nu = 0 marks these graphs apart from the pressure solve's (nu >= 1)
+  const bool graphs = op->use_graphs && !op->prof.on;
+  const GraphKey key{8, 0, 0, check_every, ctl.max_iter,
+                     {(const void*)ctl.scal, x, op->r, op->z, op->p, op->q}};
+  for (int done = 0; done < ctl.max_iter; done += check_every) {
+    if (graphs)
+      run_graph(op, key, s, [&](hipStream_t cs) { heat_iterations(op, ctl, x, check_every, cs); });
+    else
+      heat_iterations(op, ctl, x, check_every, s);
+    if (!any_active(op, ctl, s)) return;
+  }
+}
+
 }  // namespace
 
 // ==============================================================================
@@ -1118,6 +1212,70 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
     if (istatus[b] == MPP_EBREAKDOWN) in.status = MPP_EBREAKDOWN;
     if (!std::isfinite(sc[S_BB])) in.status = MPP_EINVAL;   // non-finite f
     else if (in.status == MPP_OK && !(in.rel_resid <= o.rtol)) in.status = MPP_ENOTCONVERGED;
+    worst = worse(worst, in.status);
+  }
+  return worst;
+}
+
+int mpp_heat_solve(mpp_op op, const double* t_old, const double* src, double dt, double* t,
+                   const mpp_solve_opts* opts, mpp_solve_info* info, void* stream) {
+  if (!op || !t_old || !t || !opts || !info || src == t) return MPP_EINVAL;
+  const mpp_solve_opts& o = *opts;
+  if (!(dt >= 0.0) || !std::isfinite(dt) || !(o.rtol > 0.0) || o.max_iter < 1 ||
+      o.check_every < 1 || (o.guess != MPP_GUESS_ZERO && o.guess != MPP_GUESS_GIVEN))
+    return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int B = op->batch;
+  const Level& L0 = op->lev[0];
+  const dim3 g = grid_of(L0, B);
+  const int cells = (int)L0.cells;
+  int restarts = 0;
+  try {
+    Ctl& oc = op->outer;
+    reset_ctl(op, oc, o.max_iter, s);
+    hipLaunchKernelGGL(k_heat_set_dt, dim3((B + 255) / 256), dim3(256), 0, s, oc.scal, B, dt);
+    ck_launch();
+    // the right-hand side first: t may be t_old
+    hipLaunchKernelGGL(k_heat_rhs, g, dim3(kBlock), 0, s, t_old, src, op->b, cells, oc);
+    ck_launch();
+    EpiArgs eb = epi(E_BB);
+    eb.rtol2 = o.rtol * o.rtol;
+    finish_sums(op, oc, eb, L0.bpp, s);
+    double* const x = op->x;
+    if (o.guess == MPP_GUESS_ZERO) {
+      hipLaunchKernelGGL(k_fill<double>, g, dim3(kBlock), 0, s, x, cells, 0.0);
+      ck_launch();
+    } else {
+      ck(hipMemcpyAsync(x, t, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
+    }
+    for (; restarts < 4; ++restarts) {
+      heat_pcg(op, oc, x, o.check_every, s);
+      // true residual; re-arms the problems that are not there yet
+      finish_sums(op, oc, epi(E_START), heat_residual(op, op->b, x, op->r, oc, s), s);
+      if (!any_active(op, oc, s)) break;
+    }
+    ck(hipMemcpyAsync(t, x, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
+    ck(hipMemcpyAsync(op->h_scal, oc.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
+    ck(hipMemcpyAsync(op->h_status, oc.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    ck(hipMemcpyAsync(op->h_iters, oc.iters, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    ck(hipStreamSynchronize(s));
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  int worst = MPP_OK;
+  for (int b = 0; b < B; ++b) {
+    const double* sc = op->h_scal + (size_t)b * kSlots;
+    mpp_solve_info& in = info[b];
+    in.status = op->h_status[b];
+    in.iters = op->h_iters[b];
+    in.outer_iters = std::min(restarts, 3) + 1;
+    in.reserved = 0;
+    in.bnorm = std::sqrt(sc[S_BB]);
+    in.removed_mean = 0.0;
+    in.rel_resid = sc[S_BB] > 0.0 ? std::sqrt(sc[S_RR] / sc[S_BB]) : std::sqrt(sc[S_RR]);
+    if (!std::isfinite(sc[S_BB])) in.status = MPP_EINVAL;   // non-finite input
+    else if (in.status == MPP_OK && !(in.rel_resid <= o.rtol) && sc[S_BB] > 0.0)
+      in.status = MPP_ENOTCONVERGED;
     worst = worse(worst, in.status);
   }
   return worst;

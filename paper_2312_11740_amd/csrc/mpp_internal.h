@@ -27,6 +27,8 @@ enum Slot {
   S_ALPHA,      // rz / pq
   S_SCALE,      // mixed mode: ||r|| of the outer residual that scaled the inner rhs
   S_SUM,        // scratch sum (means)
+  S_DT,         // heat diffusion: the time step (read by the kernels, so captured
+                //   iteration graphs stay valid for any dt)
   kSlots = 16
 };
 
@@ -87,6 +89,9 @@ enum KernelId {
   K_RB_ZERO,         // fused red-black sweep from a zero iterate (finest level)
   K_RB,              // fused red-black sweep
   K_RB_PROLONG,      // fused red-black sweep after adding the coarse correction
+  K_HEAT_APPLY,      // q = (dt A - I) p and p.q
+  K_HEAT_RESIDUAL,   // r = b - (dt A - I) x and ||r||^2
+  K_HEAT_JACOBI,     // z = r / diag and r.z
   kKernelIds
 };
 

@@ -99,3 +99,26 @@ def test_level_set_calls_reject_bad_arguments_before_device_work():
     assert L.mpp_ls_reinit(8, 1, a, a, c, 3, 0.1, None) == M.EINVAL       # phi0 aliases phi
     assert L.mpp_ls_reinit(8, 1, a, b, b, 3, 0.1, None) == M.EINVAL       # work aliases phi
     assert L.mpp_ls_reinit(2048, 1, a, b, c, 3, 0.1, None) == M.EINVAL    # n too large
+
+
+def test_heat_solve_rejects_bad_arguments_before_device_work():
+    L = M.load_library()
+    op, a, b = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3))   # never dereferenced
+    opts = M.SolveOpts()
+    L.mpp_default_opts(ctypes.byref(opts))
+    info = (M.SolveInfo * 1)()
+    assert L.mpp_heat_solve(None, a, None, 0.1, b, ctypes.byref(opts), info, None) == M.EINVAL
+    assert L.mpp_heat_solve(op, None, None, 0.1, b, ctypes.byref(opts), info, None) == M.EINVAL
+    assert L.mpp_heat_solve(op, a, None, 0.1, None, ctypes.byref(opts), info, None) == M.EINVAL
+    assert L.mpp_heat_solve(op, a, b, 0.1, b, ctypes.byref(opts), info, None) == M.EINVAL  # src = t
+    assert L.mpp_heat_solve(op, a, None, -1.0, b, ctypes.byref(opts), info, None) == M.EINVAL
+    assert L.mpp_heat_solve(op, a, None, float("nan"), b, ctypes.byref(opts), info,
+                            None) == M.EINVAL
+    assert L.mpp_heat_solve(op, a, None, float("inf"), b, ctypes.byref(opts), info,
+                            None) == M.EINVAL
+    assert L.mpp_heat_solve(op, a, None, 0.1, b, None, info, None) == M.EINVAL
+    opts.rtol = 0.0
+    assert L.mpp_heat_solve(op, a, None, 0.1, b, ctypes.byref(opts), info, None) == M.EINVAL
+    L.mpp_default_opts(ctypes.byref(opts))
+    opts.check_every = 0
+    assert L.mpp_heat_solve(op, a, None, 0.1, b, ctypes.byref(opts), info, None) == M.EINVAL
