@@ -250,14 +250,19 @@ int mpp_ls_reinit(int n, int batch, const double *phi0, double *phi, double *wor
 /* t_old, t: device [batch][n^3]; src: device [batch][n^3] or NULL (no source).  t
  * holds the initial guess when opts->guess is MPP_GUESS_GIVEN (ignored with
  * MPP_GUESS_ZERO) and receives T; t may be t_old, src may not be t.  dt >= 0 and
- * finite.  Solved by conjugate gradients on (dt A - I) T = -(T_old + dt f) with the
- * inverse diagonal as preconditioner, to ||b - H T|| <= opts->rtol ||b|| in FP64
- * (H = I - dt div(K grad), b = T_old + dt f); of opts only rtol, max_iter,
- * check_every and guess are used.  The true residual is checked at the end and CG
- * restarted from it (up to 4 runs).  info[batch] as for mpp_solve (removed_mean 0,
- * outer_iters = CG runs).  The matrix's condition number is about 1 + 12 dt K_max /
- * h^2, so the iterations grow as the square root of that.  Synchronous with respect to
- * the host.  Returns the worst status of the batch. */
+ * finite.  Solved to ||b - H T|| <= opts->rtol ||b|| in FP64 (H = I - dt div(K grad),
+ * b = T_old + dt f), with the true residual checked at the end.  opts->nu selects the
+ * preconditioner:
+ *   nu >= 1: the pressure solve's MG-PCG (opts->mode FP64 or MIXED, nu sweeps, the
+ *            other options as for mpp_solve) on (A - I/dt) T = -(T_old + dt f)/dt,
+ *            every level carrying its diagonal shift (1/dt, halved per coarser level);
+ *   nu == 0: CG on (dt A - I) T = -(T_old + dt f) with the inverse diagonal (FP64;
+ *            rtol, max_iter, check_every and guess are used); its iterations grow as
+ *            the square root of 1 + 12 dt K_max / h^2.
+ * dt == 0 gives T = T_old exactly (one iteration of the diagonal form).  info[batch] as
+ * for mpp_solve (removed_mean 0).  Solves on the same operator may alternate with
+ * pressure solves: the shift and the coarsest inverse follow the call.  Synchronous with
+ * respect to the host.  Returns the worst status of the batch. */
 int mpp_heat_solve(mpp_op op, const double *t_old, const double *src, double dt, double *t,
                    const mpp_solve_opts *opts, mpp_solve_info *info, void *stream);
 

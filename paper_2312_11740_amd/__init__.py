@@ -314,18 +314,23 @@ class Operator:
             raise MppError(st, "mpp_solve")
         return p, out
 
-    def heat_solve(self, t_old, dt, src=None, t=None, rtol=1e-10, max_iter=2000,
-                   check_every=4, raise_on_error=True):
+    def heat_solve(self, t_old, dt, src=None, t=None, rtol=1e-10, precond="mg", mode="fp64",
+                   nu=2, max_iter=2000, check_every=2, inner_rtol=1e-5, raise_on_error=True):
         """One backward-Euler diffusion step (I - dt div(K grad)) T = t_old + dt src on
         this operator's face coefficients, read as conductivities K (build the operator
-        with rho_neg = 1/K_neg, rho_pos = 1/K_pos; sigma plays no part).  t: optional
-        initial guess, overwritten with T (may be t_old).  Returns (T, [Info])."""
+        with rho_neg = 1/K_neg, rho_pos = 1/K_pos; sigma plays no part).  precond "mg":
+        the pressure solve's MG-PCG on the shifted operator (mode "fp64" or "mixed");
+        "jacobi": CG with the inverse diagonal (FP64).  t: optional initial guess,
+        overwritten with T (may be t_old).  Returns (T, [Info])."""
         _check_field(t_old, self.shape, "t_old")
         if src is not None:
             _check_field(src, self.shape, "src")
         opts = SolveOpts()
         load_library().mpp_default_opts(ctypes.byref(opts))
         opts.rtol, opts.max_iter, opts.check_every = float(rtol), int(max_iter), int(check_every)
+        opts.nu = {"mg": int(nu), "jacobi": 0}[precond]
+        opts.mode = {"fp64": MODE_FP64, "mixed": MODE_MIXED}[mode]
+        opts.inner_rtol = float(inner_rtol)
         if t is None:
             t = self._new()
             opts.guess = GUESS_ZERO

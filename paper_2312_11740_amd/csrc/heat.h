@@ -1,4 +1,4 @@
-// Implicit heat diffusion on the finest level: one backward-Euler step of the
+// Implicit heat diffusion: one backward-Euler step of the
 // diffusion term of the transport equation (Sec. 2) with a coefficient that changes
 // with the phase (the varDiffusion configuration of HeatAD, Sec. 3),
 //
@@ -7,10 +7,11 @@
 // K is read from an operator's face coefficients: built from the level set with
 // rho = 1/K of each phase, they hold K of the cell's phase on uncrossed faces and the
 // two conductivities in series on crossed ones.  The system is solved as
-// (dt A - I) T = -(T_old + dt f), A = div(K grad) as in the pressure operator, so the
-// matrix is negative definite like the pressure one and the CG bookkeeping of the
-// pressure solve (r.z < 0, p.q < 0, the same epilogues and vector updates) applies
-// unchanged; the preconditioner is the inverse diagonal.
+// (A - I/dt) T = -(T_old + dt f)/dt, A = div(K grad) as in the pressure operator: the
+// matrix is negative definite like the pressure one, and the pressure solve's MG-PCG
+// runs on it unchanged once every level carries its diagonal shift (the kernels' sig).
+// The kernels below serve the other preconditioner, the inverse diagonal, which solves
+// (dt A - I) T = -(T_old + dt f) with the same CG bookkeeping (r.z < 0, p.q < 0).
 #pragma once
 
 #include "stencil.h"
@@ -22,9 +23,9 @@ __global__ void k_heat_set_dt(double* scal, int B, double dt) {
   if (b < B) scal[(size_t)b * kSlots + S_DT] = dt;
 }
 
-// b = -(t_old + dt src) (src may be null) with ||b||^2 block partials
+// b = -(t_old + dt src) scale (src may be null) with ||b||^2 block partials
 __global__ void k_heat_rhs(const double* __restrict__ t_old, const double* __restrict__ src,
-                           double* __restrict__ b, int cells, Ctl ctl) {
+                           double scale, double* __restrict__ b, int cells, Ctl ctl) {
   const int pb = blockIdx.y;
   const size_t base = (size_t)pb * cells;
   const double dt = ctl.scal[(size_t)pb * kSlots + S_DT];
@@ -32,7 +33,7 @@ __global__ void k_heat_rhs(const double* __restrict__ t_old, const double* __res
   CELL_LOOP(cells) {
     double v = t_old[base + c];
     if (src) v = v + dt * src[base + c];
-    v = -v;
+    v = -v * scale;
     b[base + c] = v;
     acc += v * v;
   }
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(kStThreads)
                        (B.cd[h] & 64u) ? ir1 : ir0, w);
         const double xc = B.xc[h + 1];
         const double ax = stencil7(w, xc, B.w[h], B.e[h], B.s[h], B.nb[h], B.xc[h],
-                                   B.xc[h + 2], i, j, k, n, inv_h2);
+                                   B.xc[h + 2], i, j, k, n, inv_h2, 0.0);
         const double hx = dt * ax - xc;
         double out;
         if (KIND == 0) {

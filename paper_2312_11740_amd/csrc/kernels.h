@@ -187,10 +187,10 @@ __device__ inline void cell_faces(const Faces<T>& F, int b, size_t base, int c, 
   }
 }
 
-// (A x)_c = sum_f w_f (x_nb - x_c) / h^2
+// ((A - sig I) x)_c = sum_f w_f (x_nb - x_c) / h^2 - sig x_c
 template <typename T>
 __device__ inline T stencil_at(const T w[6], const T* x, size_t base, int c, int i, int j, int k,
-                               int n, T inv_h2) {
+                               int n, T inv_h2, T sig) {
   const size_t nn = (size_t)n * n;
   const T xc = x[base + c];
   T s = T(0);
@@ -200,7 +200,7 @@ __device__ inline T stencil_at(const T w[6], const T* x, size_t base, int c, int
   if (j < n - 1) s += w[3] * (x[base + c + n] - xc);
   if (k > 0) s += w[4] * (x[base + c - nn] - xc);
   if (k < n - 1) s += w[5] * (x[base + c + nn] - xc);
-  return s * inv_h2;
+  return s * inv_h2 - sig * xc;
 }
 
 #define CELL_LOOP(cells)                                                     \
@@ -403,12 +403,14 @@ __global__ void k_coarsen_faces(const double* __restrict__ fx, const double* __r
   }
 }
 
-// Coarsest level: dense M = -A + 11^T/m and its inverse.  One block per problem; up to
-// 64 cells by Gauss-Jordan elimination in LDS, above that by a Cholesky factor M = L L^T
-// in the [B][m][m] scratch `work` and M^{-1} column by column.
+// Coarsest level: dense M = -A + 11^T/m (sig == 0: the singular pressure operator,
+// regularised on the constants) or M = -A + sig I (a shifted operator, already definite),
+// and its inverse.  One block per problem; up to 64 cells by Gauss-Jordan elimination in
+// LDS, above that by a Cholesky factor M = L L^T in the [B][m][m] scratch `work` and
+// M^{-1} column by column.
 __global__ void __launch_bounds__(1024) k_coarse_factor(const double* __restrict__ cx, const double* __restrict__ cy,
-                                const double* __restrict__ cz, int n, double* __restrict__ work,
-                                double* __restrict__ inv) {
+                                const double* __restrict__ cz, int n, double sig,
+                                double* __restrict__ work, double* __restrict__ inv) {
   const int b = blockIdx.x;
   const int m = n * n * n;
   const size_t bm = (size_t)b * m * m, bc = (size_t)b * m;
@@ -418,7 +420,7 @@ __global__ void __launch_bounds__(1024) k_coarse_factor(const double* __restrict
   const bool lds = m <= kLdsM;
   double* M = lds ? Ms : work + bm;
   double* X = lds ? Xs : inv + bm;
-  const double inv_h2 = (double)n * (double)n, jm = 1.0 / m;
+  const double inv_h2 = (double)n * (double)n, jm = sig == 0.0 ? 1.0 / m : 0.0;
   for (size_t q = threadIdx.x; q < (size_t)m * m; q += blockDim.x) M[q] = jm;
   __syncthreads();
   for (int c = threadIdx.x; c < m; c += blockDim.x) {
@@ -435,7 +437,7 @@ __global__ void __launch_bounds__(1024) k_coarse_factor(const double* __restrict
         M[(size_t)c * m + nb[f]] -= w * inv_h2;
         d += w;
       }
-    M[(size_t)c * m + c] += d * inv_h2;
+    M[(size_t)c * m + c] += d * inv_h2 + sig;
   }
   __syncthreads();
   if (lds) {
@@ -634,6 +636,7 @@ struct SmallLevel {
   const T* bz;
   T* b;
   T* x;
+  T sig;   // diagonal shift of the level (operator A - sig I)
 };
 
 template <typename T>
@@ -683,7 +686,7 @@ __device__ void small_smooth(const SmallLevel<T>& L, size_t base, int colour, in
       if (k > 0) num += w[4] * L.x[base + c - nn];
       if (k < n - 1) num += w[5] * L.x[base + c + nn];
     }
-    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
+    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5] + L.sig * h2;
     L.x[base + c] = (num - h2 * L.b[base + c]) / den;
   }
   __syncthreads();
@@ -705,7 +708,7 @@ __device__ void small_resid_restrict(const SmallLevel<T>& F, size_t basef, const
           const int cf = i + nf * (j + nf * k);
           T w[6];
           small_faces(F, basef, cf, i, j, k, w);
-          s += F.b[basef + cf] - stencil_at(w, F.x, basef, cf, i, j, k, nf, inv_h2);
+          s += F.b[basef + cf] - stencil_at(w, F.x, basef, cf, i, j, k, nf, inv_h2, F.sig);
         }
     C.b[basec + c] = s * T(0.125);
   }

@@ -160,15 +160,22 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
 template <typename T>
 Faces<T> faces_of(const mpp_op_s* op, int l);
 
+// The shift halves per coarser level: with mean restriction and piecewise-constant
+// prolongation the coarse operator (faces = means of the fine ones at twice the spacing)
+// is half the Galerkin product, and the Galerkin product keeps a shift unchanged.
+inline double level_shift(const mpp_op_s* op, int l) { return std::ldexp(op->shift, -l); }
+
 template <>
 Faces<double> faces_of<double>(const mpp_op_s* op, int l) {
   const Level& lv = op->lev[l];
-  return Faces<double>{l == 0 ? lv.code : nullptr, lv.f64[0], lv.f64[1], lv.f64[2], op->inv_rho64};
+  return Faces<double>{l == 0 ? lv.code : nullptr, lv.f64[0], lv.f64[1], lv.f64[2], op->inv_rho64,
+                       level_shift(op, l)};
 }
 template <>
 Faces<float> faces_of<float>(const mpp_op_s* op, int l) {
   const Level& lv = op->lev[l];
-  return Faces<float>{l == 0 ? lv.code : nullptr, lv.f32[0], lv.f32[1], lv.f32[2], op->inv_rho32};
+  return Faces<float>{l == 0 ? lv.code : nullptr, lv.f32[0], lv.f32[1], lv.f32[2], op->inv_rho32,
+                      (float)level_shift(op, l)};
 }
 
 template <typename T> T* lvl_b(Level& L);
@@ -429,7 +436,8 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
   for (int q = 0; q < S.nlev; ++q) {
     Level& Lq = op->lev[l + q];
     S.lv[q] = SmallLevel<T>{Lq.n, lvl_f<T>(Lq, 0), lvl_f<T>(Lq, 1), lvl_f<T>(Lq, 2),
-                            q == 0 ? const_cast<T*>(rhs) : lvl_b<T>(Lq), q == 0 ? x : lvl_x<T>(Lq)};
+                            q == 0 ? const_cast<T*>(rhs) : lvl_b<T>(Lq), q == 0 ? x : lvl_x<T>(Lq),
+                            (T)level_shift(op, l + q)};
   }
   S.inv = op->coarse_inv;
   S.m = op->coarse_m;
@@ -658,7 +666,7 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
   // problem once it has converged, so a block may overrun the last useful iteration
   const bool graphs = op->use_graphs && !op->prof.on;
   const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter,
-                     {(const void*)ctl.scal, x, r, z, p, q}};
+                     {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
   for (int done = 0; done <= ctl.max_iter; done += check_every) {
     if (graphs)
       run_graph(op, key, s, [&](hipStream_t cs) {
@@ -862,6 +870,141 @@ const char* mpp_strerror(int st) {
 
 namespace {
 
+// Dense inverse of the coarsest level for the current shift.
+void factor_coarsest(mpp_op_s* op, hipStream_t s) {
+  const Level& Lc = op->lev[op->nlev - 1];
+  const double sc = level_shift(op, op->nlev - 1);
+  hipLaunchKernelGGL(k_coarse_factor, dim3(op->batch), dim3(1024), 0, s, Lc.f64[0], Lc.f64[1],
+                     Lc.f64[2], Lc.n, sc, op->coarse_work, op->coarse_inv);
+  ck_launch();
+  op->coarse_shift = sc;
+}
+
+// Makes A - shift I (on the finest level; halved per coarser level) the operator every
+// kernel applies; the coarsest inverse is rebuilt when its shift changes.
+void use_shift(mpp_op_s* op, double shift, hipStream_t s) {
+  op->shift = shift;
+  if (level_shift(op, op->nlev - 1) != op->coarse_shift) factor_coarsest(op, s);
+}
+
+bool opts_valid(const mpp_solve_opts& o) {
+  if (!(o.rtol > 0.0) || o.max_iter < 1 || o.nu < 1 || o.check_every < 1 || o.nu_coarse < 0 ||
+      (o.mode != MPP_MODE_FP64 && o.mode != MPP_MODE_MIXED) ||
+      (o.guess != MPP_GUESS_ZERO && o.guess != MPP_GUESS_GIVEN))
+    return false;
+  if (o.mode == MPP_MODE_MIXED && !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0)) return false;
+  return true;
+}
+
+// MG-PCG on op->b (S_BB and S_TOL2 of op->outer set) from the caller's p or from zero,
+// in FP64 or as FP64 refinement around FP32 MG-PCG; the iterate ends in op->x.
+void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
+                std::vector<int>& outer_count, std::vector<int>& istatus, hipStream_t s) {
+  const int B = op->batch;
+  const Level& L0 = op->lev[0];
+  const dim3 g = grid_of(L0, B);
+  const int cells = (int)L0.cells;
+  ensure_tuned<double>(op, s);
+  if (o.mode == MPP_MODE_MIXED) ensure_tuned<float>(op, s);
+  op->nu_c = o.nu_coarse > 0 ? o.nu_coarse : o.nu;
+  Ctl& oc = op->outer;
+  // the iterate lives in the workspace (captured launch graphs refer to it); the
+  // caller's p is copied in and out
+  double* const p = op->x;
+  if (o.guess == MPP_GUESS_ZERO) {
+    hipLaunchKernelGGL(k_fill<double>, g, dim3(kBlock), 0, s, p, cells, 0.0);
+    ck_launch();
+  } else {
+    ck(hipMemcpyAsync(p, user_p, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
+  }
+  EpiArgs start = epi(E_START);
+  if (o.mode == MPP_MODE_FP64) {
+    for (int restart = 0; restart < 4; ++restart) {
+      pcg<double>(op, oc, op->b, p, op->r, op->z, op->p, op->q, o.nu, o.check_every, 0, start, s);
+      // true residual; re-arms the problems that are not there yet
+      finish_sums(op, oc, start,
+                  launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
+      ck_launch();
+      for (int b = 0; b < B; ++b) outer_count[b] += 1;
+      if (!any_active(op, oc, s)) break;
+    }
+    return;
+  }
+  Ctl& ic = op->inner;
+  reset_ctl(op, ic, o.max_iter, s);
+  EpiArgs istart = epi(E_START_REL);
+  istart.rtol2 = o.inner_rtol * o.inner_rtol;
+  istart.gate = oc.active;
+  istart.outer_scal = oc.scal;
+  istart.outer_rtol = o.rtol;
+  bool settled = false, converged = false;
+  for (int outer = 0; outer < 40 && !settled; ++outer) {
+    finish_sums(op, oc, start,
+                launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
+    ck_launch();
+    if (!any_active(op, oc, s)) {
+      settled = converged = true;
+      break;
+    }
+    for (int b = 0; b < B; ++b) outer_count[b] += op->h_active[b];
+    hipLaunchKernelGGL(k_scale_down, g, dim3(kBlock), 0, s, op->r, op->r32, cells, oc.scal,
+                       oc.active);
+    ck_launch();
+    hipLaunchKernelGGL(k_fill<float>, g, dim3(kBlock), 0, s, op->d32, cells, 0.0f);
+    ck_launch();
+    pcg<float>(op, ic, op->r32, op->d32, op->r32, op->z32, op->p32, op->q32, o.nu,
+               o.check_every, 1, istart, s);
+    hipLaunchKernelGGL(k_correct, g, dim3(kBlock), 0, s, p, op->d32, cells, oc.scal, oc.active);
+    ck_launch();
+    // an inner breakdown or an exhausted iteration budget ends the refinement
+    ck(hipMemcpyAsync(op->h_status, ic.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    ck(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b)
+      if (op->h_status[b] != MPP_OK) settled = true;
+  }
+  if (!converged) {   // true residual of the returned iterate
+    finish_sums(op, oc, start,
+                launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
+    ck_launch();
+  }
+  ck(hipMemcpyAsync(istatus.data(), ic.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+}
+
+// op->x to the caller and the scalars, statuses and iteration counts to the host
+// (inner: the iteration counts are those of the FP32 inner solves)
+void finish_solve(mpp_op_s* op, bool inner, double* user_p, hipStream_t s) {
+  const int B = op->batch;
+  Ctl& oc = op->outer;
+  ck(hipMemcpyAsync(user_p, op->x, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
+  ck(hipMemcpyAsync(op->h_scal, oc.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
+  ck(hipMemcpyAsync(op->h_status, oc.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+  ck(hipMemcpyAsync(op->h_iters, inner ? op->inner.iters : oc.iters, sizeof(int) * B,
+                    hipMemcpyDeviceToHost, s));
+  ck(hipMemcpyAsync(op->h_active, oc.active, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+  ck(hipStreamSynchronize(s));
+}
+
+int fill_info(mpp_op_s* op, const mpp_solve_opts& o, const std::vector<int>& outer_count,
+              const std::vector<int>& istatus, mpp_solve_info* info) {
+  int worst = MPP_OK;
+  for (int b = 0; b < op->batch; ++b) {
+    const double* sc = op->h_scal + (size_t)b * kSlots;
+    mpp_solve_info& in = info[b];
+    in.status = op->h_status[b];
+    in.iters = op->h_iters[b];
+    in.outer_iters = outer_count[b];
+    in.reserved = 0;
+    in.bnorm = std::sqrt(sc[S_BB]);
+    in.removed_mean = sc[S_MEAN];
+    in.rel_resid = sc[S_BB] > 0.0 ? std::sqrt(sc[S_RR] / sc[S_BB]) : 0.0;
+    if (istatus[b] == MPP_EBREAKDOWN) in.status = MPP_EBREAKDOWN;
+    if (!std::isfinite(sc[S_BB])) in.status = MPP_EINVAL;   // non-finite input
+    else if (in.status == MPP_OK && !(in.rel_resid <= o.rtol)) in.status = MPP_ENOTCONVERGED;
+    worst = worse(worst, in.status);
+  }
+  return worst;
+}
+
 // Validates the per-problem constants into a host array [B][3].
 bool read_params(int B, const double* rho_neg, const double* rho_pos, const double* sigma,
                  std::vector<double>& host) {
@@ -908,10 +1051,7 @@ int build_into(mpp_op_s* op, const double* phi, const std::vector<double>& host,
                        Lc.f32[2]);
     ck_launch();
   }
-  const Level& Lc = op->lev[op->nlev - 1];
-  hipLaunchKernelGGL(k_coarse_factor, dim3(B), dim3(1024), 0, s, Lc.f64[0], Lc.f64[1],
-                     Lc.f64[2], Lc.n, op->coarse_work, op->coarse_inv);
-  ck_launch();
+  factor_coarsest(op, s);
   ck(hipMemcpyAsync(op->h_status, op->outer.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
   ck(hipStreamSynchronize(s));
   for (int b = 0; b < B; ++b)
@@ -1045,6 +1185,7 @@ int mpp_apply_stencil(mpp_op op, const double* x, double* y, void* stream) {
   if (!op || !x || !y || x == y) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   try {
+    use_shift(op, 0.0, s);
     timed(op, K_APPLY, alg_bytes(op, K_APPLY, sizeof(double)), s, [&] {
       launch_apply<double>(op, faces_of<double>(op, 0), x, y, op->outer, 0, nullptr, s);
     });
@@ -1076,6 +1217,7 @@ int mpp_vcycle(mpp_op op, const double* r, double* z, int nu, void* stream) {
   if (!op || !r || !z || r == z || nu < 1) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   try {
+    use_shift(op, 0.0, s);
     ensure_tuned<double>(op, s);
     op->nu_c = nu;
     vcycle<double>(op, 0, r, z, nu, nullptr, s);
@@ -1105,12 +1247,39 @@ int mpp_operator_fields(mpp_op op, double* bx, double* by, double* bz, double* k
 int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
               mpp_solve_info* info, void* stream) {
   if (!op || !f || !p || !opts || !info || f == p) return MPP_EINVAL;
+  if (!opts_valid(*opts)) return MPP_EINVAL;
   const mpp_solve_opts& o = *opts;
-  if (!(o.rtol > 0.0) || o.max_iter < 1 || o.nu < 1 || o.check_every < 1 || o.nu_coarse < 0 ||
-      (o.mode != MPP_MODE_FP64 && o.mode != MPP_MODE_MIXED) ||
-      (o.guess != MPP_GUESS_ZERO && o.guess != MPP_GUESS_GIVEN))
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int B = op->batch;
+  std::vector<int> outer_count(B, 0);
+  std::vector<int> istatus(B, MPP_OK);
+  try {
+    use_shift(op, 0.0, s);
+    Ctl& oc = op->outer;
+    reset_ctl(op, oc, o.max_iter, s);
+    make_rhs(op, oc, f, op->b, s, o.rtol, true);
+    solve_core(op, o, p, outer_count, istatus, s);
+    remove_mean(op, oc, op->x, s);
+    finish_solve(op, o.mode == MPP_MODE_MIXED, p, s);
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return fill_info(op, o, outer_count, istatus, info);
+}
+
+int mpp_heat_solve(mpp_op op, const double* t_old, const double* src, double dt, double* t,
+                   const mpp_solve_opts* opts, mpp_solve_info* info, void* stream) {
+  if (!op || !t_old || !t || !opts || !info || src == t) return MPP_EINVAL;
+  const mpp_solve_opts& o = *opts;
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return MPP_EINVAL;
+  const bool jacobi = o.nu == 0;
+  if (jacobi) {
+    if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1 ||
+        (o.guess != MPP_GUESS_ZERO && o.guess != MPP_GUESS_GIVEN))
+      return MPP_EINVAL;
+  } else if (!opts_valid(o)) {
     return MPP_EINVAL;
-  if (o.mode == MPP_MODE_MIXED && !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0)) return MPP_EINVAL;
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int B = op->batch;
   const Level& L0 = op->lev[0];
@@ -1118,167 +1287,47 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
   const int cells = (int)L0.cells;
   std::vector<int> outer_count(B, 0);
   std::vector<int> istatus(B, MPP_OK);
-  try {
-    ensure_tuned<double>(op, s);
-    if (o.mode == MPP_MODE_MIXED) ensure_tuned<float>(op, s);
-    op->nu_c = o.nu_coarse > 0 ? o.nu_coarse : o.nu;
-    Ctl& oc = op->outer;
-    reset_ctl(op, oc, o.max_iter, s);
-    make_rhs(op, oc, f, op->b, s, o.rtol, true);
-    // the iterate lives in the workspace (captured launch graphs refer to it); the
-    // caller's p is copied in and out
-    double* const user_p = p;
-    p = op->x;
-    if (o.guess == MPP_GUESS_ZERO) {
-      hipLaunchKernelGGL(k_fill<double>, g, dim3(kBlock), 0, s, p, cells, 0.0);
-      ck_launch();
-    } else {
-      ck(hipMemcpyAsync(p, user_p, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
-    }
-    EpiArgs start = epi(E_START);
-    if (o.mode == MPP_MODE_FP64) {
-      for (int restart = 0; restart < 4; ++restart) {
-        pcg<double>(op, oc, op->b, p, op->r, op->z, op->p, op->q, o.nu, o.check_every, 0, start, s);
-        // true residual; re-arms the problems that are not there yet
-        finish_sums(op, oc, start,
-                    launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
-        ck_launch();
-        for (int b = 0; b < B; ++b) outer_count[b] += 1;
-        if (!any_active(op, oc, s)) break;
-      }
-    } else {
-      Ctl& ic = op->inner;
-      reset_ctl(op, ic, o.max_iter, s);
-      EpiArgs istart = epi(E_START_REL);
-      istart.rtol2 = o.inner_rtol * o.inner_rtol;
-      istart.gate = oc.active;
-      istart.outer_scal = oc.scal;
-      istart.outer_rtol = o.rtol;
-      bool settled = false, converged = false;
-      for (int outer = 0; outer < 40 && !settled; ++outer) {
-        finish_sums(op, oc, start,
-                    launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
-        ck_launch();
-        if (!any_active(op, oc, s)) {
-          settled = converged = true;
-          break;
-        }
-        for (int b = 0; b < B; ++b) outer_count[b] += op->h_active[b];
-        hipLaunchKernelGGL(k_scale_down, g, dim3(kBlock), 0, s, op->r, op->r32, cells, oc.scal,
-                           oc.active);
-        ck_launch();
-        hipLaunchKernelGGL(k_fill<float>, g, dim3(kBlock), 0, s, op->d32, cells, 0.0f);
-        ck_launch();
-        pcg<float>(op, ic, op->r32, op->d32, op->r32, op->z32, op->p32, op->q32, o.nu,
-                   o.check_every, 1, istart, s);
-        hipLaunchKernelGGL(k_correct, g, dim3(kBlock), 0, s, p, op->d32, cells, oc.scal, oc.active);
-        ck_launch();
-        // an inner breakdown or an exhausted iteration budget ends the refinement
-        ck(hipMemcpyAsync(op->h_status, ic.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-        ck(hipStreamSynchronize(s));
-        for (int b = 0; b < B; ++b)
-          if (op->h_status[b] != MPP_OK) settled = true;
-      }
-      if (!converged) {   // true residual of the returned iterate
-        finish_sums(op, oc, start,
-                    launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
-        ck_launch();
-      }
-    }
-    remove_mean(op, oc, p, s);
-    ck(hipMemcpyAsync(user_p, p, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
-    ck(hipMemcpyAsync(op->h_scal, oc.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
-    ck(hipMemcpyAsync(op->h_status, oc.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    ck(hipMemcpyAsync(op->h_iters, (o.mode == MPP_MODE_FP64 ? oc.iters : op->inner.iters),
-                      sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    ck(hipMemcpyAsync(op->h_active, oc.active, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    if (o.mode == MPP_MODE_MIXED)
-      ck(hipMemcpyAsync(istatus.data(), op->inner.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    ck(hipStreamSynchronize(s));
-  } catch (HipError& e) {
-    return status_of(e.e);
-  }
-  int worst = MPP_OK;
-  for (int b = 0; b < B; ++b) {
-    const double* sc = op->h_scal + (size_t)b * kSlots;
-    mpp_solve_info& in = info[b];
-    in.status = op->h_status[b];
-    in.iters = op->h_iters[b];
-    in.outer_iters = outer_count[b];
-    in.reserved = 0;
-    in.bnorm = std::sqrt(sc[S_BB]);
-    in.removed_mean = sc[S_MEAN];
-    in.rel_resid = sc[S_BB] > 0.0 ? std::sqrt(sc[S_RR] / sc[S_BB]) : 0.0;
-    if (istatus[b] == MPP_EBREAKDOWN) in.status = MPP_EBREAKDOWN;
-    if (!std::isfinite(sc[S_BB])) in.status = MPP_EINVAL;   // non-finite f
-    else if (in.status == MPP_OK && !(in.rel_resid <= o.rtol)) in.status = MPP_ENOTCONVERGED;
-    worst = worse(worst, in.status);
-  }
-  return worst;
-}
-
-int mpp_heat_solve(mpp_op op, const double* t_old, const double* src, double dt, double* t,
-                   const mpp_solve_opts* opts, mpp_solve_info* info, void* stream) {
-  if (!op || !t_old || !t || !opts || !info || src == t) return MPP_EINVAL;
-  const mpp_solve_opts& o = *opts;
-  if (!(dt >= 0.0) || !std::isfinite(dt) || !(o.rtol > 0.0) || o.max_iter < 1 ||
-      o.check_every < 1 || (o.guess != MPP_GUESS_ZERO && o.guess != MPP_GUESS_GIVEN))
-    return MPP_EINVAL;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int B = op->batch;
-  const Level& L0 = op->lev[0];
-  const dim3 g = grid_of(L0, B);
-  const int cells = (int)L0.cells;
-  int restarts = 0;
+  // multigrid solves (A - I/dt) T = -(T_old + dt f) / dt; dt = 0 (T = T_old) goes to the
+  // Jacobi form, which is exact there
+  const bool mg = !jacobi && dt > 0.0;
   try {
     Ctl& oc = op->outer;
     reset_ctl(op, oc, o.max_iter, s);
     hipLaunchKernelGGL(k_heat_set_dt, dim3((B + 255) / 256), dim3(256), 0, s, oc.scal, B, dt);
     ck_launch();
     // the right-hand side first: t may be t_old
-    hipLaunchKernelGGL(k_heat_rhs, g, dim3(kBlock), 0, s, t_old, src, op->b, cells, oc);
+    hipLaunchKernelGGL(k_heat_rhs, g, dim3(kBlock), 0, s, t_old, src, mg ? 1.0 / dt : 1.0, op->b,
+                       cells, oc);
     ck_launch();
     EpiArgs eb = epi(E_BB);
     eb.rtol2 = o.rtol * o.rtol;
     finish_sums(op, oc, eb, L0.bpp, s);
-    double* const x = op->x;
-    if (o.guess == MPP_GUESS_ZERO) {
-      hipLaunchKernelGGL(k_fill<double>, g, dim3(kBlock), 0, s, x, cells, 0.0);
-      ck_launch();
+    if (mg) {
+      use_shift(op, 1.0 / dt, s);
+      solve_core(op, o, t, outer_count, istatus, s);
     } else {
-      ck(hipMemcpyAsync(x, t, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
+      double* const x = op->x;
+      if (o.guess == MPP_GUESS_ZERO) {
+        hipLaunchKernelGGL(k_fill<double>, g, dim3(kBlock), 0, s, x, cells, 0.0);
+        ck_launch();
+      } else {
+        ck(hipMemcpyAsync(x, t, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
+      }
+      for (int restart = 0; restart < 4; ++restart) {
+        heat_pcg(op, oc, x, o.check_every, s);
+        // true residual; re-arms the problems that are not there yet
+        finish_sums(op, oc, epi(E_START), heat_residual(op, op->b, x, op->r, oc, s), s);
+        for (int b = 0; b < B; ++b) outer_count[b] += 1;
+        if (!any_active(op, oc, s)) break;
+      }
     }
-    for (; restarts < 4; ++restarts) {
-      heat_pcg(op, oc, x, o.check_every, s);
-      // true residual; re-arms the problems that are not there yet
-      finish_sums(op, oc, epi(E_START), heat_residual(op, op->b, x, op->r, oc, s), s);
-      if (!any_active(op, oc, s)) break;
-    }
-    ck(hipMemcpyAsync(t, x, sizeof(double) * op->cells * B, hipMemcpyDeviceToDevice, s));
-    ck(hipMemcpyAsync(op->h_scal, oc.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
-    ck(hipMemcpyAsync(op->h_status, oc.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    ck(hipMemcpyAsync(op->h_iters, oc.iters, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    ck(hipStreamSynchronize(s));
+    finish_solve(op, mg && o.mode == MPP_MODE_MIXED, t, s);
   } catch (HipError& e) {
     return status_of(e.e);
   }
-  int worst = MPP_OK;
-  for (int b = 0; b < B; ++b) {
-    const double* sc = op->h_scal + (size_t)b * kSlots;
-    mpp_solve_info& in = info[b];
-    in.status = op->h_status[b];
-    in.iters = op->h_iters[b];
-    in.outer_iters = std::min(restarts, 3) + 1;
-    in.reserved = 0;
-    in.bnorm = std::sqrt(sc[S_BB]);
-    in.removed_mean = 0.0;
-    in.rel_resid = sc[S_BB] > 0.0 ? std::sqrt(sc[S_RR] / sc[S_BB]) : std::sqrt(sc[S_RR]);
-    if (!std::isfinite(sc[S_BB])) in.status = MPP_EINVAL;   // non-finite input
-    else if (in.status == MPP_OK && !(in.rel_resid <= o.rtol) && sc[S_BB] > 0.0)
-      in.status = MPP_ENOTCONVERGED;
-    worst = worse(worst, in.status);
-  }
-  return worst;
+  const int st = fill_info(op, o, outer_count, istatus, info);
+  for (int b = 0; b < B; ++b) info[b].removed_mean = 0.0;
+  return st;
 }
 
 }  // extern "C"
@@ -1338,6 +1387,7 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
   const int B = op->batch, r = op->n / net->n;
   const Level& L0 = op->lev[0];
   try {
+    use_shift(op, 0.0, s);
     ensure_tuned<double>(op, s);
     net_inputs(op, net, f, nullptr, net->x4, nullptr, s);
     const int st = mppnet::forward(net, net->x4, net->y, B, s);

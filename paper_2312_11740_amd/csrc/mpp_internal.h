@@ -56,6 +56,8 @@ struct Faces {
   const T* by;
   const T* bz;
   const T* inv_rho;     // [B][2]
+  T sig;                // diagonal shift of this level: the operator is A - sig I (0 for the
+                        // pressure; 1/dt halved per coarser level for implicit diffusion)
 };
 
 struct Level {
@@ -115,9 +117,10 @@ struct Prof {
 struct GraphKey {
   int tsize, nu, nu_c, iters, max_iter;
   const void* ptr[6];
+  double shift = 0.0;   // the operator's diagonal shift (a kernel argument in the graph)
   bool operator==(const GraphKey& o) const {
     if (tsize != o.tsize || nu != o.nu || nu_c != o.nu_c || iters != o.iters ||
-        max_iter != o.max_iter)
+        max_iter != o.max_iter || shift != o.shift)
       return false;
     for (int q = 0; q < 6; ++q)
       if (ptr[q] != o.ptr[q]) return false;
@@ -147,7 +150,9 @@ struct mpp_op_s {
   mpp::Level lev[mpp::kMaxLevels];
   size_t cells = 0;
   int coarse_m = 0;
-  double* coarse_inv = nullptr;   // [B][m][m] inverse of (-A_c + 11^T/m)
+  double* coarse_inv = nullptr;   // [B][m][m] inverse of (-A_c + 11^T/m), or of (-A_c + sig_c I)
+  double shift = 0.0;             // diagonal shift of the finest level in use (0: pressure)
+  double coarse_shift = 0.0;      // the coarsest level's shift coarse_inv was built for
   double* coarse_work = nullptr;  // [B][m][m] factorisation scratch
   double* rho = nullptr;          // [B][3]: rho_neg, rho_pos, sigma
   double* inv_rho64 = nullptr;    // [B][2]

@@ -146,6 +146,9 @@ __global__ void __launch_bounds__(kRbThreads)
   // the cell's side, so x = (sum of interior neighbours - h^2 rho b) / (their count)
   const T ir0 = FINE ? F.inv_rho[2 * b] : T(0), ir1 = FINE ? F.inv_rho[2 * b + 1] : T(0);
   const T hr0 = FINE ? h2 / ir0 : T(0), hr1 = FINE ? h2 / ir1 : T(0);
+  // diagonal shift times h^2; with a shift every cell takes the general update
+  const T sh2 = F.sig * h2;
+  const bool plain = sh2 == T(0);
   double acc = 0.0;
 
   // ---- plane-invariant per-thread offsets (0 where the cell does not exist) ----
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(kRbThreads)
   auto update = [&](bool nb, unsigned cd, size_t cell, int i, int j, int k, bool wl, bool wr,
                     bool ws, bool wn, bool wd, bool wu, T xw, T xe, T xs, T xn, T xd, T xu, T bb,
                     T inv1, T inv2) -> T {
-    if (FINE && (cd & 63u) == 0u) {
+    if (FINE && (cd & 63u) == 0u && plain) {
       T sum = T(0);
       if (nb) {
         sum = (wl ? xw : T(0)) + (wr ? xe : T(0));
@@ -290,7 +293,7 @@ __global__ void __launch_bounds__(kRbThreads)
       if (wd) num += w[4] * xd;
       if (wu) num += w[5] * xu;
     }
-    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
+    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5] + sh2;
     return (num - h2 * bb) / den;
   };
 

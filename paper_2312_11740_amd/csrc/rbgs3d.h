@@ -68,6 +68,9 @@ __global__ void __launch_bounds__(k3Threads)
   const T h2 = (T)(1.0 / ((double)n * (double)n));
   const T ir0 = FINE ? F.inv_rho[2 * b] : T(0), ir1 = FINE ? F.inv_rho[2 * b + 1] : T(0);
   const T hr0 = FINE ? h2 / ir0 : T(0), hr1 = FINE ? h2 / ir1 : T(0);
+  // diagonal shift times h^2; with a shift every cell takes the general update
+  const T sh2 = F.sig * h2;
+  const bool plain = sh2 == T(0);
 
   // ---- every load of the block at once ----
   constexpr int PX = (k3NX + k3Threads - 1) / k3Threads;
@@ -124,7 +127,7 @@ __global__ void __launch_bounds__(k3Threads)
   auto update = [&](bool nb, unsigned cd, size_t cell, int i, int j, int k, T xw, T xe, T xs,
                     T xn, T xd, T xu, T bb) -> T {
     const bool wl = i > 0, wr = i < n - 1, ws = j > 0, wn = j < n - 1, wd = k > 0, wu = k < n - 1;
-    if (FINE && (cd & 63u) == 0u) {
+    if (FINE && (cd & 63u) == 0u && plain) {
       T sum = T(0);
       if (nb) {
         sum = (wl ? xw : T(0)) + (wr ? xe : T(0));
@@ -147,7 +150,7 @@ __global__ void __launch_bounds__(k3Threads)
       if (wd) num += w[4] * xd;
       if (wu) num += w[5] * xu;
     }
-    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5];
+    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5] + sh2;
     return (num - h2 * bb) / den;
   };
 

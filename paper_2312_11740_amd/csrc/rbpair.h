@@ -126,6 +126,9 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   const T h2 = (T)(1.0 / ((double)n * (double)n));
   const T ir0 = F.inv_rho[2 * b], ir1 = F.inv_rho[2 * b + 1];
   const T hr0 = h2 / ir0, hr1 = h2 / ir1;
+  // diagonal shift times h^2; with a shift every cell takes the coded update
+  const T sh2 = F.sig * h2;
+  const bool shifted = sh2 != T(0);
   const T inv6 = T(1) / T(6), inv5 = T(1) / T(5), inv4 = T(1) / T(4), inv3 = T(1) / T(3);
   auto inv_of = [&](int walls) {
     return walls <= 0 ? inv6 : (walls == 1 ? inv5 : (walls == 2 ? inv4 : inv3));
@@ -258,7 +261,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     num += wf[3] * xn;
     num += wf[4] * xd;
     num += wf[5] * xu;
-    const T den = wf[0] + wf[1] + wf[2] + wf[3] + wf[4] + wf[5];
+    const T den = wf[0] + wf[1] + wf[2] + wf[3] + wf[4] + wf[5] + sh2;
     return (num - h2 * bb) / den;
   };
   // Gauss-Seidel value from the six neighbour values (zero outside the domain); inv =
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const T sum = ((xw + xe) + (xs + xn)) + (xd + xu);
     const T hr = (cd & 64u) ? hr1 : hr0;
     T v = (sum - hr * bb) * inv;
-    const bool crossed = (cd & 63u) != 0u;
+    const bool crossed = (cd & 63u) != 0u || shifted;
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(crossed) != 0, 0)) {
       if (crossed) v = relax_coded(cd, pb, off, ic, jc, kc, xw, xe, xs, xn, xd, xu, bb);
     }

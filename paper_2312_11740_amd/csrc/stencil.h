@@ -48,10 +48,10 @@ __device__ inline void load_nb(const T* xp, const uint8_t* cp, int off, int i, i
   v.cd = FINE ? cp[off] : 0u;
 }
 
-// (A x)_c from the centre value, its six neighbours and the face coefficients
+// ((A - sig I) x)_c from the centre value, its six neighbours and the face coefficients
 template <typename T>
 __device__ inline T stencil7(const T w[6], T xc, T xw, T xe, T xs, T xn, T xd, T xu, int i, int j,
-                             int k, int n, T inv_h2) {
+                             int k, int n, T inv_h2, T sig) {
   T s = T(0);
   if (i > 0) s += w[0] * (xw - xc);
   if (i < n - 1) s += w[1] * (xe - xc);
@@ -59,7 +59,7 @@ __device__ inline T stencil7(const T w[6], T xc, T xw, T xe, T xs, T xn, T xd, T
   if (j < n - 1) s += w[3] * (xn - xc);
   if (k > 0) s += w[4] * (xd - xc);
   if (k < n - 1) s += w[5] * (xu - xc);
-  return s * inv_h2;
+  return s * inv_h2 - sig * xc;
 }
 
 // Loads of one batch of kStZ planes of a thread's column, all issued before any use:
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kStThreads)
         coded_faces_at(F.bx + cell, F.by + cell, F.bz + cell, B.cd[h], i, j, k, n, nn,
                        (B.cd[h] & 64u) ? ir1 : ir0, w);
         const T ax = stencil7(w, B.xc[h + 1], B.w[h], B.e[h], B.s[h], B.nb[h], B.xc[h],
-                              B.xc[h + 2], i, j, k, n, inv_h2);
+                              B.xc[h + 2], i, j, k, n, inv_h2, F.sig);
         T out;
         if (KIND == 0) {
           out = ax;
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(kStThreads)
         T w[6];
         sweep_faces<T, FINE>(F, cell, B.cd[h], i, j, k, n, nn, ir0, ir1, w);
         s2[h >> 1] += bv[h] - stencil7(w, B.xc[h + 1], B.w[h], B.e[h], B.s[h], B.nb[h], B.xc[h],
-                                       B.xc[h + 2], i, j, k, n, inv_h2);
+                                       B.xc[h + 2], i, j, k, n, inv_h2, F.sig);
       }
     }
 #pragma unroll
