@@ -622,11 +622,15 @@ namespace mpp {
 // ------------------------------------------------------------------------------
 // the bottom of the V-cycle in one launch: levels with at most kSmallCells cells per
 // problem are smoothed, restricted, solved and prolonged by a single workgroup per
-// problem, in global memory (L2-resident at these sizes), with barriers between
-// phases.  Same operations, in the same order, as the per-level kernels.
+// problem, with barriers between phases.  Same operations, in the same order, as the
+// per-level kernels.  Every level's iterate and right-hand side live in LDS for the
+// whole launch (the first level's rhs is read in, its iterate written out at the end),
+// and so do the face coefficients when they fit (kSmallLdsBytes: all of them in FP32;
+// in FP64 they are read through the caches).
 // ------------------------------------------------------------------------------
 constexpr int kSmallCells = 4096;   // 16^3
 constexpr int kSmallBlock = 1024;
+constexpr int kSmallLdsBytes = 144 * 1024;
 
 template <typename T>
 struct SmallLevel {
@@ -646,7 +650,17 @@ struct SmallCycle {
   const double* inv;               // [B][m][m]
   int m;
   int nu;
+  int faces_in_lds;                // 1: the face coefficients are copied into LDS too
 };
+
+// LDS bytes the small cycle needs for x and b of its levels, and for their faces
+template <typename T>
+inline void small_lds_bytes(const SmallCycle<T>& S, size_t& xb, size_t& faces) {
+  size_t cells = 0;
+  for (int l = 0; l < S.nlev; ++l) cells += (size_t)S.lv[l].n * S.lv[l].n * S.lv[l].n;
+  xb = 2 * cells * sizeof(T);
+  faces = 3 * cells * sizeof(T);
+}
 
 template <typename T>
 __device__ inline void small_faces(const SmallLevel<T>& L, size_t base, int c, int i, int j, int k,
@@ -732,39 +746,82 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_cycle(SmallCycle<T> S,
                                                              const int* __restrict__ active) {
   const int b = blockIdx.x;
   if (active && !active[b]) return;
-  size_t base[kMaxLevels];
-  for (int l = 0; l < S.nlev; ++l) base[l] = (size_t)b * S.lv[l].n * S.lv[l].n * S.lv[l].n;
-  for (int l = 0; l + 1 < S.nlev; ++l) {
-    small_smooth(S.lv[l], base[l], 0, 1);
-    small_smooth(S.lv[l], base[l], 1, 0);
-    for (int q = 1; q < S.nu; ++q) {
-      small_smooth(S.lv[l], base[l], 0, 0);
-      small_smooth(S.lv[l], base[l], 1, 0);
+  __shared__ __align__(16) unsigned char lds[kSmallLdsBytes];
+  // this problem's levels, with x and b (and the faces when they fit) moved into LDS;
+  // every pointer is offset to the problem, so the level bases are 0.  The level table
+  // itself sits in LDS (dynamically indexed, it would otherwise go to scratch).
+  __shared__ SmallLevel<T> L[kMaxLevels];
+  if (threadIdx.x == 0) {
+    T* p = reinterpret_cast<T*>(lds);
+    for (int l = 0; l < S.nlev; ++l) {
+      const SmallLevel<T>& G = S.lv[l];
+      const size_t cells = (size_t)G.n * G.n * G.n, gb = (size_t)b * cells;
+      SmallLevel<T> v = G;
+      v.x = p;
+      p += cells;
+      v.b = p;
+      p += cells;
+      v.bx = G.bx + gb;
+      v.by = G.by + gb;
+      v.bz = G.bz + gb;
+      if (S.faces_in_lds) {
+        v.bx = p;
+        v.by = p + cells;
+        v.bz = p + 2 * cells;
+        p += 3 * cells;
+      }
+      L[l] = v;
     }
-    small_resid_restrict(S.lv[l], base[l], S.lv[l + 1], base[l + 1]);
+  }
+  __syncthreads();
+  for (int l = 0; l < S.nlev; ++l) {
+    const SmallLevel<T>& G = S.lv[l];
+    const size_t cells = (size_t)G.n * G.n * G.n, gb = (size_t)b * cells;
+    if (S.faces_in_lds) {
+      T* f[3] = {const_cast<T*>(L[l].bx), const_cast<T*>(L[l].by), const_cast<T*>(L[l].bz)};
+      const T* g[3] = {G.bx + gb, G.by + gb, G.bz + gb};
+      for (int a = 0; a < 3; ++a)
+        for (size_t q = threadIdx.x; q < cells; q += blockDim.x) f[a][q] = g[a][q];
+    }
+    if (l == 0)
+      for (size_t q = threadIdx.x; q < cells; q += blockDim.x) L[0].b[q] = G.b[gb + q];
+  }
+  __syncthreads();
+  for (int l = 0; l + 1 < S.nlev; ++l) {
+    small_smooth(L[l], 0, 0, 1);
+    small_smooth(L[l], 0, 1, 0);
+    for (int q = 1; q < S.nu; ++q) {
+      small_smooth(L[l], 0, 0, 0);
+      small_smooth(L[l], 0, 1, 0);
+    }
+    small_resid_restrict(L[l], 0, L[l + 1], 0);
   }
   {
     // coarsest: x = M^{-1} (-b), FP64
-    const SmallLevel<T>& L = S.lv[S.nlev - 1];
+    const SmallLevel<T>& C = L[S.nlev - 1];
     __shared__ double sb[kMaxCoarse];
     const int m = S.m;
-    const size_t bl = base[S.nlev - 1];
-    for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)L.b[bl + q];
+    for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)C.b[q];
     __syncthreads();
     const double* Mi = S.inv + (size_t)b * m * m;
     for (int r = threadIdx.x; r < m; r += blockDim.x) {
       double s = 0.0;
       for (int q = 0; q < m; ++q) s += Mi[(size_t)q * m + r] * sb[q];
-      L.x[bl + r] = (T)s;
+      C.x[r] = (T)s;
     }
     __syncthreads();
   }
   for (int l = S.nlev - 2; l >= 0; --l) {
-    small_prolong(S.lv[l], base[l], S.lv[l + 1], base[l + 1]);
+    small_prolong(L[l], 0, L[l + 1], 0);
     for (int q = 0; q < S.nu; ++q) {
-      small_smooth(S.lv[l], base[l], 1, 0);
-      small_smooth(S.lv[l], base[l], 0, 0);
+      small_smooth(L[l], 0, 1, 0);
+      small_smooth(L[l], 0, 0, 0);
     }
+  }
+  {
+    const size_t cells0 = (size_t)S.lv[0].n * S.lv[0].n * S.lv[0].n;
+    T* out = S.lv[0].x + (size_t)b * cells0;
+    for (size_t q = threadIdx.x; q < cells0; q += blockDim.x) out[q] = L[0].x[q];
   }
 }
 
