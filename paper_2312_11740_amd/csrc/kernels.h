@@ -650,178 +650,302 @@ struct SmallCycle {
   const double* inv;               // [B][m][m]
   int m;
   int nu;
-  int faces_in_lds;                // 1: the face coefficients are copied into LDS too
 };
 
-// LDS bytes the small cycle needs for x and b of its levels, and for their faces
+// LDS elements the small cycle needs: x, b and the reciprocal diagonal of every level
+// plus a residual scratch of the first level's size (`fixed`), and the faces of every
+// level (`faces`)
 template <typename T>
-inline void small_lds_bytes(const SmallCycle<T>& S, size_t& xb, size_t& faces) {
+inline void small_lds_bytes(const SmallCycle<T>& S, size_t& fixed, size_t& faces) {
   size_t cells = 0;
   for (int l = 0; l < S.nlev; ++l) cells += (size_t)S.lv[l].n * S.lv[l].n * S.lv[l].n;
-  xb = 2 * cells * sizeof(T);
+  const size_t c0 = (size_t)S.lv[0].n * S.lv[0].n * S.lv[0].n;
+  fixed = (3 * cells + c0) * sizeof(T);
   faces = 3 * cells * sizeof(T);
 }
 
-template <typename T>
-__device__ inline void small_faces(const SmallLevel<T>& L, size_t base, int c, int i, int j, int k,
-                                   T w[6]) {
-  const int n = L.n, nn = n * n;
-  w[0] = i > 0 ? L.bx[base + c] : T(0);
-  w[1] = i < n - 1 ? L.bx[base + c + 1] : T(0);
-  w[2] = j > 0 ? L.by[base + c] : T(0);
-  w[3] = j < n - 1 ? L.by[base + c + n] : T(0);
-  w[4] = k > 0 ? L.bz[base + c] : T(0);
-  w[5] = k < n - 1 ? L.bz[base + c + nn] : T(0);
+// One level as the kernel sees it: x, b and 1/diagonal in LDS; the faces in LDS (FL) or
+// in global memory.  Pointers are formed from the LDS base inside the kernel, so the
+// compiler addresses LDS directly.
+template <typename T, bool FL>
+struct SmallView {
+  int n, lg;   // lg = log2(n) when n is a power of two, else -1
+  T* x;
+  T* b;
+  T* rd;
+  const T* bx;
+  const T* by;
+  const T* bz;
+  T sig;
+};
+
+__device__ inline int small_cube(int n) { return n * n * n; }
+
+// LDS element offset of level l's block (x, b, rd [, bx, by, bz]); l == nlev: the scratch
+template <typename T, bool FL>
+__device__ inline int small_off(const SmallCycle<T>& S, int l) {
+  int off = 0;
+  for (int q = 0; q < l; ++q) off += (FL ? 6 : 3) * small_cube(S.lv[q].n);
+  return off;
 }
 
-template <typename T>
-__device__ void small_smooth(const SmallLevel<T>& L, size_t base, int colour, int from_zero) {
-  const int n = L.n, cells = n * n * n, nn = n * n, nh = n >> 1;
+template <typename T, bool FL>
+__device__ inline SmallView<T, FL> small_view(const SmallCycle<T>& S, T* lds, int pb, int l) {
+  const SmallLevel<T>& G = S.lv[l];
+  const int n = G.n, cells = small_cube(n);
+  T* p = lds + small_off<T, FL>(S, l);
+  SmallView<T, FL> v;
+  v.n = n;
+  v.lg = (n & (n - 1)) == 0 ? __builtin_ctz((unsigned)n) : -1;
+  v.x = p;
+  v.b = p + cells;
+  v.rd = p + 2 * cells;
+  if (FL) {
+    v.bx = p + 3 * cells;
+    v.by = p + 4 * cells;
+    v.bz = p + 5 * cells;
+  } else {
+    const size_t gb = (size_t)pb * cells;
+    v.bx = G.bx + gb;
+    v.by = G.by + gb;
+    v.bz = G.bz + gb;
+  }
+  v.sig = G.sig;
+  return v;
+}
+
+// (i, j, k) of cell c; shifts when n is a power of two
+__device__ inline void small_ijk(int c, int n, int lg, int& i, int& j, int& k) {
+  if (lg >= 0) {
+    i = c & (n - 1);
+    j = (c >> lg) & (n - 1);
+    k = c >> (2 * lg);
+  } else {
+    ijk(c, n, i, j, k);
+  }
+}
+
+// cell of colour `colour` with index q among the cells/2 of that colour (n even: half
+// of every x-row)
+__device__ inline int small_colour_cell(int q, int n, int lg, int colour, int& i, int& j, int& k) {
+  const int nh = n >> 1;
+  int row, ih;
+  if (lg >= 1) {
+    ih = q & (nh - 1);
+    row = q >> (lg - 1);
+    j = row & (n - 1);
+    k = row >> lg;
+  } else {
+    ih = q % nh;
+    row = q / nh;
+    j = row % n;
+    k = row / n;
+  }
+  i = 2 * ih + ((colour + j + k) & 1);
+  return i + n * (j + n * k);
+}
+
+template <typename T, bool FL>
+__device__ inline void small_faces(const SmallView<T, FL>& L, int c, int i, int j, int k, T w[6]) {
+  const int n = L.n, nn = n * n;
+  w[0] = i > 0 ? L.bx[c] : T(0);
+  w[1] = i < n - 1 ? L.bx[c + 1] : T(0);
+  w[2] = j > 0 ? L.by[c] : T(0);
+  w[3] = j < n - 1 ? L.by[c + n] : T(0);
+  w[4] = k > 0 ? L.bz[c] : T(0);
+  w[5] = k < n - 1 ? L.bz[c + nn] : T(0);
+}
+
+// rd = 1 / (sum of the faces + sig h^2) of every cell
+template <typename T, bool FL>
+__device__ void small_diag(const SmallView<T, FL>& L) {
+  const int n = L.n, cells = small_cube(n);
   const T h2 = (T)(1.0 / ((double)n * (double)n));
-  if (from_zero)   // the other colour starts at zero
-    for (int q = threadIdx.x; q < cells / 2; q += blockDim.x) {
-      const int j = (q / nh) % n, k = q / (nh * n);
-      const int i = 2 * (q % nh) + ((colour + j + k + 1) & 1);
-      L.x[base + i + n * (j + n * k)] = T(0);
-    }
-  // only the cells of this colour (n is even: half of every x-row)
-  for (int q = threadIdx.x; q < cells / 2; q += blockDim.x) {
-    const int j = (q / nh) % n, k = q / (nh * n);
-    const int i = 2 * (q % nh) + ((colour + j + k) & 1);
-    const int c = i + n * (j + n * k);
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+    int i, j, k;
+    small_ijk(c, n, L.lg, i, j, k);
     T w[6];
-    small_faces(L, base, c, i, j, k, w);
+    small_faces(L, c, i, j, k, w);
+    L.rd[c] = T(1) / (w[0] + w[1] + w[2] + w[3] + w[4] + w[5] + L.sig * h2);
+  }
+}
+
+// one colour of Gauss-Seidel; from_zero: the other colour is taken as (and set to) zero
+template <typename T, bool FL>
+__device__ void small_smooth(const SmallView<T, FL>& L, int colour, int from_zero) {
+  const int n = L.n, half = small_cube(n) / 2, nn = n * n;
+  const T h2 = (T)(1.0 / ((double)n * (double)n));
+  if (from_zero)
+    for (int q = threadIdx.x; q < half; q += blockDim.x) {
+      int i, j, k;
+      L.x[small_colour_cell(q, n, L.lg, colour + 1, i, j, k)] = T(0);
+    }
+  for (int q = threadIdx.x; q < half; q += blockDim.x) {
+    int i, j, k;
+    const int c = small_colour_cell(q, n, L.lg, colour, i, j, k);
+    T w[6];
+    small_faces(L, c, i, j, k, w);
     T num = T(0);
     if (!from_zero) {
-      if (i > 0) num += w[0] * L.x[base + c - 1];
-      if (i < n - 1) num += w[1] * L.x[base + c + 1];
-      if (j > 0) num += w[2] * L.x[base + c - n];
-      if (j < n - 1) num += w[3] * L.x[base + c + n];
-      if (k > 0) num += w[4] * L.x[base + c - nn];
-      if (k < n - 1) num += w[5] * L.x[base + c + nn];
+      if (i > 0) num += w[0] * L.x[c - 1];
+      if (i < n - 1) num += w[1] * L.x[c + 1];
+      if (j > 0) num += w[2] * L.x[c - n];
+      if (j < n - 1) num += w[3] * L.x[c + n];
+      if (k > 0) num += w[4] * L.x[c - nn];
+      if (k < n - 1) num += w[5] * L.x[c + nn];
     }
-    const T den = w[0] + w[1] + w[2] + w[3] + w[4] + w[5] + L.sig * h2;
-    L.x[base + c] = (num - h2 * L.b[base + c]) / den;
+    L.x[c] = (num - h2 * L.b[c]) * L.rd[c];
   }
   __syncthreads();
 }
 
-template <typename T>
-__device__ void small_resid_restrict(const SmallLevel<T>& F, size_t basef, const SmallLevel<T>& C,
-                                     size_t basec) {
-  const int nf = F.n, nc = C.n, cells_c = nc * nc * nc;
+// coarse b = mean over the 8 children of (b - A x): residuals of every fine cell into
+// `tmp`, then the sums over children
+template <typename T, bool FL>
+__device__ void small_resid_restrict(const SmallView<T, FL>& F, const SmallView<T, FL>& C,
+                                     T* tmp) {
+  const int nf = F.n, nc = C.n, cells_f = small_cube(nf), cells_c = small_cube(nc);
   const T inv_h2 = (T)((double)nf * (double)nf);
+  for (int c = threadIdx.x; c < cells_f; c += blockDim.x) {
+    int i, j, k;
+    small_ijk(c, nf, F.lg, i, j, k);
+    T w[6];
+    small_faces(F, c, i, j, k, w);
+    tmp[c] = F.b[c] - stencil_at(w, F.x, 0, c, i, j, k, nf, inv_h2, F.sig);
+  }
+  __syncthreads();
   for (int c = threadIdx.x; c < cells_c; c += blockDim.x) {
     int I, J, K;
-    ijk(c, nc, I, J, K);
+    small_ijk(c, nc, C.lg, I, J, K);
     T s = T(0);
     for (int e = 0; e < 2; ++e)
       for (int d = 0; d < 2; ++d)
-        for (int a = 0; a < 2; ++a) {
-          const int i = 2 * I + a, j = 2 * J + d, k = 2 * K + e;
-          const int cf = i + nf * (j + nf * k);
-          T w[6];
-          small_faces(F, basef, cf, i, j, k, w);
-          s += F.b[basef + cf] - stencil_at(w, F.x, basef, cf, i, j, k, nf, inv_h2, F.sig);
-        }
-    C.b[basec + c] = s * T(0.125);
+        for (int a = 0; a < 2; ++a)
+          s += tmp[(2 * I + a) + nf * ((2 * J + d) + nf * (2 * K + e))];
+    C.b[c] = s * T(0.125);
   }
   __syncthreads();
 }
 
-template <typename T>
-__device__ void small_prolong(const SmallLevel<T>& F, size_t basef, const SmallLevel<T>& C,
-                              size_t basec) {
-  const int nf = F.n, nc = C.n, cells_f = nf * nf * nf;
+template <typename T, bool FL>
+__device__ void small_prolong(const SmallView<T, FL>& F, const SmallView<T, FL>& C) {
+  const int nf = F.n, nc = C.n, cells_f = small_cube(nf);
   for (int c = threadIdx.x; c < cells_f; c += blockDim.x) {
     int i, j, k;
-    ijk(c, nf, i, j, k);
-    F.x[basef + c] += C.x[basec + (i >> 1) + nc * ((j >> 1) + nc * (k >> 1))];
+    small_ijk(c, nf, F.lg, i, j, k);
+    F.x[c] += C.x[(i >> 1) + nc * ((j >> 1) + nc * (k >> 1))];
   }
   __syncthreads();
 }
 
-template <typename T>
+// Copies the global arrays the cycle reads into their LDS places: the first level's
+// right-hand side and (FL) the faces of every level (at most 3 levels of at most 4096
+// cells).  Every thread issues all of its loads before its first store, so the copy
+// costs about one memory latency.
+template <typename T, bool FL>
+__device__ void small_copy_in(const SmallCycle<T>& S, T* lds, int pb) {
+  constexpr int kU = kSmallCells / kSmallBlock;
+  T v[3][4][kU];
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        v[l][a][u] = T(0);
+        if (l < S.nlev && (a < 3 ? FL : l == 0)) {
+          const SmallLevel<T>& G = S.lv[l];
+          const int c = small_cube(G.n), q = threadIdx.x + u * kSmallBlock;
+          const T* src = a == 0 ? G.bx : (a == 1 ? G.by : (a == 2 ? G.bz : G.b));
+          if (q < c) v[l][a][u] = src[(size_t)pb * c + q];
+        }
+      }
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (l < S.nlev && (a < 3 ? FL : l == 0)) {
+          const int c = small_cube(S.lv[l].n), q = threadIdx.x + u * kSmallBlock;
+          // LDS block of level l: x, b, rd, bx, by, bz
+          T* dst = lds + small_off<T, FL>(S, l) + (a < 3 ? (3 + a) * c : c);
+          if (q < c) dst[q] = v[l][a][u];
+        }
+}
+
+template <typename T, bool FL>
 __global__ void __launch_bounds__(kSmallBlock) k_small_cycle(SmallCycle<T> S,
                                                              const int* __restrict__ active) {
-  const int b = blockIdx.x;
-  if (active && !active[b]) return;
-  __shared__ __align__(16) unsigned char lds[kSmallLdsBytes];
-  // this problem's levels, with x and b (and the faces when they fit) moved into LDS;
-  // every pointer is offset to the problem, so the level bases are 0.  The level table
-  // itself sits in LDS (dynamically indexed, it would otherwise go to scratch).
-  __shared__ SmallLevel<T> L[kMaxLevels];
-  if (threadIdx.x == 0) {
-    T* p = reinterpret_cast<T*>(lds);
-    for (int l = 0; l < S.nlev; ++l) {
-      const SmallLevel<T>& G = S.lv[l];
-      const size_t cells = (size_t)G.n * G.n * G.n, gb = (size_t)b * cells;
-      SmallLevel<T> v = G;
-      v.x = p;
-      p += cells;
-      v.b = p;
-      p += cells;
-      v.bx = G.bx + gb;
-      v.by = G.by + gb;
-      v.bz = G.bz + gb;
-      if (S.faces_in_lds) {
-        v.bx = p;
-        v.by = p + cells;
-        v.bz = p + 2 * cells;
-        p += 3 * cells;
-      }
-      L[l] = v;
-    }
-  }
+  const int pb = blockIdx.x;
+  if (active && !active[pb]) return;
+  __shared__ __align__(16) unsigned char lds_raw[kSmallLdsBytes];
+  __shared__ double sb[kMaxCoarse];
+  T* const lds = reinterpret_cast<T*>(lds_raw);
+  T* const tmp = lds + small_off<T, FL>(S, S.nlev);
+  const int nl = S.nlev;
+  small_copy_in<T, FL>(S, lds, pb);
   __syncthreads();
-  for (int l = 0; l < S.nlev; ++l) {
-    const SmallLevel<T>& G = S.lv[l];
-    const size_t cells = (size_t)G.n * G.n * G.n, gb = (size_t)b * cells;
-    if (S.faces_in_lds) {
-      T* f[3] = {const_cast<T*>(L[l].bx), const_cast<T*>(L[l].by), const_cast<T*>(L[l].bz)};
-      const T* g[3] = {G.bx + gb, G.by + gb, G.bz + gb};
-      for (int a = 0; a < 3; ++a)
-        for (size_t q = threadIdx.x; q < cells; q += blockDim.x) f[a][q] = g[a][q];
-    }
-    if (l == 0)
-      for (size_t q = threadIdx.x; q < cells; q += blockDim.x) L[0].b[q] = G.b[gb + q];
-  }
+  for (int l = 0; l + 1 < nl; ++l) small_diag(small_view<T, FL>(S, lds, pb, l));
   __syncthreads();
-  for (int l = 0; l + 1 < S.nlev; ++l) {
-    small_smooth(L[l], 0, 0, 1);
-    small_smooth(L[l], 0, 1, 0);
+  for (int l = 0; l + 1 < nl; ++l) {
+    const SmallView<T, FL> V = small_view<T, FL>(S, lds, pb, l);
+    small_smooth(V, 0, 1);
+    small_smooth(V, 1, 0);
     for (int q = 1; q < S.nu; ++q) {
-      small_smooth(L[l], 0, 0, 0);
-      small_smooth(L[l], 0, 1, 0);
+      small_smooth(V, 0, 0);
+      small_smooth(V, 1, 0);
     }
-    small_resid_restrict(L[l], 0, L[l + 1], 0);
+    small_resid_restrict(V, small_view<T, FL>(S, lds, pb, l + 1), tmp);
   }
   {
-    // coarsest: x = M^{-1} (-b), FP64
-    const SmallLevel<T>& C = L[S.nlev - 1];
-    __shared__ double sb[kMaxCoarse];
+    // coarsest: x = M^{-1} (-b), FP64.  G groups of threads split the columns q of
+    // row r; their partial sums meet in the scratch (read back in a fixed order).
+    const SmallView<T, FL> C = small_view<T, FL>(S, lds, pb, nl - 1);
     const int m = S.m;
     for (int q = threadIdx.x; q < m; q += blockDim.x) sb[q] = -(double)C.b[q];
     __syncthreads();
-    const double* Mi = S.inv + (size_t)b * m * m;
-    for (int r = threadIdx.x; r < m; r += blockDim.x) {
-      double s = 0.0;
-      for (int q = 0; q < m; ++q) s += Mi[(size_t)q * m + r] * sb[q];
-      C.x[r] = (T)s;
+    const double* Mi = S.inv + (size_t)pb * m * m;
+    const int tmp_bytes = small_cube(S.lv[0].n) * (int)sizeof(T);
+    const int G = max(1, min(kSmallBlock / m, tmp_bytes / (8 * m)));
+    double* part = reinterpret_cast<double*>(tmp);
+    if (G == 1) {
+      for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < m; ++q) s += Mi[(size_t)q * m + r] * sb[q];
+        C.x[r] = (T)s;
+      }
+    } else {
+      const int t = threadIdx.x;
+      if (t < G * m) {
+        const int r = t % m, g = t / m;
+        double s = 0.0;
+#pragma unroll 4
+        for (int q = g; q < m; q += G) s += Mi[(size_t)q * m + r] * sb[q];
+        part[g * m + r] = s;
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g) s += part[g * m + r];
+        C.x[r] = (T)s;
+      }
     }
     __syncthreads();
   }
-  for (int l = S.nlev - 2; l >= 0; --l) {
-    small_prolong(L[l], 0, L[l + 1], 0);
+  for (int l = nl - 2; l >= 0; --l) {
+    const SmallView<T, FL> V = small_view<T, FL>(S, lds, pb, l);
+    small_prolong(V, small_view<T, FL>(S, lds, pb, l + 1));
     for (int q = 0; q < S.nu; ++q) {
-      small_smooth(L[l], 0, 1, 0);
-      small_smooth(L[l], 0, 0, 0);
+      small_smooth(V, 1, 0);
+      small_smooth(V, 0, 0);
     }
   }
   {
-    const size_t cells0 = (size_t)S.lv[0].n * S.lv[0].n * S.lv[0].n;
-    T* out = S.lv[0].x + (size_t)b * cells0;
-    for (size_t q = threadIdx.x; q < cells0; q += blockDim.x) out[q] = L[0].x[q];
+    const int c0 = small_cube(S.lv[0].n);
+    T* out = S.lv[0].x + (size_t)pb * c0;
+    const T* x0 = lds + small_off<T, FL>(S, 0);
+    for (int q = threadIdx.x; q < c0; q += blockDim.x) out[q] = x0[q];
   }
 }
 

@@ -442,11 +442,16 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
   S.inv = op->coarse_inv;
   S.m = op->coarse_m;
   S.nu = l == 0 ? nu : op->nu_c;
-  size_t xb = 0, fb = 0;
-  small_lds_bytes(S, xb, fb);
-  if (xb > (size_t)kSmallLdsBytes) throw HipError{hipErrorInvalidValue};   // not reached: <= 4681 cells
-  S.faces_in_lds = xb + fb <= (size_t)kSmallLdsBytes ? 1 : 0;
-  hipLaunchKernelGGL(k_small_cycle<T>, dim3(B), dim3(kSmallBlock), 0, s, S, active);
+  // x, b, reciprocal diagonals and one residual scratch always fit (<= 4681 cells in at
+  // most 3 levels, 16^3 first level: 145 KB in FP64); the faces too in FP32
+  size_t fixed = 0, fb = 0;
+  small_lds_bytes(S, fixed, fb);
+  if (fixed > (size_t)kSmallLdsBytes || S.nlev > 3 || S.m > kSmallBlock)
+    throw HipError{hipErrorInvalidValue};
+  if (fixed + fb <= (size_t)kSmallLdsBytes)
+    hipLaunchKernelGGL((k_small_cycle<T, true>), dim3(B), dim3(kSmallBlock), 0, s, S, active);
+  else
+    hipLaunchKernelGGL((k_small_cycle<T, false>), dim3(B), dim3(kSmallBlock), 0, s, S, active);
   ck_launch();
 }
 
