@@ -60,6 +60,10 @@ def lib():
         L.orc_heat_apply.argtypes = [i, P, P, P, d, P, P]
         L.orc_heat_apply.restype = None
         L.orc_heat_solve.argtypes = [i, P, P, P, d, P, P, d, i, P, P]
+        for nm in ("orc_blocks_scatter", "orc_blocks_gather"):
+            getattr(L, nm).argtypes = [i, i, i, P, P]
+        L.orc_blocks_fill_guards.argtypes = [i, i, i, P]
+        L.orc_blocks_apply.argtypes = [i, i, i, P, P, P, P, P]
         L.orc_gs_colour.argtypes = [i, P, P, P, P, P, i]
         L.orc_gs_colour.restype = None
         L.orc_restrict.argtypes = [i, P, P]
@@ -241,6 +245,44 @@ def heat_step(fc, t_old, dt, src=None, tol=1e-13, max_iter=100000, x0=None):
                                 float(tol), int(max_iter), ctypes.byref(it), ctypes.byref(rr)),
            "heat_solve")
     return x, it.value, rr.value
+
+
+def blocks_shape(n, nb, g):
+    """(blocks, padded edge) of the block layout: (n/nb)^3 blocks of (nb + 2g)^3 values."""
+    return (n // nb) ** 3, nb + 2 * g
+
+
+def blocks_scatter(grid, nb, g, blocks=None):
+    """Grid (n, n, n) -> block layout (nblk, P, P, P); guards zero unless `blocks` given."""
+    grid = _c(grid)
+    n = _n(grid)
+    nblk, P = blocks_shape(n, nb, g)
+    out = np.zeros((nblk, P, P, P)) if blocks is None else _c(blocks).copy()
+    _check(lib().orc_blocks_scatter(n, nb, g, _p(grid), _p(out)), "blocks_scatter")
+    return out
+
+
+def blocks_gather(blocks, n, nb, g):
+    blocks = _c(blocks)
+    out = np.empty((n, n, n))
+    _check(lib().orc_blocks_gather(n, nb, g, _p(blocks), _p(out)), "blocks_gather")
+    return out
+
+
+def blocks_fill_guards(blocks, n, nb, g):
+    out = _c(blocks).copy()
+    _check(lib().orc_blocks_fill_guards(n, nb, g, _p(out)), "blocks_fill_guards")
+    return out
+
+
+def blocks_apply(fc, xblk, nb, g):
+    bx, by, bz = (_c(a) for a in fc)
+    n = _n(bx)
+    xblk = _c(xblk)
+    y = np.empty_like(xblk)
+    _check(lib().orc_blocks_apply(n, nb, g, _p(bx), _p(by), _p(bz), _p(xblk), _p(y)),
+           "blocks_apply")
+    return y
 
 
 def pipeline(phi, f, rho_neg, rho_pos, sigma, kappa_override=None):

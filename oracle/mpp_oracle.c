@@ -1004,6 +1004,130 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Block-structured layout (Sec. 2: the grid is a set of blocks of cells; the  */
+/* setup command of Sec. 4 uses 16^3 blocks; Sec. 4 also has the guard-cell   */
+/* fill, which exchanges halos between blocks and applies the physical        */
+/* boundary condition).  A problem of n^3 cells is cut into (n/nb)^3 blocks   */
+/* of nb^3 cells, block (bi,bj,bk) at index bi + nbx (bj + nbx bk); each      */
+/* block is stored with g guard layers on every side as (nb+2g)^3 values, x   */
+/* fastest.  Guard cells hold the value of the cell at the same position in  */
+/* the neighbouring block; outside the domain they mirror the field about    */
+/* the wall (even reflection, the zero-gradient condition of the insulated   */
+/* and no-flux walls used throughout).                                        */
+/* ------------------------------------------------------------------------ */
+
+static size_t blk_at(int nb, int g, size_t blk, int li, int lj, int lk)
+{
+    size_t P = (size_t)nb + 2 * (size_t)g;
+    return blk * P * P * P + (size_t)(li + g) + P * ((size_t)(lj + g) + P * (size_t)(lk + g));
+}
+
+static int blk_args_ok(int n, int nb, int g)
+{
+    return n >= 1 && nb >= 1 && n % nb == 0 && g >= 0 && g <= nb;
+}
+
+/* grid -> block interiors (guards left as they are) */
+int orc_blocks_scatter(int n, int nb, int g, const double *grid, double *blocks)
+{
+    if (!blk_args_ok(n, nb, g) || !grid || !blocks)
+        return ORC_EINVAL;
+    int nbx = n / nb;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t blk = (size_t)(i / nb) + nbx * ((size_t)(j / nb) + nbx * (size_t)(k / nb));
+                blocks[blk_at(nb, g, blk, i % nb, j % nb, k % nb)] = grid[ix(n, i, j, k)];
+            }
+    return ORC_OK;
+}
+
+/* block interiors -> grid */
+int orc_blocks_gather(int n, int nb, int g, const double *blocks, double *grid)
+{
+    if (!blk_args_ok(n, nb, g) || !grid || !blocks)
+        return ORC_EINVAL;
+    int nbx = n / nb;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                size_t blk = (size_t)(i / nb) + nbx * ((size_t)(j / nb) + nbx * (size_t)(k / nb));
+                grid[ix(n, i, j, k)] = blocks[blk_at(nb, g, blk, i % nb, j % nb, k % nb)];
+            }
+    return ORC_OK;
+}
+
+/* mirror a global coordinate about the walls into [0, n) */
+static int mirror(int a, int n)
+{
+    if (a < 0)
+        return -1 - a;
+    if (a >= n)
+        return 2 * n - 1 - a;
+    return a;
+}
+
+/* every guard cell (faces, edges and corners) from the interior of the block that owns
+ * its (mirrored) position */
+int orc_blocks_fill_guards(int n, int nb, int g, double *blocks)
+{
+    if (!blk_args_ok(n, nb, g) || !blocks)
+        return ORC_EINVAL;
+    int nbx = n / nb;
+    size_t nblk = (size_t)nbx * nbx * nbx;
+    for (size_t blk = 0; blk < nblk; ++blk) {
+        int bi = (int)(blk % nbx), bj = (int)((blk / nbx) % nbx), bk = (int)(blk / ((size_t)nbx * nbx));
+        for (int lk = -g; lk < nb + g; ++lk)
+            for (int lj = -g; lj < nb + g; ++lj)
+                for (int li = -g; li < nb + g; ++li) {
+                    if (li >= 0 && li < nb && lj >= 0 && lj < nb && lk >= 0 && lk < nb)
+                        continue;
+                    int I = mirror(bi * nb + li, n), J = mirror(bj * nb + lj, n), K = mirror(bk * nb + lk, n);
+                    size_t src = (size_t)(I / nb) + nbx * ((size_t)(J / nb) + nbx * (size_t)(K / nb));
+                    blocks[blk_at(nb, g, blk, li, lj, lk)] = blocks[blk_at(nb, g, src, I % nb, J % nb, K % nb)];
+                }
+    }
+    return ORC_OK;
+}
+
+/* y = A x block by block: each interior cell reads its six neighbours from its own block
+ * (guards included) and its face coefficients from the grid-layout arrays; the guards
+ * of y are set to 0.  Walls carry a zero coefficient, so the mirrored guards there do
+ * not enter. */
+int orc_blocks_apply(int n, int nb, int g, const double *bx, const double *by, const double *bz,
+                     const double *xblk, double *yblk)
+{
+    if (!blk_args_ok(n, nb, g) || g < 1 || !bx || !by || !bz || !xblk || !yblk)
+        return ORC_EINVAL;
+    int nbx = n / nb;
+    size_t nblk = (size_t)nbx * nbx * nbx;
+    size_t P = (size_t)nb + 2 * (size_t)g;
+    double inv_h2 = (double)n * (double)n;
+    memset(yblk, 0, sizeof(double) * nblk * P * P * P);
+    for (size_t blk = 0; blk < nblk; ++blk) {
+        int bi = (int)(blk % nbx), bj = (int)((blk / nbx) % nbx), bk = (int)(blk / ((size_t)nbx * nbx));
+        for (int lk = 0; lk < nb; ++lk)
+            for (int lj = 0; lj < nb; ++lj)
+                for (int li = 0; li < nb; ++li) {
+                    int i = bi * nb + li, j = bj * nb + lj, k = bk * nb + lk;
+                    size_t c = ix(n, i, j, k);
+                    double xc = xblk[blk_at(nb, g, blk, li, lj, lk)];
+                    double w[6] = {bx[c], i < n - 1 ? bx[ix(n, i + 1, j, k)] : 0.0,
+                                   by[c], j < n - 1 ? by[ix(n, i, j + 1, k)] : 0.0,
+                                   bz[c], k < n - 1 ? bz[ix(n, i, j, k + 1)] : 0.0};
+                    double xn[6] = {xblk[blk_at(nb, g, blk, li - 1, lj, lk)], xblk[blk_at(nb, g, blk, li + 1, lj, lk)],
+                                    xblk[blk_at(nb, g, blk, li, lj - 1, lk)], xblk[blk_at(nb, g, blk, li, lj + 1, lk)],
+                                    xblk[blk_at(nb, g, blk, li, lj, lk - 1)], xblk[blk_at(nb, g, blk, li, lj, lk + 1)]};
+                    double s = 0.0;
+                    for (int f = 0; f < 6; ++f)
+                        s += w[f] * (xn[f] - xc);
+                    yblk[blk_at(nb, g, blk, li, lj, lk)] = s * inv_h2;
+                }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole pipeline: phi, f -> faces, kappa, jterm, b, p                       */
 /* ------------------------------------------------------------------------ */
 /* kappa_override: NULL to compute kappa from phi, else a per-cell field used as is. */
