@@ -438,6 +438,49 @@ def heat256(M, G, torch, args):
     print(json.dumps(rec), flush=True)
 
 
+def blocks256(M, G, torch, args):
+    """The 256^3 rising-bubble grid in the block-structured layout: 4096 blocks of 16^3
+    cells with one guard layer.  Times (HIP events over `steps` repetitions) of the
+    scatter into blocks, the guard-cell fill, the block-by-block stencil and the gather,
+    against the HBM roofline with their algorithmic bytes."""
+    dev = torch.device("cuda:0")
+    n, nb, g = 256, 16, 1
+    K, W = max(args.steps, 5), args.warmup
+    pr = G.rising_bubble_problem(0, n=n)
+    op = M.Operator(torch.from_numpy(pr.phi).to(dev), pr.rho_neg, pr.rho_pos, pr.sigma)
+    x = torch.from_numpy(np.random.default_rng(3).standard_normal((n, n, n))).to(dev)
+    xb = M.blocks_scatter(x, nb, g)
+    yb = torch.empty_like(xb)
+    xg = torch.empty_like(x)
+    P = nb + 2 * g
+    nblk = (n // nb) ** 3
+    cells, padded, guards = n ** 3, nblk * P ** 3, nblk * (P ** 3 - nb ** 3)
+    steps = {"scatter": (lambda: M.blocks_scatter(x, nb, g, out=xb), 16.0 * cells),
+             "fill_guards": (lambda: M.blocks_fill_guards(xb, n, nb, g), 16.0 * guards),
+             "apply": (lambda: op.blocks_apply(xb, nb, g, out=yb), 16.0 * padded + 24.0 * cells),
+             "gather": (lambda: M.blocks_gather(xb, n, nb, g, out=xg), 16.0 * cells)}
+    res = {}
+    for name, (fn, nbytes) in steps.items():
+        for _ in range(W + 1):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / K
+        res[name] = {"us": round(us, 2), "GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
+                     "alg_bytes": nbytes}
+    ms = (res["fill_guards"]["us"] + res["apply"]["us"]) / 1e3
+    rec = {"metric": "guard-cell fill + block stencil on the 256^3 grid in 16^3 blocks",
+           "value": round(ms, 4), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "steps": K, "warmup": W, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "blocks256", "nb": nb, "guard": g, "blocks": nblk},
+           "kernels": res}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,7 +497,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", default="rising256",
                     choices=["rising256", "batched64", "single32", "bubbles128",
-                             "projection256", "flow256", "heat256"],
+                             "projection256", "flow256", "heat256", "blocks256"],
                     help="rising256: the 256^3 sequence (default); batched64: 64 x 64^3; "
                          "single32 / bubbles128: one fixed problem, plain vs mixed")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -490,6 +533,9 @@ def main():
         return
     if args.workload == "heat256":
         heat256(M, G, torch, args)
+        return
+    if args.workload == "blocks256":
+        blocks256(M, G, torch, args)
         return
     n, K, W = args.n, args.steps, args.warmup
     prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01, rtol=1e-10)

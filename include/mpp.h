@@ -267,6 +267,42 @@ int mpp_heat_solve(mpp_op op, const double *t_old, const double *src, double dt,
                    const mpp_solve_opts *opts, mpp_solve_info *info, void *stream);
 
 /* ------------------------------------------------------------------------------
+ * Block-structured layout (Sec. 2: the grid is a set of blocks of cells; the setup
+ * command of Sec. 4 builds 16^3 blocks; Sec. 4's driver fills guard cells, exchanging
+ * halos between blocks and applying the physical boundary condition, before the
+ * physics works block by block).  A problem of n^3 cells is cut into (n/nb)^3 blocks
+ * of nb^3 cells; block (bi, bj, bk) has index bi + (n/nb) (bj + (n/nb) bk) and is stored
+ * as P^3 doubles, P = nb + 2 g (g guard layers on every side, x fastest, the interior at
+ * offsets g .. g + nb - 1); problems follow each other: [batch][blocks][P^3].  Guard
+ * cells hold the value of the cell at their position in the neighbouring block (faces,
+ * edges and corners); outside the domain the field mirrored about the wall (even
+ * reflection: the zero-gradient condition of the no-flux walls).
+ * Common requirements: 2 <= n <= 1024, 1 <= batch <= 65535, 2 <= nb, n % nb == 0,
+ * 0 <= g <= nb; device pointers; asynchronous on `stream`; MPP_EINVAL on a violated
+ * requirement, MPP_EDEVICE if a launch fails.
+ * ------------------------------------------------------------------------------ */
+
+/* grid [batch][n^3] -> the block interiors (guards are not written); grid != blocks. */
+int mpp_blocks_scatter(int n, int batch, int nb, int g, const double *grid, double *blocks,
+                       void *stream);
+
+/* the block interiors -> grid [batch][n^3]; grid != blocks. */
+int mpp_blocks_gather(int n, int batch, int nb, int g, const double *blocks, double *grid,
+                      void *stream);
+
+/* Writes every guard cell from the block interiors, in place (interiors are read only).
+ * g == 0: nothing to do. */
+int mpp_blocks_fill_guards(int n, int batch, int nb, int g, double *blocks, void *stream);
+
+/* y = A x block by block for the operator's problems (n and batch from op): each
+ * interior cell reads its six neighbours from its own block, so x's guards must have
+ * been filled; faces are the operator's grid-layout coefficients (no jump term).  y's
+ * guards are set to 0.  g >= 1, P^3 <= 8192 (the padded block is staged in LDS, e.g. nb
+ * 16 with g <= 2); x != y. */
+int mpp_blocks_apply(mpp_op op, int nb, int g, const double *x_blocks, double *y_blocks,
+                     void *stream);
+
+/* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from
  * the previous pressure or from zero): a small 3D U-Net maps the density field and
  * the right-hand side of a problem to an approximate solution that seeds the PCG.

@@ -31,7 +31,8 @@ EXPORTS = (
     "mpp_net_destroy", "mpp_net_set_params", "mpp_net_get_params", "mpp_net_forward",
     "mpp_net_loss", "mpp_net_backward", "mpp_net_get_grads", "mpp_net_adam",
     "mpp_net_features", "mpp_learned_guess", "mpp_divergence", "mpp_project",
-    "mpp_ls_advect", "mpp_ls_reinit", "mpp_heat_solve",
+    "mpp_ls_advect", "mpp_ls_reinit", "mpp_heat_solve", "mpp_blocks_scatter",
+    "mpp_blocks_gather", "mpp_blocks_fill_guards", "mpp_blocks_apply",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -120,6 +121,10 @@ def load_library(path: str = LIB_PATH):
     L.mpp_project.argtypes = [P, P, P, d, P, P, P, P]
     L.mpp_ls_advect.argtypes = [i32, i32, P, P, P, P, d, P, P]
     L.mpp_ls_reinit.argtypes = [i32, i32, P, P, P, i32, d, P]
+    for nm in ("mpp_blocks_scatter", "mpp_blocks_gather"):
+        getattr(L, nm).argtypes = [i32, i32, i32, i32, P, P, P]
+    L.mpp_blocks_fill_guards.argtypes = [i32, i32, i32, i32, P, P]
+    L.mpp_blocks_apply.argtypes = [P, i32, i32, P, P, P]
     L.mpp_heat_solve.argtypes = [P, P, P, d, P, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), P]
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
@@ -348,6 +353,19 @@ class Operator:
             raise MppError(st, "mpp_heat_solve")
         return t, out
 
+    def blocks_apply(self, x_blocks, nb, g, out=None):
+        """y = A x on the block layout (guards of x filled); y's guards are 0."""
+        shape = _blocks_dims(self.n, nb, g, self.batch if self.batched else None)
+        _check_field(x_blocks, shape, "x_blocks")
+        y = _torch().empty_like(x_blocks) if out is None else out
+        _check_field(y, shape, "y_blocks")
+        st = load_library().mpp_blocks_apply(self._h, nb, g, ctypes.c_void_p(x_blocks.data_ptr()),
+                                             ctypes.c_void_p(y.data_ptr()),
+                                             _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_blocks_apply")
+        return y
+
     def divergence(self, u, dt, out=None):
         """f = div(u)/dt of the low-face velocities u = (ux, uy, uz)."""
         for name, a in zip(("ux", "uy", "uz"), u):
@@ -467,6 +485,61 @@ def ls_reinit(phi, iters, dtau=None, phi0=None, work=None):
     if st != OK:
         raise MppError(st, "mpp_ls_reinit")
     return phi
+
+
+def _blocks_dims(n, nb, g, batch):
+    nbx = n // nb
+    shape = (nbx ** 3, nb + 2 * g, nb + 2 * g, nb + 2 * g)
+    return shape if batch is None else (batch,) + shape
+
+
+def blocks_scatter(grid, nb, g, out=None):
+    """Grid (n,n,n) or (B,n,n,n) -> block layout (nblk,P,P,P) or (B,nblk,P,P,P); guards
+    of a new `out` are 0."""
+    torch = _torch()
+    batched = grid.dim() == 4
+    n = grid.shape[-1]
+    _check_field(grid, tuple(grid.shape), "grid")
+    shape = _blocks_dims(n, nb, g, grid.shape[0] if batched else None)
+    if out is None:
+        out = torch.zeros(shape, dtype=torch.float64, device=grid.device)
+    _check_field(out, shape, "blocks")
+    st = load_library().mpp_blocks_scatter(n, grid.shape[0] if batched else 1, nb, g,
+                                           ctypes.c_void_p(grid.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(grid.device))
+    if st != OK:
+        raise MppError(st, "mpp_blocks_scatter")
+    return out
+
+
+def blocks_gather(blocks, n, nb, g, out=None):
+    """Block layout -> grid (n,n,n) or (B,n,n,n)."""
+    torch = _torch()
+    batched = blocks.dim() == 5
+    B = blocks.shape[0] if batched else 1
+    _check_field(blocks, _blocks_dims(n, nb, g, B if batched else None), "blocks")
+    shape = (B, n, n, n) if batched else (n, n, n)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=blocks.device)
+    _check_field(out, shape, "grid")
+    st = load_library().mpp_blocks_gather(n, B, nb, g, ctypes.c_void_p(blocks.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()),
+                                          _stream_handle(blocks.device))
+    if st != OK:
+        raise MppError(st, "mpp_blocks_gather")
+    return out
+
+
+def blocks_fill_guards(blocks, n, nb, g):
+    """Fills the guard cells of a block layout in place; returns it."""
+    batched = blocks.dim() == 5
+    B = blocks.shape[0] if batched else 1
+    _check_field(blocks, _blocks_dims(n, nb, g, B if batched else None), "blocks")
+    st = load_library().mpp_blocks_fill_guards(n, B, nb, g, ctypes.c_void_p(blocks.data_ptr()),
+                                               _stream_handle(blocks.device))
+    if st != OK:
+        raise MppError(st, "mpp_blocks_fill_guards")
+    return blocks
 
 
 def net_param_count() -> int:

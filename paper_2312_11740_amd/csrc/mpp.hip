@@ -21,6 +21,7 @@
 #include "guess.h"
 #include "levelset.h"
 #include "heat.h"
+#include "blocks.h"
 #include "kernels.h"
 #include "net_internal.h"
 #include "project.h"
@@ -1532,6 +1533,82 @@ int mpp_ls_reinit(int n, int batch, const double* phi0, double* phi, double* wor
     return status_of(e.e);
   }
   return MPP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------
+// block-structured layout
+// ------------------------------------------------------------------------------
+namespace {
+
+bool blk_ok(int n, int batch, int nb, int g) {
+  return n >= 2 && n <= 1024 && batch >= 1 && batch <= 65535 && nb >= 2 && n % nb == 0 &&
+         g >= 0 && g <= nb;
+}
+
+int blk_launch_status() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MPP_OK : MPP_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpp_blocks_scatter(int n, int batch, int nb, int g, const double* grid, double* blocks,
+                       void* stream) {
+  if (!blk_ok(n, batch, nb, g) || !grid || !blocks || (const void*)grid == (const void*)blocks)
+    return MPP_EINVAL;
+  const BlkShape S = blk_shape(n, nb, g);
+#define L_(NB_, G_)                                                                       \
+  hipLaunchKernelGGL((k_blk_copy<0, NB_, G_>), dim3((unsigned)S.nblk, batch), dim3(kBlkThreads), \
+                     0, reinterpret_cast<hipStream_t>(stream), S, grid, blocks)
+  MPP_BLK_DISPATCH(S, L_);
+#undef L_
+  return blk_launch_status();
+}
+
+int mpp_blocks_gather(int n, int batch, int nb, int g, const double* blocks, double* grid,
+                      void* stream) {
+  if (!blk_ok(n, batch, nb, g) || !grid || !blocks || (const void*)grid == (const void*)blocks)
+    return MPP_EINVAL;
+  const BlkShape S = blk_shape(n, nb, g);
+#define L_(NB_, G_)                                                                       \
+  hipLaunchKernelGGL((k_blk_copy<1, NB_, G_>), dim3((unsigned)S.nblk, batch), dim3(kBlkThreads), \
+                     0, reinterpret_cast<hipStream_t>(stream), S, blocks, grid)
+  MPP_BLK_DISPATCH(S, L_);
+#undef L_
+  return blk_launch_status();
+}
+
+int mpp_blocks_fill_guards(int n, int batch, int nb, int g, double* blocks, void* stream) {
+  if (!blk_ok(n, batch, nb, g) || !blocks) return MPP_EINVAL;
+  if (g == 0) return MPP_OK;
+  const BlkShape S = blk_shape(n, nb, g);
+#define L_(NB_, G_)                                                                   \
+  hipLaunchKernelGGL((k_blk_fill<NB_, G_>), dim3((unsigned)S.nblk, batch), dim3(kBlkThreads), \
+                     0, reinterpret_cast<hipStream_t>(stream), S, blocks)
+  MPP_BLK_DISPATCH(S, L_);
+#undef L_
+  return blk_launch_status();
+}
+
+int mpp_blocks_apply(mpp_op op, int nb, int g, const double* x_blocks, double* y_blocks,
+                     void* stream) {
+  if (!op || !x_blocks || !y_blocks || (const void*)x_blocks == (const void*)y_blocks)
+    return MPP_EINVAL;
+  if (!blk_ok(op->n, op->batch, nb, g) || g < 1) return MPP_EINVAL;
+  const BlkShape S = blk_shape(op->n, nb, g);
+  if (S.P3 * sizeof(double) > 65536) return MPP_EINVAL;   // the padded block is staged in LDS
+  const Level& L0 = op->lev[0];
+#define L_(NB_, G_)                                                                          \
+  hipLaunchKernelGGL((k_blk_apply<NB_, G_>), dim3((unsigned)S.nblk, op->batch), dim3(kBlkThreads), \
+                     S.P3 * sizeof(double), reinterpret_cast<hipStream_t>(stream), S, L0.f64[0], \
+                     L0.f64[1], L0.f64[2], x_blocks, y_blocks)
+  MPP_BLK_DISPATCH(S, L_);
+#undef L_
+  return blk_launch_status();
 }
 
 }  // extern "C"

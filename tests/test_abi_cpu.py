@@ -122,3 +122,22 @@ def test_heat_solve_rejects_bad_arguments_before_device_work():
     L.mpp_default_opts(ctypes.byref(opts))
     opts.check_every = 0
     assert L.mpp_heat_solve(op, a, None, 0.1, b, ctypes.byref(opts), info, None) == M.EINVAL
+
+
+def test_block_layout_calls_reject_bad_arguments_before_device_work():
+    L = M.load_library()
+    a, b, op = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3))   # never dereferenced
+    for fn in (L.mpp_blocks_scatter, L.mpp_blocks_gather):
+        assert fn(32, 1, 16, 1, a, a, None) == M.EINVAL      # aliasing
+        assert fn(30, 1, 16, 1, a, b, None) == M.EINVAL      # n % nb
+        assert fn(32, 1, 16, 17, a, b, None) == M.EINVAL     # g > nb
+        assert fn(32, 1, 16, -1, a, b, None) == M.EINVAL
+        assert fn(32, 0, 16, 1, a, b, None) == M.EINVAL      # batch
+        assert fn(32, 1, 1, 1, a, b, None) == M.EINVAL       # nb < 2
+        assert fn(2048, 1, 16, 1, a, b, None) == M.EINVAL    # n too large
+        assert fn(32, 1, 16, 1, None, b, None) == M.EINVAL
+    assert L.mpp_blocks_fill_guards(32, 1, 16, 1, None, None) == M.EINVAL
+    assert L.mpp_blocks_fill_guards(32, 1, 12, 1, a, None) == M.EINVAL
+    assert L.mpp_blocks_fill_guards(32, 1, 16, 0, a, None) == M.OK        # nothing to do
+    assert L.mpp_blocks_apply(None, 16, 1, a, b, None) == M.EINVAL
+    assert L.mpp_blocks_apply(op, 16, 1, a, a, None) == M.EINVAL
