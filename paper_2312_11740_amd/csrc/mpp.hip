@@ -1522,10 +1522,10 @@ int mpp_ls_advect(int n, int batch, const double* phi, const double* ux, const d
       !phi_out || phi_out == phi || !(dt > 0.0) || !std::isfinite(dt))
     return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int cells = n * n * n;
-  const dim3 grid((cells + kLsBlock - 1) / kLsBlock, batch);
+  const LsTiles tl = ls_tiles(n);
+  const dim3 grid(8 * ((tl.ntiles + 7) / 8), batch);
   try {
-    hipLaunchKernelGGL(k_ls_advect, grid, dim3(kLsBlock), 0, s, phi, ux, uy, uz, n, cells, dt,
+    hipLaunchKernelGGL(k_ls_advect_z, grid, dim3(kLsTX * kLsTY), 0, s, phi, ux, uy, uz, n, tl, dt,
                        phi_out);
     ck_launch();
   } catch (HipError& e) {
@@ -1542,11 +1542,14 @@ int mpp_ls_reinit(int n, int batch, const double* phi0, double* phi, double* wor
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int cells = n * n * n;
   const dim3 grid((cells + kLsBlock - 1) / kLsBlock, batch);
+  const LsTiles tl = ls_tiles(n);
+  const dim3 zgrid(8 * ((tl.ntiles + 7) / 8), batch);
   try {
     double* src = phi;
     double* dst = work;
     for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(k_ls_reinit, grid, dim3(kLsBlock), 0, s, phi0, src, n, cells, dtau, dst);
+      hipLaunchKernelGGL(k_ls_reinit_z, zgrid, dim3(kLsTX * kLsTY), 0, s, phi0, src, n, tl, dtau,
+                         dst);
       ck_launch();
       std::swap(src, dst);
     }
