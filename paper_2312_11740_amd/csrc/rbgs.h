@@ -149,6 +149,8 @@ __global__ void __launch_bounds__(kRbThreads)
   // diagonal shift times h^2; with a shift every cell takes the general update
   const T sh2 = F.sig * h2;
   const bool plain = sh2 == T(0);
+  // shifted operator, cell without a crossed face: x = (sum - hr b) / (faces + sig hr)
+  const T shr0 = FINE ? F.sig * hr0 : T(0), shr1 = FINE ? F.sig * hr1 : T(0);
   double acc = 0.0;
 
   // ---- plane-invariant per-thread offsets (0 where the cell does not exist) ----
@@ -271,16 +273,20 @@ __global__ void __launch_bounds__(kRbThreads)
   auto update = [&](bool nb, unsigned cd, size_t cell, int i, int j, int k, bool wl, bool wr,
                     bool ws, bool wn, bool wd, bool wu, T xw, T xe, T xs, T xn, T xd, T xu, T bb,
                     T inv1, T inv2) -> T {
-    if (FINE && (cd & 63u) == 0u && plain) {
+    if (FINE && (cd & 63u) == 0u) {
       T sum = T(0);
       if (nb) {
         sum = (wl ? xw : T(0)) + (wr ? xe : T(0));
         sum += (ws ? xs : T(0)) + (wn ? xn : T(0));
         sum += (wd ? xd : T(0)) + (wu ? xu : T(0));
       }
-      const T inv = (wd && wu) ? inv2 : inv1;
       const T hr = (cd & 64u) ? hr1 : hr0;
-      return (sum - hr * bb) * inv;
+      if (plain) {
+        const T inv = (wd && wu) ? inv2 : inv1;
+        return (sum - hr * bb) * inv;
+      }
+      const T cnt = T((int)wl + (int)wr + (int)ws + (int)wn + (int)wd + (int)wu);
+      return (sum - hr * bb) / (cnt + ((cd & 64u) ? shr1 : shr0));
     }
     T w[6];
     sweep_faces<T, FINE>(F, cell, cd, i, j, k, n, nn, ir0, ir1, w);

@@ -71,6 +71,8 @@ __global__ void __launch_bounds__(k3Threads)
   // diagonal shift times h^2; with a shift every cell takes the general update
   const T sh2 = F.sig * h2;
   const bool plain = sh2 == T(0);
+  // shifted operator, cell without a crossed face: x = (sum - hr b) / (faces + sig hr)
+  const T shr0 = FINE ? F.sig * hr0 : T(0), shr1 = FINE ? F.sig * hr1 : T(0);
 
   // ---- every load of the block at once ----
   constexpr int PX = (k3NX + k3Threads - 1) / k3Threads;
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(k3Threads)
   auto update = [&](bool nb, unsigned cd, size_t cell, int i, int j, int k, T xw, T xe, T xs,
                     T xn, T xd, T xu, T bb) -> T {
     const bool wl = i > 0, wr = i < n - 1, ws = j > 0, wn = j < n - 1, wd = k > 0, wu = k < n - 1;
-    if (FINE && (cd & 63u) == 0u && plain) {
+    if (FINE && (cd & 63u) == 0u) {
       T sum = T(0);
       if (nb) {
         sum = (wl ? xw : T(0)) + (wr ? xe : T(0));
@@ -135,8 +137,9 @@ __global__ void __launch_bounds__(k3Threads)
         sum += (wd ? xd : T(0)) + (wu ? xu : T(0));
       }
       const int cnt = (int)wl + (int)wr + (int)ws + (int)wn + (int)wd + (int)wu;
-      const T inv = cnt == 6 ? T(1) / T(6) : (cnt == 5 ? T(1) / T(5) : (cnt == 4 ? T(0.25) : T(1) / T(3)));
       const T hr = (cd & 64u) ? hr1 : hr0;
+      if (!plain) return (sum - hr * bb) / (T(cnt) + ((cd & 64u) ? shr1 : shr0));
+      const T inv = cnt == 6 ? T(1) / T(6) : (cnt == 5 ? T(1) / T(5) : (cnt == 4 ? T(0.25) : T(1) / T(3)));
       return (sum - hr * bb) * inv;
     }
     T w[6];

@@ -129,6 +129,8 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   // diagonal shift times h^2; with a shift every cell takes the coded update
   const T sh2 = F.sig * h2;
   const bool shifted = sh2 != T(0);
+  // shifted operator, cell without a crossed face: x = (sum - hr b) / (faces + sig hr)
+  const T shr0 = F.sig * hr0, shr1 = F.sig * hr1;
   const T inv6 = T(1) / T(6), inv5 = T(1) / T(5), inv4 = T(1) / T(4), inv3 = T(1) / T(3);
   auto inv_of = [&](int walls) {
     return walls <= 0 ? inv6 : (walls == 1 ? inv5 : (walls == 2 ? inv4 : inv3));
@@ -270,8 +272,15 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
                    T xs, T xn, T xd, T xu, T bb) -> T {
     const T sum = ((xw + xe) + (xs + xn)) + (xd + xu);
     const T hr = (cd & 64u) ? hr1 : hr0;
-    T v = (sum - hr * bb) * inv;
-    const bool crossed = (cd & 63u) != 0u || shifted;
+    T v;
+    if (shifted) {
+      // the face count from the reciprocal the caller passes (1/6, 1/5, 1/4 or 1/3)
+      const T cnt = inv == inv6 ? T(6) : (inv == inv5 ? T(5) : (inv == inv4 ? T(4) : T(3)));
+      v = (sum - hr * bb) / (cnt + ((cd & 64u) ? shr1 : shr0));
+    } else {
+      v = (sum - hr * bb) * inv;
+    }
+    const bool crossed = (cd & 63u) != 0u;
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(crossed) != 0, 0)) {
       if (crossed) v = relax_coded(cd, pb, off, ic, jc, kc, xw, xe, xs, xn, xd, xu, bb);
     }

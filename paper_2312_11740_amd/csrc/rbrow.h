@@ -186,8 +186,9 @@ __global__ void __launch_bounds__(kRowWaves * 64, kRowMinBlocks)
     const int walls = (ic == 0) + (ic == n - 1) + (jc == 0) + (jc == n - 1) + (kc == 0) + (kc == n - 1);
     const T sum = ((xw + xe) + (xs + xn)) + (xd + xu);
     const T hr = (cd & 64u) ? hr1 : hr0;
-    T v = (sum - hr * bb) * inv_of(walls);
-    const bool crossed = (cd & 63u) != 0u || shifted;
+    T v = shifted ? (sum - hr * bb) / (T(6 - walls) + ((cd & 64u) ? F.sig * hr1 : F.sig * hr0))
+                  : (sum - hr * bb) * inv_of(walls);
+    const bool crossed = (cd & 63u) != 0u;
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(crossed) != 0, 0)) {
       if (crossed) {
         T wf[6];
