@@ -120,6 +120,17 @@ def run_profiled(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None)
     return stats
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(prob, p_gpu):
     """The FP64 CPU oracle (as it stands) on one full-size step: assemble + MG-PCG to
     1e-10 on the host cores.  Returns the record and the GPU-vs-oracle error."""
@@ -135,7 +146,8 @@ def cpu_baseline(prob, p_gpu):
     if p_gpu is not None:
         err = float(np.linalg.norm(p_gpu - po) / np.linalg.norm(po))
         rr = float(O.rel_residual(d["faces"], d["b"], p_gpu))
-    rec = {"value": round(sec * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+    rec = {"value": round(sec * 1e3, 1), "unit": "ms", "cores": cores, "cpu": cpu_model(),
+           "kind": "oracle",
            "sample": "one 256^3 step (t=0) of the same sequence, zero start, assemble + "
                      "FP64 MG-PCG (nu=2) to 1e-10 (%d iterations)" % oi["iters"]}
     return rec, err, rr
@@ -208,7 +220,8 @@ def cpu_baseline_single(pr, solutions, rtol):
     po, _, oi = O.solve(pr.phi, pr.f, pr.rho_neg, pr.rho_pos, pr.sigma, tol=1e-13)
     sec = time.perf_counter() - t0
     errs = {m: float(np.linalg.norm(ph - po) / np.linalg.norm(po)) for m, ph in solutions.items()}
-    rec = {"value": round(sec * 1e3, 1), "unit": "ms", "cores": cores, "kind": "oracle",
+    rec = {"value": round(sec * 1e3, 1), "unit": "ms", "cores": cores, "cpu": cpu_model(),
+           "kind": "oracle",
            "sample": "the whole problem: assemble + FP64 MG-PCG (nu=2) to 1e-13 (%d iterations)"
                      % oi["iters"]}
     return rec, errs
