@@ -27,6 +27,12 @@
  * ||b - A p||_2 <= rtol ||b||_2, by conjugate gradients on -A preconditioned with a
  * geometric multigrid V-cycle.
  *
+ * Around the solve (sections below): the projection that produces f from the face
+ * velocities and corrects them with p; the level-set step that moves phi with the
+ * corrected velocity and keeps it a distance; an implicit heat-diffusion step on the
+ * same operator and multigrid (a diagonal shift per level); a block-structured layout
+ * with guard cells; and a learned initial guess for the solve.
+ *
  * Memory and layout.  Every array argument is DEVICE memory on the current HIP
  * device unless marked "host".  A grid field is n^3 doubles, x fastest: cell (i,j,k)
  * at offset i + n*(j + n*k).  Batched calls take [batch][n^3] contiguous fields.
