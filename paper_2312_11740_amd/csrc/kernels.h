@@ -232,38 +232,61 @@ __global__ void k_params(const double* rho, double* ir64, float* ir32, int B) {
   ir32[2 * b + 1] = (float)c;
 }
 
-// Face coefficients (low face of each cell), FP32 copies and the finest-level code.
-__global__ void k_faces(const double* __restrict__ phi, const double* __restrict__ rho, int n,
-                        int cells, uint8_t* __restrict__ code, double* __restrict__ bx,
-                        double* __restrict__ by, double* __restrict__ bz, float* __restrict__ fx,
-                        float* __restrict__ fy, float* __restrict__ fz, int* __restrict__ bad) {
+// Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous run of
+// tiles so that neighbouring tiles (which share halo rows) sit in the same L2.
+// The grid has 8 * ceil(ntiles / 8) blocks; the surplus ones get -1.
+__device__ inline int xcd_tile(int bid, int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  const int t = (bid & 7) * per + (bid >> 3);
+  return t < ntiles ? t : -1;
+}
+
+// Face coefficients (low face of each cell), FP32 copies and the finest-level code,
+// marching columns: a block owns a 64 x 4 column of cells and a chunk of kz planes, holding phi of planes k - 1, k, k + 1 of its own column
+// in registers; in-plane neighbours come through the caches.
+__global__ void __launch_bounds__(256)
+    k_faces(const double* __restrict__ phi, const double* __restrict__ rho, int n, int ntx, int nty,
+            int kz, int ntiles, uint8_t* __restrict__ code, double* __restrict__ bx,
+            double* __restrict__ by, double* __restrict__ bz, float* __restrict__ fx,
+            float* __restrict__ fy, float* __restrict__ fz, int* __restrict__ bad) {
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  if (tile < 0) return;
   const int b = blockIdx.y;
-  const size_t base = (size_t)b * cells;
-  const double rn = rho[3 * b + 0], rp = rho[3 * b + 1];
+  const int ti = tile % ntx, tj = (tile / ntx) % nty, tk = tile / (ntx * nty);
+  const int i = ti * 64 + (int)(threadIdx.x % 64), j = tj * 4 + (int)(threadIdx.x / 64);
+  if (i >= n || j >= n) return;
+  const int k0 = tk * kz, k1 = min(k0 + kz, n);
   const size_t nn = (size_t)n * n;
-  CELL_LOOP(cells) {
-    int i, j, k;
-    ijk(c, n, i, j, k);
-    const double pc = phi[base + c];
+  const size_t col = (size_t)b * nn * n + (size_t)i + (size_t)n * j;
+  const double rn = rho[3 * b + 0], rp = rho[3 * b + 1];
+  double pm = k0 > 0 ? phi[col + (size_t)(k0 - 1) * nn] : 0.0;
+  double pc = phi[col + (size_t)k0 * nn];
+  for (int k = k0; k < k1; ++k) {
+    const size_t q = col + (size_t)k * nn;
+    const double pp = k < n - 1 ? phi[q + nn] : 0.0;
+    const double pw = i > 0 ? phi[q - 1] : 0.0, pe = i < n - 1 ? phi[q + 1] : 0.0;
+    const double ps = j > 0 ? phi[q - n] : 0.0, pn = j < n - 1 ? phi[q + n] : 0.0;
     if (!isfinite(pc)) atomicOr(bad, 1);
     const bool s = plus_side(pc);
-    const double vx = i > 0 ? ghost_fluid_beta(phi[base + c - 1], pc, rn, rp) : 0.0;
-    const double vy = j > 0 ? ghost_fluid_beta(phi[base + c - n], pc, rn, rp) : 0.0;
-    const double vz = k > 0 ? ghost_fluid_beta(phi[base + c - nn], pc, rn, rp) : 0.0;
-    bx[base + c] = vx;
-    by[base + c] = vy;
-    bz[base + c] = vz;
-    fx[base + c] = (float)vx;
-    fy[base + c] = (float)vy;
-    fz[base + c] = (float)vz;
+    const double vx = i > 0 ? ghost_fluid_beta(pw, pc, rn, rp) : 0.0;
+    const double vy = j > 0 ? ghost_fluid_beta(ps, pc, rn, rp) : 0.0;
+    const double vz = k > 0 ? ghost_fluid_beta(pm, pc, rn, rp) : 0.0;
+    bx[q] = vx;
+    by[q] = vy;
+    bz[q] = vz;
+    fx[q] = (float)vx;
+    fy[q] = (float)vy;
+    fz[q] = (float)vz;
     unsigned cd = s ? 64u : 0u;
-    if (i > 0 && plus_side(phi[base + c - 1]) != s) cd |= 1u;
-    if (i < n - 1 && plus_side(phi[base + c + 1]) != s) cd |= 2u;
-    if (j > 0 && plus_side(phi[base + c - n]) != s) cd |= 4u;
-    if (j < n - 1 && plus_side(phi[base + c + n]) != s) cd |= 8u;
-    if (k > 0 && plus_side(phi[base + c - nn]) != s) cd |= 16u;
-    if (k < n - 1 && plus_side(phi[base + c + nn]) != s) cd |= 32u;
-    code[base + c] = (uint8_t)cd;
+    if (i > 0 && plus_side(pw) != s) cd |= 1u;
+    if (i < n - 1 && plus_side(pe) != s) cd |= 2u;
+    if (j > 0 && plus_side(ps) != s) cd |= 4u;
+    if (j < n - 1 && plus_side(pn) != s) cd |= 8u;
+    if (k > 0 && plus_side(pm) != s) cd |= 16u;
+    if (k < n - 1 && plus_side(pp) != s) cd |= 32u;
+    code[q] = (uint8_t)cd;
+    pm = pc;
+    pc = pp;
   }
 }
 

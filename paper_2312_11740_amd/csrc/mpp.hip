@@ -543,7 +543,10 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<T>, g1, dim3(kBlock), 0, s, in, (int)L.cells, T(0));
     hipLaunchKernelGGL(k_fill<T>, g1, dim3(kBlock), 0, s, const_cast<T*>(rhs), (int)L.cells, T(0));
     ck_launch();
-    const Faces<T> F = faces_of<T>(op, l);
+    // timed on the unshifted operator, whatever the operator's current use: the choice
+    // is cached per shape and shared by pressure and heat solves
+    Faces<T> F = faces_of<T>(op, l);
+    F.sig = T(0);
     float best = 1e30f;
     int best_kz = 0;
     // candidates: the z-marching kernel with chunks of 2 .. 32 planes, the 3D-tile kernel,
@@ -1070,8 +1073,13 @@ int build_into(mpp_op_s* op, const double* phi, const std::vector<double>& host,
   Level& L0 = op->lev[0];
   const int n = op->n, cells = (int)L0.cells;
   const dim3 g = grid_of(L0, B);
-  hipLaunchKernelGGL(k_faces, g, dim3(kBlock), 0, s, phi, op->rho, n, cells, L0.code, L0.f64[0],
-                     L0.f64[1], L0.f64[2], L0.f32[0], L0.f32[1], L0.f32[2], op->outer.status);
+  {
+    const int ntx = (n + 63) / 64, nty = (n + 3) / 4, kz = 16, nkz = (n + kz - 1) / kz;
+    const int ntiles = ntx * nty * nkz;
+    hipLaunchKernelGGL(k_faces, dim3(8 * ((ntiles + 7) / 8), B), dim3(256), 0, s, phi, op->rho, n,
+                       ntx, nty, kz, ntiles, L0.code, L0.f64[0], L0.f64[1], L0.f64[2], L0.f32[0],
+                       L0.f32[1], L0.f32[2], op->outer.status);
+  }
   ck_launch();
   hipLaunchKernelGGL(k_curvature, g, dim3(kBlock), 0, s, phi, L0.code, n, cells, op->kappa);
   ck_launch();

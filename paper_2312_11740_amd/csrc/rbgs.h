@@ -51,14 +51,6 @@ inline RbTiles rb_tiles(int n, int batch = 1, int kz = 0) {
   return t;
 }
 
-// Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous run of
-// tiles so that neighbouring tiles (which share halo rows) sit in the same L2.
-// The grid has 8 * ceil(ntiles / 8) blocks; the surplus ones get -1.
-__device__ inline int xcd_tile(int bid, int ntiles) {
-  const int per = (ntiles + 7) / 8;
-  const int t = (bid & 7) * per + (bid >> 3);
-  return t < ntiles ? t : -1;
-}
 
 inline int rb_grid(const RbTiles& t) { return 8 * ((t.ntiles + 7) / 8); }
 
