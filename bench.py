@@ -270,6 +270,22 @@ def single_problem(M, G, torch, args, which):
                       "methods": res, "cpu_baseline": cpu}), flush=True)
 
 
+def oracle_leg(fn, sample):
+    """Times one run of an oracle computation on the host cores; returns (the
+    cpu_baseline record, the computation's result)."""
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    out = fn()
+    sec = time.perf_counter() - t0
+    rec = {"value": round(sec * 1e3, 1), "unit": "ms", "cores": cores, "cpu": cpu_model(),
+           "kind": "oracle", "sample": sample}
+    return rec, out
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
 def projection256(M, G, torch, args):
     """The projection step around the solve on the 256^3 rising-bubble sequence: f =
     div(u*)/dt from seeded face velocities, the mixed solve warm-started from the
@@ -291,6 +307,7 @@ def projection256(M, G, torch, args):
         u[1][:, 0, :] = 0.0
         u[2][0, :, :] = 0.0
         us.append(u)
+    u0_host = [a.cpu().numpy() for a in us[0]]   # step 0's predicted velocity, for the oracle
     op = M.Operator(phis[0], **prm)
     p = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
     f = torch.empty_like(p)
@@ -331,6 +348,19 @@ def projection256(M, G, torch, args):
                                    "GBps": round(proj_bytes / (proj_ms * 1e-3) / 1e9, 1),
                                    "alg_bytes": proj_bytes}},
            "iters_last": info[0].iters, "div_ratio_last": ratio}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        q0 = probs[0]
+
+        def step():
+            fo = O.divergence(u0_host, dt)
+            od = O.pipeline(q0.phi, fo, prm["rho_neg"], prm["rho_pos"], prm["sigma"])
+            po, _ = O.solve_mg_pcg(od["faces"], od["b"], tol=1e-10)
+            return O.project(q0.phi, od["kappa"], po, prm["rho_neg"], prm["rho_pos"], prm["sigma"],
+                             dt, u0_host)
+        rec["cpu_baseline"], uo = oracle_leg(step, "step 0 at full size: divergence, operator, "
+                                             "FP64 MG-PCG to 1e-10 from zero, correction")
+        rec["err_vs_oracle_step0"] = max(rel_err(a.cpu().numpy(), b) for a, b in zip(us[0], uo))
     print(json.dumps(rec), flush=True)
 
 
@@ -357,6 +387,8 @@ def flow256(M, G, torch, args):
         m = (ph < 0).double()
         return float((zs * m).sum() / m.sum())
 
+    phi_init = phi.cpu().numpy()
+    phi_step1 = None
     for t in range(K + W):
         if t == W:
             torch.cuda.synchronize()
@@ -374,6 +406,8 @@ def flow256(M, G, torch, args):
         M.ls_reinit(new, 2, phi0=phi0, work=work)
         ev[2].record()
         phi = new
+        if t == 0 and W >= 1:
+            phi_step1 = phi.cpu().numpy()   # state after step 0 (a warm-up step), for the oracle
         if t >= W:
             torch.cuda.synchronize()
             t_adv.append(ev[0].elapsed_time(ev[1]))
@@ -396,6 +430,23 @@ def flow256(M, G, torch, args):
                                         "GBps": round(re_bytes / (re_ms * 1e-3) / 1e9, 1),
                                         "alg_bytes": re_bytes}},
            "solve_iters": iters, "bubble_rise": centre(phi) - z0}
+    if not args.no_cpu_baseline and phi_step1 is not None:
+        import oracle as O
+
+        def step():
+            uo = [np.zeros((n, n, n)) for _ in range(3)]
+            uo[2][1:, :, :] -= dt * g
+            fo = O.divergence(uo, dt)
+            od = O.pipeline(phi_init, fo, prm["rho_neg"], prm["rho_pos"], prm["sigma"])
+            po, _ = O.solve_mg_pcg(od["faces"], od["b"], tol=1e-10)
+            uo = O.project(phi_init, od["kappa"], po, prm["rho_neg"], prm["rho_pos"], prm["sigma"],
+                           dt, uo)
+            new = O.ls_advect(phi_init, uo, dt)
+            return O.ls_reinit(new, new, 2, 0.5 / n)
+        rec["cpu_baseline"], po1 = oracle_leg(step, "step 0 at full size: gravity, divergence, "
+                                              "operator, FP64 MG-PCG to 1e-10, correction, "
+                                              "advection, two re-distancing steps")
+        rec["err_vs_oracle_step0"] = rel_err(phi_step1, po1)
     print(json.dumps(rec), flush=True)
 
 
@@ -418,6 +469,7 @@ def heat256(M, G, torch, args):
                "mg_fp64": dict(precond="mg", mode="fp64"),
                "jacobi": dict(precond="jacobi")}
     res = {}
+    first = {}
     for name, how in methods.items():
         T = T0.clone()
         iters = []
@@ -426,6 +478,8 @@ def heat256(M, G, torch, args):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
             T, info = op.heat_solve(T, dt, t=T, rtol=1e-10, **how)
+            if t == 0 and W >= 1:
+                first[name] = T.cpu().numpy()   # step 0 (a warm-up step), for the oracle
             if t >= W:
                 iters.append(info[0].iters)
         torch.cuda.synchronize()
@@ -448,6 +502,16 @@ def heat256(M, G, torch, args):
            "data": "synthetic", "dtype": "f64+f32",
            "config": {"workload": "heat256", "dt": dt, "k_liquid": kn, "k_vapour": kp},
            "methods": res}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        t0h = T0.cpu().numpy()
+
+        def step():
+            return O.heat_step(O.heat_faces(phi.cpu().numpy(), kn, kp), t0h, dt, tol=1e-10)[0]
+        rec["cpu_baseline"], to = oracle_leg(step, "step 0 at full size: conductivity faces, "
+                                             "conjugate gradients to 1e-10 (no preconditioner)")
+        if first:
+            rec["err_vs_oracle_step0"] = {k: rel_err(v, to) for k, v in first.items()}
     print(json.dumps(rec), flush=True)
 
 
@@ -491,6 +555,18 @@ def blocks256(M, G, torch, args):
            "steps": K, "warmup": W, "data": "synthetic", "dtype": "f64",
            "config": {"workload": "blocks256", "nb": nb, "guard": g, "blocks": nblk},
            "kernels": res}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        xh = x.cpu().numpy()
+        fc = O.faces(pr.phi, pr.rho_neg, pr.rho_pos)
+
+        def step():
+            blk = O.blocks_fill_guards(O.blocks_scatter(xh, nb, g), n, nb, g)
+            return O.blocks_apply(fc, blk, nb, g)
+        rec["cpu_baseline"], yo = oracle_leg(step, "one scatter + guard fill + block stencil at "
+                                             "full size (4096 blocks)")
+        M.blocks_fill_guards(xb, n, nb, g)
+        rec["bit_exact_vs_oracle"] = bool(np.array_equal(op.blocks_apply(xb, nb, g).cpu().numpy(), yo))
     print(json.dumps(rec), flush=True)
 
 
