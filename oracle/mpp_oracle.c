@@ -30,6 +30,15 @@
  *     2000); this gives Young-Laplace p_in - p_out = 2 sigma / R for a sphere under
  *     either orientation of phi;
  *   - a cell with phi == 0 belongs to the phi <= 0 side.
+ * Around the solve (each section below states its reading):
+ *   - the projection: f = div(u*)/dt on the staggered faces, u = u* - dt beta grad p
+ *     with the jump-corrected gradient (Sec. 2);
+ *   - the level set: first-order upwind advection by the face velocities and
+ *     smoothed-sign Godunov re-distancing (Sec. 3, Multiphase / StencilsLevelSet);
+ *   - heat diffusion: one backward-Euler step with the conductivity of each phase, the
+ *     two in series on crossed faces (Sec. 2 transport equation, Sec. 3 HeatAD);
+ *   - the block-structured layout: blocks with guard cells filled from their
+ *     neighbours, mirrored at the walls (Sec. 2 blocks, Sec. 4 guard-cell fill).
  *
  * Conventions (shared with the GPU library only through this description):
  *   n^3 cells, h = 1/n, cell (i,j,k) centre ((i+1/2)h, (j+1/2)h, (k+1/2)h),
