@@ -41,6 +41,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+NU_COARSE = 0   # sweeps per level below the finest (0: as the finest); set by --nu-coarse
 
 
 def log(*a):
@@ -90,6 +91,7 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
             if t >= warmup:
                 fallbacks += sum(fell)
         p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu,
+                           nu_coarse=NU_COARSE,
                            check_every=check_every)
         if t >= warmup:
             infos.append(info[0])
@@ -109,7 +111,7 @@ def run_profiled(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None)
             p, _ = op.learned_guess(net, fs[t], sweeps=2, out=p)
         if t >= warmup:
             op.profile_start()
-        p, info = op.solve(fs[t], p=p, rtol=prm["rtol"], mode=mode, nu=nu)
+        p, info = op.solve(fs[t], p=p, rtol=prm["rtol"], mode=mode, nu=nu, nu_coarse=NU_COARSE)
         if t >= warmup:
             for k, v in op.profile_stop().items():
                 s = stats.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))
@@ -577,6 +579,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--nu", type=int, default=2)
+    ap.add_argument("--nu-coarse", type=int, default=0,
+                    help="sweeps per level below the finest (0: as --nu)")
     ap.add_argument("--methods", default="plain,plain0,mixed,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--guess-sweeps", type=int, default=2,
@@ -592,6 +596,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter scaling)")
     args = ap.parse_args()
+    global NU_COARSE
+    NU_COARSE = args.nu_coarse
 
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
