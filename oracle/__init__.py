@@ -64,6 +64,8 @@ def lib():
             getattr(L, nm).argtypes = [i, i, i, P, P]
         L.orc_blocks_fill_guards.argtypes = [i, i, i, P]
         L.orc_blocks_apply.argtypes = [i, i, i, P, P, P, P, P]
+        L.orc_amr_apply.argtypes = [i, i, P, P, P, P, P, d, d, P, P]
+        L.orc_amr_fill.argtypes = [i, i, i, P, P, P, P, P]
         L.orc_gs_colour.argtypes = [i, P, P, P, P, P, i]
         L.orc_gs_colour.restype = None
         L.orc_restrict.argtypes = [i, P, P]
@@ -283,6 +285,33 @@ def blocks_apply(fc, xblk, nb, g):
     _check(lib().orc_blocks_apply(n, nb, g, _p(bx), _p(by), _p(bz), _p(xblk), _p(y)),
            "blocks_apply")
     return y
+
+
+def amr_apply(refined0, nb, phi0, phi1, x0, x1, rho_neg, rho_pos):
+    """Composite operator of a two-level grid: refined0 (nbx^3 uint8) marks the level-0
+    blocks covered by level 1; phi0, x0 (n0^3) and phi1, x1 ((2 n0)^3) hold the two
+    levels (only leaf cells matter).  Returns (y0, y1), zero off the leaves."""
+    refined0 = np.ascontiguousarray(refined0, dtype=np.uint8)
+    phi0, phi1, x0, x1 = (_c(a) for a in (phi0, phi1, x0, x1))
+    n0 = _n(phi0)
+    y0, y1 = np.empty_like(x0), np.empty_like(x1)
+    _check(lib().orc_amr_apply(n0, nb, _p(refined0), _p(phi0), _p(phi1), _p(x0), _p(x1),
+                               float(rho_neg), float(rho_pos), _p(y0), _p(y1)), "amr_apply")
+    return y0, y1
+
+
+def amr_fill(refined0, nb, g, v0, v1):
+    """Padded blocks of both levels of a composite field with their guard cells:
+    ((n0/nb)^3, P, P, P) and ((2 n0/nb)^3, P, P, P)."""
+    refined0 = np.ascontiguousarray(refined0, dtype=np.uint8)
+    v0, v1 = _c(v0), _c(v1)
+    n0 = _n(v0)
+    P = nb + 2 * g
+    b0 = np.empty(((n0 // nb) ** 3, P, P, P))
+    b1 = np.empty(((2 * n0 // nb) ** 3, P, P, P))
+    _check(lib().orc_amr_fill(n0, nb, g, _p(refined0), _p(v0), _p(v1), _p(b0), _p(b1)),
+           "amr_fill")
+    return b0, b1
 
 
 def pipeline(phi, f, rho_neg, rho_pos, sigma, kappa_override=None):

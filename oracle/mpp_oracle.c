@@ -38,7 +38,11 @@
  *   - heat diffusion: one backward-Euler step with the conductivity of each phase, the
  *     two in series on crossed faces (Sec. 2 transport equation, Sec. 3 HeatAD);
  *   - the block-structured layout: blocks with guard cells filled from their
- *     neighbours, mirrored at the walls (Sec. 2 blocks, Sec. 4 guard-cell fill).
+ *     neighbours, mirrored at the walls (Sec. 2 blocks, Sec. 4 guard-cell fill);
+ *   - two levels of refinement (Sec. 2, Fig. 2: blocks at two resolutions): the
+ *     conservative finite-volume operator on the leaf cells, each coarse-fine flux
+ *     taken once from the fine face and shared by both sides; guard cells as the
+ *     volume average of the leaf field over the guard cell.
  *
  * Conventions (shared with the GPU library only through this description):
  *   n^3 cells, h = 1/n, cell (i,j,k) centre ((i+1/2)h, (j+1/2)h, (k+1/2)h),
@@ -1132,6 +1136,170 @@ int orc_blocks_apply(int n, int nb, int g, const double *bx, const double *by, c
                         s += w[f] * (xn[f] - xc);
                     yblk[blk_at(nb, g, blk, li, lj, lk)] = s * inv_h2;
                 }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-level composite grid (Sec. 2: blocks at two resolutions, the finer one */
+/* around the interface; Fig. 2 shows a block refined to half the spacing).   */
+/* Level 0 has n0^3 cells (h0 = 1/n0) in blocks of nb^3; refined0[b] marks the */
+/* level-0 blocks covered by level 1, whose (2 n0)^3 cells (h1 = h0 / 2) are   */
+/* meaningful only inside refined blocks.  The leaf cells are the level-0     */
+/* cells of unrefined blocks and the level-1 cells of refined ones.  The      */
+/* operator is the conservative finite-volume form                             */
+/*    (A x)_c = (1/V_c) sum_f a_f beta_f (x_nb - x_c) / d_f,                   */
+/* a_f the face area, d_f the distance between the two cell centres; across a */
+/* coarse-fine face the fine cell sees the coarse cell itself (d = 1.5 h1,    */
+/* area h1^2) and the coarse cell the sum of the four fine fluxes, so every   */
+/* flux leaves one cell and enters the other.  beta_f is the ghost-fluid      */
+/* coefficient of the two cells, lower coordinate first.  Walls: no flux.     */
+/* ------------------------------------------------------------------------ */
+
+static int amr_refined(int n0, int nb, const uint8_t *refined0, int I, int J, int K)
+{
+    int nbx = n0 / nb;
+    return refined0[(size_t)(I / nb) + nbx * ((size_t)(J / nb) + nbx * (size_t)(K / nb))] != 0;
+}
+
+int orc_amr_apply(int n0, int nb, const uint8_t *refined0, const double *phi0, const double *phi1,
+                  const double *x0, const double *x1, double rho_neg, double rho_pos, double *y0,
+                  double *y1)
+{
+    if (n0 < 1 || nb < 1 || n0 % nb || !refined0 || !phi0 || !phi1 || !x0 || !x1 || !y0 || !y1 ||
+        !(rho_neg > 0.0) || !(rho_pos > 0.0))
+        return ORC_EINVAL;
+    int n1 = 2 * n0;
+    double h0 = 1.0 / n0, h1 = 0.5 * h0;
+    double same0 = 1.0 / (h0 * h0), same1 = 1.0 / (h1 * h1);
+    double fine_side = 1.0 / (1.5 * h1 * h1), coarse_side = 1.0 / (12.0 * h1 * h1);
+    memset(y0, 0, sizeof(double) * (size_t)n0 * n0 * n0);
+    memset(y1, 0, sizeof(double) * (size_t)n1 * n1 * n1);
+#pragma omp parallel for schedule(static)
+    for (int K = 0; K < n0; ++K)
+        for (int J = 0; J < n0; ++J)
+            for (int I = 0; I < n0; ++I) {
+                if (amr_refined(n0, nb, refined0, I, J, K))
+                    continue;
+                size_t c = ix(n0, I, J, K);
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    for (int dir = -1; dir <= 1; dir += 2) {
+                        int P[3] = {I, J, K};
+                        P[d] += dir;
+                        if (P[d] < 0 || P[d] >= n0)
+                            continue;
+                        if (!amr_refined(n0, nb, refined0, P[0], P[1], P[2])) {
+                            size_t q = ix(n0, P[0], P[1], P[2]);
+                            double beta = dir > 0 ? face_beta(phi0[c], phi0[q], rho_neg, rho_pos)
+                                                  : face_beta(phi0[q], phi0[c], rho_neg, rho_pos);
+                            s += beta * (x0[q] - x0[c]) * same0;
+                        } else {
+                            /* the four fine cells across the face */
+                            int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
+                            for (int a = 0; a < 2; ++a)
+                                for (int b = 0; b < 2; ++b) {
+                                    int F[3];
+                                    F[d] = dir > 0 ? 2 * P[d] : 2 * P[d] + 1;
+                                    F[e1] = 2 * (e1 == 0 ? I : (e1 == 1 ? J : K)) + a;
+                                    F[e2] = 2 * (e2 == 0 ? I : (e2 == 1 ? J : K)) + b;
+                                    size_t q = ix(n1, F[0], F[1], F[2]);
+                                    double beta = dir > 0 ? face_beta(phi0[c], phi1[q], rho_neg, rho_pos)
+                                                          : face_beta(phi1[q], phi0[c], rho_neg, rho_pos);
+                                    s += beta * (x1[q] - x0[c]) * coarse_side;
+                                }
+                        }
+                    }
+                y0[c] = s;
+            }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                if (!amr_refined(n0, nb, refined0, i / 2, j / 2, k / 2))
+                    continue;
+                size_t c = ix(n1, i, j, k);
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    for (int dir = -1; dir <= 1; dir += 2) {
+                        int P[3] = {i, j, k};
+                        P[d] += dir;
+                        if (P[d] < 0 || P[d] >= n1)
+                            continue;
+                        if (amr_refined(n0, nb, refined0, P[0] / 2, P[1] / 2, P[2] / 2)) {
+                            size_t q = ix(n1, P[0], P[1], P[2]);
+                            double beta = dir > 0 ? face_beta(phi1[c], phi1[q], rho_neg, rho_pos)
+                                                  : face_beta(phi1[q], phi1[c], rho_neg, rho_pos);
+                            s += beta * (x1[q] - x1[c]) * same1;
+                        } else {
+                            size_t q = ix(n0, P[0] / 2, P[1] / 2, P[2] / 2);
+                            double beta = dir > 0 ? face_beta(phi1[c], phi0[q], rho_neg, rho_pos)
+                                                  : face_beta(phi0[q], phi1[c], rho_neg, rho_pos);
+                            s += beta * (x0[q] - x1[c]) * fine_side;
+                        }
+                    }
+                y1[c] = s;
+            }
+    return ORC_OK;
+}
+
+/* Guard cells of the composite grid, written into padded copies of every block of both
+ * levels ([nbx0^3][P^3] and [(2 nbx0)^3][P^3], P = nb + 2g; blocks of level 1 outside
+ * the refined region and refined blocks of level 0 are filled too, as if they were
+ * leaves).  A guard position outside the domain is mirrored about the wall on its own
+ * level.  Inside, a level-0 guard takes the level-0 value where that block is not
+ * refined and the mean of the 8 level-1 cells it covers where it is; a level-1 guard
+ * takes the level-1 value inside the refined region and the value of the level-0 cell
+ * containing it outside. */
+static double amr_value0(int n0, int nb, const uint8_t *refined0, const double *v0,
+                         const double *v1, int I, int J, int K)
+{
+    if (!amr_refined(n0, nb, refined0, I, J, K))
+        return v0[ix(n0, I, J, K)];
+    /* pairwise: x pairs, then y, then z (8 equal values give that value exactly) */
+    int n1 = 2 * n0;
+    double q[4];
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            q[b + 2 * c] = v1[ix(n1, 2 * I, 2 * J + b, 2 * K + c)] + v1[ix(n1, 2 * I + 1, 2 * J + b, 2 * K + c)];
+    return 0.125 * ((q[0] + q[1]) + (q[2] + q[3]));
+}
+
+static double amr_value1(int n0, int nb, const uint8_t *refined0, const double *v0,
+                         const double *v1, int i, int j, int k)
+{
+    if (amr_refined(n0, nb, refined0, i / 2, j / 2, k / 2))
+        return v1[ix(2 * n0, i, j, k)];
+    return v0[ix(n0, i / 2, j / 2, k / 2)];
+}
+
+int orc_amr_fill(int n0, int nb, int g, const uint8_t *refined0, const double *v0, const double *v1,
+                 double *blocks0, double *blocks1)
+{
+    if (n0 < 1 || nb < 1 || n0 % nb || g < 0 || g > nb || !refined0 || !v0 || !v1 || !blocks0 ||
+        !blocks1)
+        return ORC_EINVAL;
+    int n1 = 2 * n0;
+    for (int lev = 0; lev < 2; ++lev) {
+        int n = lev ? n1 : n0, nbx = n / nb;
+        double *blocks = lev ? blocks1 : blocks0;
+        size_t nblk = (size_t)nbx * nbx * nbx;
+        for (size_t blk = 0; blk < nblk; ++blk) {
+            int bi = (int)(blk % nbx), bj = (int)((blk / nbx) % nbx), bk = (int)(blk / ((size_t)nbx * nbx));
+            for (int lk = -g; lk < nb + g; ++lk)
+                for (int lj = -g; lj < nb + g; ++lj)
+                    for (int li = -g; li < nb + g; ++li) {
+                        int I = mirror(bi * nb + li, n), J = mirror(bj * nb + lj, n), K = mirror(bk * nb + lk, n);
+                        int inside = li >= 0 && li < nb && lj >= 0 && lj < nb && lk >= 0 && lk < nb;
+                        double v;
+                        if (inside)
+                            v = lev ? v1[ix(n1, I, J, K)] : v0[ix(n0, I, J, K)];
+                        else
+                            v = lev ? amr_value1(n0, nb, refined0, v0, v1, I, J, K)
+                                    : amr_value0(n0, nb, refined0, v0, v1, I, J, K);
+                        blocks[blk_at(nb, g, blk, li, lj, lk)] = v;
+                    }
+        }
     }
     return ORC_OK;
 }

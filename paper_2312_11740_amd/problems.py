@@ -30,6 +30,7 @@ __all__ = [
     "many_bubbles_problem",
     "random_bubbles_problem",
     "rising_bubble_problem",
+    "refine_near_interface",
     "CONFIGS",
 ]
 
@@ -160,6 +161,16 @@ CONFIGS = {
     "learned_64": dict(n=64, train=(0, 4000), held_out=(10000, 10500), sigma=0.01),
     "rising_bubble_256": dict(n=256, steps=100, rho_ratio=1000.0, sigma=0.01, rtol=1e-10),
 }
+
+
+def refine_near_interface(phi0: np.ndarray, nb: int, band: float) -> np.ndarray:
+    """Refinement flags of the blocks of nb^3 cells of phi0 ((n, n, n), [k, j, i]): 1 where
+    some cell centre of the block lies within `band` of the interface (|phi| < band), the
+    refinement around phi = 0 of Fig. 2.  Returns uint8 of shape (n/nb,)*3, [bk, bj, bi]."""
+    n = phi0.shape[0]
+    m = n // nb
+    near = np.abs(phi0) < band
+    return near.reshape(m, nb, m, nb, m, nb).any(axis=(1, 3, 5)).astype(np.uint8)
 
 
 def to_grid(a) -> np.ndarray:
