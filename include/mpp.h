@@ -309,6 +309,63 @@ int mpp_blocks_apply(mpp_op op, int nb, int g, const double *x_blocks, double *y
                      void *stream);
 
 /* ------------------------------------------------------------------------------
+ * Two-level composite grid (Sec. 2 and Fig. 2: blocks at two resolutions, the finer
+ * one where the interface is).  Level 0 is n0^3 cells (spacing 1/n0) in (n0/nb)^3
+ * blocks of nb^3 cells, all stored; refined0[b] != 0 marks the level-0 blocks covered by
+ * level 1 (spacing 1/(2 n0)).  Level 1 is stored sparsely: the 8 children of each
+ * refined block, each nb^3 level-1 cells, in the order of their parents and, within a
+ * parent, child a + 2b + 4c for its offsets a, b, c in x, y, z.  Blocks of both levels
+ * are P^3 doubles with g guard layers as in the uniform block layout (P = nb + 2g, x
+ * fastest): level 0 as [(n0/nb)^3][P^3], level 1 as [nblk1][P^3].
+ * The leaf cells are those of the unrefined level-0 blocks and of every level-1 block.
+ * The operator is the conservative finite-volume Laplacian on the leaves,
+ *     (A x)_c = (1/V_c) sum_faces area * beta * (x_other - x_c) / distance,
+ * with no flux through the walls; across a coarse-fine face the fine cell sees the
+ * coarse cell itself (centres 1.5 fine spacings apart) and the coarse cell the four
+ * fine cells across its face, so every flux leaves one leaf and enters another.  beta is
+ * the ghost-fluid coefficient of the two cells' level-set values (lower coordinate
+ * first; 1/rho on each side, the series value on a crossed face).
+ * Requirements: 2 <= n0 <= 512, 2 <= nb, n0 % nb == 0, 1 <= g <= nb; device pointers
+ * unless stated; asynchronous on `stream` unless stated; MPP_EINVAL on a violated
+ * requirement, MPP_EDEVICE if a HIP call fails.  One problem per call.
+ * ------------------------------------------------------------------------------ */
+typedef struct mpp_amr_s *mpp_amr;
+
+/* Device workspace the tables of a grid of n0^3 level-0 cells in blocks of nb^3 need
+ * (0 if the shape is invalid). */
+size_t mpp_amr_workspace_bytes(int n0, int nb);
+
+/* Builds the block tables of the refinement refined0 (HOST, (n0/nb)^3 bytes, block
+ * (bi, bj, bk) at bi + (n0/nb)(bj + (n0/nb) bk)) in `workspace` (device, owned by the
+ * caller, kept alive until mpp_amr_destroy); synchronous.  *out receives the handle. */
+int mpp_amr_create(int n0, int nb, int g, const uint8_t *refined0, void *workspace,
+                   size_t workspace_bytes, void *stream, mpp_amr *out);
+void mpp_amr_destroy(mpp_amr a);
+
+/* Number of stored level-1 blocks and (list1: HOST, may be NULL, nblk1 entries) the
+ * position of each, bi + (2 n0/nb)(bj + (2 n0/nb) bk) in level-1 block coordinates. */
+int mpp_amr_level1_blocks(mpp_amr a, int32_t *nblk1, int32_t *list1);
+
+/* Guard-cell fill of every stored block of both levels, in place (interiors are only
+ * read).  A guard position outside the domain is mirrored about the wall on its own
+ * level.  Inside, a level-0 guard takes the level-0 cell where that block is not refined
+ * and the mean of the 8 level-1 cells it covers where it is; a level-1 guard takes the
+ * level-1 cell where that block is stored and the level-0 cell containing it where it
+ * is not (guards hold the volume average of the leaf field over the guard cell).
+ * blocks1 may be NULL when nothing is refined. */
+int mpp_amr_fill_guards(mpp_amr a, double *blocks0, double *blocks1, void *stream);
+
+/* y = A x on the leaves.  phi (level set) and x in the block layout of both levels with
+ * their guards filled (mpp_amr_fill_guards).  y is written on every stored block: A x in
+ * the interiors of leaf blocks, 0 in guards and in refined level-0 blocks.  rho_neg and
+ * rho_pos (> 0) are the densities where phi <= 0 and phi > 0.  y0 and y1 distinct from
+ * each other and from the inputs; the level-1 pointers may be NULL when nothing is
+ * refined. */
+int mpp_amr_apply(mpp_amr a, const double *phi0, const double *phi1, const double *x0,
+                  const double *x1, double rho_neg, double rho_pos, double *y0, double *y1,
+                  void *stream);
+
+/* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from
  * the previous pressure or from zero): a small 3D U-Net maps the density field and
  * the right-hand side of a problem to an approximate solution that seeds the PCG.

@@ -33,6 +33,8 @@ EXPORTS = (
     "mpp_net_features", "mpp_learned_guess", "mpp_divergence", "mpp_project",
     "mpp_ls_advect", "mpp_ls_reinit", "mpp_heat_solve", "mpp_blocks_scatter",
     "mpp_blocks_gather", "mpp_blocks_fill_guards", "mpp_blocks_apply",
+    "mpp_amr_workspace_bytes", "mpp_amr_create", "mpp_amr_destroy", "mpp_amr_level1_blocks",
+    "mpp_amr_fill_guards", "mpp_amr_apply",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -125,12 +127,21 @@ def load_library(path: str = LIB_PATH):
         getattr(L, nm).argtypes = [i32, i32, i32, i32, P, P, P]
     L.mpp_blocks_fill_guards.argtypes = [i32, i32, i32, i32, P, P]
     L.mpp_blocks_apply.argtypes = [P, i32, i32, P, P, P]
+    L.mpp_amr_workspace_bytes.argtypes = [i32, i32]
+    L.mpp_amr_workspace_bytes.restype = ctypes.c_size_t
+    L.mpp_amr_create.argtypes = [i32, i32, i32, P, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    L.mpp_amr_destroy.argtypes = [P]
+    L.mpp_amr_destroy.restype = None
+    L.mpp_amr_level1_blocks.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
+    L.mpp_amr_fill_guards.argtypes = [P, P, P, P]
+    L.mpp_amr_apply.argtypes = [P, P, P, P, P, d, d, P, P, P]
     L.mpp_heat_solve.argtypes = [P, P, P, d, P, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), P]
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
                                                  "mpp_strerror", "mpp_workspace_bytes",
                                                  "mpp_net_workspace_bytes",
-                                                 "mpp_net_destroy")):
+                                                 "mpp_net_destroy", "mpp_amr_workspace_bytes",
+                                                 "mpp_amr_destroy")):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -540,6 +551,88 @@ def blocks_fill_guards(blocks, n, nb, g):
     if st != OK:
         raise MppError(st, "mpp_blocks_fill_guards")
     return blocks
+
+
+class AmrGrid:
+    """Two-level composite grid (include/mpp.h): level 0 of n0^3 cells in blocks of nb^3
+    with g guard layers, the blocks flagged in `refined0` ((n0/nb)^3 uint8, [bk, bj, bi])
+    covered by level 1 at half the spacing.  Fields are float64 CUDA tensors in the block
+    layout: level 0 (nblk0, P, P, P), level 1 (nblk1, P, P, P); `list1` holds the
+    position of each stored level-1 block."""
+
+    def __init__(self, n0, nb, g, refined0, device="cuda"):
+        torch = _torch()
+        L = load_library()
+        import numpy as np
+        flags = np.ascontiguousarray(np.asarray(refined0), dtype=np.uint8).reshape(-1)
+        self.n0, self.nb, self.g, self.P = int(n0), int(nb), int(g), int(nb) + 2 * int(g)
+        self.device = torch.device(device)
+        self.nblk0 = (self.n0 // self.nb) ** 3 if self.nb > 0 else 0
+        if flags.size != self.nblk0:
+            raise ValueError("refined0 must hold (n0/nb)^3 = %d flags" % self.nblk0)
+        nbytes = int(L.mpp_amr_workspace_bytes(self.n0, self.nb))
+        if nbytes == 0:
+            raise MppError(-1, "mpp_amr_workspace_bytes")
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        st = L.mpp_amr_create(self.n0, self.nb, self.g, flags.ctypes.data_as(ctypes.c_void_p),
+                              ctypes.c_void_p(self._ws.data_ptr()), nbytes,
+                              _stream_handle(self.device), ctypes.byref(h))
+        if st != OK:
+            raise MppError(st, "mpp_amr_create")
+        self._h = h
+        cnt = ctypes.c_int32(0)
+        L.mpp_amr_level1_blocks(self._h, ctypes.byref(cnt), None)
+        self.nblk1 = int(cnt.value)
+        self.list1 = np.zeros(max(self.nblk1, 1), dtype=np.int32)
+        L.mpp_amr_level1_blocks(self._h, ctypes.byref(cnt), self.list1.ctypes.data_as(ctypes.c_void_p))
+        self.list1 = self.list1[:self.nblk1]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            load_library().mpp_amr_destroy(h)
+            self._h = None
+
+    def shapes(self):
+        P = self.P
+        return (self.nblk0, P, P, P), (self.nblk1, P, P, P)
+
+    def empty(self):
+        torch = _torch()
+        s0, s1 = self.shapes()
+        return (torch.zeros(s0, dtype=torch.float64, device=self.device),
+                torch.zeros(s1, dtype=torch.float64, device=self.device))
+
+    def _fields(self, pairs):
+        s0, s1 = self.shapes()
+        out = []
+        for (a0, a1), what in pairs:
+            _check_field(a0, s0, what + "0")
+            if self.nblk1:
+                _check_field(a1, s1, what + "1")
+            out += [ctypes.c_void_p(a0.data_ptr()),
+                    ctypes.c_void_p(a1.data_ptr()) if self.nblk1 else None]
+        return out
+
+    def fill_guards(self, b0, b1):
+        """Guard cells of both levels in place; returns (b0, b1)."""
+        p = self._fields([((b0, b1), "blocks")])
+        st = load_library().mpp_amr_fill_guards(self._h, p[0], p[1], _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_amr_fill_guards")
+        return b0, b1
+
+    def apply(self, phi, x, rho_neg, rho_pos, y=None):
+        """y = A x on the leaves; phi, x: (level0, level1) pairs with filled guards."""
+        if y is None:
+            y = self.empty()
+        p = self._fields([(phi, "phi"), (x, "x"), (y, "y")])
+        st = load_library().mpp_amr_apply(self._h, p[0], p[1], p[2], p[3], float(rho_neg),
+                                          float(rho_pos), p[4], p[5], _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_amr_apply")
+        return y
 
 
 def net_param_count() -> int:

@@ -21,6 +21,7 @@
 #include "guess.h"
 #include "levelset.h"
 #include "heat.h"
+#include "amr.h"
 #include "blocks.h"
 #include "kernels.h"
 #include "net_internal.h"
@@ -1643,6 +1644,141 @@ int mpp_blocks_apply(mpp_op op, int nb, int g, const double* x_blocks, double* y
                      S.P3 * sizeof(double), reinterpret_cast<hipStream_t>(stream), S, L0.f64[0], \
                      L0.f64[1], L0.f64[2], x_blocks, y_blocks)
   MPP_BLK_DISPATCH(S, L_);
+#undef L_
+  return blk_launch_status();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------
+// two-level composite grid
+// ------------------------------------------------------------------------------
+struct mpp_amr_s {
+  AmrShape A;
+  uint8_t* refined0;   // device [nblk0]
+  int* map1;           // device [nbx1^3]
+  int* list1;          // device [nblk1]
+  std::vector<int> h_list1;
+};
+
+namespace {
+
+bool amr_shape_ok(int n0, int nb, int g) {
+  return n0 >= 2 && n0 <= 512 && nb >= 2 && n0 % nb == 0 && g >= 1 && g <= nb &&
+         (size_t)(nb + 2 * g) * (nb + 2 * g) * (nb + 2 * g) <= (1u << 20);
+}
+
+size_t amr_table_bytes(int n0, int nb) {
+  const size_t nbx0 = (size_t)(n0 / nb), nblk0 = nbx0 * nbx0 * nbx0;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return up(nblk0) + up(sizeof(int) * 8 * nblk0) + up(sizeof(int) * 8 * nblk0) + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mpp_amr_workspace_bytes(int n0, int nb) {
+  if (!(n0 >= 2 && n0 <= 512 && nb >= 2 && n0 % nb == 0)) return 0;
+  return amr_table_bytes(n0, nb);
+}
+
+int mpp_amr_create(int n0, int nb, int g, const uint8_t* refined0, void* workspace,
+                   size_t workspace_bytes, void* stream, mpp_amr* out) {
+  if (out) *out = nullptr;
+  if (!amr_shape_ok(n0, nb, g) || !refined0 || !workspace || !out) return MPP_EINVAL;
+  if (workspace_bytes < amr_table_bytes(n0, nb)) return MPP_ENOMEM;
+  AmrShape A;
+  A.n0 = n0;
+  A.nb = nb;
+  A.g = g;
+  A.P = nb + 2 * g;
+  A.P3 = (size_t)A.P * A.P * A.P;
+  A.nbx0 = n0 / nb;
+  A.nbx1 = 2 * A.nbx0;
+  A.nblk0 = A.nbx0 * A.nbx0 * A.nbx0;
+  // the face factors, each 1 / (centre distance * cell volume / face area)
+  const double h0 = 1.0 / n0, h1 = 0.5 * h0;
+  A.same0 = 1.0 / (h0 * h0);
+  A.same1 = 1.0 / (h1 * h1);
+  A.fine_side = 1.0 / (1.5 * h1 * h1);
+  A.coarse_side = 1.0 / (12.0 * h1 * h1);
+  std::vector<int> map1((size_t)A.nbx1 * A.nbx1 * A.nbx1, -1), list1;
+  std::vector<uint8_t> ref(A.nblk0);
+  for (int b = 0; b < A.nblk0; ++b) {
+    ref[b] = refined0[b] ? 1 : 0;
+    if (!ref[b]) continue;
+    const int bi = b % A.nbx0, bj = (b / A.nbx0) % A.nbx0, bk = b / (A.nbx0 * A.nbx0);
+    for (int ch = 0; ch < 8; ++ch) {
+      const int pos = (2 * bi + (ch & 1)) + A.nbx1 * ((2 * bj + ((ch >> 1) & 1)) +
+                                                      A.nbx1 * (2 * bk + (ch >> 2)));
+      map1[pos] = (int)list1.size();
+      list1.push_back(pos);
+    }
+  }
+  A.nblk1 = (int)list1.size();
+  mpp_amr_s* a = new (std::nothrow) mpp_amr_s();
+  if (!a) return MPP_ENOMEM;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(workspace) + 255) & ~uintptr_t(255));
+  a->A = A;
+  a->refined0 = reinterpret_cast<uint8_t*>(base);
+  a->map1 = reinterpret_cast<int*>(base + up(A.nblk0));
+  a->list1 = reinterpret_cast<int*>(base + up(A.nblk0) + up(sizeof(int) * 8 * A.nblk0));
+  a->h_list1 = list1;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(a->refined0, ref.data(), ref.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(a->map1, map1.data(), sizeof(int) * map1.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !list1.empty())
+    e = hipMemcpyAsync(a->list1, list1.data(), sizeof(int) * list1.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host tables go out of scope
+  if (e != hipSuccess) {
+    delete a;
+    return MPP_EDEVICE;
+  }
+  *out = a;
+  return MPP_OK;
+}
+
+void mpp_amr_destroy(mpp_amr a) { delete a; }
+
+int mpp_amr_level1_blocks(mpp_amr a, int32_t* nblk1, int32_t* list1) {
+  if (!a || !nblk1) return MPP_EINVAL;
+  *nblk1 = a->A.nblk1;
+  if (list1) std::copy(a->h_list1.begin(), a->h_list1.end(), list1);
+  return MPP_OK;
+}
+
+int mpp_amr_fill_guards(mpp_amr a, double* blocks0, double* blocks1, void* stream) {
+  if (!a || !blocks0 || (a->A.nblk1 > 0 && !blocks1) || blocks0 == blocks1) return MPP_EINVAL;
+  const AmrShape& A = a->A;
+#define L_(NB_, G_)                                                                          \
+  hipLaunchKernelGGL((k_amr_fill<NB_, G_>), dim3((unsigned)(A.nblk0 + A.nblk1)), dim3(kBlkThreads), \
+                     0, reinterpret_cast<hipStream_t>(stream), A, a->refined0, a->map1, a->list1, \
+                     blocks0, blocks1)
+  MPP_BLK_DISPATCH(A, L_);
+#undef L_
+  return blk_launch_status();
+}
+
+int mpp_amr_apply(mpp_amr a, const double* phi0, const double* phi1, const double* x0,
+                  const double* x1, double rho_neg, double rho_pos, double* y0, double* y1,
+                  void* stream) {
+  if (!a || !phi0 || !x0 || !y0) return MPP_EINVAL;
+  const AmrShape& A = a->A;
+  if (A.nblk1 > 0 && (!phi1 || !x1 || !y1)) return MPP_EINVAL;
+  if (!(rho_neg > 0.0) || !(rho_pos > 0.0) || !std::isfinite(rho_neg) || !std::isfinite(rho_pos))
+    return MPP_EINVAL;
+  const void* ins[4] = {phi0, phi1, x0, x1};
+  for (const void* in : ins)
+    if (in && (in == (const void*)y0 || in == (const void*)y1)) return MPP_EINVAL;
+  if (y1 && y0 == y1) return MPP_EINVAL;
+#define L_(NB_, G_)                                                                          \
+  hipLaunchKernelGGL((k_amr_apply<NB_, G_>), dim3((unsigned)(A.nblk0 + A.nblk1)), dim3(kBlkThreads), \
+                     0, reinterpret_cast<hipStream_t>(stream), A, a->refined0, a->map1, a->list1, \
+                     phi0, phi1, x0, x1, rho_neg, rho_pos, y0, y1)
+  MPP_BLK_DISPATCH(A, L_);
 #undef L_
   return blk_launch_status();
 }

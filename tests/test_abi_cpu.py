@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "mpp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mpp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mpp_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_exports():
@@ -141,3 +141,23 @@ def test_block_layout_calls_reject_bad_arguments_before_device_work():
     assert L.mpp_blocks_fill_guards(32, 1, 16, 0, a, None) == M.OK        # nothing to do
     assert L.mpp_blocks_apply(None, 16, 1, a, b, None) == M.EINVAL
     assert L.mpp_blocks_apply(op, 16, 1, a, a, None) == M.EINVAL
+
+
+def test_amr_host_validation():
+    L = M.load_library()
+    assert L.mpp_amr_workspace_bytes(30, 8) == 0          # 30 % 8
+    assert L.mpp_amr_workspace_bytes(1024, 16) == 0       # n0 > 512
+    assert L.mpp_amr_workspace_bytes(32, 8) > 0
+    flags = (ctypes.c_uint8 * 64)()
+    h = ctypes.c_void_p()
+    ws = ctypes.c_void_p(1 << 20)   # never touched: every call below fails its checks first
+    nbytes = L.mpp_amr_workspace_bytes(32, 8)
+    for n0, nb, g in ((32, 8, 0), (32, 8, 9), (30, 8, 1), (32, 1, 1)):
+        assert L.mpp_amr_create(n0, nb, g, flags, ws, nbytes, None, ctypes.byref(h)) == M.EINVAL
+        assert not h.value
+    assert L.mpp_amr_create(32, 8, 1, flags, ws, 16, None, ctypes.byref(h)) == -2   # ENOMEM
+    assert L.mpp_amr_create(32, 8, 1, None, ws, nbytes, None, ctypes.byref(h)) == M.EINVAL
+    cnt = ctypes.c_int32(0)
+    assert L.mpp_amr_level1_blocks(None, ctypes.byref(cnt), None) == M.EINVAL
+    assert L.mpp_amr_fill_guards(None, ws, None, None) == M.EINVAL
+    assert L.mpp_amr_apply(None, ws, None, ws, None, 1.0, 1.0, ws, None, None) == M.EINVAL

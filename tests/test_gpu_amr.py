@@ -1,0 +1,128 @@
+"""Two-level composite grid on the GPU against the oracle: the guard-cell fill between
+levels is a copy or a pairwise mean (bit for bit), the composite operator follows the
+oracle's order of operations (bit for bit).  Shapes: nothing refined, everything
+refined, random refinement with one and two guard layers and block edges with and
+without compile-time constants, and the 20-bubble grid of 128^3 coarse cells in 16^3
+blocks refined around the interfaces (the launch the benchmark times)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2312_11740_amd import problems as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2312_11740_amd as M  # noqa: E402
+
+DEV = "cuda:0"
+RN, RP = 1e-3, 1.0
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def level_blocks(grid, v0, v1):
+    """Dense level fields -> the grid's block layout (level 1: the stored blocks)."""
+    nb, g = grid.nb, grid.g
+    b0 = M.blocks_scatter(to_dev(v0), nb, g)
+    full1 = M.blocks_scatter(to_dev(v1), nb, g)
+    idx = torch.from_numpy(grid.list1.astype(np.int64)).to(DEV)
+    b1 = full1.index_select(0, idx).contiguous()
+    return b0, b1
+
+
+def check(n0, nb, g, flags, phi0, phi1, seed):
+    rng = np.random.default_rng(seed)
+    x0, x1 = rng.standard_normal(phi0.shape), rng.standard_normal(phi1.shape)
+    grid = M.AmrGrid(n0, nb, g, flags, DEV)
+    sel = grid.list1.astype(np.int64)
+    assert grid.nblk1 == 8 * int(flags.sum())
+    # fill, both fields
+    pb = grid.fill_guards(*level_blocks(grid, phi0, phi1))
+    xb = grid.fill_guards(*level_blocks(grid, x0, x1))
+    for got, (v0, v1) in ((pb, (phi0, phi1)), (xb, (x0, x1))):
+        r0, r1 = O.amr_fill(flags, nb, g, v0, v1)
+        assert np.array_equal(to_host(got[0]), r0)
+        assert np.array_equal(to_host(got[1]), r1[sel])
+    # operator
+    y0, y1 = grid.apply(pb, xb, RN, RP)
+    e0, e1 = O.amr_apply(flags, nb, phi0, phi1, x0, x1, RN, RP)
+    assert np.array_equal(to_host(y0), O.blocks_scatter(e0, nb, g))
+    assert np.array_equal(to_host(y1), O.blocks_scatter(e1, nb, g)[sel])
+    return grid, (y0, y1)
+
+
+def phis(n0, centres, radii):
+    return G.bubble_phi(n0, centres, radii), G.bubble_phi(2 * n0, centres, radii)
+
+
+BUBBLES = ([(0.45, 0.5, 0.55), (0.7, 0.3, 0.3)], [0.25, 0.12])
+
+
+@pytest.mark.parametrize("n0,nb,g,seed", [(32, 8, 1, 1), (32, 8, 2, 2), (32, 16, 1, 3),
+                                          (48, 16, 2, 4), (24, 4, 2, 5), (20, 10, 1, 6)])
+def test_random_refinement_matches_oracle(n0, nb, g, seed):
+    m = n0 // nb
+    flags = (np.random.default_rng(seed).random((m, m, m)) < 0.4).astype(np.uint8)
+    flags.flat[0] = 1
+    check(n0, nb, g, flags, *phis(n0, *BUBBLES), seed)
+
+
+def test_refined_around_the_interface():
+    n0, nb, g = 32, 8, 1
+    p0, p1 = phis(n0, *BUBBLES)
+    flags = G.refine_near_interface(p0, nb, 2.0 / n0)
+    assert 0 < flags.sum() < flags.size
+    check(n0, nb, g, flags, p0, p1, 11)
+
+
+def test_nothing_refined_is_the_uniform_operator():
+    n0, nb, g = 32, 8, 1
+    p0, p1 = phis(n0, *BUBBLES)
+    flags = np.zeros((4, 4, 4), np.uint8)
+    grid, (y0, _) = check(n0, nb, g, flags, p0, p1, 12)
+    assert grid.nblk1 == 0
+    # the same operator as the uniform grid's, built and applied by the solver library
+    x0 = np.random.default_rng(12).standard_normal(p0.shape)
+    op = M.Operator(to_dev(p0), RN, RP, 0.0)
+    ref = to_host(op.apply(to_dev(x0)))
+    got = to_host(M.blocks_gather(y0, n0, nb, g))
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_everything_refined():
+    n0, nb, g = 16, 8, 1
+    check(n0, nb, g, np.ones((2, 2, 2), np.uint8), *phis(n0, *BUBBLES), 13)
+
+
+def test_bad_arguments_are_rejected():
+    flags = np.zeros((4, 4, 4), np.uint8)
+    with pytest.raises(M.MppError):
+        M.AmrGrid(32, 8, 0, flags, DEV)             # no guard layer
+    with pytest.raises(M.MppError):
+        M.AmrGrid(30, 8, 1, np.zeros(27, np.uint8), DEV)   # 30 % 8
+    grid = M.AmrGrid(32, 8, 1, flags, DEV)
+    b = grid.empty()
+    with pytest.raises(M.MppError):
+        grid.apply(b, b, RN, RP, y=b)                 # y aliases x
+    with pytest.raises(M.MppError):
+        grid.apply(b, grid.empty(), -1.0, RP)         # density <= 0
+
+
+def test_full_size_many_bubbles():
+    # 20 bubbles on 128^3 coarse cells in 16^3 blocks, refined within two coarse cells of
+    # an interface: level 1 at the 256^3 spacing where it is stored
+    n0, nb, g = 128, 16, 1
+    pr = G.many_bubbles_problem(n=n0)
+    p0, p1 = phis(n0, pr.centres, pr.radii)
+    assert np.array_equal(p0, pr.phi)
+    flags = G.refine_near_interface(p0, nb, 2.0 / n0)
+    grid, _ = check(n0, nb, g, flags, p0, p1, 14)
+    assert grid.nblk1 == 8 * 194
