@@ -572,6 +572,102 @@ def blocks256(M, G, torch, args):
     print(json.dumps(rec), flush=True)
 
 
+def amr_fill_bytes(flags, nb, g, list1):
+    """Algorithmic bytes of one guard fill of the composite grid: every guard cell of
+    every stored block written once (8 B) and its source read once: one value (8 B), or
+    the 8 level-1 values a level-0 guard over a refined block averages (64 B)."""
+    m = flags.shape[0]
+    n0 = m * nb
+    P = nb + 2 * g
+    li = np.arange(-g, nb + g)
+    L = np.stack(np.meshgrid(li, li, li, indexing="ij"), -1).reshape(-1, 3)   # k, j, i
+    guard = ~np.all((L >= 0) & (L < nb), axis=1)
+    L = L[guard]
+    mir = lambda a, n: np.where(a < 0, -1 - a, np.where(a >= n, 2 * n - 1 - a, a))
+    reads0 = 0
+    for bk in range(m):
+        for bj in range(m):
+            for bi in range(m):
+                K = mir(bk * nb + L[:, 0], n0) // nb
+                J = mir(bj * nb + L[:, 1], n0) // nb
+                I = mir(bi * nb + L[:, 2], n0) // nb
+                reads0 += int(np.sum(np.where(flags[K, J, I] != 0, 64, 8)))
+    per_block = len(L)
+    return reads0 + 8 * per_block * m ** 3 + 16 * per_block * len(list1)
+
+
+def amr256(M, G, torch, args):
+    """The composite grid: 20 bubbles on 128^3 coarse cells in 16^3 blocks, the blocks
+    within two coarse cells of an interface refined to the 256^3 spacing.  Times (HIP
+    events over `steps` repetitions) of the guard fill between levels and of the
+    composite operator, against the HBM roofline with their algorithmic bytes."""
+    dev = torch.device("cuda:0")
+    n0, nb, g = 128, 16, 1
+    K, W = max(args.steps, 5), args.warmup
+    pr = G.many_bubbles_problem(n=n0)
+    p0, p1 = pr.phi, G.bubble_phi(2 * n0, pr.centres, pr.radii)
+    flags = G.refine_near_interface(p0, nb, 2.0 / n0)
+    grid = M.AmrGrid(n0, nb, g, flags, dev)
+    rng = np.random.default_rng(4)
+    x0, x1 = rng.standard_normal(p0.shape), rng.standard_normal(p1.shape)
+    idx = torch.from_numpy(grid.list1.astype(np.int64)).to(dev)
+
+    def blocks(v0, v1):
+        b1 = M.blocks_scatter(torch.from_numpy(v1).to(dev), nb, g).index_select(0, idx)
+        return M.blocks_scatter(torch.from_numpy(v0).to(dev), nb, g), b1.contiguous()
+    pb = grid.fill_guards(*blocks(p0, p1))
+    xb = grid.fill_guards(*blocks(x0, x1))
+    yb = grid.empty()
+    P = nb + 2 * g
+    nref = int(flags.sum())
+    leaf_blocks = grid.nblk0 - nref + grid.nblk1
+    leaf_cells = leaf_blocks * nb ** 3
+    steps = {"fill_guards": (lambda: grid.fill_guards(*xb),
+                             amr_fill_bytes(flags, nb, g, grid.list1)),
+             "apply": (lambda: grid.apply(pb, xb, pr.rho_neg, pr.rho_pos, y=yb),
+                       24.0 * P ** 3 * leaf_blocks + 8.0 * P ** 3 * nref)}
+    res = {}
+    for name, (fn, nbytes) in steps.items():
+        for _ in range(W + 1):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / K
+        res[name] = {"us": round(us, 2), "GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
+                     "alg_bytes": nbytes}
+    ms = (res["fill_guards"]["us"] + res["apply"]["us"]) / 1e3
+    ap = res["apply"]
+    rec = {"metric": "guard fill + composite operator on a two-level grid (128^3 coarse, "
+                     "256^3 spacing around the interfaces)",
+           "value": round(ms, 4), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "steps": K, "warmup": W, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "amr256", "n0": n0, "nb": nb, "guard": g, "bubbles": 20,
+                      "refined_level0_blocks": nref, "level1_blocks": grid.nblk1,
+                      "leaf_cells": leaf_cells},
+           "kernels": res,
+           "roofline": {"bound": "hbm", "kernel": "k_amr_apply", "achieved": ap["GBps"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ap["GBps"] / HBM_PEAK_GBS, 3), "traffic": None}}
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        def step():
+            O.amr_fill(flags, nb, g, x0, x1)
+            return O.amr_apply(flags, nb, p0, p1, x0, x1, pr.rho_neg, pr.rho_pos)
+        rec["cpu_baseline"], (e0_, e1_) = oracle_leg(step, "one guard fill + composite "
+                                                     "operator at full size")
+        grid.apply(pb, xb, pr.rho_neg, pr.rho_pos, y=yb)
+        sel = grid.list1.astype(np.int64)
+        ok0 = np.array_equal(yb[0].cpu().numpy(), O.blocks_scatter(e0_, nb, g))
+        ok1 = np.array_equal(yb[1].cpu().numpy(), O.blocks_scatter(e1_, nb, g)[sel])
+        rec["bit_exact_vs_oracle"] = bool(ok0 and ok1)
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -590,7 +686,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", default="rising256",
                     choices=["rising256", "batched64", "single32", "bubbles128",
-                             "projection256", "flow256", "heat256", "blocks256"],
+                             "projection256", "flow256", "heat256", "blocks256", "amr256"],
                     help="rising256: the 256^3 sequence (default); batched64: 64 x 64^3; "
                          "single32 / bubbles128: one fixed problem, plain vs mixed")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -631,6 +727,9 @@ def main():
         return
     if args.workload == "blocks256":
         blocks256(M, G, torch, args)
+        return
+    if args.workload == "amr256":
+        amr256(M, G, torch, args)
         return
     n, K, W = args.n, args.steps, args.warmup
     prm = dict(rho_neg=1e-3, rho_pos=1.0, sigma=0.01, rtol=1e-10)

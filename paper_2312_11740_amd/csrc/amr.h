@@ -46,31 +46,49 @@ __device__ inline size_t amr_local(int P, int g, int li, int lj, int lk) {
   return (size_t)(li + g) + (size_t)P * ((size_t)(lj + g) + (size_t)P * (size_t)(lk + g));
 }
 
-// value of level-1 cell (i, j, k) of a refined region (its block is stored)
-template <int NB, int G>
-__device__ inline double amr_fine(const AmrShape& A, const int* __restrict__ map1,
-                                  const double* __restrict__ b1, int i, int j, int k) {
-  const int nb = NB > 0 ? NB : A.nb, g = NB > 0 ? G : A.g, P = nb + 2 * g;
-  const int blk = map1[i / nb + A.nbx1 * (j / nb + A.nbx1 * (k / nb))];
-  return b1[(size_t)blk * A.P3 + amr_local(P, g, i % nb, j % nb, k % nb)];
-}
-
 // Guard cells of every stored block of both levels, in place (interiors only read).  A
 // guard position is mirrored about the walls on its own level; inside, a level-0 guard
 // takes the level-0 value where its block is not refined and the mean of the 8 level-1
 // cells it covers where it is (pairwise: x pairs, then y, then z); a level-1 guard takes
 // the level-1 value where that block is stored and the value of the level-0 cell
-// containing it where it is not.  One workgroup per stored block (level 0 first).
+// containing it where it is not.  One workgroup per stored block (level 0 first).  The
+// workgroup first looks up the 27 blocks around its own (itself included) once: a mirrored
+// guard position lies in one of them.  The children of a refined block are stored one
+// after the other (child a + 2b + 4c), so the first child's index locates all eight.
 template <int NB, int G>
 __global__ void __launch_bounds__(kBlkThreads)
     k_amr_fill(AmrShape A, const uint8_t* __restrict__ refined0, const int* __restrict__ map1,
                const int* __restrict__ list1, double* __restrict__ b0, double* __restrict__ b1) {
+  __shared__ int s_blk[27], s_kind[27];
   const int lev = (int)blockIdx.x >= A.nblk0;
   const int blk = lev ? (int)blockIdx.x - A.nblk0 : (int)blockIdx.x;
   int bi, bj, bk;
   amr_block_coords(A, lev, blk, list1, bi, bj, bk);
   const int nb = NB > 0 ? NB : A.nb, g = NB > 0 ? G : A.g, P = nb + 2 * g;
   const int n = lev ? 2 * A.n0 : A.n0;
+  const int nbx = lev ? A.nbx1 : A.nbx0;
+  if (threadIdx.x < 27) {
+    // kind 0: a block of this level (s_blk its index); kind 1: level 0 over a refined
+    // block (s_blk its first child) or level 1 over an unstored block (s_blk the level-0
+    // block containing it); kind -1: outside the domain (never used)
+    const int e = threadIdx.x;
+    const int p[3] = {bi + e % 3 - 1, bj + (e / 3) % 3 - 1, bk + e / 9 - 1};
+    int kind = -1, id = 0;
+    if (p[0] >= 0 && p[0] < nbx && p[1] >= 0 && p[1] < nbx && p[2] >= 0 && p[2] < nbx) {
+      const int pos = p[0] + nbx * (p[1] + nbx * p[2]);
+      if (lev == 0) {
+        kind = refined0[pos] != 0;
+        id = kind ? map1[2 * p[0] + A.nbx1 * (2 * p[1] + A.nbx1 * 2 * p[2])] : pos;
+      } else {
+        const int fb = map1[pos];
+        kind = fb < 0;
+        id = kind ? p[0] / 2 + A.nbx0 * (p[1] / 2 + A.nbx0 * (p[2] / 2)) : fb;
+      }
+    }
+    s_kind[e] = kind;
+    s_blk[e] = id;
+  }
+  __syncthreads();
   double* const own = (lev ? b1 : b0) + (size_t)blk * A.P3;
   const int guards = P * P * P - nb * nb * nb;
   for (int q = threadIdx.x; q < guards; q += kBlkThreads) {
@@ -78,42 +96,117 @@ __global__ void __launch_bounds__(kBlkThreads)
     blk_guard_cell(q, nb, g, P, li, lj, lk);
     const int I = blk_mirror(bi * nb + li, n), J = blk_mirror(bj * nb + lj, n),
               K = blk_mirror(bk * nb + lk, n);
+    const int e = (I / nb - bi + 1) + 3 * (J / nb - bj + 1) + 9 * (K / nb - bk + 1);
+    const int kind = s_kind[e], id = s_blk[e];
     double v;
-    if (lev == 0) {
-      const int ob = I / nb + A.nbx0 * (J / nb + A.nbx0 * (K / nb));
-      if (!refined0[ob]) {
-        v = b0[(size_t)ob * A.P3 + amr_local(P, g, I % nb, J % nb, K % nb)];
-      } else {
-        double s[4];
+    if (kind == 0) {
+      v = (lev ? b1 : b0)[(size_t)id * A.P3 + amr_local(P, g, I % nb, J % nb, K % nb)];
+    } else if (lev == 0) {
+      // the 8 level-1 cells under level-0 cell (I, J, K), in child blocks id + a + 2b + 4c
+      double s[4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+      for (int c = 0; c < 2; ++c)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
-            s[b + 2 * c] = amr_fine<NB, G>(A, map1, b1, 2 * I, 2 * J + b, 2 * K + c) +
-                           amr_fine<NB, G>(A, map1, b1, 2 * I + 1, 2 * J + b, 2 * K + c);
-        v = 0.125 * ((s[0] + s[1]) + (s[2] + s[3]));
-      }
+        for (int b = 0; b < 2; ++b) {
+          const int fj = 2 * J + b, fk = 2 * K + c;
+          double v2[2];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int fi = 2 * I + a;
+            const int ch = ((fi / nb) & 1) + 2 * ((fj / nb) & 1) + 4 * ((fk / nb) & 1);
+            v2[a] = b1[(size_t)(id + ch) * A.P3 + amr_local(P, g, fi % nb, fj % nb, fk % nb)];
+          }
+          s[b + 2 * c] = v2[0] + v2[1];
+        }
+      v = 0.125 * ((s[0] + s[1]) + (s[2] + s[3]));
     } else {
-      const int fb = map1[I / nb + A.nbx1 * (J / nb + A.nbx1 * (K / nb))];
-      if (fb >= 0) {
-        v = b1[(size_t)fb * A.P3 + amr_local(P, g, I % nb, J % nb, K % nb)];
-      } else {
-        const int Ic = I / 2, Jc = J / 2, Kc = K / 2;
-        const int ob = Ic / nb + A.nbx0 * (Jc / nb + A.nbx0 * (Kc / nb));
-        v = b0[(size_t)ob * A.P3 + amr_local(P, g, Ic % nb, Jc % nb, Kc % nb)];
-      }
+      const int Ic = I / 2, Jc = J / 2, Kc = K / 2;
+      v = b0[(size_t)id * A.P3 + amr_local(P, g, Ic % nb, Jc % nb, Kc % nb)];
     }
     own[amr_local(P, g, li, lj, lk)] = v;
   }
 }
 
+// Ghost-fluid coefficient of the face between centres a (lower) and b: 1/rho of the phase
+// when both are on one side (irn = 1/rn, irp = 1/rp, the same correctly rounded values a
+// division gives), else the series value 1 / (theta rho_a + (1 - theta) rho_b) with theta
+// the fraction of the segment on a's side.
+__device__ inline double amr_beta(double pa, double pb, double rn, double rp, double irn,
+                                  double irp) {
+#pragma clang fp contract(off)
+  const bool a = pa > 0.0, b = pb > 0.0;
+  if (a == b) return a ? irp : irn;
+  const double theta = fabs(pa) / (fabs(pa) + fabs(pb));
+  return 1.0 / (theta * (a ? rp : rn) + (1.0 - theta) * (b ? rp : rn));
+}
+
+// (A x)_c of one leaf cell c (global coordinates c[], local l[] in its block of level
+// `lev`), its value xc and level set pc, and the values xn[f], pn[f] of the six guard or
+// interior positions next to it in its padded block (f = 2 d + (dir > 0)).  other[f] is 1
+// where the block across face f is on the other level (coarser for a level-1 block,
+// refined for a level-0 block), else 0 (read only for cells on that face).  Terms in the
+// order x-, x+, y-, y+, z-, z+; the four fine cells of a coarse-fine face in the order of
+// the next two axes, cyclically.
+__device__ inline double amr_cell(const AmrShape& A, int lev, int nb, int g, int P, int n,
+                                  const int* __restrict__ map1, const double* __restrict__ phi1,
+                                  const double* __restrict__ x1, const int other[6],
+                                  const int c[3], const int l[3],
+                                  double xc, double pc, const double xn[6], const double pn[6],
+                                  double rn, double rp, double same) {
+#pragma clang fp contract(off)
+  const double irn = 1.0 / rn, irp = 1.0 / rp;
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int dir = side ? 1 : -1;
+      const int pd = c[d] + dir;
+      if (pd < 0 || pd >= n) continue;
+      const int ld = l[d] + dir;
+      const bool in_block = ld >= 0 && ld < nb;
+      const double xq = xn[2 * d + side], pq = pn[2 * d + side];
+      const bool same_level = in_block || other[2 * d + side] == 0;
+      if (lev == 1) {
+        // a neighbour on level 1 where its block is stored, else the coarse cell (both
+        // held by this block's guards)
+        const double beta = side ? amr_beta(pc, pq, rn, rp, irn, irp) : amr_beta(pq, pc, rn, rp, irn, irp);
+        s += beta * (xq - xc) * (same_level ? same : A.fine_side);
+      } else if (same_level) {
+        const double beta = side ? amr_beta(pc, pq, rn, rp, irn, irp) : amr_beta(pq, pc, rn, rp, irn, irp);
+        s += beta * (xq - xc) * same;
+      } else {
+        int e1 = d + 1, e2 = d + 2;
+        if (e1 >= 3) e1 -= 3;
+        if (e2 >= 3) e2 -= 3;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            int f[3];
+            f[d] = side ? 2 * pd : 2 * pd + 1;
+            f[e1] = 2 * c[e1] + a;
+            f[e2] = 2 * c[e2] + b;
+            const int fblk = map1[f[0] / nb + A.nbx1 * (f[1] / nb + A.nbx1 * (f[2] / nb))];
+            const size_t fo = (size_t)fblk * A.P3 + amr_local(P, g, f[0] % nb, f[1] % nb, f[2] % nb);
+            const double xf = x1[fo], pf = phi1[fo];
+            const double beta = side ? amr_beta(pc, pf, rn, rp, irn, irp) : amr_beta(pf, pc, rn, rp, irn, irp);
+            s += beta * (xf - xc) * A.coarse_side;
+          }
+      }
+    }
+  return s;
+}
+
 // y = A x on the leaves, x and phi in blocks with filled guards (g >= 1).  A level-1 cell
 // and an unrefined level-0 cell take every neighbour of their own level, and a fine
 // cell its coarse neighbours, from the guards of their own block; a level-0 cell next to
-// a refined block reads the four level-1 cells across the face from their blocks.  The
-// terms are summed in the order x-, x+, y-, y+, z-, z+ (the four fine cells of a face in
-// the order of the next two axes, cyclically).  Guards of y and every value of a refined
-// level-0 block are set to 0.  One workgroup per stored block (level 0 first).
+// a refined block reads the four level-1 cells across the face from their blocks.  Guards
+// of y and every value of a refined level-0 block are set to 0.  One workgroup per stored
+// block (level 0 first; two per block for 16^3 blocks with one guard layer, one
+// otherwise).  When a plane of the block has as many cells as the workgroup has threads,
+// each thread marches up one column, keeping the values below and at the current cell in
+// registers; otherwise the threads stride over the block.
 template <int NB, int G>
 __global__ void __launch_bounds__(kBlkThreads)
     k_amr_apply(AmrShape A, const uint8_t* __restrict__ refined0, const int* __restrict__ map1,
@@ -121,7 +214,6 @@ __global__ void __launch_bounds__(kBlkThreads)
                 const double* __restrict__ phi1, const double* __restrict__ x0,
                 const double* __restrict__ x1, double rn, double rp, double* __restrict__ y0,
                 double* __restrict__ y1) {
-#pragma clang fp contract(off)
   const int lev = (int)blockIdx.x >= A.nblk0;
   const int blk = lev ? (int)blockIdx.x - A.nblk0 : (int)blockIdx.x;
   int bi, bj, bk;
@@ -134,78 +226,98 @@ __global__ void __launch_bounds__(kBlkThreads)
   double* const yb = (lev ? y1 : y0) + base;
   const int P3 = P * P * P;
   if (lev == 0 && refined0[blk]) {
-    for (int q = threadIdx.x; q < P3; q += kBlkThreads) yb[q] = 0.0;
+    // each of the gridDim.y workgroups of the block clears its share of the planes
+    const int pl0 = P * (int)blockIdx.y / (int)gridDim.y, pl1 = P * ((int)blockIdx.y + 1) / (int)gridDim.y;
+    for (int q = pl0 * P * P + threadIdx.x; q < pl1 * P * P; q += kBlkThreads) yb[q] = 0.0;
     return;
   }
-  const int stride[3] = {1, P, P * P};
   const double same = lev ? A.same1 : A.same0;
-  for (int q = threadIdx.x; q < P3; q += kBlkThreads) {
-    const int l[3] = {q % P - g, (q / P) % P - g, q / (P * P) - g};
-    double out = 0.0;
-    if (l[0] >= 0 && l[0] < nb && l[1] >= 0 && l[1] < nb && l[2] >= 0 && l[2] < nb) {
-      const int c[3] = {bi * nb + l[0], bj * nb + l[1], bk * nb + l[2]};
-      const double xc = xb[q], pc = pb[q];
-      double s = 0.0;
+  // level of the block across each face (a face on a wall is never read)
+  int other[6];
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int dir = -1; dir <= 1; dir += 2) {
-          const int pd = c[d] + dir;
-          if (pd < 0 || pd >= n) continue;
-          const int ld = l[d] + dir;
-          const bool in_block = ld >= 0 && ld < nb;
-          int e1 = d + 1, e2 = d + 2;
-          if (e1 >= 3) e1 -= 3;
-          if (e2 >= 3) e2 -= 3;
-          if (lev == 1) {
-            // neighbour on level 1 where its block is stored, else the coarse cell (both
-            // in this block's guards)
-            bool same_level = in_block;
-            if (!in_block) {
-              int p[3] = {c[0], c[1], c[2]};
-              p[d] = pd;
-              same_level = map1[p[0] / nb + A.nbx1 * (p[1] / nb + A.nbx1 * (p[2] / nb))] >= 0;
-            }
-            const int qn = q + dir * stride[d];
-            const double xq = xb[qn], pq = pb[qn];
-            const double beta = dir > 0 ? ghost_fluid_beta(pc, pq, rn, rp)
-                                        : ghost_fluid_beta(pq, pc, rn, rp);
-            s += beta * (xq - xc) * (same_level ? same : A.fine_side);
-          } else {
-            bool fine = false;
-            if (!in_block) {
-              int p[3] = {c[0], c[1], c[2]};
-              p[d] = pd;
-              fine = refined0[p[0] / nb + A.nbx0 * (p[1] / nb + A.nbx0 * (p[2] / nb))] != 0;
-            }
-            if (!fine) {
-              const int qn = q + dir * stride[d];
-              const double xq = xb[qn], pq = pb[qn];
-              const double beta = dir > 0 ? ghost_fluid_beta(pc, pq, rn, rp)
-                                          : ghost_fluid_beta(pq, pc, rn, rp);
-              s += beta * (xq - xc) * same;
-            } else {
-#pragma unroll
-              for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                  int f[3];
-                  f[d] = dir > 0 ? 2 * pd : 2 * pd + 1;
-                  f[e1] = 2 * c[e1] + a;
-                  f[e2] = 2 * c[e2] + b;
-                  const int fblk = map1[f[0] / nb + A.nbx1 * (f[1] / nb + A.nbx1 * (f[2] / nb))];
-                  const size_t fo = (size_t)fblk * A.P3 + amr_local(P, g, f[0] % nb, f[1] % nb, f[2] % nb);
-                  const double xq = x1[fo], pq = phi1[fo];
-                  const double beta = dir > 0 ? ghost_fluid_beta(pc, pq, rn, rp)
-                                              : ghost_fluid_beta(pq, pc, rn, rp);
-                  s += beta * (xq - xc) * A.coarse_side;
-                }
-            }
-          }
-        }
-      out = s;
+  for (int f = 0; f < 6; ++f) {
+    int p[3] = {bi, bj, bk};
+    p[f >> 1] += (f & 1) ? 1 : -1;
+    const int nbx = lev ? A.nbx1 : A.nbx0;
+    other[f] = 0;
+    if (p[f >> 1] >= 0 && p[f >> 1] < nbx)
+      other[f] = lev ? (map1[p[0] + nbx * (p[1] + nbx * p[2])] < 0)
+                     : (refined0[p[0] + nbx * (p[1] + nbx * p[2])] != 0);
+  }
+  if constexpr (NB == 16 && G == 1) {
+    // Two workgroups per block (blockIdx.y: lower or upper 8 planes).  The 10 padded
+    // planes x and phi of a half need are staged in LDS (51840 bytes, three workgroups
+    // per compute unit) with every load in flight at once; each thread then marches up
+    // one column of the half.  A half writes y on 9 of the 18 padded planes.
+    constexpr int PPl = 18 * 18, HZ = 8, NPL = HZ + 2;
+    __shared__ double sx[NPL * PPl], sp[NPL * PPl];
+    const int hz = blockIdx.y;
+    const int k0 = hz * HZ;   // first interior plane of the half; padded plane k0 is below it
+    const double* const xs = xb + (size_t)k0 * PPl;
+    const double* const ps = pb + (size_t)k0 * PPl;
+    for (int t = threadIdx.x; t < NPL * PPl; t += kBlkThreads) {
+      sx[t] = xs[t];
+      sp[t] = ps[t];
     }
-    yb[q] = out;
+    for (int t = threadIdx.x; t < 9 * PPl; t += kBlkThreads) {
+      const int pk = hz * 9 + t / PPl, pj = (t % PPl) / 18, pi = t % 18;
+      if (pk == 0 || pk == 17 || pj == 0 || pj == 17 || pi == 0 || pi == 17)
+        yb[(size_t)pk * PPl + pj * 18 + pi] = 0.0;
+    }
+    __syncthreads();
+    const int li = threadIdx.x % 16, lj = threadIdx.x / 16;
+    for (int kk = 0; kk < HZ; ++kk) {
+      const int lk = k0 + kk;
+      const int t = (kk + 1) * PPl + (lj + 1) * 18 + (li + 1);
+      const double xn[6] = {sx[t - 1], sx[t + 1], sx[t - 18], sx[t + 18], sx[t - PPl], sx[t + PPl]};
+      const double pn[6] = {sp[t - 1], sp[t + 1], sp[t - 18], sp[t + 18], sp[t - PPl], sp[t + PPl]};
+      const int c[3] = {bi * 16 + li, bj * 16 + lj, bk * 16 + lk};
+      const int l[3] = {li, lj, lk};
+      yb[amr_local(18, 1, li, lj, lk)] = amr_cell(A, lev, 16, 1, 18, n, map1, phi1, x1,
+                                                  other, c, l, sx[t], sp[t], xn, pn, rn, rp, same);
+    }
+  } else if constexpr (NB > 0 && NB * NB == kBlkThreads) {
+    const int guards = P3 - NB * NB * NB;
+    for (int q = threadIdx.x; q < guards; q += kBlkThreads) {
+      int li, lj, lk;
+      blk_guard_cell(q, NB, G, P, li, lj, lk);
+      yb[amr_local(P, G, li, lj, lk)] = 0.0;
+    }
+    const int li = threadIdx.x % NB, lj = threadIdx.x / NB;
+    const int PP = P * P;
+    int q = (int)amr_local(P, G, li, lj, 0);
+    double xlo = xb[q - PP], plo = pb[q - PP], xc = xb[q], pc = pb[q];
+    for (int lk = 0; lk < NB; ++lk, q += PP) {
+      const double xn[6] = {xb[q - 1], xb[q + 1], xb[q - P], xb[q + P], xlo, xb[q + PP]};
+      const double pn[6] = {pb[q - 1], pb[q + 1], pb[q - P], pb[q + P], plo, pb[q + PP]};
+      const int c[3] = {bi * NB + li, bj * NB + lj, bk * NB + lk};
+      const int l[3] = {li, lj, lk};
+      yb[q] = amr_cell(A, lev, NB, G, P, n, map1, phi1, x1, other, c, l, xc, pc, xn, pn, rn,
+                       rp, same);
+      xlo = xc;
+      plo = pc;
+      xc = xn[5];
+      pc = pn[5];
+    }
+  } else {
+    const int stride[3] = {1, P, P * P};
+    for (int q = threadIdx.x; q < P3; q += kBlkThreads) {
+      const int l[3] = {q % P - g, (q / P) % P - g, q / (P * P) - g};
+      double out = 0.0;
+      if (l[0] >= 0 && l[0] < nb && l[1] >= 0 && l[1] < nb && l[2] >= 0 && l[2] < nb) {
+        const int c[3] = {bi * nb + l[0], bj * nb + l[1], bk * nb + l[2]};
+        double xn[6], pn[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int qn = q + ((f & 1) ? 1 : -1) * stride[f >> 1];
+          xn[f] = xb[qn];
+          pn[f] = pb[qn];
+        }
+        out = amr_cell(A, lev, nb, g, P, n, map1, phi1, x1, other, c, l, xb[q], pb[q], xn, pn,
+                       rn, rp, same);
+      }
+      yb[q] = out;
+    }
   }
 }
 

@@ -1775,7 +1775,7 @@ int mpp_amr_apply(mpp_amr a, const double* phi0, const double* phi1, const doubl
     if (in && (in == (const void*)y0 || in == (const void*)y1)) return MPP_EINVAL;
   if (y1 && y0 == y1) return MPP_EINVAL;
 #define L_(NB_, G_)                                                                          \
-  hipLaunchKernelGGL((k_amr_apply<NB_, G_>), dim3((unsigned)(A.nblk0 + A.nblk1)), dim3(kBlkThreads), \
+  hipLaunchKernelGGL((k_amr_apply<NB_, G_>), dim3((unsigned)(A.nblk0 + A.nblk1), (NB_ == 16 && G_ == 1) ? 2 : 1), dim3(kBlkThreads), \
                      0, reinterpret_cast<hipStream_t>(stream), A, a->refined0, a->map1, a->list1, \
                      phi0, phi1, x0, x1, rho_neg, rho_pos, y0, y1)
   MPP_BLK_DISPATCH(A, L_);
