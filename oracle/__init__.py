@@ -66,6 +66,8 @@ def lib():
         L.orc_blocks_apply.argtypes = [i, i, i, P, P, P, P, P]
         L.orc_amr_apply.argtypes = [i, i, P, P, P, P, P, d, d, P, P]
         L.orc_amr_fill.argtypes = [i, i, i, P, P, P, P, P]
+        L.orc_amr_solve.argtypes = [i, i, P, P, P, d, d, P, P, P, P, d, i,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.orc_gs_colour.argtypes = [i, P, P, P, P, P, i]
         L.orc_gs_colour.restype = None
         L.orc_restrict.argtypes = [i, P, P]
@@ -312,6 +314,24 @@ def amr_fill(refined0, nb, g, v0, v1):
     _check(lib().orc_amr_fill(n0, nb, g, _p(refined0), _p(v0), _p(v1), _p(b0), _p(b1)),
            "amr_fill")
     return b0, b1
+
+
+def amr_solve(refined0, nb, phi0, phi1, b0, b1, rho_neg, rho_pos, rtol=1e-10, max_iter=100000,
+              x0=None, x1=None):
+    """A x = b on the leaves of the composite grid (b's weighted mean removed), Jacobi-
+    preconditioned CG in the volume-weighted inner product; returns (x0, x1, iters,
+    rel_residual), x of zero weighted mean and zero off the leaves."""
+    refined0 = np.ascontiguousarray(refined0, dtype=np.uint8)
+    phi0, phi1, b0, b1 = (_c(a) for a in (phi0, phi1, b0, b1))
+    n0 = _n(phi0)
+    x0 = np.zeros_like(b0) if x0 is None else _c(x0).copy()
+    x1 = np.zeros_like(b1) if x1 is None else _c(x1).copy()
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    _check(lib().orc_amr_solve(n0, nb, _p(refined0), _p(phi0), _p(phi1), float(rho_neg),
+                               float(rho_pos), _p(b0), _p(b1), _p(x0), _p(x1), float(rtol),
+                               int(max_iter), ctypes.byref(it), ctypes.byref(rel)), "amr_solve")
+    return x0, x1, it.value, rel.value
 
 
 def pipeline(phi, f, rho_neg, rho_pos, sigma, kappa_override=None):

@@ -1162,11 +1162,23 @@ static int amr_refined(int n0, int nb, const uint8_t *refined0, int I, int J, in
     return refined0[(size_t)(I / nb) + nbx * ((size_t)(J / nb) + nbx * (size_t)(K / nb))] != 0;
 }
 
+/* diag != 0: the operator's diagonal instead (x read as 1 at the cell, 0 elsewhere) */
+static int amr_op(int n0, int nb, const uint8_t *refined0, const double *phi0, const double *phi1,
+                  const double *x0, const double *x1, double rho_neg, double rho_pos, double *y0,
+                  double *y1, int diag);
+
 int orc_amr_apply(int n0, int nb, const uint8_t *refined0, const double *phi0, const double *phi1,
                   const double *x0, const double *x1, double rho_neg, double rho_pos, double *y0,
                   double *y1)
 {
-    if (n0 < 1 || nb < 1 || n0 % nb || !refined0 || !phi0 || !phi1 || !x0 || !x1 || !y0 || !y1 ||
+    return amr_op(n0, nb, refined0, phi0, phi1, x0, x1, rho_neg, rho_pos, y0, y1, 0);
+}
+
+static int amr_op(int n0, int nb, const uint8_t *refined0, const double *phi0, const double *phi1,
+                  const double *x0, const double *x1, double rho_neg, double rho_pos, double *y0,
+                  double *y1, int diag)
+{
+    if (n0 < 1 || nb < 1 || n0 % nb || !refined0 || !phi0 || !phi1 || (!diag && (!x0 || !x1)) || !y0 || !y1 ||
         !(rho_neg > 0.0) || !(rho_pos > 0.0))
         return ORC_EINVAL;
     int n1 = 2 * n0;
@@ -1193,7 +1205,7 @@ int orc_amr_apply(int n0, int nb, const uint8_t *refined0, const double *phi0, c
                             size_t q = ix(n0, P[0], P[1], P[2]);
                             double beta = dir > 0 ? face_beta(phi0[c], phi0[q], rho_neg, rho_pos)
                                                   : face_beta(phi0[q], phi0[c], rho_neg, rho_pos);
-                            s += beta * (x0[q] - x0[c]) * same0;
+                            s += beta * ((diag ? 0.0 : x0[q]) - (diag ? 1.0 : x0[c])) * same0;
                         } else {
                             /* the four fine cells across the face */
                             int e1 = (d + 1) % 3, e2 = (d + 2) % 3;
@@ -1206,7 +1218,7 @@ int orc_amr_apply(int n0, int nb, const uint8_t *refined0, const double *phi0, c
                                     size_t q = ix(n1, F[0], F[1], F[2]);
                                     double beta = dir > 0 ? face_beta(phi0[c], phi1[q], rho_neg, rho_pos)
                                                           : face_beta(phi1[q], phi0[c], rho_neg, rho_pos);
-                                    s += beta * (x1[q] - x0[c]) * coarse_side;
+                                    s += beta * ((diag ? 0.0 : x1[q]) - (diag ? 1.0 : x0[c])) * coarse_side;
                                 }
                         }
                     }
@@ -1230,12 +1242,12 @@ int orc_amr_apply(int n0, int nb, const uint8_t *refined0, const double *phi0, c
                             size_t q = ix(n1, P[0], P[1], P[2]);
                             double beta = dir > 0 ? face_beta(phi1[c], phi1[q], rho_neg, rho_pos)
                                                   : face_beta(phi1[q], phi1[c], rho_neg, rho_pos);
-                            s += beta * (x1[q] - x1[c]) * same1;
+                            s += beta * ((diag ? 0.0 : x1[q]) - (diag ? 1.0 : x1[c])) * same1;
                         } else {
                             size_t q = ix(n0, P[0] / 2, P[1] / 2, P[2] / 2);
                             double beta = dir > 0 ? face_beta(phi1[c], phi0[q], rho_neg, rho_pos)
                                                   : face_beta(phi0[q], phi1[c], rho_neg, rho_pos);
-                            s += beta * (x0[q] - x1[c]) * fine_side;
+                            s += beta * ((diag ? 0.0 : x0[q]) - (diag ? 1.0 : x1[c])) * fine_side;
                         }
                     }
                 y1[c] = s;
@@ -1302,6 +1314,128 @@ int orc_amr_fill(int n0, int nb, int g, const uint8_t *refined0, const double *v
         }
     }
     return ORC_OK;
+}
+
+/* Solve A x = b on the leaves of the composite grid by conjugate gradients preconditioned
+ * with the inverse diagonal, in the volume-weighted inner product <u, v> = sum_leaves
+ * V_c u_c v_c, in which A is symmetric and -A positive semi-definite (constants are its
+ * null space, the Neumann walls).  b's weighted mean is removed first (the total volume
+ * is 1); x (in: the initial guess, out: the solution) is returned with zero weighted
+ * mean.  Stops when ||b' - A x|| <= rtol ||b'|| in the weighted norm (b' = b - mean).
+ * Values off the leaves are ignored on input and zero on output. */
+typedef struct {
+    int n0, nb;
+    const uint8_t *refined0;
+    size_t m0, m1;
+    double v0, v1;   /* cell volumes */
+} amr_ctx;
+
+static int amr_leaf(const amr_ctx *C, int lev, size_t c)
+{
+    int n = lev ? 2 * C->n0 : C->n0;
+    int i = (int)(c % n), j = (int)((c / n) % n), k = (int)(c / ((size_t)n * n));
+    if (lev)
+        return amr_refined(C->n0, C->nb, C->refined0, i / 2, j / 2, k / 2);
+    return !amr_refined(C->n0, C->nb, C->refined0, i, j, k);
+}
+
+static double amr_dot(const amr_ctx *C, const double *a0, const double *a1, const double *b0,
+                      const double *b1)
+{
+    double s0 = 0.0, s1 = 0.0;
+    for (size_t c = 0; c < C->m0; ++c)
+        if (amr_leaf(C, 0, c))
+            s0 += a0[c] * (b0 ? b0[c] : 1.0);
+    for (size_t c = 0; c < C->m1; ++c)
+        if (amr_leaf(C, 1, c))
+            s1 += a1[c] * (b1 ? b1[c] : 1.0);
+    return C->v0 * s0 + C->v1 * s1;
+}
+
+int orc_amr_solve(int n0, int nb, const uint8_t *refined0, const double *phi0, const double *phi1,
+                  double rho_neg, double rho_pos, const double *b0, const double *b1, double *x0,
+                  double *x1, double rtol, int max_iter, int *iters_out, double *relres_out)
+{
+    if (n0 < 1 || nb < 1 || n0 % nb || !refined0 || !phi0 || !phi1 || !b0 || !b1 || !x0 ||
+        !x1 || !(rtol > 0.0) || max_iter < 0 || !(rho_neg > 0.0) || !(rho_pos > 0.0))
+        return ORC_EINVAL;
+    amr_ctx C = {n0, nb, refined0, (size_t)n0 * n0 * n0, (size_t)8 * n0 * n0 * n0,
+                 1.0 / ((double)n0 * n0 * n0), 1.0 / (8.0 * n0 * n0 * n0)};
+    size_t m0 = C.m0, m1 = C.m1;
+    double *buf = (double *)calloc(7 * (m0 + m1), sizeof(double));
+    if (!buf)
+        return ORC_ENOMEM;
+    double *r0 = buf, *r1 = r0 + m0, *z0 = r1 + m1, *z1 = z0 + m0, *p0 = z1 + m1, *p1 = p0 + m0;
+    double *q0 = p1 + m1, *q1 = q0 + m0, *d0 = q1 + m1, *d1 = d0 + m0, *bb0 = d1 + m1,
+           *bb1 = bb0 + m0, *t0 = bb1 + m1, *t1 = t0 + m0;
+    /* diagonal (negated: positive) */
+    amr_op(n0, nb, refined0, phi0, phi1, NULL, NULL, rho_neg, rho_pos, d0, d1, 1);
+    double mean = amr_dot(&C, b0, b1, NULL, NULL);
+    for (size_t c = 0; c < m0; ++c) {
+        bb0[c] = amr_leaf(&C, 0, c) ? b0[c] - mean : 0.0;
+        if (!amr_leaf(&C, 0, c)) x0[c] = 0.0;
+    }
+    for (size_t c = 0; c < m1; ++c) {
+        bb1[c] = amr_leaf(&C, 1, c) ? b1[c] - mean : 0.0;
+        if (!amr_leaf(&C, 1, c)) x1[c] = 0.0;
+    }
+    double bnorm = sqrt(amr_dot(&C, bb0, bb1, bb0, bb1));
+    orc_amr_apply(n0, nb, refined0, phi0, phi1, x0, x1, rho_neg, rho_pos, q0, q1);
+    for (size_t c = 0; c < m0; ++c) r0[c] = bb0[c] - q0[c];
+    for (size_t c = 0; c < m1; ++c) r1[c] = bb1[c] - q1[c];
+    int status = ORC_ENOTCONVERGED, it = 0;
+    if (bnorm == 0.0) {
+        status = ORC_OK;
+    } else {
+        for (size_t c = 0; c < m0; ++c) z0[c] = d0[c] != 0.0 ? r0[c] / -d0[c] : 0.0;
+        for (size_t c = 0; c < m1; ++c) z1[c] = d1[c] != 0.0 ? r1[c] / -d1[c] : 0.0;
+        memcpy(p0, z0, sizeof(double) * m0);
+        memcpy(p1, z1, sizeof(double) * m1);
+        double rz = amr_dot(&C, r0, r1, z0, z1);
+        for (it = 0; it < max_iter;) {
+            if (sqrt(amr_dot(&C, r0, r1, r0, r1)) <= rtol * bnorm) {
+                status = ORC_OK;
+                break;
+            }
+            orc_amr_apply(n0, nb, refined0, phi0, phi1, p0, p1, rho_neg, rho_pos, q0, q1);
+            double pq = amr_dot(&C, p0, p1, q0, q1);   /* <p, A p> < 0 */
+            if (!(pq < 0.0)) {
+                status = ORC_EBREAKDOWN;
+                break;
+            }
+            /* with M = -A: the step along p of CG on M x = -b' (p, z built from r = b' - A x
+             * are the negatives of those CG builds from its residual -r) */
+            double alpha = -rz / pq;
+            for (size_t c = 0; c < m0; ++c) {
+                x0[c] -= alpha * p0[c];
+                r0[c] += alpha * q0[c];
+                z0[c] = d0[c] != 0.0 ? r0[c] / -d0[c] : 0.0;
+            }
+            for (size_t c = 0; c < m1; ++c) {
+                x1[c] -= alpha * p1[c];
+                r1[c] += alpha * q1[c];
+                z1[c] = d1[c] != 0.0 ? r1[c] / -d1[c] : 0.0;
+            }
+            ++it;
+            double rz_new = amr_dot(&C, r0, r1, z0, z1);
+            double beta = rz_new / rz;
+            rz = rz_new;
+            for (size_t c = 0; c < m0; ++c) p0[c] = z0[c] + beta * p0[c];
+            for (size_t c = 0; c < m1; ++c) p1[c] = z1[c] + beta * p1[c];
+        }
+    }
+    double xm = amr_dot(&C, x0, x1, NULL, NULL);
+    for (size_t c = 0; c < m0; ++c) x0[c] = amr_leaf(&C, 0, c) ? x0[c] - xm : 0.0;
+    for (size_t c = 0; c < m1; ++c) x1[c] = amr_leaf(&C, 1, c) ? x1[c] - xm : 0.0;
+    /* the true residual of the returned x */
+    orc_amr_apply(n0, nb, refined0, phi0, phi1, x0, x1, rho_neg, rho_pos, t0, t1);
+    for (size_t c = 0; c < m0; ++c) t0[c] = amr_leaf(&C, 0, c) ? bb0[c] - t0[c] : 0.0;
+    for (size_t c = 0; c < m1; ++c) t1[c] = amr_leaf(&C, 1, c) ? bb1[c] - t1[c] : 0.0;
+    double rel = bnorm > 0.0 ? sqrt(amr_dot(&C, t0, t1, t0, t1)) / bnorm : 0.0;
+    if (iters_out) *iters_out = it;
+    if (relres_out) *relres_out = rel;
+    free(buf);
+    return status;
 }
 
 /* ------------------------------------------------------------------------ */

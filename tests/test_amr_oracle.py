@@ -248,3 +248,51 @@ def test_rejects_bad_arguments():
         O.amr_apply(np.zeros((3, 3, 3), np.uint8), 3, p0, p1, p0, p1, RN, RP)   # 8 % 3
     with pytest.raises(O.OracleError):
         O.amr_fill(np.zeros((2, 2, 2), np.uint8), 4, 5, p0, p1)                 # g > nb
+
+
+def test_solve_reaches_its_residual():
+    n0, nb = 8, 2
+    p0, p1 = level_phis(n0, 31)
+    flags = random_flags(n0 // nb, 31, 0.4)
+    rng = np.random.default_rng(31)
+    b0, b1 = rng.standard_normal(p0.shape), rng.standard_normal(p1.shape)
+    x0, x1, it, rel = O.amr_solve(flags, nb, p0, p1, b0, b1, 1e-3, 1.0, rtol=1e-11)
+    assert rel <= 1e-11 and it > 0
+    # recomputed from the operator, with b's weighted mean removed
+    m0, m1 = leaf_mask0(flags, nb), leaf_mask1(flags, nb)
+    v0, v1 = volumes(n0)
+    mean = v0 * b0[m0].sum() + v1 * b1[m1].sum()
+    a0, a1 = O.amr_apply(flags, nb, p0, p1, x0, x1, 1e-3, 1.0)
+    r0, r1 = np.where(m0, b0 - mean - a0, 0.0), np.where(m1, b1 - mean - a1, 0.0)
+    bb0, bb1 = np.where(m0, b0 - mean, 0.0), np.where(m1, b1 - mean, 0.0)
+    assert np.sqrt(wdot(flags, nb, r0, r1, r0, r1)) <= 1.01e-11 * np.sqrt(wdot(flags, nb, bb0, bb1, bb0, bb1))
+    assert abs(wdot(flags, nb, x0, x1, np.ones_like(x0), np.ones_like(x1))) < 1e-14
+    assert np.all(x0[~m0] == 0.0) and np.all(x1[~m1] == 0.0)
+
+
+def test_solve_recovers_a_manufactured_solution():
+    n0, nb = 8, 4
+    p0, p1 = level_phis(n0, 32)
+    flags = random_flags(n0 // nb, 32, 0.5)
+    m0, m1 = leaf_mask0(flags, nb), leaf_mask1(flags, nb)
+    rng = np.random.default_rng(32)
+    s0, s1 = np.where(m0, rng.standard_normal(p0.shape), 0.0), np.where(m1, rng.standard_normal(p1.shape), 0.0)
+    v0, v1 = volumes(n0)
+    sm = v0 * s0[m0].sum() + v1 * s1[m1].sum()
+    s0, s1 = np.where(m0, s0 - sm, 0.0), np.where(m1, s1 - sm, 0.0)
+    b0, b1 = O.amr_apply(flags, nb, p0, p1, s0, s1, RN, RP)
+    x0, x1, it, rel = O.amr_solve(flags, nb, p0, p1, b0, b1, RN, RP, rtol=1e-13)
+    scale = max(np.abs(s0).max(), np.abs(s1).max())
+    assert np.abs(x0 - s0).max() <= 1e-6 * scale and np.abs(x1 - s1).max() <= 1e-6 * scale
+
+
+def test_solve_without_refinement_is_the_uniform_solve():
+    n0, nb = 8, 4
+    p0, p1 = level_phis(n0, 33)
+    b0 = np.random.default_rng(33).standard_normal(p0.shape)
+    none = np.zeros((2, 2, 2), np.uint8)
+    x0, _, _, rel = O.amr_solve(none, nb, p0, p1, b0, np.zeros_like(p1), RN, RP, rtol=1e-13)
+    b = b0 - b0.mean()
+    ref = O.solve_jacobi_pcg(O.faces(p0, RN, RP), b, tol=1e-13)
+    ref = ref[0] if isinstance(ref, tuple) else ref
+    assert np.abs(x0 - ref).max() <= 1e-7 * np.abs(ref).max()
