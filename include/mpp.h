@@ -365,6 +365,29 @@ int mpp_amr_apply(mpp_amr a, const double *phi0, const double *phi1, const doubl
                   const double *x1, double rho_neg, double rho_pos, double *y0, double *y1,
                   void *stream);
 
+/* Device workspace mpp_amr_solve needs for this grid (0 if a is NULL): five vectors in
+ * the block layout of both levels plus per-block partial sums. */
+size_t mpp_amr_solve_work_bytes(mpp_amr a);
+
+/* Solves A x = b on the leaves by conjugate gradients preconditioned with the inverse
+ * diagonal, in the volume-weighted inner product sum_leaves V_c u_c v_c (A is symmetric
+ * in it, -A positive semi-definite with the constants as null space: the Neumann walls).
+ * The weighted mean of b is removed first (the domain's volume is 1); x is returned with
+ * zero weighted mean.  Stops when the weighted norm of the residual b' - A x is at most
+ * rtol times that of b', polled every 8 iterations, or after max_iter iterations.
+ * phi: level set with filled guards; b: interiors of the leaf blocks; x: in, the initial
+ * guess on the leaves; out, the solution on the leaves with its guards filled (values of
+ * refined level-0 blocks are left as they are).  work: device, >=
+ * mpp_amr_solve_work_bytes(a), owned by the caller.  *iters: iterations done; *rel_resid:
+ * the weighted relative residual of the returned x, recomputed from it (both HOST, may be
+ * NULL).  Synchronous.  MPP_OK, MPP_ENOTCONVERGED (x holds the last iterate),
+ * MPP_EBREAKDOWN, MPP_EINVAL (x aliasing b or phi, rtol <= 0, max_iter < 0, ...),
+ * MPP_ENOMEM (work too small). */
+int mpp_amr_solve(mpp_amr a, const double *phi0, const double *phi1, double rho_neg,
+                  double rho_pos, const double *b0, const double *b1, double *x0, double *x1,
+                  double rtol, int32_t max_iter, void *work, size_t work_bytes, int32_t *iters,
+                  double *rel_resid, void *stream);
+
 /* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from
  * the previous pressure or from zero): a small 3D U-Net maps the density field and

@@ -34,7 +34,7 @@ EXPORTS = (
     "mpp_ls_advect", "mpp_ls_reinit", "mpp_heat_solve", "mpp_blocks_scatter",
     "mpp_blocks_gather", "mpp_blocks_fill_guards", "mpp_blocks_apply",
     "mpp_amr_workspace_bytes", "mpp_amr_create", "mpp_amr_destroy", "mpp_amr_level1_blocks",
-    "mpp_amr_fill_guards", "mpp_amr_apply",
+    "mpp_amr_fill_guards", "mpp_amr_apply", "mpp_amr_solve_work_bytes", "mpp_amr_solve",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -135,13 +135,17 @@ def load_library(path: str = LIB_PATH):
     L.mpp_amr_level1_blocks.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
     L.mpp_amr_fill_guards.argtypes = [P, P, P, P]
     L.mpp_amr_apply.argtypes = [P, P, P, P, P, d, d, P, P, P]
+    L.mpp_amr_solve_work_bytes.argtypes = [P]
+    L.mpp_amr_solve_work_bytes.restype = ctypes.c_size_t
+    L.mpp_amr_solve.argtypes = [P, P, P, d, d, P, P, P, P, d, i32, P, ctypes.c_size_t,
+                                ctypes.POINTER(i32), ctypes.POINTER(d), P]
     L.mpp_heat_solve.argtypes = [P, P, P, d, P, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), P]
     for name in (n for n in EXPORTS if n not in ("mpp_default_opts", "mpp_destroy_operator",
                                                  "mpp_strerror", "mpp_workspace_bytes",
                                                  "mpp_net_workspace_bytes",
                                                  "mpp_net_destroy", "mpp_amr_workspace_bytes",
-                                                 "mpp_amr_destroy")):
+                                                 "mpp_amr_destroy", "mpp_amr_solve_work_bytes")):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -622,6 +626,28 @@ class AmrGrid:
         if st != OK:
             raise MppError(st, "mpp_amr_fill_guards")
         return b0, b1
+
+    def solve(self, phi, b, rho_neg, rho_pos, x=None, rtol=1e-10, max_iter=100000):
+        """x with A x = b - mean(b) on the leaves (Jacobi-preconditioned CG, zero weighted
+        mean); phi: (level0, level1) blocks with filled guards; b: (level0, level1)
+        blocks; x: initial guess, updated in place (zeros if None).  Returns (x, Info)."""
+        torch = _torch()
+        if x is None:
+            x = self.empty()
+        p = self._fields([(phi, "phi"), (b, "b"), (x, "x")])
+        L = load_library()
+        nbytes = int(L.mpp_amr_solve_work_bytes(self._h))
+        if getattr(self, "_work", None) is None or self._work.numel() < nbytes:
+            self._work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        st = L.mpp_amr_solve(self._h, p[0], p[1], float(rho_neg), float(rho_pos), p[2], p[3],
+                             p[4], p[5], float(rtol), int(max_iter),
+                             ctypes.c_void_p(self._work.data_ptr()), nbytes, ctypes.byref(it),
+                             ctypes.byref(rel), _stream_handle(self.device))
+        if st not in (OK, ENOTCONVERGED):
+            raise MppError(st, "mpp_amr_solve")
+        return x, Info(st, int(it.value), 0, float(rel.value), 0.0, 0.0)
 
     def apply(self, phi, x, rho_neg, rho_pos, y=None):
         """y = A x on the leaves; phi, x: (level0, level1) pairs with filled guards."""

@@ -146,7 +146,9 @@ __device__ inline double amr_beta(double pa, double pb, double rn, double rp, do
 // where the block across face f is on the other level (coarser for a level-1 block,
 // refined for a level-0 block), else 0 (read only for cells on that face).  Terms in the
 // order x-, x+, y-, y+, z-, z+; the four fine cells of a coarse-fine face in the order of
-// the next two axes, cyclically.
+// the next two axes, cyclically.  DIAG: the diagonal A_cc instead (x read as 1 at c and 0
+// at every neighbour).
+template <bool DIAG = false>
 __device__ inline double amr_cell(const AmrShape& A, int lev, int nb, int g, int P, int n,
                                   const int* __restrict__ map1, const double* __restrict__ phi1,
                                   const double* __restrict__ x1, const int other[6],
@@ -189,7 +191,7 @@ __device__ inline double amr_cell(const AmrShape& A, int lev, int nb, int g, int
             f[e2] = 2 * c[e2] + b;
             const int fblk = map1[f[0] / nb + A.nbx1 * (f[1] / nb + A.nbx1 * (f[2] / nb))];
             const size_t fo = (size_t)fblk * A.P3 + amr_local(P, g, f[0] % nb, f[1] % nb, f[2] % nb);
-            const double xf = x1[fo], pf = phi1[fo];
+            const double xf = DIAG ? 0.0 : x1[fo], pf = phi1[fo];
             const double beta = side ? amr_beta(pc, pf, rn, rp, irn, irp) : amr_beta(pf, pc, rn, rp, irn, irp);
             s += beta * (xf - xc) * A.coarse_side;
           }
@@ -318,6 +320,191 @@ __global__ void __launch_bounds__(kBlkThreads)
       }
       yb[q] = out;
     }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Conjugate gradients on the composite grid, preconditioned with the inverse diagonal, in
+// the volume-weighted inner product <u, v> = sum over leaves of V_c u_c v_c (A is
+// symmetric in it and -A positive semi-definite).  Vectors live in the block layout of
+// both levels; only the interiors of leaf blocks are read or written.  Every reduction is
+// a per-block partial followed by one workgroup summing the partials in a fixed order, so
+// results do not depend on scheduling.  Scalars stay on the device.
+// ------------------------------------------------------------------------------------
+enum AmrSlot { AS_MEAN, AS_BB, AS_RZ, AS_RR, AS_ALPHA, AS_BETA, AS_FLAG, AS_XMEAN, AS_COUNT };
+
+// -diag(A) on the interiors of leaf blocks (phi with filled guards)
+template <int NB, int G>
+__global__ void __launch_bounds__(kBlkThreads)
+    k_amr_negdiag(AmrShape A, const uint8_t* __restrict__ refined0, const int* __restrict__ map1,
+                  const int* __restrict__ list1, const double* __restrict__ phi0,
+                  const double* __restrict__ phi1, double rn, double rp, double* __restrict__ d0,
+                  double* __restrict__ d1) {
+  const int lev = (int)blockIdx.x >= A.nblk0;
+  const int blk = lev ? (int)blockIdx.x - A.nblk0 : (int)blockIdx.x;
+  if (lev == 0 && refined0[blk]) return;
+  int bi, bj, bk;
+  amr_block_coords(A, lev, blk, list1, bi, bj, bk);
+  const int nb = NB > 0 ? NB : A.nb, g = NB > 0 ? G : A.g, P = nb + 2 * g;
+  const int n = lev ? 2 * A.n0 : A.n0;
+  const int nbx = lev ? A.nbx1 : A.nbx0;
+  int other[6];
+  for (int f = 0; f < 6; ++f) {
+    int p[3] = {bi, bj, bk};
+    p[f >> 1] += (f & 1) ? 1 : -1;
+    other[f] = 0;
+    if (p[f >> 1] >= 0 && p[f >> 1] < nbx)
+      other[f] = lev ? (map1[p[0] + nbx * (p[1] + nbx * p[2])] < 0)
+                     : (refined0[p[0] + nbx * (p[1] + nbx * p[2])] != 0);
+  }
+  const size_t base = (size_t)blk * A.P3;
+  const double* const pb = (lev ? phi1 : phi0) + base;
+  double* const db = (lev ? d1 : d0) + base;
+  const int stride[3] = {1, P, P * P};
+  const double zero[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < nb * nb * nb; t += kBlkThreads) {
+    const int l[3] = {t % nb, (t / nb) % nb, t / (nb * nb)};
+    const int c[3] = {bi * nb + l[0], bj * nb + l[1], bk * nb + l[2]};
+    const int q = (int)amr_local(P, g, l[0], l[1], l[2]);
+    double pn[6];
+    for (int f = 0; f < 6; ++f) pn[f] = pb[q + ((f & 1) ? 1 : -1) * stride[f >> 1]];
+    db[q] = -amr_cell<true>(A, lev, nb, g, P, n, map1, phi1, nullptr, other, c, l, 1.0, pb[q],
+                            zero, pn, rn, rp, lev ? A.same1 : A.same0);
+  }
+}
+
+// sum over the workgroup of v (every thread passes its value; thread 0 gets the total)
+__device__ inline double amr_block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBlkThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Vector steps over the interiors of leaf blocks, each with up to two weighted partial
+// sums per block (part[blockIdx.x] and part[nblocks + blockIdx.x]):
+//   MEAN:  partial <u, 1>                              (u = a)
+//   INIT:  r = b - S[MEAN] (a = b), partial <r, r>
+//   RES:   r -= q, z = r / negd, p = z, partials <r, z>, <r, r>
+//   DOT:   partial <p, q>
+//   STEP:  x -= S[ALPHA] p, r += S[ALPHA] q, z = r / negd, partials <r, z>, <r, r>
+//   DIR:   p = z + S[BETA] p
+//   SHIFT: x -= S[XMEAN]
+// Refined level-0 blocks contribute 0 and are left as they are.
+enum AmrVec { AV_MEAN, AV_INIT, AV_RES, AV_DOT, AV_STEP, AV_DIR, AV_SHIFT };
+
+struct AmrVecs {
+  double *x[2], *r[2], *z[2], *p[2], *q[2];
+  const double *b[2], *negd[2];
+};
+
+template <int MODE, int NB, int G>
+__global__ void __launch_bounds__(kBlkThreads)
+    k_amr_vec(AmrShape A, const uint8_t* __restrict__ refined0, AmrVecs V,
+              const double* __restrict__ S, double* __restrict__ part) {
+#pragma clang fp contract(off)
+  __shared__ double sh[kBlkThreads];
+  const int lev = (int)blockIdx.x >= A.nblk0;
+  const int blk = lev ? (int)blockIdx.x - A.nblk0 : (int)blockIdx.x;
+  const int nblocks = A.nblk0 + A.nblk1;
+  if (lev == 0 && refined0[blk]) {
+    if (threadIdx.x == 0) {
+      part[blockIdx.x] = 0.0;
+      part[nblocks + blockIdx.x] = 0.0;
+    }
+    return;
+  }
+  const int nb = NB > 0 ? NB : A.nb, g = NB > 0 ? G : A.g, P = nb + 2 * g;
+  const size_t base = (size_t)blk * A.P3;
+  double* const x = V.x[lev] + base;
+  double* const r = V.r[lev] + base;
+  double* const z = V.z[lev] + base;
+  double* const p = V.p[lev] + base;
+  double* const q = V.q[lev] + base;
+  const double* const bb = V.b[lev] ? V.b[lev] + base : nullptr;
+  const double* const nd = V.negd[lev] + base;
+  const double alpha = S[AS_ALPHA], beta = S[AS_BETA];
+  double s1 = 0.0, s2 = 0.0;
+  for (int t = threadIdx.x; t < nb * nb * nb; t += kBlkThreads) {
+    const int c = (int)amr_local(P, g, t % nb, (t / nb) % nb, t / (nb * nb));
+    if (MODE == AV_MEAN) {
+      s1 += bb[c];
+    } else if (MODE == AV_INIT) {
+      const double v = bb[c] - S[AS_MEAN];
+      r[c] = v;
+      s1 += v * v;
+    } else if (MODE == AV_RES || MODE == AV_STEP) {
+      double rv;
+      if (MODE == AV_RES) {
+        rv = r[c] - q[c];
+      } else {
+        x[c] = x[c] - alpha * p[c];
+        rv = r[c] + alpha * q[c];
+      }
+      const double zv = rv / nd[c];
+      r[c] = rv;
+      z[c] = zv;
+      if (MODE == AV_RES) p[c] = zv;
+      s1 += rv * zv;
+      s2 += rv * rv;
+    } else if (MODE == AV_DOT) {
+      s1 += p[c] * q[c];
+    } else if (MODE == AV_DIR) {
+      p[c] = z[c] + beta * p[c];
+    } else if (MODE == AV_SHIFT) {
+      x[c] = x[c] - S[AS_XMEAN];
+    }
+  }
+  if (MODE == AV_DIR || MODE == AV_SHIFT) return;
+  const double vol = lev ? 1.0 / (8.0 * (double)A.n0 * A.n0 * A.n0) : 1.0 / ((double)A.n0 * A.n0 * A.n0);
+  const double t1 = amr_block_sum(s1, sh);
+  const double t2 = (MODE == AV_RES || MODE == AV_STEP) ? amr_block_sum(s2, sh) : 0.0;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = vol * t1;
+    part[nblocks + blockIdx.x] = vol * t2;
+  }
+}
+
+// One workgroup: sums the partials (thread t takes t, t + 256, ..., then a tree) and
+// updates the scalars for the step that produced them.
+enum AmrFin { AF_MEAN, AF_BB, AF_RZ0, AF_ALPHA, AF_BETA, AF_XMEAN, AF_RR };
+
+__global__ void __launch_bounds__(kBlkThreads)
+    k_amr_finish(int MODE, const double* __restrict__ part, int nblocks, double* __restrict__ S) {
+  __shared__ double sh[kBlkThreads];
+  double a = 0.0, b = 0.0;
+  for (int t = threadIdx.x; t < nblocks; t += kBlkThreads) {
+    a += part[t];
+    b += part[nblocks + t];
+  }
+  const double ta = amr_block_sum(a, sh);
+  const double tb = amr_block_sum(b, sh);
+  if (threadIdx.x != 0) return;
+  switch (MODE) {
+    case AF_MEAN: S[AS_MEAN] = ta; break;
+    case AF_BB: S[AS_BB] = ta; break;
+    case AF_RZ0: S[AS_RZ] = ta; S[AS_RR] = tb; break;
+    case AF_ALPHA:
+      // <p, A p> < 0 unless p = 0 (then the search has nothing left to do)
+      if (ta < 0.0) {
+        S[AS_ALPHA] = -S[AS_RZ] / ta;
+      } else {
+        S[AS_ALPHA] = 0.0;
+        S[AS_FLAG] = 1.0;
+      }
+      break;
+    case AF_BETA:
+      S[AS_BETA] = S[AS_RZ] != 0.0 ? ta / S[AS_RZ] : 0.0;
+      S[AS_RZ] = ta;
+      S[AS_RR] = tb;
+      break;
+    case AF_XMEAN: S[AS_XMEAN] = ta; break;
+    case AF_RR: S[AS_RR] = tb; break;
   }
 }
 

@@ -1784,3 +1784,175 @@ int mpp_amr_apply(mpp_amr a, const double* phi0, const double* phi1, const doubl
 }
 
 }  // extern "C"
+
+namespace {
+
+struct AmrWork {
+  double* v[5][2];   // r, z, p, q, negd; each level 0 then level 1
+  double* part;      // [2][nblocks]
+  double* S;         // [AS_COUNT]
+  size_t bytes;      // total
+};
+
+AmrWork amr_work_layout(const AmrShape& A, void* base) {
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t n0 = (size_t)A.nblk0 * A.P3, n1 = (size_t)A.nblk1 * A.P3;
+  const size_t vec = up(sizeof(double) * (n0 + n1));
+  const size_t nblocks = (size_t)A.nblk0 + A.nblk1;
+  AmrWork W;
+  char* b = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
+  for (int i = 0; i < 5; ++i) {
+    W.v[i][0] = reinterpret_cast<double*>(b + i * vec);
+    W.v[i][1] = W.v[i][0] + n0;
+  }
+  W.part = reinterpret_cast<double*>(b + 5 * vec);
+  W.S = reinterpret_cast<double*>(b + 5 * vec + up(sizeof(double) * 2 * nblocks));
+  W.bytes = 5 * vec + up(sizeof(double) * 2 * nblocks) + up(sizeof(double) * AS_COUNT) + 256;
+  return W;
+}
+
+void amr_launch_fill(const mpp_amr_s* a, double* b0, double* b1, hipStream_t s) {
+  const AmrShape& A = a->A;
+#define L_(NB_, G_)                                                                           \
+  hipLaunchKernelGGL((k_amr_fill<NB_, G_>), dim3((unsigned)(A.nblk0 + A.nblk1)), dim3(kBlkThreads), \
+                     0, s, A, a->refined0, a->map1, a->list1, b0, b1)
+  MPP_BLK_DISPATCH(A, L_);
+#undef L_
+}
+
+void amr_launch_apply(const mpp_amr_s* a, const double* phi0, const double* phi1,
+                      const double* x0, const double* x1, double rn, double rp, double* y0,
+                      double* y1, hipStream_t s) {
+  const AmrShape& A = a->A;
+#define L_(NB_, G_)                                                                           \
+  hipLaunchKernelGGL((k_amr_apply<NB_, G_>),                                                  \
+                     dim3((unsigned)(A.nblk0 + A.nblk1), (NB_ == 16 && G_ == 1) ? 2 : 1),     \
+                     dim3(kBlkThreads), 0, s, A, a->refined0, a->map1, a->list1, phi0, phi1, x0, \
+                     x1, rn, rp, y0, y1)
+  MPP_BLK_DISPATCH(A, L_);
+#undef L_
+}
+
+template <int MODE>
+void amr_launch_vec(const mpp_amr_s* a, const AmrVecs& V, const AmrWork& W, hipStream_t s) {
+  const AmrShape& A = a->A;
+#define L_(NB_, G_)                                                                           \
+  hipLaunchKernelGGL((k_amr_vec<MODE, NB_, G_>), dim3((unsigned)(A.nblk0 + A.nblk1)),        \
+                     dim3(kBlkThreads), 0, s, A, a->refined0, V, W.S, W.part)
+  MPP_BLK_DISPATCH(A, L_);
+#undef L_
+}
+
+void amr_launch_finish(const mpp_amr_s* a, int mode, const AmrWork& W, hipStream_t s) {
+  hipLaunchKernelGGL(k_amr_finish, dim3(1), dim3(kBlkThreads), 0, s, mode, W.part,
+                     a->A.nblk0 + a->A.nblk1, W.S);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mpp_amr_solve_work_bytes(mpp_amr a) {
+  if (!a) return 0;
+  return amr_work_layout(a->A, nullptr).bytes;
+}
+
+int mpp_amr_solve(mpp_amr a, const double* phi0, const double* phi1, double rho_neg,
+                  double rho_pos, const double* b0, const double* b1, double* x0, double* x1,
+                  double rtol, int32_t max_iter, void* work, size_t work_bytes, int32_t* iters,
+                  double* rel_resid, void* stream) {
+  if (iters) *iters = 0;
+  if (rel_resid) *rel_resid = 0.0;
+  if (!a || !phi0 || !b0 || !x0 || !work) return MPP_EINVAL;
+  const AmrShape& A = a->A;
+  if (A.nblk1 > 0 && (!phi1 || !b1 || !x1)) return MPP_EINVAL;
+  if (!(rho_neg > 0.0) || !(rho_pos > 0.0) || !std::isfinite(rho_neg) || !std::isfinite(rho_pos))
+    return MPP_EINVAL;
+  if (!(rtol > 0.0) || max_iter < 0) return MPP_EINVAL;
+  if ((const void*)x0 == (const void*)b0 || (const void*)x0 == (const void*)phi0 ||
+      (x1 && ((const void*)x1 == (const void*)b1 || (const void*)x1 == (const void*)phi1)))
+    return MPP_EINVAL;
+  if (work_bytes < amr_work_layout(A, nullptr).bytes) return MPP_ENOMEM;
+  const AmrWork W = amr_work_layout(A, work);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  AmrVecs V;
+  for (int l = 0; l < 2; ++l) {
+    V.x[l] = l ? x1 : x0;
+    V.r[l] = W.v[0][l];
+    V.z[l] = W.v[1][l];
+    V.p[l] = W.v[2][l];
+    V.q[l] = W.v[3][l];
+    V.negd[l] = W.v[4][l];
+    V.b[l] = l ? b1 : b0;
+  }
+  const char* base = reinterpret_cast<const char*>(W.v[0][0]);
+  if (hipMemsetAsync(W.v[0][0], 0, (size_t)(reinterpret_cast<const char*>(W.S) - base) +
+                                         sizeof(double) * AS_COUNT, s) != hipSuccess)
+    return MPP_EDEVICE;
+  {
+    const AmrShape& AA = A;
+#define L_(NB_, G_)                                                                           \
+    hipLaunchKernelGGL((k_amr_negdiag<NB_, G_>), dim3((unsigned)(AA.nblk0 + AA.nblk1)),       \
+                       dim3(kBlkThreads), 0, s, AA, a->refined0, a->map1, a->list1, phi0, phi1, \
+                       rho_neg, rho_pos, W.v[4][0], W.v[4][1])
+    MPP_BLK_DISPATCH(AA, L_);
+#undef L_
+  }
+  // b' = b - <b, 1>, r = b' - A x, z = p = r / -diag
+  amr_launch_vec<AV_MEAN>(a, V, W, s);
+  amr_launch_finish(a, AF_MEAN, W, s);
+  amr_launch_vec<AV_INIT>(a, V, W, s);
+  amr_launch_finish(a, AF_BB, W, s);
+  amr_launch_fill(a, x0, x1, s);
+  amr_launch_apply(a, phi0, phi1, x0, x1, rho_neg, rho_pos, W.v[3][0], W.v[3][1], s);
+  amr_launch_vec<AV_RES>(a, V, W, s);
+  amr_launch_finish(a, AF_RZ0, W, s);
+  int st = MPP_ENOTCONVERGED, it = 0;
+  const int check_every = 8;
+  double h[AS_COUNT];
+  for (;;) {
+    if (it % check_every == 0 || it == max_iter) {
+      if (hipMemcpyAsync(h, W.S, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return MPP_EDEVICE;
+      if (!(h[AS_RR] > rtol * rtol * h[AS_BB])) {   // also b' = 0
+        st = MPP_OK;
+        break;
+      }
+      if (!std::isfinite(h[AS_RR]) || h[AS_FLAG] != 0.0) {
+        st = MPP_EBREAKDOWN;
+        break;
+      }
+      if (it == max_iter) break;
+    }
+    amr_launch_fill(a, W.v[2][0], W.v[2][1], s);
+    amr_launch_apply(a, phi0, phi1, W.v[2][0], W.v[2][1], rho_neg, rho_pos, W.v[3][0], W.v[3][1], s);
+    amr_launch_vec<AV_DOT>(a, V, W, s);
+    amr_launch_finish(a, AF_ALPHA, W, s);
+    amr_launch_vec<AV_STEP>(a, V, W, s);
+    amr_launch_finish(a, AF_BETA, W, s);
+    amr_launch_vec<AV_DIR>(a, V, W, s);
+    ++it;
+  }
+  // x of zero weighted mean, then its true residual
+  AmrVecs VX = V;
+  VX.b[0] = x0;
+  VX.b[1] = x1;
+  amr_launch_vec<AV_MEAN>(a, VX, W, s);
+  amr_launch_finish(a, AF_XMEAN, W, s);
+  amr_launch_vec<AV_SHIFT>(a, V, W, s);
+  amr_launch_vec<AV_INIT>(a, V, W, s);
+  amr_launch_fill(a, x0, x1, s);
+  amr_launch_apply(a, phi0, phi1, x0, x1, rho_neg, rho_pos, W.v[3][0], W.v[3][1], s);
+  amr_launch_vec<AV_RES>(a, V, W, s);
+  amr_launch_finish(a, AF_RR, W, s);
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(h, W.S, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return MPP_EDEVICE;
+  if (iters) *iters = it;
+  if (rel_resid) *rel_resid = h[AS_BB] > 0.0 ? std::sqrt(h[AS_RR] / h[AS_BB]) : 0.0;
+  return st;
+}
+
+}  // extern "C"

@@ -126,3 +126,72 @@ def test_full_size_many_bubbles():
     flags = G.refine_near_interface(p0, nb, 2.0 / n0)
     grid, _ = check(n0, nb, g, flags, p0, p1, 14)
     assert grid.nblk1 == 8 * 194
+
+
+def solve_case(n0, nb, g, flags, phi0, phi1, seed, rtol):
+    rng = np.random.default_rng(seed)
+    b0, b1 = rng.standard_normal(phi0.shape), rng.standard_normal(phi1.shape)
+    grid = M.AmrGrid(n0, nb, g, flags, DEV)
+    pb = grid.fill_guards(*level_blocks(grid, phi0, phi1))
+    bb = level_blocks(grid, b0, b1)
+    x, info = grid.solve(pb, bb, RN, RP, rtol=rtol)
+    assert info.status == M.OK and info.rel_resid <= rtol
+    sel = grid.list1.astype(np.int64)
+    # back to dense level fields (leaves only)
+    xg0 = to_host(M.blocks_gather(x[0], n0, nb, g))
+    full1 = np.zeros(((2 * n0 // nb) ** 3, nb + 2 * g, nb + 2 * g, nb + 2 * g))
+    full1[sel] = to_host(x[1])
+    xg1 = O.blocks_gather(full1, 2 * n0, nb, g)
+    return grid, (b0, b1), (xg0, xg1), info
+
+
+@pytest.mark.parametrize("n0,nb,g,seed", [(16, 4, 1, 21), (32, 8, 1, 22), (32, 16, 1, 23),
+                                          (24, 8, 2, 24)])
+def test_solve_matches_oracle(n0, nb, g, seed):
+    p0, p1 = phis(n0, *BUBBLES)
+    m = n0 // nb
+    flags = G.refine_near_interface(p0, nb, 2.0 / n0)
+    if flags.sum() == 0:
+        flags.flat[0] = 1
+    rtol = 1e-11
+    grid, (b0, b1), (x0, x1), info = solve_case(n0, nb, g, flags, p0, p1, seed, rtol)
+    # the residual of the GPU solution under the oracle's operator
+    m0 = ~np.repeat(np.repeat(np.repeat(flags, nb, 0), nb, 1), nb, 2).astype(bool)
+    m1 = np.repeat(np.repeat(np.repeat(flags, 2 * nb, 0), 2 * nb, 1), 2 * nb, 2).astype(bool)
+    x0, x1 = np.where(m0, x0, 0.0), np.where(m1, x1, 0.0)
+    v0, v1 = 1.0 / n0 ** 3, 1.0 / (2 * n0) ** 3
+    mean = v0 * b0[m0].sum() + v1 * b1[m1].sum()
+    a0, a1 = O.amr_apply(flags, nb, p0, p1, x0, x1, RN, RP)
+    r0, r1 = np.where(m0, b0 - mean - a0, 0.0), np.where(m1, b1 - mean - a1, 0.0)
+    bp0, bp1 = np.where(m0, b0 - mean, 0.0), np.where(m1, b1 - mean, 0.0)
+    wn = lambda u0, u1: np.sqrt(v0 * np.sum(u0 * u0) + v1 * np.sum(u1 * u1))
+    assert wn(r0, r1) <= 1.5 * rtol * wn(bp0, bp1)
+    assert abs(v0 * x0[m0].sum() + v1 * x1[m1].sum()) <= 1e-12 * wn(x0, x1)
+    # and the oracle's own solution of the same system: the two differ by at most
+    # |r_gpu - r_oracle| / lambda_min, lambda_min the smallest nonzero eigenvalue of -A in
+    # the weighted norm, taken as a third of pi^2 / rho_max (the continuous Neumann
+    # eigenvalue with the smallest coefficient, with room for the discretisation)
+    o0, o1, _, orel = O.amr_solve(flags, nb, p0, p1, b0, b1, RN, RP, rtol=rtol / 10)
+    assert orel <= rtol / 5     # its recursive residual met rtol / 10; the true one drifts
+    lam_min = np.pi ** 2 / max(RN, RP) / 3.0
+    assert wn(x0 - o0, x1 - o1) <= 1.5 * (info.rel_resid + orel) * wn(bp0, bp1) / lam_min
+
+
+def test_solve_without_refinement_is_the_uniform_solve():
+    n0, nb, g = 32, 8, 1
+    p0, p1 = phis(n0, *BUBBLES)
+    flags = np.zeros((4, 4, 4), np.uint8)
+    grid, (b0, _), (x0, _), info = solve_case(n0, nb, g, flags, p0, p1, 25, 1e-11)
+    assert grid.nblk1 == 0
+    op = M.Operator(to_dev(p0), RN, RP, 0.0)
+    r = b0 - b0.mean() - to_host(op.apply(to_dev(x0)))
+    assert np.linalg.norm(r) <= 1.5e-11 * np.linalg.norm(b0 - b0.mean())
+
+
+def test_solve_arguments():
+    grid = M.AmrGrid(16, 8, 1, np.zeros((2, 2, 2), np.uint8), DEV)
+    b = grid.empty()
+    with pytest.raises(M.MppError):
+        grid.solve(b, b, RN, RP, x=b)           # x aliases b
+    with pytest.raises(M.MppError):
+        grid.solve(b, grid.empty(), RN, RP, rtol=0.0)
