@@ -639,6 +639,20 @@ def amr256(M, G, torch, args):
         us = e0.elapsed_time(e1) * 1e3 / K
         res[name] = {"us": round(us, 2), "GBps": round(nbytes / (us * 1e-6) / 1e9, 1),
                      "alg_bytes": nbytes}
+    # the composite Poisson solve (b uniform in [-1, 1] on the leaves), warm-up then timed
+    f0, f1 = rng.uniform(-1, 1, p0.shape), rng.uniform(-1, 1, p1.shape)
+    fb = blocks(f0, f1)
+    solve = {}
+    for rep in range(2):
+        xs = grid.empty()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, info = grid.solve(pb, fb, pr.rho_neg, pr.rho_pos, x=xs, rtol=1e-10)
+        torch.cuda.synchronize()
+        solve = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "iters": info.iters,
+                 "rel_resid": info.rel_resid, "status": info.status}
+    solve["ms_per_iter"] = round(solve["ms"] / max(solve["iters"], 1), 4)
+    res["solve"] = solve
     ms = (res["fill_guards"]["us"] + res["apply"]["us"]) / 1e3
     ap = res["apply"]
     rec = {"metric": "guard fill + composite operator on a two-level grid (128^3 coarse, "
@@ -665,6 +679,29 @@ def amr256(M, G, torch, args):
         ok0 = np.array_equal(yb[0].cpu().numpy(), O.blocks_scatter(e0_, nb, g))
         ok1 = np.array_equal(yb[1].cpu().numpy(), O.blocks_scatter(e1_, nb, g)[sel])
         rec["bit_exact_vs_oracle"] = bool(ok0 and ok1)
+        # the solve's residual recomputed by the oracle from the GPU solution, and the
+        # oracle's own solver timed over a bounded number of iterations
+        full1 = np.zeros(((2 * n0 // nb) ** 3, P, P, P))
+        full1[sel] = xs[1].cpu().numpy()
+        gx0 = O.blocks_gather(xs[0].cpu().numpy(), n0, nb, g)
+        gx1 = O.blocks_gather(full1, 2 * n0, nb, g)
+        m0 = ~np.repeat(np.repeat(np.repeat(flags, nb, 0), nb, 1), nb, 2).astype(bool)
+        m1 = np.repeat(np.repeat(np.repeat(flags, 2 * nb, 0), 2 * nb, 1), 2 * nb, 2).astype(bool)
+        gx0, gx1 = np.where(m0, gx0, 0.0), np.where(m1, gx1, 0.0)
+        v0, v1 = 1.0 / n0 ** 3, 1.0 / (2 * n0) ** 3
+        mean = v0 * f0[m0].sum() + v1 * f1[m1].sum()
+        a0, a1 = O.amr_apply(flags, nb, p0, p1, gx0, gx1, pr.rho_neg, pr.rho_pos)
+        r0, r1 = np.where(m0, f0 - mean - a0, 0.0), np.where(m1, f1 - mean - a1, 0.0)
+        q0, q1 = np.where(m0, f0 - mean, 0.0), np.where(m1, f1 - mean, 0.0)
+        wn = lambda u0, u1: float(np.sqrt(v0 * np.sum(u0 * u0) + v1 * np.sum(u1 * u1)))
+        res["solve"]["rel_resid_by_oracle"] = wn(r0, r1) / wn(q0, q1)
+        t0 = time.perf_counter()
+        try:
+            O.amr_solve(flags, nb, p0, p1, f0, f1, pr.rho_neg, pr.rho_pos, rtol=1e-10, max_iter=10)
+        except O.OracleError:   # not converged after 10 iterations, as expected
+            pass
+        per_it = (time.perf_counter() - t0) / 10
+        res["solve"]["oracle_ms_per_iter"] = round(per_it * 1e3, 1)
     print(json.dumps(rec), flush=True)
 
 
