@@ -369,9 +369,15 @@ int mpp_amr_apply(mpp_amr a, const double *phi0, const double *phi1, const doubl
  * the block layout of both levels plus per-block partial sums. */
 size_t mpp_amr_solve_work_bytes(mpp_amr a);
 
-/* Solves A x = b on the leaves by conjugate gradients preconditioned with the inverse
- * diagonal, in the volume-weighted inner product sum_leaves V_c u_c v_c (A is symmetric
- * in it, -A positive semi-definite with the constants as null space: the Neumann walls).
+/* Solves A x = b on the leaves by preconditioned conjugate gradients in the volume-
+ * weighted inner product sum_leaves V_c u_c v_c (A is symmetric in it, -A positive
+ * semi-definite with the constants as null space: the Neumann walls).  coarse == NULL:
+ * the preconditioner is the inverse diagonal.  Otherwise a two-level multigrid cycle:
+ * two damped Jacobi sweeps (weight 0.8) on the leaves, the residual averaged over every
+ * level-0 cell and corrected by one FP64 V-cycle of `coarse` (two sweeps per level), the
+ * correction given to every leaf of the cell, two more Jacobi sweeps.  `coarse` is an
+ * operator of batch 1 on the n0^3 level-0 grid, built (mpp_build_operator) from the
+ * level-0 level set in grid layout and the same densities.
  * The weighted mean of b is removed first (the domain's volume is 1); x is returned with
  * zero weighted mean.  Stops when the weighted norm of the residual b' - A x is at most
  * rtol times that of b', polled every 8 iterations, or after max_iter iterations.
@@ -383,10 +389,10 @@ size_t mpp_amr_solve_work_bytes(mpp_amr a);
  * NULL).  Synchronous.  MPP_OK, MPP_ENOTCONVERGED (x holds the last iterate),
  * MPP_EBREAKDOWN, MPP_EINVAL (x aliasing b or phi, rtol <= 0, max_iter < 0, ...),
  * MPP_ENOMEM (work too small). */
-int mpp_amr_solve(mpp_amr a, const double *phi0, const double *phi1, double rho_neg,
-                  double rho_pos, const double *b0, const double *b1, double *x0, double *x1,
-                  double rtol, int32_t max_iter, void *work, size_t work_bytes, int32_t *iters,
-                  double *rel_resid, void *stream);
+int mpp_amr_solve(mpp_amr a, mpp_op coarse, const double *phi0, const double *phi1,
+                  double rho_neg, double rho_pos, const double *b0, const double *b1, double *x0,
+                  double *x1, double rtol, int32_t max_iter, void *work, size_t work_bytes,
+                  int32_t *iters, double *rel_resid, void *stream);
 
 /* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from

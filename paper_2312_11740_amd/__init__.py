@@ -79,6 +79,9 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libmpp.so is not built: run `python -m paper_2312_11740_amd.build` "
                            "(hipcc --offload-arch=gfx950)")
+    # torch first: its HIP runtime must be the one the library's calls resolve to, so
+    # that device pointers and streams from torch are valid in the library
+    _torch()
     L = ctypes.CDLL(path)
     P, i32, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     L.mpp_default_opts.argtypes = [ctypes.POINTER(SolveOpts)]
@@ -137,7 +140,7 @@ def load_library(path: str = LIB_PATH):
     L.mpp_amr_apply.argtypes = [P, P, P, P, P, d, d, P, P, P]
     L.mpp_amr_solve_work_bytes.argtypes = [P]
     L.mpp_amr_solve_work_bytes.restype = ctypes.c_size_t
-    L.mpp_amr_solve.argtypes = [P, P, P, d, d, P, P, P, P, d, i32, P, ctypes.c_size_t,
+    L.mpp_amr_solve.argtypes = [P, P, P, P, d, d, P, P, P, P, d, i32, P, ctypes.c_size_t,
                                 ctypes.POINTER(i32), ctypes.POINTER(d), P]
     L.mpp_heat_solve.argtypes = [P, P, P, d, P, ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(SolveInfo), P]
@@ -627,10 +630,12 @@ class AmrGrid:
             raise MppError(st, "mpp_amr_fill_guards")
         return b0, b1
 
-    def solve(self, phi, b, rho_neg, rho_pos, x=None, rtol=1e-10, max_iter=100000):
-        """x with A x = b - mean(b) on the leaves (Jacobi-preconditioned CG, zero weighted
-        mean); phi: (level0, level1) blocks with filled guards; b: (level0, level1)
-        blocks; x: initial guess, updated in place (zeros if None).  Returns (x, Info)."""
+    def solve(self, phi, b, rho_neg, rho_pos, x=None, rtol=1e-10, max_iter=100000, coarse=None):
+        """x with A x = b - mean(b) on the leaves (preconditioned CG, zero weighted mean);
+        phi: (level0, level1) blocks with filled guards; b: (level0, level1) blocks; x:
+        initial guess, updated in place (zeros if None); coarse: None (the inverse
+        diagonal) or an Operator on the level-0 grid (a two-level multigrid cycle).
+        Returns (x, Info)."""
         torch = _torch()
         if x is None:
             x = self.empty()
@@ -641,7 +646,8 @@ class AmrGrid:
             self._work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         it = ctypes.c_int32(0)
         rel = ctypes.c_double(0.0)
-        st = L.mpp_amr_solve(self._h, p[0], p[1], float(rho_neg), float(rho_pos), p[2], p[3],
+        st = L.mpp_amr_solve(self._h, coarse._h if coarse is not None else None, p[0], p[1],
+                             float(rho_neg), float(rho_pos), p[2], p[3],
                              p[4], p[5], float(rtol), int(max_iter),
                              ctypes.c_void_p(self._work.data_ptr()), nbytes, ctypes.byref(it),
                              ctypes.byref(rel), _stream_handle(self.device))

@@ -395,18 +395,29 @@ __device__ inline double amr_block_sum(double v, double* sh) {
 //   STEP:  x -= S[ALPHA] p, r += S[ALPHA] q, z = r / negd, partials <r, z>, <r, r>
 //   DIR:   p = z + S[BETA] p
 //   SHIFT: x -= S[XMEAN]
+// and the steps of the two-level preconditioner z ~= (-A)^{-1} r:
+//   MOVE:  x -= S[ALPHA] p, r += S[ALPHA] q
+//   R:     r -= q, partial <r, r> (second slot)
+//   JAC0:  z = omega r / negd
+//   JAC:   z += omega (r + t) / negd            (t = A z: damped Jacobi on -A z = r)
+//   CADD:  z -= zc(parent level-0 cell)         (zc ~= A0^{-1} of the averaged residual)
+//   ZDOT:  partials <r, z>, <r, r>
+//   ZDOTP: as ZDOT, and p = z
 // Refined level-0 blocks contribute 0 and are left as they are.
-enum AmrVec { AV_MEAN, AV_INIT, AV_RES, AV_DOT, AV_STEP, AV_DIR, AV_SHIFT };
+enum AmrVec { AV_MEAN, AV_INIT, AV_RES, AV_DOT, AV_STEP, AV_DIR, AV_SHIFT, AV_MOVE, AV_R,
+              AV_JAC0, AV_JAC, AV_CADD, AV_ZDOT, AV_ZDOTP };
 
 struct AmrVecs {
-  double *x[2], *r[2], *z[2], *p[2], *q[2];
+  double *x[2], *r[2], *z[2], *p[2], *q[2], *t[2];
   const double *b[2], *negd[2];
+  const double* zc;   // coarse correction on the level-0 grid (n0^3, x fastest)
+  double omega;       // Jacobi damping of the multigrid smoother
 };
 
 template <int MODE, int NB, int G>
 __global__ void __launch_bounds__(kBlkThreads)
-    k_amr_vec(AmrShape A, const uint8_t* __restrict__ refined0, AmrVecs V,
-              const double* __restrict__ S, double* __restrict__ part) {
+    k_amr_vec(AmrShape A, const uint8_t* __restrict__ refined0, const int* __restrict__ list1,
+              AmrVecs V, const double* __restrict__ S, double* __restrict__ part) {
 #pragma clang fp contract(off)
   __shared__ double sh[kBlkThreads];
   const int lev = (int)blockIdx.x >= A.nblk0;
@@ -426,13 +437,39 @@ __global__ void __launch_bounds__(kBlkThreads)
   double* const z = V.z[lev] + base;
   double* const p = V.p[lev] + base;
   double* const q = V.q[lev] + base;
+  double* const tt = V.t[lev] ? V.t[lev] + base : nullptr;
   const double* const bb = V.b[lev] ? V.b[lev] + base : nullptr;
   const double* const nd = V.negd[lev] + base;
-  const double alpha = S[AS_ALPHA], beta = S[AS_BETA];
+  const double alpha = S[AS_ALPHA], beta = S[AS_BETA], om = V.omega;
+  int bi = 0, bj = 0, bk = 0;
+  if (MODE == AV_CADD) amr_block_coords(A, lev, blk, list1, bi, bj, bk);
   double s1 = 0.0, s2 = 0.0;
   for (int t = threadIdx.x; t < nb * nb * nb; t += kBlkThreads) {
-    const int c = (int)amr_local(P, g, t % nb, (t / nb) % nb, t / (nb * nb));
-    if (MODE == AV_MEAN) {
+    const int li = t % nb, lj = (t / nb) % nb, lk = t / (nb * nb);
+    const int c = (int)amr_local(P, g, li, lj, lk);
+    if (MODE == AV_MOVE) {
+      x[c] = x[c] - alpha * p[c];
+      r[c] = r[c] + alpha * q[c];
+    } else if (MODE == AV_R) {
+      const double rv = r[c] - q[c];
+      r[c] = rv;
+      s2 += rv * rv;
+    } else if (MODE == AV_JAC0) {
+      z[c] = om * r[c] / nd[c];
+    } else if (MODE == AV_JAC) {
+      z[c] = z[c] + om * (r[c] + tt[c]) / nd[c];
+    } else if (MODE == AV_CADD) {
+      // the parent level-0 cell of a level-1 cell is at half its coordinates
+      const int I = lev ? (bi * nb + li) >> 1 : bi * nb + li;
+      const int J = lev ? (bj * nb + lj) >> 1 : bj * nb + lj;
+      const int K = lev ? (bk * nb + lk) >> 1 : bk * nb + lk;
+      z[c] = z[c] - V.zc[(size_t)I + (size_t)A.n0 * ((size_t)J + (size_t)A.n0 * K)];
+    } else if (MODE == AV_ZDOT || MODE == AV_ZDOTP) {
+      const double rv = r[c], zv = z[c];
+      if (MODE == AV_ZDOTP) p[c] = zv;
+      s1 += rv * zv;
+      s2 += rv * rv;
+    } else if (MODE == AV_MEAN) {
       s1 += bb[c];
     } else if (MODE == AV_INIT) {
       const double v = bb[c] - S[AS_MEAN];
@@ -460,10 +497,15 @@ __global__ void __launch_bounds__(kBlkThreads)
       x[c] = x[c] - S[AS_XMEAN];
     }
   }
-  if (MODE == AV_DIR || MODE == AV_SHIFT) return;
+  if (MODE == AV_DIR || MODE == AV_SHIFT || MODE == AV_MOVE || MODE == AV_JAC0 ||
+      MODE == AV_JAC || MODE == AV_CADD)
+    return;
   const double vol = lev ? 1.0 / (8.0 * (double)A.n0 * A.n0 * A.n0) : 1.0 / ((double)A.n0 * A.n0 * A.n0);
   const double t1 = amr_block_sum(s1, sh);
-  const double t2 = (MODE == AV_RES || MODE == AV_STEP) ? amr_block_sum(s2, sh) : 0.0;
+  const double t2 = (MODE == AV_RES || MODE == AV_STEP || MODE == AV_R || MODE == AV_ZDOT ||
+                     MODE == AV_ZDOTP)
+                        ? amr_block_sum(s2, sh)
+                        : 0.0;
   if (threadIdx.x == 0) {
     part[blockIdx.x] = vol * t1;
     part[nblocks + blockIdx.x] = vol * t2;
@@ -505,6 +547,48 @@ __global__ void __launch_bounds__(kBlkThreads)
       break;
     case AF_XMEAN: S[AS_XMEAN] = ta; break;
     case AF_RR: S[AS_RR] = tb; break;
+  }
+}
+
+// Volume average over every level-0 cell of a + b (b may be null), two composite fields,
+// onto the level-0 grid (n0^3, x fastest): the level-0 value where the block is not
+// refined, else the mean of the 8 level-1 cells (pairwise: x pairs, then y, then z).
+template <int NB, int G>
+__global__ void __launch_bounds__(kBlkThreads)
+    k_amr_restrict(AmrShape A, const uint8_t* __restrict__ refined0, const int* __restrict__ map1,
+                   const double* __restrict__ a0, const double* __restrict__ a1,
+                   const double* __restrict__ b0, const double* __restrict__ b1,
+                   double* __restrict__ out) {
+  const int nb = NB > 0 ? NB : A.nb, g = NB > 0 ? G : A.g, P = nb + 2 * g;
+  const int n0 = A.n0;
+  const size_t cells = (size_t)n0 * n0 * n0;
+  for (size_t c = (size_t)blockIdx.x * kBlkThreads + threadIdx.x; c < cells;
+       c += (size_t)gridDim.x * kBlkThreads) {
+    const int I = (int)(c % n0), J = (int)((c / n0) % n0), K = (int)(c / ((size_t)n0 * n0));
+    const int ob = I / nb + A.nbx0 * (J / nb + A.nbx0 * (K / nb));
+    double v;
+    if (!refined0[ob]) {
+      const size_t o = (size_t)ob * A.P3 + amr_local(P, g, I % nb, J % nb, K % nb);
+      v = b0 ? a0[o] + b0[o] : a0[o];
+    } else {
+      // children of a refined block are stored one after the other from the first
+      const int id = map1[2 * (I / nb) + A.nbx1 * (2 * (J / nb) + A.nbx1 * 2 * (K / nb))];
+      double s[4];
+      for (int cc = 0; cc < 2; ++cc)
+        for (int b = 0; b < 2; ++b) {
+          const int fj = 2 * J + b, fk = 2 * K + cc;
+          double v2[2];
+          for (int a = 0; a < 2; ++a) {
+            const int fi = 2 * I + a;
+            const int ch = ((fi / nb) & 1) + 2 * ((fj / nb) & 1) + 4 * ((fk / nb) & 1);
+            const size_t o = (size_t)(id + ch) * A.P3 + amr_local(P, g, fi % nb, fj % nb, fk % nb);
+            v2[a] = b1 ? a1[o] + b1[o] : a1[o];
+          }
+          s[b + 2 * cc] = v2[0] + v2[1];
+        }
+      v = 0.125 * ((s[0] + s[1]) + (s[2] + s[3]));
+    }
+    out[c] = v;
   }
 }
 

@@ -1788,7 +1788,9 @@ int mpp_amr_apply(mpp_amr a, const double* phi0, const double* phi1, const doubl
 namespace {
 
 struct AmrWork {
-  double* v[5][2];   // r, z, p, q, negd; each level 0 then level 1
+  double* v[6][2];   // r, z, p, q, negd, t; each level 0 then level 1
+  double* rc;        // averaged residual on the level-0 grid
+  double* zc;        // its coarse correction
   double* part;      // [2][nblocks]
   double* S;         // [AS_COUNT]
   size_t bytes;      // total
@@ -1801,13 +1803,17 @@ AmrWork amr_work_layout(const AmrShape& A, void* base) {
   const size_t nblocks = (size_t)A.nblk0 + A.nblk1;
   AmrWork W;
   char* b = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     W.v[i][0] = reinterpret_cast<double*>(b + i * vec);
     W.v[i][1] = W.v[i][0] + n0;
   }
-  W.part = reinterpret_cast<double*>(b + 5 * vec);
-  W.S = reinterpret_cast<double*>(b + 5 * vec + up(sizeof(double) * 2 * nblocks));
-  W.bytes = 5 * vec + up(sizeof(double) * 2 * nblocks) + up(sizeof(double) * AS_COUNT) + 256;
+  const size_t grid = up(sizeof(double) * (size_t)A.n0 * A.n0 * A.n0);
+  W.rc = reinterpret_cast<double*>(b + 6 * vec);
+  W.zc = reinterpret_cast<double*>(b + 6 * vec + grid);
+  W.part = reinterpret_cast<double*>(b + 6 * vec + 2 * grid);
+  W.S = reinterpret_cast<double*>(b + 6 * vec + 2 * grid + up(sizeof(double) * 2 * nblocks));
+  W.bytes = 6 * vec + 2 * grid + up(sizeof(double) * 2 * nblocks) + up(sizeof(double) * AS_COUNT) +
+            256;
   return W;
 }
 
@@ -1838,9 +1844,50 @@ void amr_launch_vec(const mpp_amr_s* a, const AmrVecs& V, const AmrWork& W, hipS
   const AmrShape& A = a->A;
 #define L_(NB_, G_)                                                                           \
   hipLaunchKernelGGL((k_amr_vec<MODE, NB_, G_>), dim3((unsigned)(A.nblk0 + A.nblk1)),        \
-                     dim3(kBlkThreads), 0, s, A, a->refined0, V, W.S, W.part)
+                     dim3(kBlkThreads), 0, s, A, a->refined0, a->list1, V, W.S, W.part)
   MPP_BLK_DISPATCH(A, L_);
 #undef L_
+}
+
+// Two-level multigrid preconditioner z ~= (-A)^{-1} r, symmetric in the weighted inner
+// product: kAmrNu damped Jacobi sweeps on -A z = r (the first from z = 0), the coarse
+// correction (the residual r + A z averaged over every level-0 cell, one FP64 V-cycle of
+// the level-0 operator on it, its negative given to every leaf of the cell), kAmrNu more
+// sweeps; then the partial sums of <r, z> and <r, r> (and p = z when FIRST).
+constexpr int kAmrNu = 2;
+constexpr double kAmrOmega = 0.8;
+
+template <bool FIRST>
+void amr_precondition(const mpp_amr_s* a, mpp_op coarse, const double* phi0, const double* phi1,
+                      double rn, double rp, const AmrVecs& V, const AmrWork& W, hipStream_t s) {
+  const AmrShape& A = a->A;
+  auto az = [&]() {   // t = A z
+    amr_launch_fill(a, V.z[0], V.z[1], s);
+    amr_launch_apply(a, phi0, phi1, V.z[0], V.z[1], rn, rp, V.t[0], V.t[1], s);
+  };
+  amr_launch_vec<AV_JAC0>(a, V, W, s);
+  for (int i = 1; i < kAmrNu; ++i) {
+    az();
+    amr_launch_vec<AV_JAC>(a, V, W, s);
+  }
+  az();
+  const size_t cells = (size_t)A.n0 * A.n0 * A.n0;
+  const unsigned grid = (unsigned)std::min<size_t>((cells + kBlkThreads - 1) / kBlkThreads, 8192);
+#define L_(NB_, G_)                                                                           \
+  hipLaunchKernelGGL((k_amr_restrict<NB_, G_>), dim3(grid), dim3(kBlkThreads), 0, s, A,      \
+                     a->refined0, a->map1, V.r[0], V.r[1], V.t[0], V.t[1], W.rc)
+  MPP_BLK_DISPATCH(A, L_);
+#undef L_
+  use_shift(coarse, 0.0, s);
+  ensure_tuned<double>(coarse, s);
+  coarse->nu_c = 2;
+  vcycle<double>(coarse, 0, W.rc, W.zc, 2, nullptr, s);
+  amr_launch_vec<AV_CADD>(a, V, W, s);
+  for (int i = 0; i < kAmrNu; ++i) {
+    az();
+    amr_launch_vec<AV_JAC>(a, V, W, s);
+  }
+  amr_launch_vec<FIRST ? AV_ZDOTP : AV_ZDOT>(a, V, W, s);
 }
 
 void amr_launch_finish(const mpp_amr_s* a, int mode, const AmrWork& W, hipStream_t s) {
@@ -1857,14 +1904,15 @@ size_t mpp_amr_solve_work_bytes(mpp_amr a) {
   return amr_work_layout(a->A, nullptr).bytes;
 }
 
-int mpp_amr_solve(mpp_amr a, const double* phi0, const double* phi1, double rho_neg,
-                  double rho_pos, const double* b0, const double* b1, double* x0, double* x1,
-                  double rtol, int32_t max_iter, void* work, size_t work_bytes, int32_t* iters,
-                  double* rel_resid, void* stream) {
+int mpp_amr_solve(mpp_amr a, mpp_op coarse, const double* phi0, const double* phi1,
+                  double rho_neg, double rho_pos, const double* b0, const double* b1, double* x0,
+                  double* x1, double rtol, int32_t max_iter, void* work, size_t work_bytes,
+                  int32_t* iters, double* rel_resid, void* stream) {
   if (iters) *iters = 0;
   if (rel_resid) *rel_resid = 0.0;
   if (!a || !phi0 || !b0 || !x0 || !work) return MPP_EINVAL;
   const AmrShape& A = a->A;
+  if (coarse && (coarse->n != A.n0 || coarse->batch != 1)) return MPP_EINVAL;
   if (A.nblk1 > 0 && (!phi1 || !b1 || !x1)) return MPP_EINVAL;
   if (!(rho_neg > 0.0) || !(rho_pos > 0.0) || !std::isfinite(rho_neg) || !std::isfinite(rho_pos))
     return MPP_EINVAL;
@@ -1883,8 +1931,11 @@ int mpp_amr_solve(mpp_amr a, const double* phi0, const double* phi1, double rho_
     V.p[l] = W.v[2][l];
     V.q[l] = W.v[3][l];
     V.negd[l] = W.v[4][l];
+    V.t[l] = W.v[5][l];
     V.b[l] = l ? b1 : b0;
   }
+  V.zc = W.zc;
+  V.omega = kAmrOmega;
   const char* base = reinterpret_cast<const char*>(W.v[0][0]);
   if (hipMemsetAsync(W.v[0][0], 0, (size_t)(reinterpret_cast<const char*>(W.S) - base) +
                                          sizeof(double) * AS_COUNT, s) != hipSuccess)
@@ -1905,7 +1956,16 @@ int mpp_amr_solve(mpp_amr a, const double* phi0, const double* phi1, double rho_
   amr_launch_finish(a, AF_BB, W, s);
   amr_launch_fill(a, x0, x1, s);
   amr_launch_apply(a, phi0, phi1, x0, x1, rho_neg, rho_pos, W.v[3][0], W.v[3][1], s);
-  amr_launch_vec<AV_RES>(a, V, W, s);
+  try {
+    if (coarse) {
+      amr_launch_vec<AV_R>(a, V, W, s);
+      amr_precondition<true>(a, coarse, phi0, phi1, rho_neg, rho_pos, V, W, s);
+    } else {
+      amr_launch_vec<AV_RES>(a, V, W, s);
+    }
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
   amr_launch_finish(a, AF_RZ0, W, s);
   int st = MPP_ENOTCONVERGED, it = 0;
   const int check_every = 8;
@@ -1929,7 +1989,16 @@ int mpp_amr_solve(mpp_amr a, const double* phi0, const double* phi1, double rho_
     amr_launch_apply(a, phi0, phi1, W.v[2][0], W.v[2][1], rho_neg, rho_pos, W.v[3][0], W.v[3][1], s);
     amr_launch_vec<AV_DOT>(a, V, W, s);
     amr_launch_finish(a, AF_ALPHA, W, s);
-    amr_launch_vec<AV_STEP>(a, V, W, s);
+    if (coarse) {
+      amr_launch_vec<AV_MOVE>(a, V, W, s);
+      try {
+        amr_precondition<false>(a, coarse, phi0, phi1, rho_neg, rho_pos, V, W, s);
+      } catch (HipError& e) {
+        return status_of(e.e);
+      }
+    } else {
+      amr_launch_vec<AV_STEP>(a, V, W, s);
+    }
     amr_launch_finish(a, AF_BETA, W, s);
     amr_launch_vec<AV_DIR>(a, V, W, s);
     ++it;

@@ -128,13 +128,14 @@ def test_full_size_many_bubbles():
     assert grid.nblk1 == 8 * 194
 
 
-def solve_case(n0, nb, g, flags, phi0, phi1, seed, rtol):
+def solve_case(n0, nb, g, flags, phi0, phi1, seed, rtol, two_level=False):
     rng = np.random.default_rng(seed)
     b0, b1 = rng.standard_normal(phi0.shape), rng.standard_normal(phi1.shape)
     grid = M.AmrGrid(n0, nb, g, flags, DEV)
     pb = grid.fill_guards(*level_blocks(grid, phi0, phi1))
     bb = level_blocks(grid, b0, b1)
-    x, info = grid.solve(pb, bb, RN, RP, rtol=rtol)
+    coarse = M.Operator(to_dev(phi0), RN, RP, 0.0) if two_level else None
+    x, info = grid.solve(pb, bb, RN, RP, rtol=rtol, coarse=coarse)
     assert info.status == M.OK and info.rel_resid <= rtol
     sel = grid.list1.astype(np.int64)
     # back to dense level fields (leaves only)
@@ -145,16 +146,17 @@ def solve_case(n0, nb, g, flags, phi0, phi1, seed, rtol):
     return grid, (b0, b1), (xg0, xg1), info
 
 
+@pytest.mark.parametrize("two_level", [False, True])
 @pytest.mark.parametrize("n0,nb,g,seed", [(16, 4, 1, 21), (32, 8, 1, 22), (32, 16, 1, 23),
                                           (24, 8, 2, 24)])
-def test_solve_matches_oracle(n0, nb, g, seed):
+def test_solve_matches_oracle(n0, nb, g, seed, two_level):
     p0, p1 = phis(n0, *BUBBLES)
     m = n0 // nb
     flags = G.refine_near_interface(p0, nb, 2.0 / n0)
     if flags.sum() == 0:
         flags.flat[0] = 1
     rtol = 1e-11
-    grid, (b0, b1), (x0, x1), info = solve_case(n0, nb, g, flags, p0, p1, seed, rtol)
+    grid, (b0, b1), (x0, x1), info = solve_case(n0, nb, g, flags, p0, p1, seed, rtol, two_level)
     # the residual of the GPU solution under the oracle's operator
     m0 = ~np.repeat(np.repeat(np.repeat(flags, nb, 0), nb, 1), nb, 2).astype(bool)
     m1 = np.repeat(np.repeat(np.repeat(flags, 2 * nb, 0), 2 * nb, 1), 2 * nb, 2).astype(bool)
@@ -195,3 +197,22 @@ def test_solve_arguments():
         grid.solve(b, b, RN, RP, x=b)           # x aliases b
     with pytest.raises(M.MppError):
         grid.solve(b, grid.empty(), RN, RP, rtol=0.0)
+
+
+def test_two_level_preconditioner_cuts_iterations():
+    n0, nb, g = 32, 8, 1
+    p0, p1 = phis(n0, *BUBBLES)
+    flags = G.refine_near_interface(p0, nb, 2.0 / n0)
+    _, _, _, jac = solve_case(n0, nb, g, flags, p0, p1, 26, 1e-10)
+    _, _, _, two = solve_case(n0, nb, g, flags, p0, p1, 26, 1e-10, two_level=True)
+    print("iterations: inverse diagonal %d, two-level %d" % (jac.iters, two.iters))
+    assert two.iters * 3 <= jac.iters, (two.iters, jac.iters)
+
+
+def test_two_level_needs_the_level0_grid():
+    n0, nb = 16, 8
+    grid = M.AmrGrid(n0, nb, 1, np.zeros((2, 2, 2), np.uint8), DEV)
+    b = grid.empty()
+    wrong = M.Operator(to_dev(G.bubble_phi(32, *BUBBLES)), RN, RP, 0.0)   # 32^3, not 16^3
+    with pytest.raises(M.MppError):
+        grid.solve(b, grid.empty(), RN, RP, coarse=wrong)
