@@ -42,7 +42,8 @@
  *   - two levels of refinement (Sec. 2, Fig. 2: blocks at two resolutions): the
  *     conservative finite-volume operator on the leaf cells, each coarse-fine flux
  *     taken once from the fine face and shared by both sides; guard cells as the
- *     volume average of the leaf field over the guard cell.
+ *     volume average of the leaf field over the guard cell; the solve on it by CG with
+ *     the inverse diagonal in the volume-weighted inner product.
  *
  * Conventions (shared with the GPU library only through this description):
  *   n^3 cells, h = 1/n, cell (i,j,k) centre ((i+1/2)h, (j+1/2)h, (k+1/2)h),
