@@ -67,7 +67,8 @@ BUBBLES = ([(0.45, 0.5, 0.55), (0.7, 0.3, 0.3)], [0.25, 0.12])
 
 
 @pytest.mark.parametrize("n0,nb,g,seed", [(32, 8, 1, 1), (32, 8, 2, 2), (32, 16, 1, 3),
-                                          (48, 16, 2, 4), (24, 4, 2, 5), (20, 10, 1, 6)])
+                                          (48, 16, 2, 4), (24, 4, 2, 5), (20, 10, 1, 6),
+                                          (16, 2, 2, 7), (12, 4, 3, 8), (18, 3, 1, 9)])
 def test_random_refinement_matches_oracle(n0, nb, g, seed):
     m = n0 // nb
     flags = (np.random.default_rng(seed).random((m, m, m)) < 0.4).astype(np.uint8)
@@ -216,3 +217,21 @@ def test_two_level_needs_the_level0_grid():
     wrong = M.Operator(to_dev(G.bubble_phi(32, *BUBBLES)), RN, RP, 0.0)   # 32^3, not 16^3
     with pytest.raises(M.MppError):
         grid.solve(b, grid.empty(), RN, RP, coarse=wrong)
+
+
+def test_solve_stops_at_max_iter():
+    n0, nb, g = 16, 4, 1
+    p0, p1 = phis(n0, *BUBBLES)
+    flags = G.refine_near_interface(p0, nb, 2.0 / n0)
+    grid = M.AmrGrid(n0, nb, g, flags, DEV)
+    pb = grid.fill_guards(*level_blocks(grid, p0, p1))
+    rng = np.random.default_rng(27)
+    bb = level_blocks(grid, rng.standard_normal(p0.shape), rng.standard_normal(p1.shape))
+    x, info = grid.solve(pb, bb, RN, RP, rtol=1e-12, max_iter=5)
+    assert info.status == M.ENOTCONVERGED and info.iters == 5
+    assert 0.0 < info.rel_resid < 1.0
+    # and zero right-hand side: converged at once with x = 0
+    z = grid.empty()
+    x, info = grid.solve(pb, z, RN, RP, rtol=1e-10)
+    assert info.status == M.OK and info.iters == 0
+    assert float(x[0].abs().max()) == 0.0
