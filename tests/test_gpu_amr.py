@@ -235,3 +235,25 @@ def test_solve_stops_at_max_iter():
     x, info = grid.solve(pb, z, RN, RP, rtol=1e-10)
     assert info.status == M.OK and info.iters == 0
     assert float(x[0].abs().max()) == 0.0
+
+
+def test_full_size_two_level_solve():
+    # the benchmarked solve: 20 bubbles, 128^3 coarse in 16^3 blocks, refined near the
+    # interfaces; the GPU solution's residual recomputed by the oracle's operator
+    n0, nb, g = 128, 16, 1
+    pr = G.many_bubbles_problem(n=n0)
+    p0, p1 = phis(n0, pr.centres, pr.radii)
+    flags = G.refine_near_interface(p0, nb, 2.0 / n0)
+    rtol = 1e-10
+    grid, (b0, b1), (x0, x1), info = solve_case(n0, nb, g, flags, p0, p1, 28, rtol, True)
+    assert info.iters < 1500
+    m0 = ~np.repeat(np.repeat(np.repeat(flags, nb, 0), nb, 1), nb, 2).astype(bool)
+    m1 = np.repeat(np.repeat(np.repeat(flags, 2 * nb, 0), 2 * nb, 1), 2 * nb, 2).astype(bool)
+    x0, x1 = np.where(m0, x0, 0.0), np.where(m1, x1, 0.0)
+    v0, v1 = 1.0 / n0 ** 3, 1.0 / (2 * n0) ** 3
+    mean = v0 * b0[m0].sum() + v1 * b1[m1].sum()
+    a0, a1 = O.amr_apply(flags, nb, p0, p1, x0, x1, RN, RP)
+    r0, r1 = np.where(m0, b0 - mean - a0, 0.0), np.where(m1, b1 - mean - a1, 0.0)
+    q0, q1 = np.where(m0, b0 - mean, 0.0), np.where(m1, b1 - mean, 0.0)
+    wn = lambda u0, u1: np.sqrt(v0 * np.sum(u0 * u0) + v1 * np.sum(u1 * u1))
+    assert wn(r0, r1) <= 1.5 * rtol * wn(q0, q1)
