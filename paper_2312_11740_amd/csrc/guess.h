@@ -20,39 +20,61 @@ __device__ inline uint16_t bf16_rne(double v) {
 
 // coarse[b][v][0..2] = means over the r^3 block of cell v of 1/rho, b and p (0 when p is
 // NULL).  1/rho of a fine cell is that of its side (bit 6 of the finest-level code).
-__global__ void k_feat_coarsen(const uint8_t* __restrict__ code, const double* __restrict__ inv_rho,
-                               const double* __restrict__ b, const double* __restrict__ p, int nf,
-                               int r, int nc, int batch, double* __restrict__ coarse) {
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t cc = (size_t)nc * nc * nc;
-  if (idx >= cc * batch) return;
-  const int q = (int)(idx / cc), l = (int)(idx % cc);
-  const int I = l % nc, J = (l / nc) % nc, K = l / (nc * nc);
-  const size_t base = (size_t)q * nf * nf * nf;
-  double sr = 0.0, sb = 0.0, sp = 0.0;
-  for (int dz = 0; dz < r; ++dz)
-    for (int dy = 0; dy < r; ++dy)
-      for (int dx = 0; dx < r; ++dx) {
-        const size_t c = base + ((size_t)(K * r + dz) * nf + (J * r + dy)) * nf + (I * r + dx);
-        sr += inv_rho[2 * q + ((code[c] >> 6) & 1)];
-        sb += b[c];
-        if (p) sp += p[c];
-      }
-  const double inv = 1.0 / ((double)r * r * r);
-  coarse[3 * idx + 0] = sr * inv;
-  coarse[3 * idx + 1] = sb * inv;
-  coarse[3 * idx + 2] = sp * inv;
+// Grid: (cells of a problem / 256, problems), 256 threads.  R > 0: r == R at compile
+// time (the rows unroll); R == 0: r from the argument.  Each workgroup also writes the
+// sum of the squared coarse b means of its cells to part[problem][blockIdx.x] (summed
+// in a fixed order), from which k_feat_rms takes the rms.
+template <int R>
+__global__ void __launch_bounds__(256)
+    k_feat_coarsen(const uint8_t* __restrict__ code, const double* __restrict__ inv_rho,
+                   const double* __restrict__ b, const double* __restrict__ p, int nf, int r_arg,
+                   int nc, double* __restrict__ coarse, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int r = R > 0 ? R : r_arg;
+  const unsigned l = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned cc = (unsigned)nc * nc * nc;
+  const int q = blockIdx.y;
+  if (l >= cc) {
+    red[threadIdx.x] = 0.0;
+  } else {
+    const size_t idx = (size_t)q * cc + l;
+    const int I = (int)(l % (unsigned)nc), J = (int)((l / (unsigned)nc) % (unsigned)nc),
+              K = (int)(l / ((unsigned)nc * nc));
+    const size_t base = (size_t)q * nf * nf * nf;
+    double sr = 0.0, sb = 0.0, sp = 0.0;
+    for (int dz = 0; dz < r; ++dz)
+      for (int dy = 0; dy < r; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < r; ++dx) {
+          const size_t c = base + ((size_t)(K * r + dz) * nf + (J * r + dy)) * nf + (I * r + dx);
+          sr += inv_rho[2 * q + ((code[c] >> 6) & 1)];
+          sb += b[c];
+          if (p) sp += p[c];
+        }
+    const double inv = 1.0 / ((double)r * r * r);
+    coarse[3 * idx + 0] = sr * inv;
+    coarse[3 * idx + 1] = sb * inv;
+    coarse[3 * idx + 2] = sp * inv;
+    red[threadIdx.x] = (sb * inv) * (sb * inv);
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)q * gridDim.x + blockIdx.x] = red[0];
 }
 
-// rms of the coarse right-hand side per problem (one block each)
+// rms of the coarse right-hand side per problem (one block each) from the nparts
+// partial sums k_feat_coarsen left per problem
 __global__ void __launch_bounds__(1024)
-    k_feat_rms(const double* __restrict__ coarse, int cells, double* __restrict__ rms64,
+    k_feat_rms(const double* __restrict__ part, int nparts, int cells, double* __restrict__ rms64,
                float* __restrict__ rms32) {
   __shared__ double red[1024];
   const int q = blockIdx.x, tid = threadIdx.x;
-  const double* c = coarse + (size_t)q * cells * 3;
+  const double* c = part + (size_t)q * nparts;
   double s = 0.0;
-  for (int v = tid; v < cells; v += 1024) s += c[3 * v + 1] * c[3 * v + 1];
+  for (int v = tid; v < nparts; v += 1024) s += c[v];
   red[tid] = s;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
@@ -83,15 +105,19 @@ __global__ void k_feat_write(const double* __restrict__ coarse, const double* __
 }
 
 // p[fine cell] = rms h^2 * trilinear interpolation of y at the cell's centre (cell-centred
-// coarse values, clamped at the walls; h = 1 / nc)
+// coarse values, clamped at the walls; h = 1 / nc).  Grid: (cells of a problem / 256,
+// problems); R as for k_feat_coarsen.
+template <int R>
 __global__ void k_guess_prolong(const float* __restrict__ y, const double* __restrict__ rms64,
-                                int nc, int r, int batch, double* __restrict__ p) {
-  const int nf = nc * r;
-  const size_t cf = (size_t)nf * nf * nf;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= cf * batch) return;
-  const int q = (int)(idx / cf), l = (int)(idx % cf);
-  const int fi[3] = {l % nf, (l / nf) % nf, l / (nf * nf)};
+                                int nc, int r_arg, double* __restrict__ p) {
+  const int r = R > 0 ? R : r_arg;
+  const unsigned nf = (unsigned)(nc * r);
+  const unsigned cf = nf * nf * nf;
+  const unsigned l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= cf) return;
+  const int q = blockIdx.y;
+  const size_t idx = (size_t)q * cf + l;
+  const int fi[3] = {(int)(l % nf), (int)((l / nf) % nf), (int)(l / (nf * nf))};
   int i0[3], i1[3];
   double w1[3];
   for (int a = 0; a < 3; ++a) {

@@ -1392,13 +1392,20 @@ void net_inputs(mpp_op_s* op, mpp_net_s* net, const double* f, const double* p, 
   const int cells_c = nc * nc * nc;
   reset_ctl(op, op->inner, 1, s);
   make_rhs(op, op->inner, f, op->b, s, 0.0, true);
-  const size_t work = (size_t)cells_c * B;
-  const unsigned nb = (unsigned)((work + 255) / 256);
-  hipLaunchKernelGGL(k_feat_coarsen, dim3(nb), dim3(256), 0, s, op->lev[0].code, op->inv_rho64,
-                     op->b, p, op->n, r, nc, B, net->coarse);
+  const dim3 cgrid((unsigned)((cells_c + 255) / 256), B);
+  const unsigned nb = (unsigned)(((size_t)cells_c * B + 255) / 256);
+  // the per-workgroup partial sums of the rms go to the prediction buffer, which the
+  // network only writes later (cgrid.x doubles per problem, far below its n^3 floats)
+  double* part = reinterpret_cast<double*>(net->y);
+  if (r == 4)
+    hipLaunchKernelGGL(k_feat_coarsen<4>, cgrid, dim3(256), 0, s, op->lev[0].code, op->inv_rho64,
+                       op->b, p, op->n, r, nc, net->coarse, part);
+  else
+    hipLaunchKernelGGL(k_feat_coarsen<0>, cgrid, dim3(256), 0, s, op->lev[0].code, op->inv_rho64,
+                       op->b, p, op->n, r, nc, net->coarse, part);
   ck_launch();
-  hipLaunchKernelGGL(k_feat_rms, dim3(B), dim3(1024), 0, s, net->coarse, cells_c, net->rms64,
-                     net->rms32);
+  hipLaunchKernelGGL(k_feat_rms, dim3(B), dim3(1024), 0, s, part, (int)cgrid.x, cells_c,
+                     net->rms64, net->rms32);
   ck_launch();
   hipLaunchKernelGGL(k_feat_write, dim3(nb), dim3(256), 0, s, net->coarse, net->rms64, nc, B, x,
                      t);
@@ -1437,8 +1444,11 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
     const int st = mppnet::forward(net, net->x4, net->y, B, s);
     if (st != MPP_OK) return st;
     const size_t work = L0.cells * B;
-    hipLaunchKernelGGL(k_guess_prolong, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s,
-                       net->y, net->rms64, net->n, r, B, p);
+    const dim3 pgrid((unsigned)((L0.cells + 255) / 256), B);
+    if (r == 4)
+      hipLaunchKernelGGL(k_guess_prolong<4>, pgrid, dim3(256), 0, s, net->y, net->rms64, net->n, r, p);
+    else
+      hipLaunchKernelGGL(k_guess_prolong<0>, pgrid, dim3(256), 0, s, net->y, net->rms64, net->n, r, p);
     ck_launch();
     Ctl& ctl = op->inner;
     remove_mean(op, ctl, p, s);
