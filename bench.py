@@ -25,6 +25,9 @@ Also reported: the dominant kernel's achieved HBM bandwidth (algorithmic bytes p
 launch / mean launch time from HIP events in a profiled repeat of the timed steps),
 and the CPU oracle timed on the host cores on a bounded sample (one full-size solve).
 
+Other workloads (--workload) measure the steps around the solve, the heat step, the
+block layout and the two-level composite grid, each with the oracle timed beside it.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -729,7 +732,10 @@ def main():
                     choices=["rising256", "batched64", "single32", "bubbles128",
                              "projection256", "flow256", "heat256", "blocks256", "amr256"],
                     help="rising256: the 256^3 sequence (default); batched64: 64 x 64^3; "
-                         "single32 / bubbles128: one fixed problem, plain vs mixed")
+                         "single32 / bubbles128: one fixed problem, plain vs mixed; "
+                         "projection256 / flow256: the steps around the solve; heat256: "
+                         "implicit heat diffusion; blocks256: block layout; amr256: the "
+                         "two-level composite grid (fill, operator, solves)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device copy of this many bytes (counter scaling)")
     args = ap.parse_args()
