@@ -646,8 +646,9 @@ def amr256(M, G, torch, args):
     f0, f1 = rng.uniform(-1, 1, p0.shape), rng.uniform(-1, 1, p1.shape)
     fb = blocks(f0, f1)
     # preconditioned by the inverse diagonal, and by the two-level multigrid cycle with the
-    # level-0 operator (the one reported last, whose x the oracle checks)
-    coarse = M.Operator(torch.from_numpy(p0).to(dev), pr.rho_neg, pr.rho_pos, 0.0)
+    # level-0 operator whose faces next to refined blocks come from the fine level (the one
+    # reported last, whose x the oracle checks)
+    coarse = grid.coarse_operator(torch.from_numpy(p0).to(dev), pb, pr.rho_neg, pr.rho_pos)
     for name, cop in (("solve_jacobi", None), ("solve", coarse)):
         for rep in range(2):
             xs = grid.empty()

@@ -377,7 +377,8 @@ size_t mpp_amr_solve_work_bytes(mpp_amr a);
  * level-0 cell and corrected by one FP64 V-cycle of `coarse` (two sweeps per level), the
  * correction given to every leaf of the cell, two more Jacobi sweeps.  `coarse` is an
  * operator of batch 1 on the n0^3 level-0 grid, built (mpp_build_operator) from the
- * level-0 level set in grid layout and the same densities.
+ * level-0 level set in grid layout and the same densities, best with its faces next to
+ * refined blocks taken from the fine level (mpp_amr_coarse_operator).
  * The weighted mean of b is removed first (the domain's volume is 1); x is returned with
  * zero weighted mean.  Stops when the weighted norm of the residual b' - A x is at most
  * rtol times that of b', polled every 8 iterations, or after max_iter iterations.
@@ -393,6 +394,17 @@ int mpp_amr_solve(mpp_amr a, mpp_op coarse, const double *phi0, const double *ph
                   double rho_neg, double rho_pos, const double *b0, const double *b1, double *x0,
                   double *x1, double rtol, int32_t max_iter, void *work, size_t work_bytes,
                   int32_t *iters, double *rel_resid, void *stream);
+
+/* Makes `op` (batch 1, built on the n0^3 level-0 grid from the level-0 level set phi0,
+ * device grid layout) the level-0 operator of mpp_amr_solve's two-level cycle for this
+ * grid: every level-0 face touching a refined block takes the mean of the four
+ * fine-level coefficients across it (between two refined blocks the four pairs of
+ * level-1 cells, across a coarse-fine face the four level-1 cells and the level-0 cell;
+ * phi1: level-1 level set in the block layout), marked as crossed in the cell codes;
+ * then the coarser levels and the coarsest inverse are rebuilt from the new faces.  The
+ * operator's pressure-solve terms (curvature, jump) are left as they were. */
+int mpp_amr_coarse_operator(mpp_amr a, mpp_op op, const double *phi0, const double *phi1,
+                            double rho_neg, double rho_pos, void *stream);
 
 /* ------------------------------------------------------------------------------
  * Learned initial guess.  Not part of the paper's method (whose solver starts from

@@ -35,6 +35,7 @@ EXPORTS = (
     "mpp_blocks_gather", "mpp_blocks_fill_guards", "mpp_blocks_apply",
     "mpp_amr_workspace_bytes", "mpp_amr_create", "mpp_amr_destroy", "mpp_amr_level1_blocks",
     "mpp_amr_fill_guards", "mpp_amr_apply", "mpp_amr_solve_work_bytes", "mpp_amr_solve",
+    "mpp_amr_coarse_operator",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -138,6 +139,7 @@ def load_library(path: str = LIB_PATH):
     L.mpp_amr_level1_blocks.argtypes = [P, ctypes.POINTER(ctypes.c_int32), P]
     L.mpp_amr_fill_guards.argtypes = [P, P, P, P]
     L.mpp_amr_apply.argtypes = [P, P, P, P, P, d, d, P, P, P]
+    L.mpp_amr_coarse_operator.argtypes = [P, P, P, P, d, d, P]
     L.mpp_amr_solve_work_bytes.argtypes = [P]
     L.mpp_amr_solve_work_bytes.restype = ctypes.c_size_t
     L.mpp_amr_solve.argtypes = [P, P, P, P, d, d, P, P, P, P, d, i32, P, ctypes.c_size_t,
@@ -629,6 +631,20 @@ class AmrGrid:
         if st != OK:
             raise MppError(st, "mpp_amr_fill_guards")
         return b0, b1
+
+    def coarse_operator(self, phi0, phi, rho_neg, rho_pos):
+        """The level-0 Operator of the two-level cycle, built from phi0 ((n0,)*3 float64
+        CUDA tensor) with its faces next to refined blocks averaged from the fine level
+        (phi: (level0, level1) blocks with filled guards)."""
+        op = Operator(phi0, rho_neg, rho_pos, 0.0)
+        p = self._fields([(phi, "phi")])
+        st = load_library().mpp_amr_coarse_operator(self._h, op._h,
+                                                    ctypes.c_void_p(phi0.data_ptr()), p[1],
+                                                    float(rho_neg), float(rho_pos),
+                                                    _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_amr_coarse_operator")
+        return op
 
     def solve(self, phi, b, rho_neg, rho_pos, x=None, rtol=1e-10, max_iter=100000, coarse=None):
         """x with A x = b - mean(b) on the leaves (preconditioned CG, zero weighted mean);

@@ -592,4 +592,78 @@ __global__ void __launch_bounds__(kBlkThreads)
   }
 }
 
+// The level-0 operator of the two-level cycle, made to see the fine level: every face of
+// the level-0 grid that touches a refined block takes the mean of the four fine-level
+// coefficients across it (as the uniform hierarchy averages faces from level to level):
+// between two refined blocks the coefficients of the four pairs of level-1 cells, across
+// a coarse-fine face those of the four level-1 cells and the level-0 cell.  The faces are
+// written in the grid layout of the operator (low face of each cell, FP64 and FP32), and
+// every cell's code byte marks each of its faces so changed as crossed, so that every
+// sweep reads the face arrays there.  One thread per level-0 cell; each writes only its
+// own faces and code byte.
+template <int NB, int G>
+__global__ void __launch_bounds__(256)
+    k_amr_coarse_faces(AmrShape A, const uint8_t* __restrict__ refined0,
+                       const int* __restrict__ map1, const double* __restrict__ phi0,
+                       const double* __restrict__ phi1, double rn, double rp,
+                       uint8_t* __restrict__ code, double* __restrict__ bx, double* __restrict__ by,
+                       double* __restrict__ bz, float* __restrict__ fx, float* __restrict__ fy,
+                       float* __restrict__ fz) {
+#pragma clang fp contract(off)
+  const int nb = NB > 0 ? NB : A.nb, g = NB > 0 ? G : A.g, P = nb + 2 * g;
+  const int n0 = A.n0;
+  const size_t cells = (size_t)n0 * n0 * n0;
+  const double irn = 1.0 / rn, irp = 1.0 / rp;
+  auto refined = [&](int I, int J, int K) {
+    return refined0[I / nb + A.nbx0 * (J / nb + A.nbx0 * (K / nb))] != 0;
+  };
+  // level set at level-1 cell f of a refined block, else at the level-0 cell containing it
+  auto phi_at = [&](const int f[3]) {
+    const int I = f[0] >> 1, J = f[1] >> 1, K = f[2] >> 1;
+    if (!refined(I, J, K)) return phi0[(size_t)I + (size_t)n0 * ((size_t)J + (size_t)n0 * K)];
+    const int blk = map1[f[0] / nb + A.nbx1 * (f[1] / nb + A.nbx1 * (f[2] / nb))];
+    return phi1[(size_t)blk * A.P3 + amr_local(P, g, f[0] % nb, f[1] % nb, f[2] % nb)];
+  };
+  double* const bd[3] = {bx, by, bz};
+  float* const fd[3] = {fx, fy, fz};
+  for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < cells; c += (size_t)gridDim.x * 256) {
+    const int C[3] = {(int)(c % n0), (int)((c / n0) % n0), (int)(c / ((size_t)n0 * n0))};
+    const bool rc = refined(C[0], C[1], C[2]);
+    unsigned mark = 0;
+    for (int d = 0; d < 3; ++d) {
+      int e1 = d + 1, e2 = d + 2;
+      if (e1 >= 3) e1 -= 3;
+      if (e2 >= 3) e2 -= 3;
+      // low face: between c - e_d and c
+      if (C[d] > 0) {
+        int L[3] = {C[0], C[1], C[2]};
+        L[d] -= 1;
+        if (rc || refined(L[0], L[1], L[2])) {
+          double s[4];
+          for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+              int lo[3], hi[3];
+              lo[d] = 2 * C[d] - 1;
+              hi[d] = 2 * C[d];
+              lo[e1] = hi[e1] = 2 * C[e1] + a;
+              lo[e2] = hi[e2] = 2 * C[e2] + b;
+              s[a + 2 * b] = amr_beta(phi_at(lo), phi_at(hi), rn, rp, irn, irp);
+            }
+          const double v = 0.25 * ((s[0] + s[1]) + (s[2] + s[3]));
+          bd[d][c] = v;
+          fd[d][c] = (float)v;
+          mark |= 1u << (2 * d);
+        }
+      }
+      // high face: its value is written by the cell above; only the mark is ours
+      if (C[d] < n0 - 1) {
+        int H[3] = {C[0], C[1], C[2]};
+        H[d] += 1;
+        if (rc || refined(H[0], H[1], H[2])) mark |= 2u << (2 * d);
+      }
+    }
+    if (mark) code[c] = (uint8_t)(code[c] | mark);
+  }
+}
+
 }  // namespace mpp

@@ -2035,3 +2035,42 @@ int mpp_amr_solve(mpp_amr a, mpp_op coarse, const double* phi0, const double* ph
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int mpp_amr_coarse_operator(mpp_amr a, mpp_op op, const double* phi0, const double* phi1,
+                            double rho_neg, double rho_pos, void* stream) {
+  if (!a || !op || !phi0) return MPP_EINVAL;
+  const AmrShape& A = a->A;
+  if (op->n != A.n0 || op->batch != 1 || (A.nblk1 > 0 && !phi1)) return MPP_EINVAL;
+  if (!(rho_neg > 0.0) || !(rho_pos > 0.0) || !std::isfinite(rho_neg) || !std::isfinite(rho_pos))
+    return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Level& L0 = op->lev[0];
+  const size_t cells = (size_t)A.n0 * A.n0 * A.n0;
+  const unsigned grid = (unsigned)std::min<size_t>((cells + 255) / 256, 8192);
+  try {
+#define L_(NB_, G_)                                                                           \
+    hipLaunchKernelGGL((k_amr_coarse_faces<NB_, G_>), dim3(grid), dim3(256), 0, s, A,         \
+                       a->refined0, a->map1, phi0, phi1, rho_neg, rho_pos, L0.code, L0.f64[0],  \
+                       L0.f64[1], L0.f64[2], L0.f32[0], L0.f32[1], L0.f32[2])
+    MPP_BLK_DISPATCH(A, L_);
+#undef L_
+    ck_launch();
+    // the coarser levels and the coarsest inverse from the new faces
+    for (int l = 1; l < op->nlev; ++l) {
+      Level& Lf = op->lev[l - 1];
+      Level& Lc = op->lev[l];
+      hipLaunchKernelGGL(k_coarsen_faces, grid_of(Lc, 1), dim3(kBlock), 0, s, Lf.f64[0], Lf.f64[1],
+                         Lf.f64[2], Lf.n, Lc.f64[0], Lc.f64[1], Lc.f64[2], Lc.f32[0], Lc.f32[1],
+                         Lc.f32[2]);
+      ck_launch();
+    }
+    factor_coarsest(op, s);
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
+}  // extern "C"

@@ -161,3 +161,4 @@ def test_amr_host_validation():
     assert L.mpp_amr_level1_blocks(None, ctypes.byref(cnt), None) == M.EINVAL
     assert L.mpp_amr_fill_guards(None, ws, None, None) == M.EINVAL
     assert L.mpp_amr_apply(None, ws, None, ws, None, 1.0, 1.0, ws, None, None) == M.EINVAL
+    assert L.mpp_amr_coarse_operator(None, None, ws, None, 1.0, 1.0, None) == M.EINVAL
