@@ -373,9 +373,9 @@ size_t mpp_amr_solve_work_bytes(mpp_amr a);
  * weighted inner product sum_leaves V_c u_c v_c (A is symmetric in it, -A positive
  * semi-definite with the constants as null space: the Neumann walls).  coarse == NULL:
  * the preconditioner is the inverse diagonal.  Otherwise a two-level multigrid cycle:
- * two damped Jacobi sweeps (weight 0.8) on the leaves, the residual averaged over every
+ * a damped Jacobi sweep (weight 0.8) on the leaves, the residual averaged over every
  * level-0 cell and corrected by one FP64 V-cycle of `coarse` (two sweeps per level), the
- * correction given to every leaf of the cell, two more Jacobi sweeps.  `coarse` is an
+ * correction given to every leaf of the cell, one more Jacobi sweep.  `coarse` is an
  * operator of batch 1 on the n0^3 level-0 grid, built (mpp_build_operator) from the
  * level-0 level set in grid layout and the same densities, best with its faces next to
  * refined blocks taken from the fine level (mpp_amr_coarse_operator).

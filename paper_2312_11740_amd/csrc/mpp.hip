@@ -1864,7 +1864,7 @@ void amr_launch_vec(const mpp_amr_s* a, const AmrVecs& V, const AmrWork& W, hipS
 // correction (the residual r + A z averaged over every level-0 cell, one FP64 V-cycle of
 // the level-0 operator on it, its negative given to every leaf of the cell), kAmrNu more
 // sweeps; then the partial sums of <r, z> and <r, r> (and p = z when FIRST).
-constexpr int kAmrNu = 2;
+constexpr int kAmrNu = 1;
 constexpr double kAmrOmega = 0.8;
 
 template <bool FIRST>
