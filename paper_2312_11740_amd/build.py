@@ -19,7 +19,10 @@ HIPCC_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
-    # no packed FP32 instructions: some of their forms have given wrong results
+    # device code without packed FP32 instructions (v_pk_add/mul/fma_f32), some of whose
+    # forms have given wrong results: -O3 emits several hundred of them in these sources
+    # without this flag and none with it.  The host pass does not know the feature and
+    # says so once per source ("not a recognized feature ... ignoring"); that is harmless.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-result",
