@@ -476,6 +476,35 @@ int mpp_net_get_grads(mpp_net net, float *grads, void *stream);
  * t the count of steps since creation or the last set_params. */
 int mpp_net_adam(mpp_net net, float lr, float beta1, float beta2, float eps, void *stream);
 
+/* Training on samples the solver generated (mpp_net_features of solved problems: the
+ * density field and right-hand side as inputs, the solution as target).  Runs `steps`
+ * training steps, each: draw `batch` of the `count` samples, forward pass, the loss of
+ * mpp_net_loss, backward pass, one Adam step (as mpp_net_adam).  Step number g =
+ * first_step + s (s = 0 .. steps-1; first_step lets a long run be split into calls) uses
+ * the samples idx(q), q = g * batch + j, j = 0 .. batch-1: q mod count when seed == 0
+ * (in order), otherwise output number q of the SplitMix64 stream started at seed, mod
+ * count (a counter-based draw: any step's batch follows from seed and g alone).  Its
+ * learning rate is lr0 * (lr1 / lr0)^(g / (total_steps - 1)), geometric from lr0 at step 0
+ * to lr1 at step total_steps - 1 (lr0 throughout when total_steps <= 1).
+ * x: device BF16 bits [count][n^3][4]; t: device FP32 [count][n^3] (zero-mean targets);
+ * losses: device FP32 [steps][batch] per-sample losses before each step's update (may be
+ * NULL).  Requires 1 <= batch <= the network's batch_max, count >= 1, steps >= 0,
+ * first_step >= 0, lr0, lr1, eps > 0 and finite, 0 <= beta1, beta2 < 1; else MPP_EINVAL
+ * before any device work.  Asynchronous. */
+typedef struct {
+    int32_t batch;        /* samples per step */
+    int32_t steps;        /* steps in this call */
+    int64_t first_step;   /* global number of the first step (schedule and draw) */
+    int64_t total_steps;  /* length of the whole schedule */
+    float lr0, lr1;       /* learning rate at step 0 and at step total_steps - 1 */
+    float beta1, beta2, eps;  /* Adam constants, e.g. 0.9, 0.999, 1e-8 */
+    int32_t reserved;
+    uint64_t seed;        /* 0: samples in order; else the SplitMix64 seed of the draw */
+} mpp_net_train_opts;
+
+int mpp_net_train(mpp_net net, const uint16_t *x, const float *t, int64_t count,
+                  const mpp_net_train_opts *opts, float *losses, void *stream);
+
 /* Network inputs (and optionally targets) of the problems of an operator whose size
  * is r * n for an integer r >= 1 (op batch <= net batch_max).  b is the solver's
  * right-hand side (f + jterm, mean-projected); coarse values are means over r^3

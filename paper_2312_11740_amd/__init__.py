@@ -35,7 +35,7 @@ EXPORTS = (
     "mpp_blocks_gather", "mpp_blocks_fill_guards", "mpp_blocks_apply",
     "mpp_amr_workspace_bytes", "mpp_amr_create", "mpp_amr_destroy", "mpp_amr_level1_blocks",
     "mpp_amr_fill_guards", "mpp_amr_apply", "mpp_amr_solve_work_bytes", "mpp_amr_solve",
-    "mpp_amr_coarse_operator",
+    "mpp_amr_coarse_operator", "mpp_net_train",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -55,6 +55,14 @@ class SolveInfo(ctypes.Structure):
                 ("outer_iters", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("rel_resid", ctypes.c_double), ("removed_mean", ctypes.c_double),
                 ("bnorm", ctypes.c_double)]
+
+
+class NetTrainOpts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("first_step", ctypes.c_int64), ("total_steps", ctypes.c_int64),
+                ("lr0", ctypes.c_float), ("lr1", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class KernelStat(ctypes.Structure):
@@ -120,6 +128,7 @@ def load_library(path: str = LIB_PATH):
     L.mpp_net_get_grads.argtypes = [P, P, P]
     L.mpp_net_adam.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, P]
+    L.mpp_net_train.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(NetTrainOpts), P, P]
     L.mpp_net_features.argtypes = [P, P, P, P, P, P, P, P]
     L.mpp_learned_guess.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                     P]
@@ -810,13 +819,37 @@ class Net:
         if st != OK:
             raise MppError(st, "mpp_net_adam")
 
-    def train_step(self, x, t, lr=1e-3):
-        """forward, loss, backward, Adam; returns the per-sample losses (device)."""
-        y = self.forward(x)
-        lo, dy = self.loss(y, t)
-        self.backward(dy)
-        self.adam(lr)
+    def train(self, x, t, steps, batch, lr=1e-3, lr_final=None, seed=0, first_step=0,
+              total_steps=None, beta1=0.9, beta2=0.999, eps=1e-8, losses=True):
+        """`steps` training steps of `batch` samples drawn from the stored samples x
+        (bfloat16 (count, n, n, n, 4)) and targets t (float32 (count, n, n, n)), in one
+        call of mpp_net_train: step g = first_step + s draws its samples from `seed` (0: in
+        order) and takes the learning rate lr * (lr_final / lr)^(g / (total_steps - 1)).
+        Returns the per-sample losses (float32 (steps, batch), device) or None."""
+        torch = _torch()
+        count = x.shape[0]
+        self._check(x, torch.bfloat16, (count, self.n, self.n, self.n, 4), "x")
+        self._check(t, torch.float32, (count, self.n, self.n, self.n), "t")
+        o = NetTrainOpts(batch=int(batch), steps=int(steps), first_step=int(first_step),
+                         total_steps=int(steps if total_steps is None else total_steps),
+                         lr0=float(lr), lr1=float(lr if lr_final is None else lr_final),
+                         beta1=float(beta1), beta2=float(beta2), eps=float(eps), reserved=0,
+                         seed=int(seed) & (2**64 - 1))
+        lo = torch.empty((max(int(steps), 1), int(batch)), dtype=torch.float32,
+                         device=self.device) if losses else None
+        st = load_library().mpp_net_train(self._h, ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(t.data_ptr()), int(count),
+                                          ctypes.byref(o),
+                                          ctypes.c_void_p(lo.data_ptr() if lo is not None else 0),
+                                          self._stream())
+        if st != OK:
+            raise MppError(st, "mpp_net_train")
         return lo
+
+    def train_step(self, x, t, lr=1e-3):
+        """One training step on exactly the samples given (forward, loss, backward, Adam,
+        through mpp_net_train in order); returns the per-sample losses (device)."""
+        return self.train(x, t, 1, x.shape[0], lr=lr)[0]
 
     def features(self, op, f, p=None):
         """Network inputs x (bf16) of the operator's problems, targets t (float32, when p

@@ -638,6 +638,18 @@ __global__ void k_correct(double* __restrict__ x, const float* __restrict__ d, i
   CELL_LOOP(cells) x[base + c] += s * (double)d[base + c];
 }
 
+// Residual refinement: a problem whose inner solve ended in a breakdown or ran out of
+// the inner iteration budget stops refining (its outer status takes the inner one, so
+// the next outer residual does not re-arm it); the other problems go on.
+__global__ void k_stop_failed(int B, const int* __restrict__ istatus, int* __restrict__ ostatus,
+                              int* __restrict__ oactive) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B && istatus[b] != MPP_OK && ostatus[b] == MPP_OK) {
+    ostatus[b] = istatus[b];
+    oactive[b] = 0;
+  }
+}
+
 }  // namespace mpp
 
 namespace mpp {

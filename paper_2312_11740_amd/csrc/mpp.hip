@@ -976,13 +976,13 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
   istart.gate = oc.active;
   istart.outer_scal = oc.scal;
   istart.outer_rtol = o.rtol;
-  bool settled = false, converged = false;
-  for (int outer = 0; outer < 40 && !settled; ++outer) {
+  bool settled = false;
+  for (int outer = 0; outer < 40; ++outer) {
     finish_sums(op, oc, start,
                 launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
     ck_launch();
     if (!any_active(op, oc, s)) {
-      settled = converged = true;
+      settled = true;
       break;
     }
     for (int b = 0; b < B; ++b) outer_count[b] += op->h_active[b];
@@ -995,13 +995,13 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
                o.check_every, 1, istart, s);
     hipLaunchKernelGGL(k_correct, g, dim3(kBlock), 0, s, p, op->d32, cells, oc.scal, oc.active);
     ck_launch();
-    // an inner breakdown or an exhausted iteration budget ends the refinement
-    ck(hipMemcpyAsync(op->h_status, ic.status, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-    ck(hipStreamSynchronize(s));
-    for (int b = 0; b < B; ++b)
-      if (op->h_status[b] != MPP_OK) settled = true;
+    // an inner breakdown or an exhausted iteration budget ends the refinement of that
+    // problem only
+    hipLaunchKernelGGL(k_stop_failed, dim3((B + 255) / 256), dim3(256), 0, s, B, ic.status,
+                       oc.status, oc.active);
+    ck_launch();
   }
-  if (!converged) {   // true residual of the returned iterate
+  if (!settled) {   // 40 refinement steps: true residual of the returned iterate
     finish_sums(op, oc, start,
                 launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
     ck_launch();

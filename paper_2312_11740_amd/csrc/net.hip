@@ -93,6 +93,9 @@ size_t net_layout(mpp_net_s* net, int n, int bmax, char* base) {
   net->cpart_floats = (size_t)kMaxChanParts * 64;
   net->cpart = cv.take<float>(net->cpart_floats);
   net->y = cv.take<float>(c0);
+  net->tt = cv.take<float>(c0);
+  net->dy = cv.take<float>(c0);
+  net->lossb = cv.take<float>(bmax);
   net->coarse = cv.take<double>(c0 * 3);
   net->rms64 = cv.take<double>(bmax);
   net->rms32 = cv.take<float>(bmax);
@@ -197,6 +200,9 @@ void conv_wgrad(mpp_net_s* net, int l, const uint16_t* gz, int batch, hipStream_
   int chunk_len = ((cells + chunks - 1) / chunks + 31) / 32 * 32;
   chunks = (cells + chunk_len - 1) / chunk_len;
   const int nparts = batch * chunks;
+  // the partials must fit the buffer sized in net_layout (batches above kMaxParts once
+  // overran it into the arrays after it)
+  if ((size_t)nparts * L.co * kp > net->part_floats) throw NetHipError{hipErrorInvalidValue};
   const dim3 grid(nparts, yblocks);
   const ConvSrc src = layer_src(net, l);
 #define NET_WG(CO, CI, CA)                                                                   \
@@ -341,6 +347,22 @@ int set_params_impl(mpp_net_s* net, const float* params, hipStream_t s) {
 }
 
 void forward_impl(mpp_net_s* net, const uint16_t* x4, float* y, int batch, hipStream_t s);
+
+bool adam_args_ok(float lr, float beta1, float beta2, float eps) {
+  return lr > 0.f && std::isfinite(lr) && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f &&
+         beta2 < 1.f && eps > 0.f && std::isfinite(eps);
+}
+
+// One Adam step with the current gradient (bias corrections from the step count).
+void adam_impl(mpp_net_s* net, float lr, float beta1, float beta2, float eps, hipStream_t s) {
+  net->step += 1;
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, net->step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, net->step)));
+  hipLaunchKernelGGL(k_adam, dim3(blocks(net->nparams, 256)), dim3(256), 0, s, net->w, net->m,
+                     net->v, net->g, net->nparams, lr, beta1, beta2, eps, c1, c2);
+  ck_launch();
+  net->weights_fresh = false;
+}
 
 }  // namespace
 
@@ -492,21 +514,50 @@ int mpp_net_backward(mpp_net net, const float* dy, int32_t batch, void* stream) 
 }
 
 int mpp_net_adam(mpp_net net, float lr, float beta1, float beta2, float eps, void* stream) {
-  if (!net || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
-      !(eps > 0.f))
-    return MPP_EINVAL;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  net->step += 1;
-  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, net->step)));
-  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, net->step)));
+  if (!net || !adam_args_ok(lr, beta1, beta2, eps)) return MPP_EINVAL;
   try {
-    hipLaunchKernelGGL(k_adam, dim3(blocks(net->nparams, 256)), dim3(256), 0, s, net->w, net->m,
-                       net->v, net->g, net->nparams, lr, beta1, beta2, eps, c1, c2);
-    ck_launch();
+    adam_impl(net, lr, beta1, beta2, eps, reinterpret_cast<hipStream_t>(stream));
   } catch (NetHipError&) {
     return MPP_EDEVICE;
   }
-  net->weights_fresh = false;
+  return MPP_OK;
+}
+
+int mpp_net_train(mpp_net net, const uint16_t* x, const float* t, int64_t count,
+                  const mpp_net_train_opts* o, float* losses, void* stream) {
+  // everything that does not need the handle first (the handle is read last)
+  if (!net || !x || !t || !o || count < 1 || o->batch < 1 || o->steps < 0 ||
+      o->first_step < 0 || o->total_steps < 0 ||
+      !adam_args_ok(o->lr0, o->beta1, o->beta2, o->eps) || !(o->lr1 > 0.f) ||
+      !std::isfinite(o->lr1))
+    return MPP_EINVAL;
+  if (o->batch > net->bmax) return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int n = net->n, cells = n * n * n, B = o->batch;
+  const unsigned gx = std::max(1u, std::min(blocks(cells, 256), 2048u / (unsigned)B));
+  try {
+    for (int32_t q = 0; q < o->steps; ++q) {
+      const int64_t step = o->first_step + q;
+      // learning rate of this step on the geometric schedule lr0 -> lr1 over total_steps
+      double lr = o->lr0;
+      if (o->total_steps > 1)
+        lr = (double)o->lr0 * std::pow((double)o->lr1 / (double)o->lr0,
+                                       (double)step / (double)(o->total_steps - 1));
+      hipLaunchKernelGGL(k_gather_samples, dim3(gx, B), dim3(256), 0, s,
+                         reinterpret_cast<const uint2*>(x), t, cells, (int64_t)count, o->seed,
+                         step, B, reinterpret_cast<uint2*>(net->x4), net->tt);
+      ck_launch();
+      forward_impl(net, net->x4, net->y, B, s);
+      float* lo = losses ? losses + (size_t)q * B : net->lossb;
+      hipLaunchKernelGGL(k_loss, dim3(B), dim3(1024), 0, s, net->y, net->tt, cells, 1.0f / B,
+                         net->dy, lo);
+      ck_launch();
+      backward(net, net->dy, B, s);
+      adam_impl(net, (float)lr, o->beta1, o->beta2, o->eps, s);
+    }
+  } catch (NetHipError&) {
+    return MPP_EDEVICE;
+  }
   return MPP_OK;
 }
 

@@ -62,6 +62,10 @@ struct mpp_net_s {
   size_t cpart_floats = 0;
   // scratch of the solver glue: network output, coarse means, rms per sample
   float* y = nullptr;          // [bmax][n^3]
+  // training staging (mpp_net_train): targets of the drawn batch, dloss/dy, losses
+  float* tt = nullptr;         // [bmax][n^3]
+  float* dy = nullptr;         // [bmax][n^3]
+  float* lossb = nullptr;      // [bmax]
   double* coarse = nullptr;    // [bmax][n^3][3]: mean 1/rho, mean b, mean p
   double* rms64 = nullptr;     // [bmax]
   float* rms32 = nullptr;      // [bmax]

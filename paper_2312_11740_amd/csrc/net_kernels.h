@@ -517,6 +517,33 @@ __global__ void __launch_bounds__(1024)
 }
 
 // Adam on the FP32 parameters; c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
+// Training batch of step `step` (global count): sample j of the batch is sample
+// idx(q), q = step * batch + j, of the `count` stored ones: q mod count in order when
+// seed == 0, otherwise SplitMix64 (Steele, Lea & Flood 2014) output number q of the
+// stream started at `seed`, mod count.  Copies its inputs (4 BF16 channels per cell) and
+// target into the network's staging arrays; one thread per (cell, sample).
+__device__ inline int64_t train_sample(uint64_t seed, int64_t q, int64_t count) {
+  if (seed == 0) return q % count;
+  uint64_t z = seed + (uint64_t)(q + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (int64_t)(z % (uint64_t)count);
+}
+
+__global__ void __launch_bounds__(256)
+    k_gather_samples(const uint2* __restrict__ x, const float* __restrict__ t, int cells,
+                     int64_t count, uint64_t seed, int64_t step, int batch,
+                     uint2* __restrict__ xs, float* __restrict__ ts) {
+  const int j = blockIdx.y;
+  const int64_t src = train_sample(seed, step * batch + j, count);
+  const size_t so = (size_t)src * cells, dof = (size_t)j * cells;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x) {
+    xs[dof + c] = x[so + c];
+    ts[dof + c] = t[so + c];
+  }
+}
+
 __global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, size_t np, float lr, float b1, float b2,
                        float eps, float c1, float c2) {

@@ -162,3 +162,28 @@ def test_amr_host_validation():
     assert L.mpp_amr_fill_guards(None, ws, None, None) == M.EINVAL
     assert L.mpp_amr_apply(None, ws, None, ws, None, 1.0, 1.0, ws, None, None) == M.EINVAL
     assert L.mpp_amr_coarse_operator(None, None, ws, None, 1.0, 1.0, None) == M.EINVAL
+
+
+def test_net_train_rejects_bad_arguments_before_device_work():
+    """mpp_net_train checks its arguments before it reads the handle or touches memory
+    (the pointers below are never dereferenced)."""
+    L = M.load_library()
+    net, x, t, lo = (ctypes.c_void_p(0x1000 * k) for k in (1, 2, 3, 4))
+
+    def opts(**kw):
+        o = M.NetTrainOpts(batch=4, steps=2, first_step=0, total_steps=2, lr0=1e-3, lr1=1e-4,
+                           beta1=0.9, beta2=0.999, eps=1e-8, reserved=0, seed=7)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return ctypes.byref(o)
+    nan, inf = float("nan"), float("inf")
+    assert L.mpp_net_train(None, x, t, 10, opts(), lo, None) == M.EINVAL
+    assert L.mpp_net_train(net, None, t, 10, opts(), lo, None) == M.EINVAL
+    assert L.mpp_net_train(net, x, None, 10, opts(), lo, None) == M.EINVAL
+    assert L.mpp_net_train(net, x, t, 10, None, lo, None) == M.EINVAL
+    assert L.mpp_net_train(net, x, t, 0, opts(), lo, None) == M.EINVAL          # count
+    for bad in (dict(batch=0), dict(steps=-1), dict(first_step=-3), dict(total_steps=-1),
+                dict(lr0=0.0), dict(lr0=-1e-3), dict(lr0=nan), dict(lr1=0.0), dict(lr1=inf),
+                dict(beta1=1.0), dict(beta1=-0.1), dict(beta2=1.0), dict(eps=0.0),
+                dict(eps=nan)):
+        assert L.mpp_net_train(net, x, t, 10, opts(**bad), lo, None) == M.EINVAL, bad

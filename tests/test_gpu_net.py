@@ -304,9 +304,10 @@ def oracle_guess(params, phi, f, rn, rp, sg, r, sweeps):
     return p, res, d
 
 
-@pytest.mark.parametrize("sweeps", [0, 2])
-def test_learned_guess_matches_oracle(sweeps):
-    nf, nn = 32, 16
+@pytest.mark.parametrize("nf,nn,sweeps", [(32, 16, 0), (32, 16, 2), (64, 16, 0), (64, 16, 2)])
+def test_learned_guess_matches_oracle(nf, nn, sweeps):
+    """r = nf / nn = 2 (the kernels' run-time coarsening factor) and r = 4 (the
+    compile-time factor the 256^3 benchmark uses with the 64^3 network)."""
     seeds = [21, 22]
     phi, f, rn, rp, sg = problem_batch(nf, seeds)
     params = sparse_params(12)
@@ -356,13 +357,8 @@ def test_training_reduces_loss_and_iterations():
     assert all(i.status == 0 for i in infos)
     net = M.Net(n, len(train_seeds), seed=1, device=DEV)
     x, t, _ = net.features(op, fd, p)
-    bs = 8
-    losses = []
-    torch.manual_seed(0)
-    for it in range(300):
-        idx = torch.randint(0, len(train_seeds), (bs,), device=DEV)
-        lo = net.train_step(x[idx].contiguous(), t[idx].contiguous(), lr=1e-3)
-        losses.append(float(lo.mean()))
+    # 300 steps of 8 samples drawn from the 32 triples, in one mpp_net_train call
+    losses = to_host(net.train(x, t, 300, 8, lr=1e-3, seed=2024)).mean(axis=1)
     print("loss first %.3f last %.3f" % (np.mean(losses[:10]), np.mean(losses[-10:])), flush=True)
     assert np.mean(losses[-20:]) < 0.7 * np.mean(losses[:10])
     phi2, f2, rn2, rp2, sg2 = problem_batch(n, test_seeds)
@@ -379,3 +375,95 @@ def test_training_reduces_loss_and_iterations():
           % (it0, it1, sum(fell)), flush=True)
     assert all(i.status == 0 and i.rel_resid <= 1e-10 for i in learned)
     assert it1 < it0
+
+
+def splitmix64_index(seed, q, count):
+    """Output number q of the SplitMix64 stream started at seed (Steele, Lea & Flood 2014),
+    mod count: the draw mpp_net_train documents, written out here from its definition."""
+    m = 2 ** 64 - 1
+    z = (seed + (q + 1) * 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    z ^= z >> 31
+    return z % count
+
+
+@pytest.mark.parametrize("seed", [0, 987654321])
+def test_net_train_equals_the_four_call_sequence(seed):
+    """mpp_net_train is the sequence draw / forward / loss / backward / Adam run by the
+    library: the same steps made by separate calls on the same samples (drawn here from
+    the documented generator) give the same parameters and losses, bit for bit, on a
+    learning-rate schedule that changes every step."""
+    n, count, batch, steps = 16, 6, 2, 4
+    rng = np.random.default_rng(5)
+    x = to_dev(input_case(n, count, 6), torch.bfloat16)
+    t = rng.normal(size=(count, n, n, n))
+    t = to_dev((t - t.mean(axis=(1, 2, 3), keepdims=True)).astype(np.float32))
+    params = params_case(17)
+    a = make_net(n, batch, params)
+    b = make_net(n, batch, params)
+    lo_a = to_host(a.train(x, t, steps, batch, lr=1e-3, lr_final=2e-4, seed=seed))
+    lr0, lr1 = float(np.float32(1e-3)), float(np.float32(2e-4))
+    lo_b = []
+    for g in range(steps):
+        idx = [splitmix64_index(seed, g * batch + j, count) if seed else (g * batch + j) % count
+               for j in range(batch)]
+        xi = x[torch.tensor(idx, device=DEV)].contiguous()
+        ti = t[torch.tensor(idx, device=DEV)].contiguous()
+        y = b.forward(xi)
+        lo, dy = b.loss(y, ti)
+        b.backward(dy)
+        b.adam(lr0 * (lr1 / lr0) ** (g / (steps - 1)))
+        lo_b.append(to_host(lo))
+    assert np.array_equal(lo_a, np.stack(lo_b))
+    assert np.array_equal(a.get_params(), b.get_params())
+    assert not np.array_equal(a.get_params(), params.astype(np.float32))
+
+
+def test_net_train_split_into_calls_equals_one_call():
+    """first_step / total_steps: a run cut into calls continues the draw and the schedule."""
+    n, count, batch = 16, 5, 2
+    rng = np.random.default_rng(8)
+    x = to_dev(input_case(n, count, 9), torch.bfloat16)
+    t = rng.normal(size=(count, n, n, n))
+    t = to_dev((t - t.mean(axis=(1, 2, 3), keepdims=True)).astype(np.float32))
+    params = params_case(19)
+    a, b = make_net(n, batch, params), make_net(n, batch, params)
+    a.train(x, t, 5, batch, lr=1e-3, lr_final=1e-4, seed=77)
+    b.train(x, t, 2, batch, lr=1e-3, lr_final=1e-4, seed=77, first_step=0, total_steps=5)
+    b.train(x, t, 3, batch, lr=1e-3, lr_final=1e-4, seed=77, first_step=2, total_steps=5)
+    assert np.array_equal(a.get_params(), b.get_params())
+
+
+def test_net_train_rejects_a_batch_above_batch_max():
+    n = 16
+    net = M.Net(n, 2, device=DEV)
+    x = torch.zeros((4, n, n, n, 4), dtype=torch.bfloat16, device=DEV)
+    t = torch.zeros((4, n, n, n), dtype=torch.float32, device=DEV)
+    with pytest.raises(M.MppError) as ei:
+        net.train(x, t, 1, 3)
+    assert ei.value.status == M.EINVAL
+
+
+def test_weight_gradient_of_a_batch_above_512():
+    """Batches above 512 samples (more weight-gradient partials than the fixed minimum the
+    buffer holds; they once overran it): 600 copies of one sample give 600 times its
+    gradient (exact regime: sparse weights, integer inputs)."""
+    n, batch = 16, 600
+    params = sparse_params(23)
+    x1 = int_input(n, 1, 24)
+    dy1 = np.random.default_rng(25).integers(-4, 5, (1, n, n, n)) * 2.0 ** -6
+    one = make_net(n, 1, params)
+    one.forward(to_dev(x1, torch.bfloat16))
+    one.backward(to_dev(dy1.astype(np.float32)))
+    g1 = one.get_grads().astype(np.float64)
+    many = make_net(n, batch, params)
+    xb = to_dev(x1, torch.bfloat16).expand(batch, n, n, n, 4).contiguous()
+    dyb = to_dev(dy1.astype(np.float32)).expand(batch, n, n, n).contiguous()
+    many.forward(xb)
+    many.backward(dyb)
+    g = many.get_grads().astype(np.float64)
+    assert np.all(np.isfinite(g))
+    # the per-sample sums are exact; adding 600 of them in FP32 rounds, by at most
+    # (batch - 1) units of 2^-24 relative to the total
+    assert np.max(np.abs(g - batch * g1)) <= batch * 2.0 ** -24 * np.max(np.abs(batch * g1))

@@ -255,12 +255,23 @@ def test_non_finite_phi_rejected():
 # ---------------------------------------------------------------------------------
 # full size: the 256^3 rising-bubble step, as the benchmark runs it
 # ---------------------------------------------------------------------------------
-@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "learned"])
 def test_rising_bubble_256_full_size(mode):
+    """One step of the 256^3 rising-bubble sequence as the benchmark runs it: FP64, mixed,
+    and the benchmarked method (the trained 64^3 network's guess on 4^3-block means,
+    prolonged, two sweeps, then the mixed solve from it)."""
     pr = G.rising_bubble_problem(0, n=256)
     print("256^3 %s: building" % mode, flush=True)
     op = M.Operator(to_dev(pr.phi), pr.rho_neg, pr.rho_pos, pr.sigma)
-    p, infos = op.solve(to_dev(pr.f), rtol=1e-10, mode=mode)
+    fd = to_dev(pr.f)
+    if mode == "learned":
+        net = M.Net(64, 1, device=DEV)
+        net.load(M.TRAINED_WEIGHTS)
+        g, fell = op.learned_guess(net, fd, sweeps=2)
+        assert fell == [0]          # the guess itself is used, not the zero fallback
+        p, infos = op.solve(fd, g, rtol=1e-10, mode="mixed")
+    else:
+        p, infos = op.solve(fd, rtol=1e-10, mode=mode)
     print(mode, infos[0], flush=True)
     od = O.pipeline(pr.phi, pr.f, pr.rho_neg, pr.rho_pos, pr.sigma)
     ph = to_host(p)
@@ -341,7 +352,7 @@ def test_batched_64_problems_64cubed(mode):
                                                                        max(iters)), flush=True)
     assert all(i.status == M.OK and i.rel_resid <= 1e-10 for i in infos)
     ph = to_host(p)
-    for b in (0, 17, 40, 63):     # sampled against the oracle and against a lone solve
+    for b in range(B):           # every problem against the oracle's solution
         q = probs[b]
         check_solution(q.phi, q.f, q.rho_neg, q.rho_pos, q.sigma, ph[b], infos[b])
     q = probs[5]
@@ -472,3 +483,34 @@ def test_row_sweep_kernel_matches_march(n, monkeypatch):
                                ph[b] if B > 1 else ph, infos[b], rtol=2e-11)
         op.close()
     assert np.array_equal(z["march"], z["row16"])
+
+
+def test_mixed_batch_one_problem_out_of_budget_others_converge():
+    """Residual refinement stops per problem: in a batch where one problem (20 bubbles at
+    density ratio 1000) runs out of the inner iteration budget, the other (one phase) still
+    refines to 1e-10 and returns OK; the first returns ENOTCONVERGED with its last iterate."""
+    n, budget = 64, 16
+    hard = G.many_bubbles_problem(n=n, count=20, seed=1)
+    f_easy = np.random.default_rng(33).uniform(-1, 1, (n, n, n))
+    phi_easy = 1.0 + np.random.default_rng(34).random((n, n, n))     # one phase everywhere
+    # preconditions, from lone solves: the easy problem fits the budget and needs more than
+    # one refinement step; the hard one does not fit
+    lone_e = M.Operator(to_dev(phi_easy), 1e-3, 1.0, 0.01)
+    _, ie = lone_e.solve(to_dev(f_easy), rtol=1e-10, mode="mixed", max_iter=budget)
+    assert ie[0].status == M.OK and ie[0].outer_iters >= 2
+    lone_h = M.Operator(to_dev(hard.phi), hard.rho_neg, hard.rho_pos, hard.sigma)
+    _, ih = lone_h.solve(to_dev(hard.f), rtol=1e-10, mode="mixed", max_iter=budget,
+                         raise_on_error=False)
+    assert ih[0].status == M.ENOTCONVERGED
+    print("lone: easy %s / hard %s" % (ie[0], ih[0]), flush=True)
+    op = M.Operator(to_dev(np.stack([hard.phi, phi_easy])), [hard.rho_neg, 1e-3],
+                    [hard.rho_pos, 1.0], [hard.sigma, 0.01])
+    p, infos = op.solve(to_dev(np.stack([hard.f, f_easy])), rtol=1e-10, mode="mixed",
+                        max_iter=budget, raise_on_error=False)
+    print("batch: %s / %s" % (infos[0], infos[1]), flush=True)
+    assert infos[0].status == M.ENOTCONVERGED and 1e-10 < infos[0].rel_resid < 1.0
+    assert infos[1].status == M.OK and infos[1].outer_iters == ie[0].outer_iters
+    ph = to_host(p)
+    check_solution(phi_easy, f_easy, 1e-3, 1.0, 0.01, ph[1], infos[1])
+    od = O.pipeline(hard.phi, hard.f, hard.rho_neg, hard.rho_pos, hard.sigma)
+    assert abs(O.rel_residual(od["faces"], od["b"], ph[0]) - infos[0].rel_resid) <= 0.05 * infos[0].rel_resid
