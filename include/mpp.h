@@ -242,6 +242,18 @@ int mpp_ls_advect(int n, int batch, const double *phi, const double *ux, const d
 int mpp_ls_reinit(int n, int batch, const double *phi0, double *phi, double *work, int iters,
                   double dtau, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): mpp_ls_reinit without the work array.
+ * The pseudo-time ping-pong uses a scratch field that the library holds for each GPU it
+ * runs on until the process ends (2^24 doubles, 128 MiB: one 256^3 field); the call
+ * allocates nothing.  n^3 * batch above 2^24 gives MPP_ENOMEM, other arguments as for
+ * mpp_ls_reinit (MPP_EINVAL), all before any device work.  Results equal mpp_ls_reinit's
+ * bit for bit.  Every call on one GPU shares that GPU's scratch field: calls that overlap
+ * on one GPU (other streams, other threads) race and must be serialised by the caller.
+ * Asynchronous. */
+int mpp_ls_reinit_noalloc(int n, int batch, const double *phi0, double *phi, int iters,
+                          double dtau, void *stream);
+
 /* ------------------------------------------------------------------------------
  * Implicit heat diffusion (the diffusion term of the transport equation of Sec. 2
  * with a coefficient that changes with the phase: the varDiffusion configuration of

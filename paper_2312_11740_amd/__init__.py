@@ -35,7 +35,7 @@ EXPORTS = (
     "mpp_blocks_gather", "mpp_blocks_fill_guards", "mpp_blocks_apply",
     "mpp_amr_workspace_bytes", "mpp_amr_create", "mpp_amr_destroy", "mpp_amr_level1_blocks",
     "mpp_amr_fill_guards", "mpp_amr_apply", "mpp_amr_solve_work_bytes", "mpp_amr_solve",
-    "mpp_amr_coarse_operator", "mpp_net_train",
+    "mpp_amr_coarse_operator", "mpp_net_train", "mpp_ls_reinit_noalloc",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -136,6 +136,7 @@ def load_library(path: str = LIB_PATH):
     L.mpp_project.argtypes = [P, P, P, d, P, P, P, P]
     L.mpp_ls_advect.argtypes = [i32, i32, P, P, P, P, d, P, P]
     L.mpp_ls_reinit.argtypes = [i32, i32, P, P, P, i32, d, P]
+    L.mpp_ls_reinit_noalloc.argtypes = [i32, i32, P, P, i32, d, P]
     for nm in ("mpp_blocks_scatter", "mpp_blocks_gather"):
         getattr(L, nm).argtypes = [i32, i32, i32, i32, P, P, P]
     L.mpp_blocks_fill_guards.argtypes = [i32, i32, i32, i32, P, P]
@@ -513,6 +514,23 @@ def ls_reinit(phi, iters, dtau=None, phi0=None, work=None):
                                       _stream_handle(phi.device))
     if st != OK:
         raise MppError(st, "mpp_ls_reinit")
+    return phi
+
+
+REINIT_NOALLOC_MAX_CELLS = 1 << 24
+
+
+def ls_reinit_noalloc(phi, phi0, iters, dtau=None):
+    """ls_reinit through mpp_ls_reinit_noalloc: no work array, nothing allocated (phi0 is
+    required, so the call makes no copy either); at most 2^24 cells over the batch."""
+    n, batch = _grid_shape(phi)
+    _check_field(phi0, phi.shape, "phi0")
+    dtau = 0.5 / n if dtau is None else dtau
+    st = load_library().mpp_ls_reinit_noalloc(n, batch, ctypes.c_void_p(phi0.data_ptr()),
+                                              ctypes.c_void_p(phi.data_ptr()), int(iters),
+                                              float(dtau), _stream_handle(phi.device))
+    if st != OK:
+        raise MppError(st, "mpp_ls_reinit_noalloc")
     return phi
 
 

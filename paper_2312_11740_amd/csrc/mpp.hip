@@ -1502,6 +1502,69 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
 // ------------------------------------------------------------------------------
 // the projection around the solve
 // ------------------------------------------------------------------------------
+namespace {
+
+bool reinit_args_ok(int n, int batch, const double* phi0, const double* phi, int iters,
+                    double dtau) {
+  return n >= 2 && n <= 1024 && batch >= 1 && batch <= 65535 && phi0 && phi && iters >= 0 &&
+         phi0 != phi && dtau > 0.0 && std::isfinite(dtau);
+}
+
+// iters re-distancing steps ping-ponging between phi and work; the result ends in phi
+int reinit_run(int n, int batch, const double* phi0, double* phi, double* work, int iters,
+               double dtau, hipStream_t s) {
+  const int cells = n * n * n;
+  const dim3 grid((cells + kLsBlock - 1) / kLsBlock, batch);
+  const LsTiles tl = ls_tiles(n);
+  const dim3 zgrid(8 * ((tl.ntiles + 7) / 8), batch);
+  try {
+    double* src = phi;
+    double* dst = work;
+    for (int it = 0; it < iters; ++it) {
+      hipLaunchKernelGGL(k_ls_reinit_z, zgrid, dim3(kLsTX * kLsTY), 0, s, phi0, src, n, tl, dtau,
+                         dst);
+      ck_launch();
+      std::swap(src, dst);
+    }
+    if (src != phi) {
+      hipLaunchKernelGGL(k_ls_copy, grid, dim3(kLsBlock), 0, s, src, cells, phi);
+      ck_launch();
+    }
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
+// Scratch of the allocation-free re-distancing entry point: one field of up to
+// kReinitScratchDoubles values, a copy per device, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, never a device address: kernels and copies
+// only ever get the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device and kept in reinit_scratch_ptr.
+constexpr size_t kReinitScratchDoubles = size_t(1) << 24;   // 128 MiB: one 256^3 field
+static __device__ __align__(256) double scratch[kReinitScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int reinit_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return MPP_EDEVICE;
+  if (dev >= kMaxDevices) return MPP_EDEVICE;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return MPP_EDEVICE;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return MPP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mpp_divergence(mpp_op op, const double* ux, const double* uy, const double* uz, double dt,
@@ -1555,31 +1618,20 @@ int mpp_ls_advect(int n, int batch, const double* phi, const double* ux, const d
 
 int mpp_ls_reinit(int n, int batch, const double* phi0, double* phi, double* work, int iters,
                   double dtau, void* stream) {
-  if (n < 2 || n > 1024 || batch < 1 || batch > 65535 || !phi0 || !phi || !work || iters < 0 ||
-      phi0 == phi || phi0 == work || phi == work || !(dtau > 0.0) || !std::isfinite(dtau))
+  if (!reinit_args_ok(n, batch, phi0, phi, iters, dtau) || !work || phi0 == work || phi == work)
     return MPP_EINVAL;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int cells = n * n * n;
-  const dim3 grid((cells + kLsBlock - 1) / kLsBlock, batch);
-  const LsTiles tl = ls_tiles(n);
-  const dim3 zgrid(8 * ((tl.ntiles + 7) / 8), batch);
-  try {
-    double* src = phi;
-    double* dst = work;
-    for (int it = 0; it < iters; ++it) {
-      hipLaunchKernelGGL(k_ls_reinit_z, zgrid, dim3(kLsTX * kLsTY), 0, s, phi0, src, n, tl, dtau,
-                         dst);
-      ck_launch();
-      std::swap(src, dst);
-    }
-    if (src != phi) {
-      hipLaunchKernelGGL(k_ls_copy, grid, dim3(kLsBlock), 0, s, src, cells, phi);
-      ck_launch();
-    }
-  } catch (HipError& e) {
-    return status_of(e.e);
-  }
-  return MPP_OK;
+  return reinit_run(n, batch, phi0, phi, work, iters, dtau, reinterpret_cast<hipStream_t>(stream));
+}
+
+int mpp_ls_reinit_noalloc(int n, int batch, const double* phi0, double* phi, int iters,
+                          double dtau, void* stream) {
+  if (!reinit_args_ok(n, batch, phi0, phi, iters, dtau)) return MPP_EINVAL;
+  if ((size_t)n * n * n * (size_t)batch > kReinitScratchDoubles) return MPP_ENOMEM;
+  double* work = nullptr;
+  const int st = reinit_scratch(&work);
+  if (st != MPP_OK) return st;
+  if (work == phi0 || work == phi) return MPP_EINVAL;
+  return reinit_run(n, batch, phi0, phi, work, iters, dtau, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -187,3 +187,20 @@ def test_net_train_rejects_bad_arguments_before_device_work():
                 dict(beta1=1.0), dict(beta1=-0.1), dict(beta2=1.0), dict(eps=0.0),
                 dict(eps=nan)):
         assert L.mpp_net_train(net, x, t, 10, opts(**bad), lo, None) == M.EINVAL, bad
+
+
+def test_reinit_noalloc_rejects_bad_and_oversized_arguments_before_device_work():
+    """The allocation-free re-distancing call refuses a batch beyond its fixed scratch field
+    (2^24 cells) with MPP_ENOMEM, and the usual bad arguments with MPP_EINVAL, before any
+    device call (the pointers are never dereferenced)."""
+    L = M.load_library()
+    a, b = (ctypes.c_void_p(0x1000 * k) for k in (1, 2))
+    assert L.mpp_ls_reinit_noalloc(256, 2, a, b, 2, 0.001, None) == M.ENOMEM    # 2 x 256^3
+    assert L.mpp_ls_reinit_noalloc(512, 1, a, b, 2, 0.001, None) == M.ENOMEM
+    assert L.mpp_ls_reinit_noalloc(1, 1, a, b, 2, 0.001, None) == M.EINVAL      # n < 2
+    assert L.mpp_ls_reinit_noalloc(8, 0, a, b, 2, 0.001, None) == M.EINVAL      # batch
+    assert L.mpp_ls_reinit_noalloc(8, 1, a, a, 2, 0.001, None) == M.EINVAL      # aliasing
+    assert L.mpp_ls_reinit_noalloc(8, 1, None, b, 2, 0.001, None) == M.EINVAL
+    assert L.mpp_ls_reinit_noalloc(8, 1, a, b, -1, 0.001, None) == M.EINVAL     # iters
+    assert L.mpp_ls_reinit_noalloc(8, 1, a, b, 2, 0.0, None) == M.EINVAL        # dtau
+    assert L.mpp_ls_reinit_noalloc(8, 1, a, b, 2, float("nan"), None) == M.EINVAL
