@@ -29,7 +29,6 @@
 #include "rbgs.h"
 #include "rbgs3d.h"
 #include "rbpair.h"
-#include "rbrow.h"
 #include "stencil.h"
 
 using namespace mpp;
@@ -144,7 +143,6 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     op->pstride = std::max(op->pstride, grid3(tiles3(sizes[l])));
     for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2) {
       op->pstride = std::max(op->pstride, rb_grid(pr_tiles(sizes[l], kz)));
-      op->pstride = std::max(op->pstride, row_grid(row_tiles(sizes[l], kz)));
     }
   }
   op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
@@ -344,22 +342,6 @@ int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs
               const T* ec, T* out, int c1, const Ctl& ctl, int dot, const int* active,
               hipStream_t s) {
   const int n = op->lev[l].n, B = op->batch;
-  if (kz <= -100) {   // the row kernel, chunks of -kz - 100 planes (an n = 64 C finest level)
-    if constexpr (FINE) {
-      const RowTiles tl = row_tiles(n, -kz - 100);
-      const dim3 grid(row_grid(tl), B);
-      if (n == 256)
-        hipLaunchKernelGGL((k_rb_row<T, MODE, 4>), grid, dim3(kRowWaves * 64), 0, s, F, n, tl, rhs,
-                           in, ec, out, c1, ctl, dot, active);
-      else if (n == 128)
-        hipLaunchKernelGGL((k_rb_row<T, MODE, 2>), grid, dim3(kRowWaves * 64), 0, s, F, n, tl, rhs,
-                           in, ec, out, c1, ctl, dot, active);
-      else
-        throw HipError{hipErrorInvalidValue};
-      return (int)grid.x;
-    }
-    throw HipError{hipErrorInvalidValue};
-  }
   if (kz <= -2) {
     if constexpr (FINE) {
       if (n % 2 == 0) {
@@ -501,22 +483,16 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
   op->tuned[w] = true;
   const char* env = std::getenv("MPP_AUTOTUNE");
   if (env && env[0] == '0') return;
-  // MPP_SWEEP=march, =tile, =pair[K] or =row[K] fixes the sweep kernel of every level (no
-  // timing; pair: the pair kernel with K-plane chunks (default 16) on an even finest
-  // level, row: the row kernel on a 128^3 or 256^3 finest level, z-marching below)
+  // MPP_SWEEP=march, =tile or =pair[K] fixes the sweep kernel of every level (no timing;
+  // pair: the pair kernel with K-plane chunks (default 16) on an even finest level,
+  // z-marching below)
   const char* force = std::getenv("MPP_SWEEP");
   if (force && (std::strcmp(force, "march") == 0 || std::strcmp(force, "tile") == 0 ||
-                std::strncmp(force, "pair", 4) == 0 || std::strncmp(force, "row", 3) == 0)) {
+                std::strncmp(force, "pair", 4) == 0)) {
     for (int l = 0; l < op->nlev; ++l) op->kz[w][l] = force[0] == 't' ? -1 : 0;
     if (force[0] == 'p' && op->lev[0].n % 2 == 0) {
       const int kz = std::atoi(force + 4);
       op->kz[w][0] = -(kz >= 2 && kz <= 2 * kRbKZ ? kz : 16);
-    }
-    // the row kernel (a wave per row, no block synchronisation): never faster than the
-    // pair kernel here, so only on request
-    if (force[0] == 'r' && (op->lev[0].n == 128 || op->lev[0].n == 256)) {
-      const int kz = std::atoi(force + 3);
-      op->kz[w][0] = -100 - (kz >= 2 && kz <= 2 * kRbKZ ? kz : 16);
     }
     return;
   }

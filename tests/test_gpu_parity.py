@@ -458,33 +458,6 @@ def test_solve_wide_batch_small_problems():
         check_solution(q.phi, q.f, q.rho_neg, q.rho_pos, q.sigma, ph[b], infos[b])
 
 
-@pytest.mark.parametrize("n", [128, 256])
-def test_row_sweep_kernel_matches_march(n, monkeypatch):
-    """The barrier-free row kernel (a wave per row, n = 64 C): V-cycles equal the
-    z-marching kernel's bit for bit (FP64, every mode of the fused sweep on the finest
-    level), and mixed solves (FP32 sweeps) meet the oracle."""
-    B = 2 if n == 128 else 1
-    cases = [bubbles_case(n, 60 + s) for s in range(B)]
-    phi = np.stack([c[0] for c in cases]) if B > 1 else cases[0][0]
-    f = np.stack([c[1] for c in cases]) if B > 1 else cases[0][1]
-    shape = phi.shape
-    r = to_dev(np.random.default_rng(7).standard_normal(shape))
-    z = {}
-    for kind in ("march", "row16"):
-        monkeypatch.setenv("MPP_SWEEP", kind)
-        prm = ([c[2] for c in cases], [c[3] for c in cases], [c[4] for c in cases])
-        op = M.Operator(to_dev(phi), *prm)
-        z[kind] = to_host(op.vcycle(r))
-        if kind == "row16":
-            p, infos = op.solve(to_dev(f), rtol=2e-11, mode="mixed")
-            ph = to_host(p)
-            for b in range(B):
-                check_solution(phi[b] if B > 1 else phi, f[b] if B > 1 else f, *cases[b][2:],
-                               ph[b] if B > 1 else ph, infos[b], rtol=2e-11)
-        op.close()
-    assert np.array_equal(z["march"], z["row16"])
-
-
 def test_mixed_batch_one_problem_out_of_budget_others_converge():
     """Residual refinement stops per problem: in a batch where one problem (20 bubbles at
     density ratio 1000) runs out of the inner iteration budget, the other (one phase) still
