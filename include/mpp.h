@@ -98,7 +98,21 @@ typedef struct {
     double inner_rtol;    /* mixed mode: tightest inner FP32 target (e.g. 1e-5); each
                            * refinement step asks only for the reduction it still
                            * needs, between inner_rtol and 1/2 */
+    int32_t deflate;      /* 1: deflate the regions of the lighter phase (below), 0: plain
+                           * MG-PCG */
+    int32_t reserved;     /* 0 */
 } mpp_solve_opts;
+
+/* Deflation (opts->deflate = 1).  Every connected region of the lighter phase (a bubble,
+ * through cell faces) adds a slow mode to the multigrid-preconditioned operator at a high
+ * density ratio.  Up to 32 regions per problem (the first 32 by their smallest cell index)
+ * are deflated: with Z the indicator fields of the regions and E = Z^T A Z, CG runs on
+ * P A x = P b, P = I - A Z E^{-1} Z^T, and the solution takes x + Z E^{-1} Z^T (b - A x)
+ * at the end (Nicolaides 1987; Tang & Vuik 2007).  The regions and the cells next to
+ * their boundaries are found once per operator build, at the first deflated solve.  The
+ * solution is the same (to the tolerance); only the iteration count changes.  Problems
+ * with equal densities, no region or regions whose band exceeds an eighth of the cells
+ * are solved without deflation.  Pressure solves only (mpp_heat_solve ignores it). */
 
 typedef struct {
     int32_t status;       /* MPP_OK, MPP_ENOTCONVERGED or MPP_EBREAKDOWN */
@@ -111,7 +125,7 @@ typedef struct {
 } mpp_solve_info;
 
 /* Default options: rtol 1e-10, max_iter 500, FP64, zero guess, nu 2, check_every 2,
- * nu_coarse 0 (as nu), inner_rtol 1e-5. */
+ * nu_coarse 0 (as nu), inner_rtol 1e-5, deflate 1. */
 void mpp_default_opts(mpp_solve_opts *opts);
 
 /* Bytes of device workspace an operator of this shape needs (0 if desc is invalid). */

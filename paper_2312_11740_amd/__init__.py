@@ -47,7 +47,8 @@ class Desc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("guess", ctypes.c_int32), ("nu", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("nu_coarse", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("nu_coarse", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+                ("deflate", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -324,11 +325,13 @@ class Operator:
         return [sizes[i] for i in range(nl.value)]
 
     def solve(self, f, p=None, rtol=1e-10, mode="fp64", max_iter=500, nu=2, check_every=2,
-              inner_rtol=1e-5, raise_on_error=True, nu_coarse=0):
-        """Returns (p, [Info per problem]).  p: optional initial guess (overwritten)."""
+              inner_rtol=1e-5, raise_on_error=True, nu_coarse=0, deflate=True):
+        """Returns (p, [Info per problem]).  p: optional initial guess (overwritten).
+        deflate: deflate the lighter phase's regions (mpp_solve_opts.deflate)."""
         _check_field(f, self.shape, "f")
         opts = SolveOpts()
         load_library().mpp_default_opts(ctypes.byref(opts))
+        opts.deflate = 1 if deflate else 0
         opts.rtol, opts.max_iter, opts.nu = float(rtol), int(max_iter), int(nu)
         opts.check_every, opts.inner_rtol = int(check_every), float(inner_rtol)
         opts.nu_coarse = int(nu_coarse)

@@ -76,6 +76,9 @@ struct EpiArgs {
   // and its target; the inner target is relaxed to what the outer step still needs
   const double* outer_scal;
   double outer_rtol;
+  // E_START_REL of a deflated solve: the target is relative to scal[S_SUM] (the norm^2
+  // of the residual before deflation) instead of the deflated residual's
+  int rel_base;
 };
 
 __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& e) {
@@ -88,7 +91,8 @@ __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& 
       s[S_TOL2] = e.rtol2 * tot;
       break;
     case E_START_REL: {
-      s[S_BB] = tot;
+      const double base = e.rel_base ? s[S_SUM] : tot;
+      s[S_BB] = base;
       double rel2 = e.rtol2;
       if (e.outer_scal) {
         // the refinement step only has to bring ||r|| below outer_rtol ||b||: ask the
@@ -98,7 +102,7 @@ __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& 
         const double need2 = 0.25 * e.outer_rtol * e.outer_rtol * os[S_BB] / os[S_RR];
         rel2 = fmin(0.25, fmax(rel2, need2));
       }
-      s[S_TOL2] = rel2 * tot;
+      s[S_TOL2] = rel2 * base;
     }
       [[fallthrough]];
     case E_START:

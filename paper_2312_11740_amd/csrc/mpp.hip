@@ -23,6 +23,7 @@
 #include "heat.h"
 #include "amr.h"
 #include "blocks.h"
+#include "deflate.h"
 #include "kernels.h"
 #include "net_internal.h"
 #include "project.h"
@@ -146,7 +147,31 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     }
   }
   op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
+  // the band correction of a deflated CG appends its partials after a producer's
+  op->pstride += kDefBandBlocks;
   op->partials = cv.take<double>((size_t)B * op->pstride);
+  // deflation: region ids, the band (capacity one eighth of the cells), E and its inverse
+  {
+    Defl& D = op->defl;
+    D.cap = (int)(op->cells / 8 + 64);
+    op->defl_rblk = (int)std::max<size_t>(1, std::min<size_t>(256, op->cells / 8192));
+    D.pcap = std::max(kDefBandBlocks, op->defl_rblk);
+    D.lab = cv.take<uint8_t>(C);
+    D.bcell = cv.take<int>((size_t)B * D.cap);
+    D.blab = cv.take<uint32_t>((size_t)B * D.cap);
+    D.bval = cv.take<double>((size_t)B * D.cap * kDefPairs);
+    D.bcount = cv.take<int>((size_t)B);
+    D.k = cv.take<int>((size_t)B);
+    D.einv = cv.take<double>((size_t)B * kDefMax * kDefMax);
+    D.zb = cv.take<double>((size_t)B * kDefMax);
+    D.coef = cv.take<double>((size_t)B * kDefMax);
+    D.part = cv.take<double>((size_t)B * D.pcap * kDefMax);
+    op->defl_e = cv.take<double>((size_t)B * kDefMax * kDefMax);
+    op->defl_light = cv.take<int>((size_t)B);
+    op->defl_flag = cv.take<int>((size_t)B);
+    op->defl_total = cv.take<int>((size_t)B);
+    op->defl_over = cv.take<int>((size_t)B);
+  }
   op->counters = cv.take<unsigned>((size_t)B);
   for (Ctl* c : {&op->outer, &op->inner}) {
     c->scal = cv.take<double>((size_t)B * kSlots);
@@ -256,7 +281,7 @@ void launch_resid_restrict(const mpp_op_s* op, int l, Faces<T> F, const T* rhs, 
 const char* kKernelNames[kKernelIds] = {
     "apply_dot", "residual", "smooth_colour", "resid_restrict", "prolong_add",  "dot",
     "update_p",  "update_xr", "coarse_vcycle", "apply",        "rb_sweep_zero", "rb_sweep",
-    "rb_sweep_prolong", "heat_apply", "heat_residual", "heat_jacobi"};
+    "rb_sweep_prolong", "heat_apply", "heat_residual", "heat_jacobi", "deflation"};
 
 hipEvent_t prof_event(Prof& P) {
   if (P.used == P.pool.size()) {
@@ -608,6 +633,139 @@ void run_graph(mpp_op_s* op, const GraphKey& key, hipStream_t s, F&& enqueue) {
 }
 
 // ------------------------------------------------------------------------------
+// deflation of the light-phase regions (deflate.h): built at the first deflated solve
+// after a build or update, from the operator's faces; host syncs are part of the build
+// ------------------------------------------------------------------------------
+void build_deflation(mpp_op_s* op, hipStream_t s) {
+  op->defl_ready = true;
+  op->defl_any = false;
+  const int B = op->batch;
+  op->h_defl_k.assign(B, 0);
+  Defl& D = op->defl;
+  const dim3 gb((B + 255) / 256);
+  hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, D.k, B, 0);
+  hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, D.bcount, B, 0);
+  ck_launch();
+  bool want = false;
+  for (int b = 0; b < B; ++b) want = want || op->h_defl_light[b] >= 0;
+  if (!want) return;
+  const Level& L0 = op->lev[0];
+  const int n = op->n, cells = (int)L0.cells;
+  const dim3 g = grid_of(L0, B);
+  // the CG vectors are free between solves: labels and compaction counts live there
+  int* lab = reinterpret_cast<int*>(op->q);
+  int* counts = reinterpret_cast<int*>(op->z);
+  std::vector<int> h(B);
+  auto to_host = [&](const int* d) {
+    ck(hipMemcpyAsync(h.data(), d, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+    ck(hipStreamSynchronize(s));
+  };
+  ck(hipMemcpyAsync(op->defl_light, op->h_defl_light.data(), sizeof(int) * B,
+                    hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_ccl_init, g, dim3(kBlock), 0, s, L0.code, cells, op->defl_light, lab);
+  ck_launch();
+  // propagation rounds, four per check, until a check finds no change (labels only
+  // decrease, so this ends; the cap is a guard)
+  for (int round = 0; round < 65536; round += 4) {
+    hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, op->defl_flag, B, 0);
+    for (int t = 0; t < 4; ++t)
+      hipLaunchKernelGGL(k_ccl_round, g, dim3(kBlock), 0, s, n, lab, op->defl_flag);
+    ck_launch();
+    to_host(op->defl_flag);
+    bool changed = false;
+    for (int b = 0; b < B; ++b) changed = changed || h[b] != 0;
+    if (!changed) break;
+  }
+  // the first kDefMax components of each problem (by smallest cell index) become
+  // regions 1..k
+  const int nblk = (cells + kDefChunk - 1) / kDefChunk;
+  hipLaunchKernelGGL(k_root_count, dim3(nblk, B), dim3(kDefThreads), 0, s, lab, cells, counts,
+                     nblk);
+  hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk, op->defl_total);
+  hipLaunchKernelGGL(k_root_mark, dim3(nblk, B), dim3(kDefThreads), 0, s, lab, cells, counts, nblk);
+  hipLaunchKernelGGL(k_region_ids, g, dim3(kBlock), 0, s, lab, cells, D.lab);
+  ck_launch();
+  to_host(op->defl_total);
+  bool any = false;
+  for (int b = 0; b < B; ++b) {
+    h[b] = op->h_defl_light[b] < 0 ? 0 : std::min(h[b], kDefMax);
+    any = any || h[b] > 0;
+  }
+  if (!any) return;
+  ck(hipMemcpyAsync(D.k, h.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, op->defl_over, B, 0);
+  // the band in cell order, E = Z^T A Z, its inverse; a problem that does not fit is
+  // not deflated
+  const Faces<double> F = faces_of<double>(op, 0);
+  hipLaunchKernelGGL(k_band_count, dim3(nblk, B), dim3(kDefThreads), 0, s, F, D.lab, n, D.k, counts,
+                     nblk);
+  hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk, op->defl_total);
+  hipLaunchKernelGGL(k_band_write, dim3(nblk, B), dim3(kDefThreads), 0, s, F, D.lab, n, D.k, counts,
+                     nblk, D, op->defl_over);
+  ck_launch();
+  to_host(op->defl_total);
+  for (int b = 0; b < B; ++b) h[b] = std::min(h[b], D.cap);
+  ck(hipMemcpyAsync(D.bcount, h.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_defl_e, dim3(kDefMax, B), dim3(kDefThreads), 0, s, D, op->defl_e);
+  hipLaunchKernelGGL(k_defl_inverse, dim3(B), dim3(kDefMax * kDefMax), 0, s, op->defl_e, D,
+                     op->defl_over);
+  hipLaunchKernelGGL(k_defl_off, gb, dim3(256), 0, s, D, op->defl_over, B);
+  ck_launch();
+  to_host(D.k);
+  for (int b = 0; b < B; ++b) {
+    op->h_defl_k[b] = h[b];
+    op->defl_any = op->defl_any || h[b] > 0;
+  }
+}
+
+// Start of a deflated CG: zb = Z^T rhs, coef = E^{-1} (zb - (A Z)^T x) and r -= A Z coef on
+// the band, the change of ||r||^2 appended to the residual's partials (at `off`)
+template <typename T>
+void defl_start(mpp_op_s* op, Ctl& ctl, const T* rhs, const T* x, T* r, int xzero, int off,
+                hipStream_t s) {
+  const Defl& D = op->defl;
+  const int B = op->batch, cells = (int)op->lev[0].cells;
+  hipLaunchKernelGGL(k_region_sums<T>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s, rhs, D.lab,
+                     cells, D, (const int*)nullptr);
+  hipLaunchKernelGGL(k_defl_zb, dim3(B), dim3(64), 0, s, D, op->defl_rblk, (const int*)nullptr);
+  if (!xzero)
+    hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, x, cells,
+                       D, (const int*)nullptr);
+  hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, xzero ? 0 : 1, (const int*)nullptr);
+  hipLaunchKernelGGL(k_band_fix<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, r, cells, D,
+                     ctl, -1, off, (const int*)nullptr);
+  ck_launch();
+}
+
+// z <- P^T z = z - Z E^{-1} (A Z)^T z for the active problems
+template <typename T>
+void defl_project(mpp_op_s* op, const Ctl& ctl, T* z, hipStream_t s) {
+  const Defl& D = op->defl;
+  const int B = op->batch, cells = (int)op->lev[0].cells;
+  timed(op, K_DEFL, 0.0, s, [&] {
+    hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, z, cells, D,
+                       ctl.active);
+    hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 2, ctl.active);
+    hipLaunchKernelGGL(k_region_add<T>, grid_of(op->lev[0], B), dim3(kBlock), 0, s, z, D.lab, cells,
+                       D, ctl.active);
+  });
+  ck_launch();
+}
+
+// End of a deflated CG: x += Z E^{-1} Z^T (rhs - A x) (zb of the start, the band sums of x)
+template <typename T>
+void defl_end(mpp_op_s* op, T* x, hipStream_t s) {
+  const Defl& D = op->defl;
+  const int B = op->batch, cells = (int)op->lev[0].cells;
+  hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, x, cells, D,
+                     (const int*)nullptr);
+  hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 1, (const int*)nullptr);
+  hipLaunchKernelGGL(k_region_add<T>, grid_of(op->lev[0], B), dim3(kBlock), 0, s, x, D.lab, cells,
+                     D, (const int*)nullptr);
+  ck_launch();
+}
+
+// ------------------------------------------------------------------------------
 // Preconditioned CG on -A for every problem whose ctl.active flag is set by the
 // start epilogue.  Uses ctl.scal[S_TOL2] as the per-problem target on ||r||^2.
 // ------------------------------------------------------------------------------
@@ -638,18 +796,39 @@ void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu
   const Faces<T> F = faces_of<T>(op, 0);
   const int cells = (int)L0.cells;
   const EpiArgs erz = epi(E_RZ), epq = epi(E_PQ), err = epi(E_RR_ITER);
+  const bool defl = op->defl_use;
   for (int it = 0; it < iters; ++it) {
     int parts = 0;
     timed(op, K_APPLY_DOT, alg_bytes(op, K_APPLY_DOT, sizeof(T)), s,
           [&] { parts = launch_apply<T>(op, F, p, q, ctl, 1, ctl.active, s); });
     ck_launch();
-    finish_sums(op, ctl, epq, parts, s);
+    if (defl) {   // p.(P q) = p.q - a.s, s = (A Z)^T p over the band, a = E^{-1} s
+      timed(op, K_DEFL, 0.0, s, [&] {
+        hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, op->batch), dim3(kDefThreads), 0,
+                           s, p, cells, op->defl, ctl.active);
+        hipLaunchKernelGGL(k_finish_pq_defl, dim3(op->batch), dim3(1024), 0, s, ctl, parts, epq,
+                           op->defl);
+      });
+      ck_launch();
+    } else {
+      finish_sums(op, ctl, epq, parts, s);
+    }
     timed(op, K_UPDATE_XR, alg_bytes(op, K_UPDATE_XR, sizeof(T)), s, [&] {
       hipLaunchKernelGGL(k_update_xr<T>, g, dim3(kBlock), 0, s, x, r, p, q, cells, ctl, err);
     });
     ck_launch();
-    finish_sums(op, ctl, err, L0.bpp, s);
+    if (defl) {   // r += alpha (A Z) a on the band (r -= alpha P q), ||r||^2 corrected
+      timed(op, K_DEFL, 0.0, s, [&] {
+        hipLaunchKernelGGL(k_band_fix<T>, dim3(kDefBandBlocks, op->batch), dim3(kDefThreads), 0, s,
+                           r, cells, op->defl, ctl, (int)S_ALPHA, L0.bpp, ctl.active);
+      });
+      ck_launch();
+      finish_sums(op, ctl, err, L0.bpp + kDefBandBlocks, s);
+    } else {
+      finish_sums(op, ctl, err, L0.bpp, s);
+    }
     vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
+    if (defl) defl_project<T>(op, ctl, z, s);
     timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
       hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 0);
     });
@@ -668,11 +847,32 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
   timed(op, K_RESIDUAL, alg_bytes(op, K_RESIDUAL, sizeof(T)), s,
         [&] { parts = launch_residual<T>(op, F, rhs, x, r, ctl, xzero, s); });
   ck_launch();
-  finish_sums(op, ctl, start, parts, s);
-  if (!any_active(op, ctl, s)) return;
+  const bool defl = op->defl_use;
+  EpiArgs start_ = start;
+  if (defl) {   // CG on the deflated system: r <- P r
+    // a relative target stays relative to ||r|| before deflation: the jump term, which
+    // dominates b, is almost entirely A times a constant per region, so P r can be tiny
+    EpiArgs eb = epi(E_STORE_MEAN);
+    eb.slot = S_SUM;
+    eb.inv_cells = 1.0;
+    finish_sums(op, ctl, eb, parts, s);
+    start_.rel_base = 1;
+    defl_start<T>(op, ctl, rhs, x, r, xzero, parts, s);
+    parts += kDefBandBlocks;
+  }
+  finish_sums(op, ctl, start_, parts, s);
+  // the iterate of a deflated CG takes its component in the regions at the end
+  auto done_ = [&] {
+    if (defl) defl_end<T>(op, x, s);
+  };
+  if (!any_active(op, ctl, s)) {
+    done_();
+    return;
+  }
   EpiArgs erz = epi(E_RZ);
   erz.first = 1;
   vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
+  if (defl) defl_project<T>(op, ctl, z, s);
   timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
     hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 1);
   });
@@ -680,7 +880,7 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
   // iterations in blocks of check_every; the kernels themselves stop working on a
   // problem once it has converged, so a block may overrun the last useful iteration
   const bool graphs = op->use_graphs && !op->prof.on;
-  const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter,
+  const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter, defl ? 1 : 0,
                      {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
   for (int done = 0; done <= ctl.max_iter; done += check_every) {
     if (graphs)
@@ -689,8 +889,9 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
       });
     else
       pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, s);
-    if (!any_active(op, ctl, s)) return;
+    if (!any_active(op, ctl, s)) break;
   }
+  done_();
 }
 
 void reset_ctl(mpp_op_s* op, Ctl& ctl, int max_iter, hipStream_t s) {
@@ -833,7 +1034,7 @@ void heat_pcg(mpp_op_s* op, Ctl& ctl, double* x, int check_every, hipStream_t s)
   ck_launch();
   // nu = 0 marks these graphs apart from the pressure solve's (nu >= 1)
   const bool graphs = op->use_graphs && !op->prof.on;
-  const GraphKey key{8, 0, 0, check_every, ctl.max_iter,
+  const GraphKey key{8, 0, 0, check_every, ctl.max_iter, 0,
                      {(const void*)ctl.scal, x, op->r, op->z, op->p, op->q}};
   for (int done = 0; done < ctl.max_iter; done += check_every) {
     if (graphs)
@@ -861,6 +1062,8 @@ void mpp_default_opts(mpp_solve_opts* o) {
   o->nu_coarse = 0;
   o->check_every = 2;
   o->inner_rtol = 1e-5;
+  o->deflate = 1;
+  o->reserved = 0;
 }
 
 size_t mpp_workspace_bytes(const mpp_desc* desc) {
@@ -908,6 +1111,7 @@ bool opts_valid(const mpp_solve_opts& o) {
       (o.guess != MPP_GUESS_ZERO && o.guess != MPP_GUESS_GIVEN))
     return false;
   if (o.mode == MPP_MODE_MIXED && !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0)) return false;
+  if (o.deflate != 0 && o.deflate != 1) return false;
   return true;
 }
 
@@ -922,6 +1126,13 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
   ensure_tuned<double>(op, s);
   if (o.mode == MPP_MODE_MIXED) ensure_tuned<float>(op, s);
   op->nu_c = o.nu_coarse > 0 ? o.nu_coarse : o.nu;
+  // deflation of the light-phase regions: pressure solves only (a shifted operator has no
+  // such slow modes)
+  op->defl_use = false;
+  if (o.deflate && op->shift == 0.0) {
+    if (!op->defl_ready) build_deflation(op, s);
+    op->defl_use = op->defl_any;
+  }
   Ctl& oc = op->outer;
   // the iterate lives in the workspace (captured launch graphs refer to it); the
   // caller's p is copied in and out
@@ -1041,6 +1252,12 @@ bool read_params(int B, const double* rho_neg, const double* rho_pos, const doub
 // operator's workspace.  Returns MPP_EINVAL for a non-finite phi.
 int build_into(mpp_op_s* op, const double* phi, const std::vector<double>& host, hipStream_t s) {
   const int B = op->batch;
+  op->defl_ready = false;   // built again at the next deflated solve
+  op->h_defl_light.assign(B, -1);
+  for (int b = 0; b < B; ++b) {   // the lighter phase's side bit (phi > 0: 1)
+    const double rn = host[3 * b], rp = host[3 * b + 1];
+    op->h_defl_light[b] = rn < rp ? 0 : (rp < rn ? 1 : -1);
+  }
   ck(hipMemcpyAsync(op->rho, host.data(), sizeof(double) * 3 * B, hipMemcpyHostToDevice, s));
   // the outer status array doubles as the non-finite flag during the build
   ck(hipMemsetAsync(op->outer.status, 0, sizeof(int) * B, s));

@@ -76,6 +76,27 @@ struct Level {
   int bpp = 1;              // blocks per problem of the cell kernels on this level
 };
 
+// Deflation of the light-phase regions (the kernels and the method: deflate.h).
+constexpr int kDefMax = 32;          // regions per problem
+constexpr int kDefPairs = 4;         // (region, value) pairs per band cell: own + 3 others
+constexpr int kDefBandBlocks = 32;   // blocks over a problem's band list
+
+// Per-problem deflation state in device memory.
+struct Defl {
+  uint8_t* lab;      // [B][cells] region (1..k) of each cell, 0 outside every region
+  int* bcell;        // [B][cap] band cells (cell index in the problem), in cell order
+  uint32_t* blab;    // [B][cap] regions of the pairs, a byte each (byte 0: the cell's own)
+  double* bval;      // [B][cap][kDefPairs] (A z_j) at the cell
+  int* bcount;       // [B] band cells (0: the problem is not deflated)
+  int* k;            // [B] regions (0: not deflated)
+  double* einv;      // [B][kDefMax][kDefMax] E^{-1}
+  double* zb;        // [B][kDefMax] Z^T b of the right-hand side of the current CG
+  double* coef;      // [B][kDefMax] a = E^{-1} s (per iteration) / the start and end terms
+  double* part;      // [B][pcap][kDefMax] per-block sums over regions
+  int cap;           // band cells a problem can hold
+  int pcap;          // blocks of part per problem
+};
+
 // Kernel classes timed by the profiler.
 enum KernelId {
   K_APPLY_DOT = 0,   // q = A p and p.q
@@ -94,6 +115,7 @@ enum KernelId {
   K_HEAT_APPLY,      // q = (dt A - I) p and p.q
   K_HEAT_RESIDUAL,   // r = b - (dt A - I) x and ||r||^2
   K_HEAT_JACOBI,     // z = r / diag and r.z
+  K_DEFL,            // deflation: band sums, the corrected p.q, the band correction of r
   kKernelIds
 };
 
@@ -116,11 +138,12 @@ struct Prof {
 // A captured block of CG iterations and what it was captured for.
 struct GraphKey {
   int tsize, nu, nu_c, iters, max_iter;
+  int defl;
   const void* ptr[6];
   double shift = 0.0;   // the operator's diagonal shift (a kernel argument in the graph)
   bool operator==(const GraphKey& o) const {
     if (tsize != o.tsize || nu != o.nu || nu_c != o.nu_c || iters != o.iters ||
-        max_iter != o.max_iter || shift != o.shift)
+        max_iter != o.max_iter || defl != o.defl || shift != o.shift)
       return false;
     for (int q = 0; q < 6; ++q)
       if (ptr[q] != o.ptr[q]) return false;
@@ -168,6 +191,19 @@ struct mpp_op_s {
   double* partials = nullptr;
   unsigned* counters = nullptr;
   int pstride = 0;
+  // deflation (built at the first deflated solve after a build or update)
+  mpp::Defl defl{};
+  double* defl_e = nullptr;       // [B][kDefMax][kDefMax] E = Z^T A Z
+  int* defl_light = nullptr;      // [B] side bit of the lighter phase, -1: none
+  int* defl_flag = nullptr;       // [B] changed flags of the labelling rounds
+  int* defl_total = nullptr;      // [B] totals of the compactions
+  int* defl_over = nullptr;       // [B] problems whose deflation does not fit
+  int defl_rblk = 1;              // blocks per problem of the region sums
+  bool defl_ready = false;        // built for the current operator
+  bool defl_use = false;          // the CG being run is deflated
+  std::vector<int> h_defl_light;  // host: side bit of the lighter phase per problem, -1 none
+  bool defl_any = false;          // some problem is deflated
+  std::vector<int> h_defl_k;      // host copy of defl.k
   // host mirrors for polling
   int* h_active = nullptr;
   int* h_iters = nullptr;
