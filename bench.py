@@ -8,12 +8,14 @@ operator for that step's level set and solve to a relative residual of 1e-10,
 warm-started from the previous step's pressure.  Inputs (phi_t, f_t) for every
 step are resident in HBM before the timed region.
 
-Four methods run on the same steps:
+Methods run on the same steps:
   plain   -- FP64 multigrid-preconditioned CG warm-started from the previous step's
-             pressure (the baseline),
+             pressure (the baseline: no deflation),
   plain0  -- the same from a zero initial guess,
-  mixed   -- FP32 multigrid-preconditioned CG inside FP64 residual refinement, warm
-             started likewise,
+  plain_d -- plain with the bubble regions deflated,
+  mixed   -- FP32 multigrid-preconditioned CG inside FP64 residual refinement, deflated,
+             warm started likewise,
+  mixed0  -- mixed from a zero initial guess,
   learned -- mixed, started from the learned guess: the U-Net trained on 64^3 problems
              (weights shipped with the package) applied to the step's inputs averaged
              over 4^3 blocks, its prediction prolonged to 256^3, scaled to the energy
@@ -75,7 +77,7 @@ def measured_traffic(kernel):
 
 
 def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None, zero=False,
-                 guess_sweeps=2, check_every=2):
+                 guess_sweeps=2, check_every=2, deflate=True):
     """warmup + steps projection solves, each warm-started from the previous step (or,
     with a network, from the learned guess; with zero, from zero); returns (mean ms per
     timed step, infos of the timed steps, learned-guess fallbacks)."""
@@ -90,12 +92,12 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
             t0 = time.perf_counter()
         op.update(phis[t], prm["rho_neg"], prm["rho_pos"], prm["sigma"])
         if net is not None:
-            p, fell = op.learned_guess(net, fs[t], sweeps=guess_sweeps, out=p)
+            p, fell = op.learned_guess(net, fs[t], sweeps=guess_sweeps, out=p,
+                                       judge="deflated" if deflate else "plain")
             if t >= warmup:
                 fallbacks += sum(fell)
         p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu,
-                           nu_coarse=NU_COARSE,
-                           check_every=check_every)
+                           nu_coarse=NU_COARSE, check_every=check_every, deflate=deflate)
         if t >= warmup:
             infos.append(info[0])
     torch.cuda.synchronize()
@@ -104,17 +106,20 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
     return ms, infos, fallbacks
 
 
-def run_profiled(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None):
+def run_profiled(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None, zero=False,
+                 deflate=True):
     p = torch.zeros_like(fs[0])
     stats = {}
     op = M.Operator(phis[0], prm["rho_neg"], prm["rho_pos"], prm["sigma"], workspace=ws)
     for t in range(warmup + steps):
         op.update(phis[t], prm["rho_neg"], prm["rho_pos"], prm["sigma"])
         if net is not None:
-            p, _ = op.learned_guess(net, fs[t], sweeps=2, out=p)
+            p, _ = op.learned_guess(net, fs[t], sweeps=2, out=p,
+                                    judge="deflated" if deflate else "plain")
         if t >= warmup:
             op.profile_start()
-        p, info = op.solve(fs[t], p=p, rtol=prm["rtol"], mode=mode, nu=nu, nu_coarse=NU_COARSE)
+        p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu,
+                           nu_coarse=NU_COARSE, deflate=deflate)
         if t >= warmup:
             for k, v in op.profile_stop().items():
                 s = stats.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))
@@ -190,15 +195,16 @@ def batched64(M, G, torch, args):
     sg = [q.sigma for q in probs]
     op = M.Operator(phi, rn, rp, sg)
     res = {}
-    for meth, mode in (("plain", "fp64"), ("mixed", "mixed")):
+    for meth, mode, dfl in (("plain", "fp64", False), ("plain_d", "fp64", True),
+                            ("mixed_nd", "mixed", False), ("mixed", "mixed", True)):
         for _ in range(args.warmup):
             op.update(phi, rn, rp, sg)
-            op.solve(f, rtol=1e-10, mode=mode, nu=args.nu)
+            op.solve(f, rtol=1e-10, mode=mode, nu=args.nu, deflate=dfl)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             op.update(phi, rn, rp, sg)
-            p, infos = op.solve(f, rtol=1e-10, mode=mode, nu=args.nu)
+            p, infos = op.solve(f, rtol=1e-10, mode=mode, nu=args.nu, deflate=dfl)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         res[meth] = {"ms_per_batch": round(ms, 3),
@@ -246,13 +252,14 @@ def single_problem(M, G, torch, args, which):
     f = torch.from_numpy(pr.f).to(dev)
     op = M.Operator(phi, pr.rho_neg, pr.rho_pos, pr.sigma)
     res, sols = {}, {}
-    for meth, mode in (("plain", "fp64"), ("mixed", "mixed")):
+    for meth, mode, dfl in (("plain", "fp64", False), ("plain_d", "fp64", True),
+                            ("mixed_nd", "mixed", False), ("mixed", "mixed", True)):
         for _ in range(args.warmup):
-            op.solve(f, rtol=rtol, mode=mode, nu=args.nu)
+            op.solve(f, rtol=rtol, mode=mode, nu=args.nu, deflate=dfl)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            p, infos = op.solve(f, rtol=rtol, mode=mode, nu=args.nu)
+            p, infos = op.solve(f, rtol=rtol, mode=mode, nu=args.nu, deflate=dfl)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         sols[meth] = p.cpu().numpy()
@@ -722,7 +729,7 @@ def main():
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--nu-coarse", type=int, default=0,
                     help="sweeps per level below the finest (0: as --nu)")
-    ap.add_argument("--methods", default="plain,plain0,mixed,learned")
+    ap.add_argument("--methods", default="plain,plain0,plain_d,mixed,mixed0,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--guess-sweeps", type=int, default=2,
                     help="red-black sweeps applied to the learned guess")
@@ -788,18 +795,25 @@ def main():
     ws = torch.empty(M.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    MODES = {"plain": "fp64", "plain0": "fp64", "mixed": "mixed", "learned": "mixed"}
+    MODES = {"plain": "fp64", "plain0": "fp64", "plain_d": "fp64", "mixed": "mixed",
+             "mixed0": "mixed", "learned": "mixed"}
+    DEFLATE = {"plain": False, "plain0": False, "plain_d": True, "mixed": True, "mixed0": True,
+               "learned": True}
+    ZERO = {"plain0", "mixed0"}
     net = None
     if "learned" in args.methods.split(","):
         net = M.Net(64, 1, device=dev)
         net.load(M.TRAINED_WEIGHTS)
+    # untimed burn-in: the first solves after start-up run at lower clocks, which would
+    # otherwise bias whichever method is timed first
+    run_sequence(M, torch, ws, phis, fs, prm, "fp64", args.nu, min(K, 3), 1, None, zero=True)
     results = {}
     for meth in args.methods.split(","):
         mode = MODES[meth]
         ms, infos, fb = run_sequence(M, torch, ws, phis, fs, prm, mode, args.nu, K, W,
-                                     net if meth == "learned" else None, zero=meth == "plain0",
+                                     net if meth == "learned" else None, zero=meth in ZERO,
                                      guess_sweeps=args.guess_sweeps,
-                                     check_every=args.check_every)
+                                     check_every=args.check_every, deflate=DEFLATE[meth])
         worst = max(i.rel_resid for i in infos)
         ok = all(i.status == M.OK for i in infos) and worst <= prm["rtol"]
         results[meth] = dict(ms=ms, iters=[i.iters for i in infos],
@@ -822,7 +836,8 @@ def main():
     if not args.no_profile:
         mode = MODES[best]
         stats = run_profiled(M, torch, ws, phis, fs, prm, mode, args.nu, K, W,
-                             net if best == "learned" else None)
+                             net if best == "learned" else None, zero=best in ZERO,
+                             deflate=DEFLATE[best])
         kernels = {k: dict(launches=v["launches"], mean_us=1e3 * v["ms"] / v["launches"],
                            GBps=(v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["bytes"] else None,
                            share=None)
@@ -849,8 +864,10 @@ def main():
         op = M.Operator(phis[0], prm["rho_neg"], prm["rho_pos"], prm["sigma"], workspace=ws)
         g0 = None
         if best == "learned":
-            g0, _ = op.learned_guess(net, fs[0], sweeps=2)
-        p0, _ = op.solve(fs[0], p=g0, rtol=prm["rtol"], mode=MODES[best], nu=args.nu)
+            g0, _ = op.learned_guess(net, fs[0], sweeps=2,
+                                     judge="deflated" if DEFLATE[best] else "plain")
+        p0, _ = op.solve(fs[0], p=g0, rtol=prm["rtol"], mode=MODES[best], nu=args.nu,
+                         deflate=DEFLATE[best])
         p0h = p0.cpu().numpy()
         op.close()
         cpu, err, rr = cpu_baseline(probs[0], p0h)
@@ -870,8 +887,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"plain": "f64", "plain0": "f64", "mixed": "f32+f64",
-                  "learned": "bf16+f32+f64"}[best],
+        "dtype": {"plain": "f64", "plain0": "f64", "plain_d": "f64", "mixed": "f32+f64",
+                  "mixed0": "f32+f64", "learned": "bf16+f32+f64"}[best],
         "data": "synthetic",
         "config": {"workload": "rising bubble %d^3, density ratio 1000, sigma 0.01, one "
                                "projection solve (operator build + MG-PCG to 1e-10, warm "
@@ -882,7 +899,8 @@ def main():
                                      if best == "learned" else None)},
         "methods": {m: {"ms_per_step": round(r["ms"], 3), "iters": r["iters"],
                         "outer": r["outer"], "max_rel_resid": r["max_rel_resid"],
-                        "ok": r["ok"], "guess_fallbacks": r["fallbacks"]}
+                        "ok": r["ok"], "guess_fallbacks": r["fallbacks"],
+                        "deflated": DEFLATE[m]}
                     for m, r in results.items()},
         "speedup_vs_plain_fp64": (round(plain_ms / value, 3) if plain_ms else None),
         "speedup_vs_best_plain": (round(min(results[m]["ms"] for m in ("plain", "plain0")

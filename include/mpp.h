@@ -547,11 +547,17 @@ int mpp_net_features(mpp_net net, mpp_op op, const double *f, const double *p, u
  * operator's grid by trilinear interpolation of the cell values (clamped at the
  * walls), its mean removed, scaled by (p.b) / (p.Ap) (the multiple of the prediction
  * closest to the solution in the energy norm, so never farther than zero), then
- * `sweeps` (0..8) red-black Gauss-Seidel sweeps on A p = b.  A problem whose guess is
- * not finite or has ||b - A p|| >= ||b|| gets p = 0 instead and fell_back[b] = 1 (host
- * int32 [batch], may be NULL).  p: device FP64 [batch][(r n)^3]. */
+ * `sweeps` (0..8) red-black Gauss-Seidel sweeps on A p = b.  The solver judges the
+ * guess against a zero start as the solve will see them: judge MPP_JUDGE_PLAIN compares
+ * ||b - A p|| with ||b|| (for a solve without deflation), MPP_JUDGE_DEFLATED compares
+ * ||P (b - A p)|| with ||P b|| (for a deflated solve; P as in the deflation note above).
+ * A problem whose guess is not finite or does not start below the zero start gets p = 0
+ * instead and fell_back[b] = 1 (host int32 [batch], may be NULL).  p: device FP64
+ * [batch][(r n)^3]. */
+#define MPP_JUDGE_PLAIN 0
+#define MPP_JUDGE_DEFLATED 1
 int mpp_learned_guess(mpp_op op, mpp_net net, const double *f, double *p, int32_t sweeps,
-                      int32_t *fell_back, void *stream);
+                      int32_t judge, int32_t *fell_back, void *stream);
 
 const char *mpp_strerror(int status);
 

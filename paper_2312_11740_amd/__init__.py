@@ -131,7 +131,8 @@ def load_library(path: str = LIB_PATH):
                                ctypes.c_float, P]
     L.mpp_net_train.argtypes = [P, P, P, ctypes.c_int64, ctypes.POINTER(NetTrainOpts), P, P]
     L.mpp_net_features.argtypes = [P, P, P, P, P, P, P, P]
-    L.mpp_learned_guess.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+    L.mpp_learned_guess.argtypes = [P, P, P, P, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32),
                                     P]
     L.mpp_divergence.argtypes = [P, P, P, P, d, P, P]
     L.mpp_project.argtypes = [P, P, P, d, P, P, P, P]
@@ -426,16 +427,18 @@ class Operator:
             raise MppError(st, "mpp_project")
         return u
 
-    def learned_guess(self, net, f, sweeps=2, out=None):
+    def learned_guess(self, net, f, sweeps=2, out=None, judge="plain"):
         """Initial guess from the network (device float64, the operator's shape) and the
-        per-problem fallback flags (1 where the guess was replaced by zero)."""
+        per-problem fallback flags (1 where the guess was replaced by zero).  judge:
+        "plain" (for a solve without deflation) or "deflated" (for a deflated one)."""
         _check_field(f, self.shape, "f")
         p = self._new() if out is None else out
         _check_field(p, self.shape, "out")
         flags = (ctypes.c_int32 * self.batch)()
+        jd = {"plain": 0, "deflated": 1}[judge]
         st = load_library().mpp_learned_guess(self._h, net._h, ctypes.c_void_p(f.data_ptr()),
-                                              ctypes.c_void_p(p.data_ptr()), int(sweeps), flags,
-                                              _stream_handle(self.device))
+                                              ctypes.c_void_p(p.data_ptr()), int(sweeps), jd,
+                                              flags, _stream_handle(self.device))
         if st != OK:
             raise MppError(st, "mpp_learned_guess")
         return p, [int(v) for v in flags]

@@ -36,44 +36,57 @@ constexpr int kDefThreads = 256;
 constexpr int kDefChunk = 4096;      // cells per block of the compactions over the grid
 
 // ---- labels of the light-phase regions --------------------------------------------
-// light[b]: side bit (0: phi <= 0, 1: phi > 0) of the lighter phase, -1: no deflation
-__global__ void k_ccl_init(const uint8_t* __restrict__ code, int cells,
-                           const int* __restrict__ light, int* __restrict__ lab) {
+// light[b]: side bit (0: phi <= 0, 1: phi > 0) of the lighter phase, -1: no deflation.
+// The light cells are first compacted into a list (cell order); the labels are kept in a
+// grid-sized array but only ever read at light cells (a neighbour's phase comes from its
+// code byte), so nothing else of the array needs a value.
+__device__ inline bool is_light(const uint8_t* __restrict__ code, size_t base, int c, int ls) {
+  return ls >= 0 && (int)((code[base + c] >> 6) & 1) == ls;
+}
+
+__global__ void k_ccl_init(const int* __restrict__ list, const int* __restrict__ lcount, int lcap,
+                           int cells, int* __restrict__ lab) {
   const int b = blockIdx.y;
-  const size_t base = (size_t)b * cells;
-  const int ls = light[b];
-  CELL_LOOP(cells) {
-    const int side = (code[base + c] >> 6) & 1;
-    lab[base + c] = (ls >= 0 && side == ls) ? c : -1;
+  const int cnt = lcount[b];
+  const int* Lst = list + (size_t)b * lcap;
+  int* L = lab + (size_t)b * cells;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const int c = Lst[q];
+    L[c] = c;
   }
 }
 
-// One round of propagation: smallest label among the cell and its face neighbours, then
-// up to four steps along the labels, and the old label's cell takes the new one too
-// (labels only decrease and always name a cell of the same component).
-__global__ void k_ccl_round(int n, int* __restrict__ lab, int* __restrict__ changed) {
+// One round of propagation over the light cells: smallest label among the cell and its
+// light face neighbours, then up to four steps along the labels, and the old label's cell
+// takes the new one too (labels only decrease and always name a cell of the same
+// component).
+__global__ void k_ccl_round(int n, const uint8_t* __restrict__ code, const int* __restrict__ light,
+                            const int* __restrict__ list, const int* __restrict__ lcount, int lcap,
+                            int* __restrict__ lab, int* __restrict__ changed) {
   const int b = blockIdx.y;
   const int cells = n * n * n;
   const size_t base = (size_t)b * cells;
+  const int ls = light[b];
+  const int cnt = lcount[b];
+  const int* Lst = list + (size_t)b * lcap;
   int* L = lab + base;
+  const int nn = n * n;
   int any = 0;
-  CELL_LOOP(cells) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const int c = Lst[q];
     const int old = L[c];
-    if (old < 0) continue;
     int i, j, k;
     ijk(c, n, i, j, k);
     int m = old;
-    const int nn = n * n;
-    int v;
-    if (i > 0 && (v = L[c - 1]) >= 0) m = min(m, v);
-    if (i < n - 1 && (v = L[c + 1]) >= 0) m = min(m, v);
-    if (j > 0 && (v = L[c - n]) >= 0) m = min(m, v);
-    if (j < n - 1 && (v = L[c + n]) >= 0) m = min(m, v);
-    if (k > 0 && (v = L[c - nn]) >= 0) m = min(m, v);
-    if (k < n - 1 && (v = L[c + nn]) >= 0) m = min(m, v);
+    if (i > 0 && is_light(code, base, c - 1, ls)) m = min(m, L[c - 1]);
+    if (i < n - 1 && is_light(code, base, c + 1, ls)) m = min(m, L[c + 1]);
+    if (j > 0 && is_light(code, base, c - n, ls)) m = min(m, L[c - n]);
+    if (j < n - 1 && is_light(code, base, c + n, ls)) m = min(m, L[c + n]);
+    if (k > 0 && is_light(code, base, c - nn, ls)) m = min(m, L[c - nn]);
+    if (k < n - 1 && is_light(code, base, c + nn, ls)) m = min(m, L[c + nn]);
     for (int t = 0; t < 4; ++t) {
       const int m2 = L[m];
-      if (m2 >= 0 && m2 < m) m = m2;
+      if (m2 < m) m = m2;
       else break;
     }
     if (m < old) {
@@ -140,17 +153,67 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-// roots: cells whose label is their own index
+// light cells of each problem: per-block counts over chunks of cells
 __global__ void __launch_bounds__(kDefThreads)
-    k_root_count(const int* __restrict__ lab, int cells, int* __restrict__ counts, int nblk) {
+    k_light_count(const uint8_t* __restrict__ code, int cells, const int* __restrict__ light,
+                  int* __restrict__ counts, int nblk) {
   const int b = blockIdx.y;
-  const int* L = lab + (size_t)b * cells;
+  const size_t base = (size_t)b * cells;
+  const int ls = light[b];
   __shared__ int sh[kDefThreads / 64];
   int cnt = 0;
   const int c0 = blockIdx.x * kDefChunk;
-  for (int c = c0 + threadIdx.x; c < min(c0 + kDefChunk, cells); c += kDefThreads)
+  if (ls >= 0)
+    for (int c = c0 + threadIdx.x; c < min(c0 + kDefChunk, cells); c += kDefThreads)
+      cnt += is_light(code, base, c, ls);
+  int v = cnt;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int q = 0; q < kDefThreads / 64; ++q) s += sh[q];
+    counts[(size_t)b * nblk + blockIdx.x] = s;
+  }
+}
+
+// the light cells in cell order (a problem with more than lcap of them: not written)
+__global__ void __launch_bounds__(kDefThreads)
+    k_light_write(const uint8_t* __restrict__ code, int cells, const int* __restrict__ light,
+                  const int* __restrict__ offs, const int* __restrict__ total, int nblk,
+                  int* __restrict__ list, int lcap) {
+  const int b = blockIdx.y;
+  const int ls = light[b];
+  if (ls < 0 || total[b] > lcap) return;
+  const size_t base = (size_t)b * cells;
+  __shared__ int sh[kDefThreads / 64];
+  int rank0 = offs[(size_t)b * nblk + blockIdx.x];
+  const int c0 = blockIdx.x * kDefChunk;
+  for (int s0 = c0; s0 < min(c0 + kDefChunk, cells); s0 += kDefThreads) {
+    const int c = s0 + threadIdx.x;
+    const bool hit = c < cells && is_light(code, base, c, ls);
+    int tot = 0;
+    const int r = block_rank(hit, tot, sh);
+    if (hit) list[(size_t)b * lcap + rank0 + r] = c;
+    rank0 += tot;
+  }
+}
+
+// roots (cells whose label is their own index): per-block counts over chunks of the list
+__global__ void __launch_bounds__(kDefThreads)
+    k_root_count(const int* __restrict__ lab, int cells, const int* __restrict__ list,
+                 const int* __restrict__ lcount, int lcap, int* __restrict__ counts, int nblk) {
+  const int b = blockIdx.y;
+  const int* L = lab + (size_t)b * cells;
+  const int* Lst = list + (size_t)b * lcap;
+  const int cnt_l = lcount[b];
+  __shared__ int sh[kDefThreads / 64];
+  int cnt = 0;
+  const int q0 = blockIdx.x * kDefChunk;
+  for (int q = q0 + threadIdx.x; q < min(q0 + kDefChunk, cnt_l); q += kDefThreads) {
+    const int c = Lst[q];
     cnt += L[c] == c;
-  // wave sums, then the block sum in a fixed order
+  }
   int v = cnt;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -164,15 +227,19 @@ __global__ void __launch_bounds__(kDefThreads)
 
 // the first kDefMax roots of each problem (in cell order) are marked -(rank + 2)
 __global__ void __launch_bounds__(kDefThreads)
-    k_root_mark(int* __restrict__ lab, int cells, const int* __restrict__ offs, int nblk) {
+    k_root_mark(int* __restrict__ lab, int cells, const int* __restrict__ list,
+                const int* __restrict__ lcount, int lcap, const int* __restrict__ offs, int nblk) {
   const int b = blockIdx.y;
   int* L = lab + (size_t)b * cells;
+  const int* Lst = list + (size_t)b * lcap;
+  const int cnt_l = lcount[b];
   __shared__ int sh[kDefThreads / 64];
   int base_rank = offs[(size_t)b * nblk + blockIdx.x];
-  const int c0 = blockIdx.x * kDefChunk;
-  for (int s0 = c0; s0 < min(c0 + kDefChunk, cells); s0 += kDefThreads) {
-    const int c = s0 + threadIdx.x;
-    const bool hit = c < cells && L[c] == c;
+  const int q0 = blockIdx.x * kDefChunk;
+  for (int s0 = q0; s0 < min(q0 + kDefChunk, cnt_l); s0 += kDefThreads) {
+    const int q = s0 + threadIdx.x;
+    const int c = q < cnt_l ? Lst[q] : 0;
+    const bool hit = q < cnt_l && L[c] == c;
     int total = 0;
     const int r = block_rank(hit, total, sh);
     if (hit && base_rank + r < kDefMax) L[c] = -(base_rank + r + 2);
@@ -181,16 +248,26 @@ __global__ void __launch_bounds__(kDefThreads)
   }
 }
 
-// region id of every cell (0 outside the kept regions)
-__global__ void k_region_ids(const int* __restrict__ lab, int cells, uint8_t* __restrict__ out) {
+__global__ void k_u8_fill(uint8_t* __restrict__ v, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    v[i] = 0;
+}
+
+// region id of every light cell (the other cells keep the 0 of the fill)
+__global__ void k_region_ids(const int* __restrict__ lab, int cells, const int* __restrict__ list,
+                             const int* __restrict__ lcount, int lcap, uint8_t* __restrict__ out) {
   const int b = blockIdx.y;
   const size_t base = (size_t)b * cells;
   const int* L = lab + base;
-  CELL_LOOP(cells) {
+  const int* Lst = list + (size_t)b * lcap;
+  const int cnt = lcount[b];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const int c = Lst[q];
     const int l = L[c];
     int id = 0;
     if (l <= -2) id = -l - 1;
-    else if (l >= 0) {
+    else {
       const int r = L[l];
       if (r <= -2) id = -r - 1;
     }
@@ -409,8 +486,8 @@ __global__ void k_defl_off(Defl D, const int* __restrict__ overflow, int B) {
 }
 
 // ---- per-solve and per-iteration pieces ---------------------------------------------
-// Sums of v over each region: per-block partials part[b][blk][j] (thread sums in LDS,
-// added in a fixed order)
+// Sums of v over each region (over the light cells): per-block partials part[b][blk][j]
+// (thread sums in LDS, added in a fixed order)
 template <typename T>
 __global__ void __launch_bounds__(kDefThreads)
     k_region_sums(const T* __restrict__ v, const uint8_t* __restrict__ lab, int cells, Defl D,
@@ -421,7 +498,10 @@ __global__ void __launch_bounds__(kDefThreads)
   __shared__ double acc[kDefMax][kDefThreads];
   for (int j = 0; j < k; ++j) acc[j][threadIdx.x] = 0.0;
   const size_t base = (size_t)b * cells;
-  for (int c = blockIdx.x * kDefThreads + threadIdx.x; c < cells; c += gridDim.x * kDefThreads) {
+  const int* Lst = D.light + (size_t)b * D.lcap;
+  const int cnt = D.lcount[b];
+  for (int q = blockIdx.x * kDefThreads + threadIdx.x; q < cnt; q += gridDim.x * kDefThreads) {
+    const int c = Lst[q];
     const int l = lab[base + c];
     if (l) acc[l - 1][threadIdx.x] += (double)v[base + c];
   }
@@ -465,12 +545,19 @@ __global__ void __launch_bounds__(kDefThreads)
   }
 }
 
-// Block sums of the regions over nblk partials, in block order
+// Totals of the regions over nblk per-block partials, by the block's first wave: lane l
+// adds the partials l, l + 64, ... and the wave sums them in a fixed order (deterministic;
+// the partials of a region load in parallel instead of one chain).  out[j] for j < k is
+// valid after the caller's barrier.
 __device__ inline void region_totals(const Defl& D, int b, int nblk, int k, double* out) {
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double s = 0.0;
-    for (int q = 0; q < nblk; ++q) s += D.part[((size_t)b * D.pcap + q) * kDefMax + j];
-    out[j] = s;
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const double* P = D.part + (size_t)b * D.pcap * kDefMax;
+  for (int j = 0; j < k; ++j) {
+    double t = 0.0;
+    for (int q = lane; q < nblk; q += 64) t += P[(size_t)q * kDefMax + j];
+    t = wave_sum(t);
+    if (lane == 0) out[j] = t;
   }
 }
 
@@ -544,16 +631,36 @@ __global__ void __launch_bounds__(kDefThreads)
   if (threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + off + blockIdx.x] = s;
 }
 
-// x += coef of its region on every cell of a region
+// x += coef of its region on every cell of a region (over the light cells).  proj: the
+// block first computes coef = -E^{-1} s itself from the band partials of x (the
+// projection x <- P^T x), else coef is read as it is.
 template <typename T>
-__global__ void k_region_add(T* __restrict__ x, const uint8_t* __restrict__ lab, int cells, Defl D,
-                             const int* __restrict__ active) {
+__global__ void __launch_bounds__(kDefThreads)
+    k_region_add(T* __restrict__ x, const uint8_t* __restrict__ lab, int cells, Defl D, int proj,
+                 const int* __restrict__ active) {
   const int b = blockIdx.y;
   const int k = D.k[b];
   if (k <= 0 || (active && !active[b])) return;
+  __shared__ double a[kDefMax];
+  __shared__ double s[kDefMax];
+  if (proj) {
+    region_totals(D, b, kDefBandBlocks, k, s);
+    __syncthreads();
+    if (threadIdx.x < k) {
+      const double* Ei = D.einv + ((size_t)b * kDefMax + threadIdx.x) * kDefMax;
+      double t = 0.0;
+      for (int j = 0; j < k; ++j) t += Ei[j] * s[j];
+      a[threadIdx.x] = -t;
+    }
+  } else if (threadIdx.x < k) {
+    a[threadIdx.x] = D.coef[(size_t)b * kDefMax + threadIdx.x];
+  }
+  __syncthreads();
   const size_t base = (size_t)b * cells;
-  const double* a = D.coef + (size_t)b * kDefMax;
-  CELL_LOOP(cells) {
+  const int* Lst = D.light + (size_t)b * D.lcap;
+  const int cnt = D.lcount[b];
+  for (int q = blockIdx.x * kDefThreads + threadIdx.x; q < cnt; q += gridDim.x * kDefThreads) {
+    const int c = Lst[q];
     const int l = lab[base + c];
     if (l) x[base + c] = (T)((double)x[base + c] + a[l - 1]);
   }

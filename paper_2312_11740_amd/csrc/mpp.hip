@@ -154,9 +154,11 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
   {
     Defl& D = op->defl;
     D.cap = (int)(op->cells / 8 + 64);
-    op->defl_rblk = (int)std::max<size_t>(1, std::min<size_t>(256, op->cells / 8192));
-    D.pcap = std::max(kDefBandBlocks, op->defl_rblk);
+    D.lcap = (int)(op->cells / 4 + 64);
+    D.pcap = std::max(kDefBandBlocks, kDefRegionBlocks);
     D.lab = cv.take<uint8_t>(C);
+    D.light = cv.take<int>((size_t)B * D.lcap);
+    D.lcount = cv.take<int>((size_t)B);
     D.bcell = cv.take<int>((size_t)B * D.cap);
     D.blab = cv.take<uint32_t>((size_t)B * D.cap);
     D.bval = cv.take<double>((size_t)B * D.cap * kDefPairs);
@@ -645,13 +647,13 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
   const dim3 gb((B + 255) / 256);
   hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, D.k, B, 0);
   hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, D.bcount, B, 0);
+  hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, D.lcount, B, 0);
   ck_launch();
   bool want = false;
   for (int b = 0; b < B; ++b) want = want || op->h_defl_light[b] >= 0;
   if (!want) return;
   const Level& L0 = op->lev[0];
   const int n = op->n, cells = (int)L0.cells;
-  const dim3 g = grid_of(L0, B);
   // the CG vectors are free between solves: labels and compaction counts live there
   int* lab = reinterpret_cast<int*>(op->q);
   int* counts = reinterpret_cast<int*>(op->z);
@@ -660,16 +662,39 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
     ck(hipMemcpyAsync(h.data(), d, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     ck(hipStreamSynchronize(s));
   };
+  auto to_dev = [&](int* d) {
+    ck(hipMemcpyAsync(d, h.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  };
   ck(hipMemcpyAsync(op->defl_light, op->h_defl_light.data(), sizeof(int) * B,
                     hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_ccl_init, g, dim3(kBlock), 0, s, L0.code, cells, op->defl_light, lab);
+  // the light cells in cell order (a problem with more than lcap of them: not deflated)
+  const int nblk = (cells + kDefChunk - 1) / kDefChunk;
+  hipLaunchKernelGGL(k_light_count, dim3(nblk, B), dim3(kDefThreads), 0, s, L0.code, cells,
+                     op->defl_light, counts, nblk);
+  hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk, op->defl_total);
+  hipLaunchKernelGGL(k_light_write, dim3(nblk, B), dim3(kDefThreads), 0, s, L0.code, cells,
+                     op->defl_light, counts, op->defl_total, nblk, D.light, D.lcap);
   ck_launch();
-  // propagation rounds, four per check, until a check finds no change (labels only
-  // decrease, so this ends; the cap is a guard)
-  for (int round = 0; round < 65536; round += 4) {
+  to_host(op->defl_total);
+  int lmax = 0;
+  for (int b = 0; b < B; ++b) {
+    if (op->h_defl_light[b] < 0 || h[b] > D.lcap) h[b] = 0;
+    lmax = std::max(lmax, h[b]);
+  }
+  if (lmax == 0) return;
+  to_dev(D.lcount);
+  const int lblk = std::min(4096, (lmax + 255) / 256);
+  op->defl_rblk = std::min(kDefRegionBlocks, (lmax + 255) / 256);
+  // propagation rounds over the light cells, eight per check, until a check finds no
+  // change (labels only decrease, so this ends; the cap is a guard)
+  hipLaunchKernelGGL(k_ccl_init, dim3(lblk, B), dim3(256), 0, s, D.light, D.lcount, D.lcap, cells,
+                     lab);
+  ck_launch();
+  for (int round = 0; round < 65536; round += 8) {
     hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, op->defl_flag, B, 0);
-    for (int t = 0; t < 4; ++t)
-      hipLaunchKernelGGL(k_ccl_round, g, dim3(kBlock), 0, s, n, lab, op->defl_flag);
+    for (int t = 0; t < 8; ++t)
+      hipLaunchKernelGGL(k_ccl_round, dim3(lblk, B), dim3(256), 0, s, n, L0.code, op->defl_light,
+                         D.light, D.lcount, D.lcap, lab, op->defl_flag);
     ck_launch();
     to_host(op->defl_flag);
     bool changed = false;
@@ -678,21 +703,27 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
   }
   // the first kDefMax components of each problem (by smallest cell index) become
   // regions 1..k
-  const int nblk = (cells + kDefChunk - 1) / kDefChunk;
-  hipLaunchKernelGGL(k_root_count, dim3(nblk, B), dim3(kDefThreads), 0, s, lab, cells, counts,
-                     nblk);
-  hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk, op->defl_total);
-  hipLaunchKernelGGL(k_root_mark, dim3(nblk, B), dim3(kDefThreads), 0, s, lab, cells, counts, nblk);
-  hipLaunchKernelGGL(k_region_ids, g, dim3(kBlock), 0, s, lab, cells, D.lab);
+  const int nblk_l = (lmax + kDefChunk - 1) / kDefChunk;
+  hipLaunchKernelGGL(k_root_count, dim3(nblk_l, B), dim3(kDefThreads), 0, s, lab, cells, D.light,
+                     D.lcount, D.lcap, counts, nblk_l);
+  hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk_l, op->defl_total);
+  hipLaunchKernelGGL(k_root_mark, dim3(nblk_l, B), dim3(kDefThreads), 0, s, lab, cells, D.light,
+                     D.lcount, D.lcap, counts, nblk_l);
+  hipLaunchKernelGGL(k_u8_fill, dim3(1024), dim3(256), 0, s, D.lab, op->cells * B);
+  hipLaunchKernelGGL(k_region_ids, dim3(lblk, B), dim3(256), 0, s, lab, cells, D.light, D.lcount,
+                     D.lcap, D.lab);
   ck_launch();
   to_host(op->defl_total);
   bool any = false;
+  std::vector<int> lc(B);
+  ck(hipMemcpyAsync(lc.data(), D.lcount, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+  ck(hipStreamSynchronize(s));
   for (int b = 0; b < B; ++b) {
-    h[b] = op->h_defl_light[b] < 0 ? 0 : std::min(h[b], kDefMax);
+    h[b] = lc[b] > 0 ? std::min(h[b], kDefMax) : 0;
     any = any || h[b] > 0;
   }
   if (!any) return;
-  ck(hipMemcpyAsync(D.k, h.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  to_dev(D.k);
   hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, op->defl_over, B, 0);
   // the band in cell order, E = Z^T A Z, its inverse; a problem that does not fit is
   // not deflated
@@ -705,7 +736,7 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
   ck_launch();
   to_host(op->defl_total);
   for (int b = 0; b < B; ++b) h[b] = std::min(h[b], D.cap);
-  ck(hipMemcpyAsync(D.bcount, h.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  to_dev(D.bcount);
   hipLaunchKernelGGL(k_defl_e, dim3(kDefMax, B), dim3(kDefThreads), 0, s, D, op->defl_e);
   hipLaunchKernelGGL(k_defl_inverse, dim3(B), dim3(kDefMax * kDefMax), 0, s, op->defl_e, D,
                      op->defl_over);
@@ -745,9 +776,8 @@ void defl_project(mpp_op_s* op, const Ctl& ctl, T* z, hipStream_t s) {
   timed(op, K_DEFL, 0.0, s, [&] {
     hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, z, cells, D,
                        ctl.active);
-    hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 2, ctl.active);
-    hipLaunchKernelGGL(k_region_add<T>, grid_of(op->lev[0], B), dim3(kBlock), 0, s, z, D.lab, cells,
-                       D, ctl.active);
+    hipLaunchKernelGGL(k_region_add<T>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s, z, D.lab,
+                       cells, D, 1, ctl.active);
   });
   ck_launch();
 }
@@ -760,8 +790,8 @@ void defl_end(mpp_op_s* op, T* x, hipStream_t s) {
   hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, x, cells, D,
                      (const int*)nullptr);
   hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 1, (const int*)nullptr);
-  hipLaunchKernelGGL(k_region_add<T>, grid_of(op->lev[0], B), dim3(kBlock), 0, s, x, D.lab, cells,
-                     D, (const int*)nullptr);
+  hipLaunchKernelGGL(k_region_add<T>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s, x, D.lab,
+                     cells, D, 0, (const int*)nullptr);
   ck_launch();
 }
 
@@ -1624,8 +1654,9 @@ int mpp_net_features(mpp_net net, mpp_op op, const double* f, const double* p, u
 }
 
 int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_t sweeps,
-                      int32_t* fell_back, void* stream) {
-  if (!op || !net || !f || !p || f == p || sweeps < 0 || sweeps > 8 || !net_fits(op, net))
+                      int32_t judge, int32_t* fell_back, void* stream) {
+  if (!op || !net || !f || !p || f == p || sweeps < 0 || sweeps > 8 || !net_fits(op, net) ||
+      (judge != MPP_JUDGE_PLAIN && judge != MPP_JUDGE_DEFLATED))
     return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int B = op->batch, r = op->n / net->n;
@@ -1633,6 +1664,9 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
   try {
     use_shift(op, 0.0, s);
     ensure_tuned<double>(op, s);
+    // the deflated judge needs the regions (their build uses the scratch vectors below)
+    const bool dj = judge == MPP_JUDGE_DEFLATED;
+    if (dj && !op->defl_ready) build_deflation(op, s);
     net_inputs(op, net, f, nullptr, net->x4, nullptr, s);
     const int st = mppnet::forward(net, net->x4, net->y, B, s);
     if (st != MPP_OK) return st;
@@ -1672,10 +1706,41 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
     }
     if (sweeps & 1)
       ck(hipMemcpyAsync(p, op->q, sizeof(double) * work, hipMemcpyDeviceToDevice, s));
-    // fallback check on ||b - A p|| against ||b||
-    finish_sums(op, ctl, epi(E_START),
-                launch_residual<double>(op, F, op->b, p, op->r, ctl, 0, s), s);
-    ck_launch();
+    if (!dj) {
+      // fallback check on ||b - A p|| against ||b||
+      finish_sums(op, ctl, epi(E_START),
+                  launch_residual<double>(op, F, op->b, p, op->r, ctl, 0, s), s);
+      ck_launch();
+    } else {
+      // the deflated solve starts from P (b - A p) with the guess and from P b without it:
+      // ||P (b - A p)||^2 into S_RR, ||P b||^2 into S_BB (norms before the band correction
+      // plus its change; problems without regions compare the plain norms)
+      const Defl& D = op->defl;
+      const int cells = (int)L0.cells;
+      EpiArgs es = epi(E_STORE_MEAN);
+      es.inv_cells = 1.0;
+      const int parts = launch_residual<double>(op, F, op->b, p, op->r, ctl, 0, s);
+      hipLaunchKernelGGL(k_region_sums<double>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s,
+                         (const double*)op->b, D.lab, cells, D, (const int*)nullptr);
+      hipLaunchKernelGGL(k_defl_zb, dim3(B), dim3(64), 0, s, D, op->defl_rblk, (const int*)nullptr);
+      hipLaunchKernelGGL(k_band_sums<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
+                         (const double*)p, cells, D, (const int*)nullptr);
+      hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 1, (const int*)nullptr);
+      hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
+                         op->r, cells, D, ctl, -1, parts, (const int*)nullptr);
+      ck_launch();
+      es.slot = S_RR;
+      finish_sums(op, ctl, es, parts + kDefBandBlocks, s);
+      hipLaunchKernelGGL(k_dot<double>, g, dim3(kBlock), 0, s, (const double*)op->b,
+                         (const double*)op->b, cells, ctl, es, (const int*)nullptr);
+      ck(hipMemcpyAsync(op->z, op->b, sizeof(double) * work, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 0, (const int*)nullptr);
+      hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
+                         op->z, cells, D, ctl, -1, L0.bpp, (const int*)nullptr);
+      ck_launch();
+      es.slot = S_BB;
+      finish_sums(op, ctl, es, L0.bpp + kDefBandBlocks, s);
+    }
     ck(hipMemcpyAsync(op->h_scal, ctl.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
     ck(hipStreamSynchronize(s));
     for (int q = 0; q < B; ++q) {

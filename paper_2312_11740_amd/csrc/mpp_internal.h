@@ -80,6 +80,7 @@ struct Level {
 constexpr int kDefMax = 32;          // regions per problem
 constexpr int kDefPairs = 4;         // (region, value) pairs per band cell: own + 3 others
 constexpr int kDefBandBlocks = 32;   // blocks over a problem's band list
+constexpr int kDefRegionBlocks = 256;  // at most this many blocks over a problem's light cells
 
 // Per-problem deflation state in device memory.
 struct Defl {
@@ -93,7 +94,10 @@ struct Defl {
   double* zb;        // [B][kDefMax] Z^T b of the right-hand side of the current CG
   double* coef;      // [B][kDefMax] a = E^{-1} s (per iteration) / the start and end terms
   double* part;      // [B][pcap][kDefMax] per-block sums over regions
+  int* light;        // [B][lcap] cells of the lighter phase, in cell order
+  int* lcount;       // [B] their number (0: the problem is not deflated)
   int cap;           // band cells a problem can hold
+  int lcap;          // light-phase cells a problem can hold
   int pcap;          // blocks of part per problem
 };
 

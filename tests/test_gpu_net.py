@@ -469,3 +469,32 @@ def test_weight_gradient_of_a_batch_above_512():
     # the per-sample sums are exact; adding 600 of them in FP32 rounds, by at most
     # (batch - 1) units of 2^-24 relative to the total
     assert np.max(np.abs(g - batch * g1)) <= batch * 2.0 ** -24 * np.max(np.abs(batch * g1))
+
+
+def test_deflated_judge_keeps_the_guess_or_zero():
+    """MPP_JUDGE_DEFLATED computes the same guess as the plain judge and only decides
+    differently whether to keep it: each problem gets either that guess or zero; a
+    deflated solve from the result meets the oracle."""
+    nf, nn = 64, 16
+    seeds = [41, 42, 43]
+    phi, f, rn, rp, sg = problem_batch(nf, seeds)
+    op = M.Operator(to_dev(phi), rn, rp, sg)
+    net = make_net(nn, len(seeds), params_case(3))
+    fd = to_dev(f)
+    gp, fp = op.learned_guess(net, fd, sweeps=2, judge="plain")
+    gd, fdj = op.learned_guess(net, fd, sweeps=2, judge="deflated")
+    gp, gd = to_host(gp), to_host(gd)
+    print("fallbacks plain %s deflated %s" % (fp, fdj), flush=True)
+    for b in range(len(seeds)):
+        if fdj[b]:
+            assert np.all(gd[b] == 0.0)
+        else:
+            assert fp[b] == 0 and np.array_equal(gd[b], gp[b])
+    p, infos = op.solve(fd, to_dev(gd), rtol=1e-10, mode="mixed")
+    ph = to_host(p)
+    for b in range(len(seeds)):
+        d = O.pipeline(phi[b], f[b], rn[b], rp[b], sg[b])
+        assert infos[b].status == M.OK
+        assert O.rel_residual(d["faces"], d["b"], ph[b]) <= 1.05e-10
+        po, _ = O.solve_mg_pcg(d["faces"], d["b"], tol=1e-13)
+        assert rel2(ph[b], po) <= 1e-8
