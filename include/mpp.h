@@ -177,6 +177,13 @@ int mpp_vcycle(mpp_op op, const double *r, double *z, int nu, void *stream);
 int mpp_operator_fields(mpp_op op, double *beta_x, double *beta_y, double *beta_z,
                         double *kappa, double *jterm, void *stream);
 
+/* The deflation data of the operator (built now if a solve has not built it yet): the
+ * region of every cell (labels: device [batch][n^3] bytes, 0 outside every region, or
+ * NULL), the number of regions per problem (k: host [batch]; 0 when the problem is not
+ * deflated) and E = Z^T A Z (host [batch][32][32], the first k rows and columns used, or
+ * NULL).  Synchronous. */
+int mpp_deflation_info(mpp_op op, uint8_t *labels, int32_t *k, double *E, void *stream);
+
 /* Number of multigrid levels and the size of each (host array of up to 16). */
 int mpp_levels(mpp_op op, int32_t *nlevels, int32_t *sizes);
 

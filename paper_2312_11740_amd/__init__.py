@@ -35,7 +35,7 @@ EXPORTS = (
     "mpp_blocks_gather", "mpp_blocks_fill_guards", "mpp_blocks_apply",
     "mpp_amr_workspace_bytes", "mpp_amr_create", "mpp_amr_destroy", "mpp_amr_level1_blocks",
     "mpp_amr_fill_guards", "mpp_amr_apply", "mpp_amr_solve_work_bytes", "mpp_amr_solve",
-    "mpp_amr_coarse_operator", "mpp_net_train", "mpp_ls_reinit_noalloc",
+    "mpp_amr_coarse_operator", "mpp_net_train", "mpp_ls_reinit_noalloc", "mpp_deflation_info",
 )
 FLAG_NO_GRAPHS = 1
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     L.mpp_vcycle.argtypes = [P, P, P, i32, P]
     L.mpp_operator_fields.argtypes = [P, P, P, P, P, P, P]
     L.mpp_levels.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.mpp_deflation_info.argtypes = [P, P, P, P, P]
     L.mpp_destroy_operator.argtypes = [P]
     L.mpp_destroy_operator.restype = None
     L.mpp_profile_start.argtypes = [P]
@@ -316,6 +317,21 @@ class Operator:
         if st != OK:
             raise MppError(st, "mpp_operator_fields")
         return out
+
+    def deflation_info(self):
+        """(labels uint8 CUDA tensor of the operator's shape, k per problem, E as a float64
+        numpy array [batch][32][32]) of the deflation regions."""
+        import numpy as np
+        torch = _torch()
+        lab = torch.empty(self.shape, dtype=torch.uint8, device=self.device)
+        k = (ctypes.c_int32 * self.batch)()
+        E = np.empty((self.batch, 32, 32))
+        st = load_library().mpp_deflation_info(self._h, ctypes.c_void_p(lab.data_ptr()), k,
+                                               E.ctypes.data_as(ctypes.c_void_p),
+                                               _stream_handle(self.device))
+        if st != OK:
+            raise MppError(st, "mpp_deflation_info")
+        return lab, [int(v) for v in k], E
 
     def levels(self):
         nl = ctypes.c_int32(0)

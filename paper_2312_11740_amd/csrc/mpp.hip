@@ -1440,6 +1440,36 @@ void mpp_destroy_operator(mpp_op op) {
   free_op(op);
 }
 
+int mpp_deflation_info(mpp_op op, uint8_t* labels, int32_t* k, double* E, void* stream) {
+  if (!op || !k) return MPP_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  try {
+    if (!op->defl_ready) build_deflation(op, s);
+    const int B = op->batch;
+    for (int b = 0; b < B; ++b) k[b] = op->h_defl_k[b];
+    if (labels) {
+      if (op->defl_any) {
+        ck(hipMemcpyAsync(labels, op->defl.lab, op->cells * B, hipMemcpyDeviceToDevice, s));
+      } else {
+        hipLaunchKernelGGL(k_u8_fill, dim3(1024), dim3(256), 0, s, labels, op->cells * B);
+        ck_launch();
+      }
+    }
+    if (E) {
+      const size_t bytes = sizeof(double) * B * kDefMax * kDefMax;
+      if (op->defl_any) {
+        ck(hipMemcpyAsync(E, op->defl_e, bytes, hipMemcpyDeviceToHost, s));
+      } else {
+        std::memset(E, 0, bytes);
+      }
+    }
+    ck(hipStreamSynchronize(s));
+  } catch (HipError& e) {
+    return status_of(e.e);
+  }
+  return MPP_OK;
+}
+
 int mpp_levels(mpp_op op, int32_t* nlevels, int32_t* sizes) {
   if (!op || !nlevels) return MPP_EINVAL;
   *nlevels = op->nlev;
