@@ -174,6 +174,7 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     op->defl_total = cv.take<int>((size_t)B);
     op->defl_over = cv.take<int>((size_t)B);
   }
+  op->tail_mask = cv.take<int>((size_t)B);
   op->counters = cv.take<unsigned>((size_t)B);
   for (Ctl* c : {&op->outer, &op->inner}) {
     c->scal = cv.take<double>((size_t)B * kSlots);
@@ -405,7 +406,7 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
   Level& Lc = op->lev[l + 1];
   const Faces<T> F = faces_of<T>(op, l);
   T* tmp = l == 0 ? level0_tmp<T>(op) : lvl_t<T>(L);
-  const int kz = op->kz[sizeof(T) == 4][l];
+  const int kz = op->tail ? op->kz_tail[sizeof(T) == 4][l] : op->kz[sizeof(T) == 4][l];
   const Ctl ctl = dctl ? *dctl : op->outer;
   const bool fine = l == 0;
   int nparts = 0;
@@ -492,12 +493,13 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
 // size)
 // ------------------------------------------------------------------------------
 struct TuneKey {
-  int n, batch, tsize, nl;
+  int n, batch, tsize, nl, tail;
   bool operator<(const TuneKey& o) const {
     if (n != o.n) return n < o.n;
     if (batch != o.batch) return batch < o.batch;
     if (tsize != o.tsize) return tsize < o.tsize;
-    return nl < o.nl;
+    if (nl != o.nl) return nl < o.nl;
+    return tail < o.tail;
   }
 };
 std::mutex g_tune_mu;
@@ -509,7 +511,10 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
   if (op->tuned[w]) return;
   op->tuned[w] = true;
   const char* env = std::getenv("MPP_AUTOTUNE");
-  if (env && env[0] == '0') return;
+  if (env && env[0] == '0') {
+    for (int l = 0; l < op->nlev; ++l) op->kz_tail[w][l] = op->kz[w][l];
+    return;
+  }
   // MPP_SWEEP=march, =tile or =pair[K] fixes the sweep kernel of every level (no timing;
   // pair: the pair kernel with K-plane chunks (default 16) on an even finest level,
   // z-marching below)
@@ -521,21 +526,31 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
       const int kz = std::atoi(force + 4);
       op->kz[w][0] = -(kz >= 2 && kz <= 2 * kRbKZ ? kz : 16);
     }
+    for (int l = 0; l < op->nlev; ++l) op->kz_tail[w][l] = op->kz[w][l];
     return;
   }
   const int B = op->batch;
+  // the tail schedule is timed with problem 0 alone active
+  if (B > 1) {
+    hipLaunchKernelGGL(k_int_fill, dim3((B + 255) / 256), dim3(256), 0, s, op->tail_mask, B, 0);
+    hipLaunchKernelGGL(k_int_fill, dim3(1), dim3(1), 0, s, op->tail_mask, 1, 1);
+    ck_launch();
+  }
   hipEvent_t e0, e1;
   ck(hipEventCreate(&e0));
   ck(hipEventCreate(&e1));
-  for (int l = 0; l + 1 < op->nlev; ++l) {
+  for (int l = 0; l + 1 < op->nlev; ++l)
+   for (int tail = 0; tail < (B > 1 ? 2 : 1); ++tail) {
     Level& L = op->lev[l];
     if (L.cells <= (size_t)kSmallCells) break;
-    const TuneKey key{op->n, B, (int)sizeof(T), L.n};
+    int* slot = tail ? &op->kz_tail[w][l] : &op->kz[w][l];
+    const int* mask = tail ? op->tail_mask : nullptr;
+    const TuneKey key{op->n, B, (int)sizeof(T), L.n, tail};
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune.find(key);
       if (it != g_tune.end()) {
-        op->kz[w][l] = it->second;
+        *slot = it->second;
         continue;
       }
     }
@@ -564,10 +579,10 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
       auto launch = [&] {
         if (l == 0)
           launch_rb<T, 0, true>(op, l, kz, F, rhs, in, (const T*)nullptr, out, 0, op->outer, 0,
-                                (const int*)nullptr, s);
+                                mask, s);
         else
           launch_rb<T, 0, false>(op, l, kz, F, rhs, in, (const T*)nullptr, out, 0, op->outer, 0,
-                                 (const int*)nullptr, s);
+                                 mask, s);
       };
       launch();
       ck(hipEventRecord(e0, s));
@@ -582,11 +597,13 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
         best_kz = kz;
       }
     }
-    op->kz[w][l] = best_kz;
+    *slot = best_kz;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune.emplace(key, best_kz);   // the first tuning of a shape wins
-    op->kz[w][l] = g_tune[key];
+    *slot = g_tune[key];
   }
+  if (B == 1)
+    for (int l = 0; l < op->nlev; ++l) op->kz_tail[w][l] = op->kz[w][l];
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -893,12 +910,24 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
   finish_sums(op, ctl, start_, parts, s);
   // the iterate of a deflated CG takes its component in the regions at the end
   auto done_ = [&] {
+    op->tail = false;
     if (defl) defl_end<T>(op, x, s);
   };
   if (!any_active(op, ctl, s)) {
     done_();
     return;
   }
+  // few live problems of a batch: the tail schedule (more, smaller tiles per problem)
+  // (MPP_TAIL=0 keeps the full-batch schedule throughout)
+  const int B = op->batch;
+  const char* tail_env = std::getenv("MPP_TAIL");
+  const bool tail_ok = B > 1 && !(tail_env && tail_env[0] == '0');
+  auto set_tail = [&] {
+    int live = 0;
+    for (int b = 0; b < B; ++b) live += op->h_active[b] != 0;
+    op->tail = tail_ok && live <= std::max(1, B / 8);
+  };
+  set_tail();
   EpiArgs erz = epi(E_RZ);
   erz.first = 1;
   vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
@@ -910,9 +939,9 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
   // iterations in blocks of check_every; the kernels themselves stop working on a
   // problem once it has converged, so a block may overrun the last useful iteration
   const bool graphs = op->use_graphs && !op->prof.on;
-  const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter, defl ? 1 : 0,
-                     {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
   for (int done = 0; done <= ctl.max_iter; done += check_every) {
+    const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter, defl ? 1 : 0,
+                       op->tail ? 1 : 0, {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
     if (graphs)
       run_graph(op, key, s, [&](hipStream_t cs) {
         pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, cs);
@@ -920,6 +949,7 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     else
       pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, s);
     if (!any_active(op, ctl, s)) break;
+    set_tail();
   }
   done_();
 }
@@ -1064,7 +1094,7 @@ void heat_pcg(mpp_op_s* op, Ctl& ctl, double* x, int check_every, hipStream_t s)
   ck_launch();
   // nu = 0 marks these graphs apart from the pressure solve's (nu >= 1)
   const bool graphs = op->use_graphs && !op->prof.on;
-  const GraphKey key{8, 0, 0, check_every, ctl.max_iter, 0,
+  const GraphKey key{8, 0, 0, check_every, ctl.max_iter, 0, 0,
                      {(const void*)ctl.scal, x, op->r, op->z, op->p, op->q}};
   for (int done = 0; done < ctl.max_iter; done += check_every) {
     if (graphs)

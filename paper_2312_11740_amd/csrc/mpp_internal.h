@@ -142,12 +142,12 @@ struct Prof {
 // A captured block of CG iterations and what it was captured for.
 struct GraphKey {
   int tsize, nu, nu_c, iters, max_iter;
-  int defl;
+  int defl, tail;
   const void* ptr[6];
   double shift = 0.0;   // the operator's diagonal shift (a kernel argument in the graph)
   bool operator==(const GraphKey& o) const {
     if (tsize != o.tsize || nu != o.nu || nu_c != o.nu_c || iters != o.iters ||
-        max_iter != o.max_iter || defl != o.defl || shift != o.shift)
+        max_iter != o.max_iter || defl != o.defl || tail != o.tail || shift != o.shift)
       return false;
     for (int q = 0; q < 6; ++q)
       if (ptr[q] != o.ptr[q]) return false;
@@ -170,6 +170,11 @@ struct mpp_op_s {
   hipStream_t cap_stream = nullptr;
   double* x = nullptr;              // FP64 iterate (the caller's p is copied in and out)
   int kz[2][mpp::kMaxLevels] = {};  // tuned z-chunk of the fused sweeps [fp32?][level], 0 = default
+  // the sweep kernels tuned for a batch of which one problem is left (the tail of a
+  // batched solve: few live problems want more, smaller tiles each)
+  int kz_tail[2][mpp::kMaxLevels] = {};
+  bool tail = false;                // the CG block being run uses kz_tail
+  int* tail_mask = nullptr;         // [B] device: problem 0 active (tuning the tail)
   bool tuned[2] = {false, false};
   int nu_c = 2;                     // sweeps per level below the finest
   int n = 0, batch = 0, nlev = 0;

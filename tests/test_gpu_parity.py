@@ -361,6 +361,33 @@ def test_batched_64_problems_64cubed(mode):
     assert rel2(ph[5], to_host(p1)) <= 1e-8
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_batched_tail_schedule_agrees(mode, monkeypatch):
+    """Once at most an eighth of a batch is still iterating, the sweeps switch to the
+    tiles tuned for one live problem: the same half sweeps, so the answers match the
+    full-batch schedule to rounding and every problem meets the oracle."""
+    n, B = 48, 16
+    # two hard problems (ratio 1000) among fourteen easy ones (ratio 2)
+    cases = [bubbles_case(n, 300 + s, ratio=1000.0 if s in (3, 11) else 2.0)
+             for s in range(B)]
+    phi = to_dev(np.stack([c[0] for c in cases]))
+    f = to_dev(np.stack([c[1] for c in cases]))
+    out = {}
+    for tail in ("0", "1"):
+        monkeypatch.setenv("MPP_TAIL", tail)
+        op = M.Operator(phi, [c[2] for c in cases], [c[3] for c in cases],
+                        [c[4] for c in cases])
+        p, infos = op.solve(f, rtol=1e-10, mode=mode)
+        out[tail] = (to_host(p), infos)
+        op.close()
+    its = [i.iters for i in out["1"][1]]
+    assert sorted(its)[B - B // 8 - 1] + 4 < max(its)    # the tail was reached
+    for b in range(B):
+        assert abs(out["0"][1][b].iters - its[b]) <= 1, b
+        assert rel2(out["1"][0][b], out["0"][0][b]) <= 1e-9, b
+        check_solution(*cases[b], out["1"][0][b], out["1"][1][b])
+
+
 def test_autotuned_chunks_do_not_change_the_answer():
     # the tuner only picks tile shapes: solutions agree with the default shapes
     import os
