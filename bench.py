@@ -817,7 +817,8 @@ def main():
         net.load(M.TRAINED_WEIGHTS)
     # untimed burn-in: the first solves after start-up run at lower clocks, which would
     # otherwise bias whichever method is timed first
-    run_sequence(M, torch, ws, phis, fs, prm, "fp64", args.nu, min(K, 3), 1, None, zero=True)
+    run_sequence(M, torch, ws, phis, fs, prm, "fp64", args.nu, min(len(phis), 3), 0, None,
+                 zero=True)
     results = {}
     for meth in args.methods.split(","):
         mode = MODES[meth]
