@@ -344,7 +344,9 @@ def projection256(M, G, torch, args):
         ev[0].record()
         op.divergence(us[t], dt, out=f)
         ev[1].record()
-        p, info = op.solve(f, p=p, rtol=1e-10, mode="mixed", nu=args.nu)
+        # deflated mixed solve from zero: with the bubbles deflated, the previous step's
+        # pressure is a worse start than zero
+        p, info = op.solve(f, p=p, zero=True, rtol=1e-10, mode="mixed", nu=args.nu)
         ev[2].record()
         op.project(phis[t], p, dt, us[t])
         ev[3].record()
@@ -420,7 +422,9 @@ def flow256(M, G, torch, args):
         u[2][1:, :, :] -= dt * g
         op.update(phi, **prm)
         f = op.divergence(u, dt)
-        p, info = op.solve(f, p=p, rtol=1e-10, mode="mixed", nu=args.nu)
+        # deflated mixed solve from zero: with the bubbles deflated, the previous step's
+        # pressure is a worse start than zero
+        p, info = op.solve(f, p=p, zero=True, rtol=1e-10, mode="mixed", nu=args.nu)
         op.project(phi, p, dt, u)
         ev[0].record()
         new = M.ls_advect(phi, u, dt)

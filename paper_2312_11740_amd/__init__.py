@@ -342,9 +342,10 @@ class Operator:
         return [sizes[i] for i in range(nl.value)]
 
     def solve(self, f, p=None, rtol=1e-10, mode="fp64", max_iter=500, nu=2, check_every=2,
-              inner_rtol=1e-5, raise_on_error=True, nu_coarse=0, deflate=True):
-        """Returns (p, [Info per problem]).  p: optional initial guess (overwritten).
-        deflate: deflate the lighter phase's regions (mpp_solve_opts.deflate)."""
+              inner_rtol=1e-5, raise_on_error=True, nu_coarse=0, deflate=True, zero=False):
+        """Returns (p, [Info per problem]).  p: optional initial guess (overwritten); with
+        zero=True p is only the output array and the solve starts from zero.  deflate:
+        deflate the lighter phase's regions (mpp_solve_opts.deflate)."""
         _check_field(f, self.shape, "f")
         opts = SolveOpts()
         load_library().mpp_default_opts(ctypes.byref(opts))
@@ -358,7 +359,7 @@ class Operator:
             opts.guess = GUESS_ZERO
         else:
             _check_field(p, self.shape, "p")
-            opts.guess = GUESS_GIVEN
+            opts.guess = GUESS_ZERO if zero else GUESS_GIVEN
         infos = (SolveInfo * self.batch)()
         st = load_library().mpp_solve(self._h, ctypes.c_void_p(f.data_ptr()),
                                       ctypes.c_void_p(p.data_ptr()), ctypes.byref(opts), infos,
