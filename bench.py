@@ -344,9 +344,10 @@ def projection256(M, G, torch, args):
         ev[0].record()
         op.divergence(us[t], dt, out=f)
         ev[1].record()
-        # deflated mixed solve from zero: with the bubbles deflated, the previous step's
-        # pressure is a worse start than zero
-        p, info = op.solve(f, p=p, zero=True, rtol=1e-10, mode="mixed", nu=args.nu)
+        # mixed solve warm-started from the previous step's pressure, without deflation:
+        # div(u*)/dt carries no jump term for deflation to remove, and the pressure moves
+        # little between steps (measured faster than a deflated solve from zero or warm)
+        p, info = op.solve(f, p=p, rtol=1e-10, mode="mixed", nu=args.nu, deflate=False)
         ev[2].record()
         op.project(phis[t], p, dt, us[t])
         ev[3].record()
@@ -422,9 +423,10 @@ def flow256(M, G, torch, args):
         u[2][1:, :, :] -= dt * g
         op.update(phi, **prm)
         f = op.divergence(u, dt)
-        # deflated mixed solve from zero: with the bubbles deflated, the previous step's
-        # pressure is a worse start than zero
-        p, info = op.solve(f, p=p, zero=True, rtol=1e-10, mode="mixed", nu=args.nu)
+        # mixed solve warm-started from the previous step's pressure, without deflation:
+        # div(u*)/dt carries no jump term for deflation to remove, and the pressure moves
+        # little between steps (measured faster than a deflated solve from zero or warm)
+        p, info = op.solve(f, p=p, rtol=1e-10, mode="mixed", nu=args.nu, deflate=False)
         op.project(phi, p, dt, u)
         ev[0].record()
         new = M.ls_advect(phi, u, dt)
