@@ -1225,9 +1225,22 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
   istart.outer_rtol = o.rtol;
   bool settled = false;
   for (int outer = 0; outer < 40; ++outer) {
-    finish_sums(op, oc, start,
-                launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
+    int parts = launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s);
     ck_launch();
+    if (op->defl_use) {
+      // the regions' share of the correction in FP64: x += Z E^{-1} Z^T (b - A x) and
+      // r -= A Z E^{-1} Z^T r, so that the FP32 inner solve never carries the large
+      // per-region constants of the solution (in FP32 they would limit the true
+      // residual reduction of a refinement step to about 1e-4)
+      timed(op, K_DEFL, 0.0, s, [&] {
+        defl_start<double>(op, oc, op->b, p, op->r, 0, parts, s);
+        hipLaunchKernelGGL(k_region_add<double>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s,
+                           p, op->defl.lab, cells, op->defl, 0, (const int*)nullptr);
+      });
+      ck_launch();
+      parts += kDefBandBlocks;
+    }
+    finish_sums(op, oc, start, parts, s);
     if (!any_active(op, oc, s)) {
       settled = true;
       break;
