@@ -60,10 +60,14 @@ __global__ void k_ccl_init(const int* __restrict__ list, const int* __restrict__
 // light face neighbours, then up to four steps along the labels, and the old label's cell
 // takes the new one too (labels only decrease and always name a cell of the same
 // component).
+// prev: the previous round's changed flags (nullptr for the first round of a batch); a
+// round after one that changed nothing has nothing to do.
 __global__ void k_ccl_round(int n, const uint8_t* __restrict__ code, const int* __restrict__ light,
                             const int* __restrict__ list, const int* __restrict__ lcount, int lcap,
-                            int* __restrict__ lab, int* __restrict__ changed) {
+                            int* __restrict__ lab, const int* __restrict__ prev,
+                            int* __restrict__ changed) {
   const int b = blockIdx.y;
+  if (prev && prev[b] == 0) return;
   const int cells = n * n * n;
   const size_t base = (size_t)b * cells;
   const int ls = light[b];
@@ -101,6 +105,25 @@ __global__ void k_ccl_round(int n, const uint8_t* __restrict__ code, const int* 
 __global__ void k_int_fill(int* __restrict__ v, int count, int value) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) v[i] = value;
+}
+
+// Counts that follow from a compaction, on the device: the light cells of a problem
+// (none if it has no lighter phase or more than lcap of them), its regions (the first
+// kDefMax components; none without light cells) and its band cells (at most cap).
+__global__ void k_light_done(int* __restrict__ lcount, const int* __restrict__ total,
+                             const int* __restrict__ light, int lcap, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) lcount[b] = (light[b] >= 0 && total[b] <= lcap) ? total[b] : 0;
+}
+__global__ void k_regions_done(int* __restrict__ k, const int* __restrict__ total,
+                               const int* __restrict__ lcount, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) k[b] = lcount[b] > 0 ? min(total[b], kDefMax) : 0;
+}
+__global__ void k_band_done(int* __restrict__ bcount, const int* __restrict__ total, int cap,
+                            int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) bcount[b] = min(total[b], cap);
 }
 
 // ---- deterministic compaction over the cells of a problem ---------------------------

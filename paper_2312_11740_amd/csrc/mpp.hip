@@ -170,7 +170,7 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     D.part = cv.take<double>((size_t)B * D.pcap * kDefMax);
     op->defl_e = cv.take<double>((size_t)B * kDefMax * kDefMax);
     op->defl_light = cv.take<int>((size_t)B);
-    op->defl_flag = cv.take<int>((size_t)B);
+    op->defl_flag = cv.take<int>((size_t)kCclBatch * B);
     op->defl_total = cv.take<int>((size_t)B);
     op->defl_over = cv.take<int>((size_t)B);
   }
@@ -679,11 +679,12 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
     ck(hipMemcpyAsync(h.data(), d, sizeof(int) * B, hipMemcpyDeviceToHost, s));
     ck(hipStreamSynchronize(s));
   };
-  auto to_dev = [&](int* d) {
-    ck(hipMemcpyAsync(d, h.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
-  };
   ck(hipMemcpyAsync(op->defl_light, op->h_defl_light.data(), sizeof(int) * B,
                     hipMemcpyHostToDevice, s));
+  // Counts stay on the device: kernels over the light list read its length there and
+  // are launched for the largest list the workspace holds (grid-stride loops, or chunks
+  // past the end that do nothing), so the host waits only for the labelling rounds and
+  // once at the end.
   // the light cells in cell order (a problem with more than lcap of them: not deflated)
   const int nblk = (cells + kDefChunk - 1) / kDefChunk;
   hipLaunchKernelGGL(k_light_count, dim3(nblk, B), dim3(kDefThreads), 0, s, L0.code, cells,
@@ -691,36 +692,34 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk, op->defl_total);
   hipLaunchKernelGGL(k_light_write, dim3(nblk, B), dim3(kDefThreads), 0, s, L0.code, cells,
                      op->defl_light, counts, op->defl_total, nblk, D.light, D.lcap);
+  hipLaunchKernelGGL(k_light_done, gb, dim3(256), 0, s, D.lcount, op->defl_total, op->defl_light,
+                     D.lcap, B);
   ck_launch();
-  to_host(op->defl_total);
-  int lmax = 0;
-  for (int b = 0; b < B; ++b) {
-    if (op->h_defl_light[b] < 0 || h[b] > D.lcap) h[b] = 0;
-    lmax = std::max(lmax, h[b]);
-  }
-  if (lmax == 0) return;
-  to_dev(D.lcount);
-  const int lblk = std::min(4096, (lmax + 255) / 256);
-  op->defl_rblk = std::min(kDefRegionBlocks, (lmax + 255) / 256);
-  // propagation rounds over the light cells, eight per check, until a check finds no
-  // change (labels only decrease, so this ends; the cap is a guard)
+  const int lblk = std::min(512, (D.lcap + 255) / 256);
+  op->defl_rblk = std::min(kDefRegionBlocks, (D.lcap + 255) / 256);
+  // propagation rounds over the light cells in batches of kCclBatch, each round with its
+  // own changed flag, until the last round of a batch changed nothing (labels only
+  // decrease, so this ends; the cap is a guard)
   hipLaunchKernelGGL(k_ccl_init, dim3(lblk, B), dim3(256), 0, s, D.light, D.lcount, D.lcap, cells,
                      lab);
   ck_launch();
-  for (int round = 0; round < 65536; round += 8) {
-    hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, op->defl_flag, B, 0);
-    for (int t = 0; t < 8; ++t)
+  const dim3 gf((kCclBatch * B + 255) / 256);
+  for (int round = 0; round < 65536; round += kCclBatch) {
+    hipLaunchKernelGGL(k_int_fill, gf, dim3(256), 0, s, op->defl_flag, kCclBatch * B, 0);
+    for (int t = 0; t < kCclBatch; ++t)
       hipLaunchKernelGGL(k_ccl_round, dim3(lblk, B), dim3(256), 0, s, n, L0.code, op->defl_light,
-                         D.light, D.lcount, D.lcap, lab, op->defl_flag);
+                         D.light, D.lcount, D.lcap, lab,
+                         t ? (const int*)op->defl_flag + (size_t)(t - 1) * B : (const int*)nullptr,
+                         op->defl_flag + (size_t)t * B);
     ck_launch();
-    to_host(op->defl_flag);
+    to_host(op->defl_flag + (size_t)(kCclBatch - 1) * B);
     bool changed = false;
     for (int b = 0; b < B; ++b) changed = changed || h[b] != 0;
     if (!changed) break;
   }
   // the first kDefMax components of each problem (by smallest cell index) become
   // regions 1..k
-  const int nblk_l = (lmax + kDefChunk - 1) / kDefChunk;
+  const int nblk_l = (D.lcap + kDefChunk - 1) / kDefChunk;
   hipLaunchKernelGGL(k_root_count, dim3(nblk_l, B), dim3(kDefThreads), 0, s, lab, cells, D.light,
                      D.lcount, D.lcap, counts, nblk_l);
   hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk_l, op->defl_total);
@@ -729,19 +728,9 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
   hipLaunchKernelGGL(k_u8_fill, dim3(1024), dim3(256), 0, s, D.lab, op->cells * B);
   hipLaunchKernelGGL(k_region_ids, dim3(lblk, B), dim3(256), 0, s, lab, cells, D.light, D.lcount,
                      D.lcap, D.lab);
-  ck_launch();
-  to_host(op->defl_total);
-  bool any = false;
-  std::vector<int> lc(B);
-  ck(hipMemcpyAsync(lc.data(), D.lcount, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-  ck(hipStreamSynchronize(s));
-  for (int b = 0; b < B; ++b) {
-    h[b] = lc[b] > 0 ? std::min(h[b], kDefMax) : 0;
-    any = any || h[b] > 0;
-  }
-  if (!any) return;
-  to_dev(D.k);
+  hipLaunchKernelGGL(k_regions_done, gb, dim3(256), 0, s, D.k, op->defl_total, D.lcount, B);
   hipLaunchKernelGGL(k_int_fill, gb, dim3(256), 0, s, op->defl_over, B, 0);
+  ck_launch();
   // the band in cell order, E = Z^T A Z, its inverse; a problem that does not fit is
   // not deflated
   const Faces<double> F = faces_of<double>(op, 0);
@@ -750,10 +739,8 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk, op->defl_total);
   hipLaunchKernelGGL(k_band_write, dim3(nblk, B), dim3(kDefThreads), 0, s, F, D.lab, n, D.k, counts,
                      nblk, D, op->defl_over);
+  hipLaunchKernelGGL(k_band_done, gb, dim3(256), 0, s, D.bcount, op->defl_total, D.cap, B);
   ck_launch();
-  to_host(op->defl_total);
-  for (int b = 0; b < B; ++b) h[b] = std::min(h[b], D.cap);
-  to_dev(D.bcount);
   hipLaunchKernelGGL(k_defl_e, dim3(kDefMax, B), dim3(kDefThreads), 0, s, D, op->defl_e);
   hipLaunchKernelGGL(k_defl_inverse, dim3(B), dim3(kDefMax * kDefMax), 0, s, op->defl_e, D,
                      op->defl_over);

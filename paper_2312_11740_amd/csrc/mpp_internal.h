@@ -79,6 +79,7 @@ struct Level {
 // Deflation of the light-phase regions (the kernels and the method: deflate.h).
 constexpr int kDefMax = 32;          // regions per problem
 constexpr int kDefPairs = 4;         // (region, value) pairs per band cell: own + 3 others
+constexpr int kCclBatch = 8;         // labelling rounds launched between host checks
 constexpr int kDefBandBlocks = 32;   // blocks over a problem's band list
 constexpr int kDefRegionBlocks = 256;  // at most this many blocks over a problem's light cells
 
@@ -204,7 +205,7 @@ struct mpp_op_s {
   mpp::Defl defl{};
   double* defl_e = nullptr;       // [B][kDefMax][kDefMax] E = Z^T A Z
   int* defl_light = nullptr;      // [B] side bit of the lighter phase, -1: none
-  int* defl_flag = nullptr;       // [B] changed flags of the labelling rounds
+  int* defl_flag = nullptr;       // [kCclBatch][B] changed flags of a batch of labelling rounds
   int* defl_total = nullptr;      // [B] totals of the compactions
   int* defl_over = nullptr;       // [B] problems whose deflation does not fit
   int defl_rblk = 1;              // blocks per problem of the region sums
