@@ -608,13 +608,41 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
   (void)hipEventDestroy(e1);
 }
 
-bool any_active(mpp_op_s* op, const Ctl& ctl, hipStream_t s) {
+bool any_active(mpp_op_s* op, const Ctl& ctl, hipStream_t s, bool scal = false) {
   ck(hipMemcpyAsync(op->h_active, ctl.active, sizeof(int) * op->batch, hipMemcpyDeviceToHost, s));
+  if (scal)
+    ck(hipMemcpyAsync(op->h_scal, ctl.scal, sizeof(double) * op->batch * kSlots,
+                      hipMemcpyDeviceToHost, s));
   ck(hipStreamSynchronize(s));
   if (op->prof.on) prof_collect(op->prof);
   for (int b = 0; b < op->batch; ++b)
     if (op->h_active[b]) return true;
   return false;
+}
+
+// Iterations until the next convergence poll, from the scalars of the last poll (in
+// op->h_scal): the slowest live problem's remaining iterations at its rate since the
+// previous poll (rr_prev; the reference norm S_BB before the first), less one, between 1
+// and 16; check_every for a problem that reduces ||r||^2 by less than 10 % per iteration.
+// A poll costs a host round trip and an iteration launched after every problem has
+// converged costs its launches, so the poll aims one iteration short.
+int next_poll(mpp_op_s* op, int check_every, int last_step, std::vector<double>& rr_prev) {
+  int need = 1;
+  for (int b = 0; b < op->batch; ++b) {
+    const double* sc = op->h_scal + (size_t)b * kSlots;
+    const double rr = sc[S_RR], tol2 = sc[S_TOL2];
+    const double prev = rr_prev[b] > 0.0 ? rr_prev[b] : sc[S_BB];
+    rr_prev[b] = rr;
+    if (!op->h_active[b] || !(rr > tol2) || !(tol2 > 0.0) || !(prev > 0.0)) continue;
+    const double rate = std::pow(rr / prev, 1.0 / last_step);
+    if (!(rate > 0.0 && rate < 0.9)) {
+      need = std::max(need, check_every);
+      continue;
+    }
+    const double rem = std::ceil(std::log(tol2 / rr) / std::log(rate));
+    need = std::max(need, (int)std::min(rem, 64.0));
+  }
+  return std::max(1, std::min(16, need - 1));
 }
 
 // ------------------------------------------------------------------------------
@@ -870,9 +898,11 @@ void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu
   }
 }
 
+// known_active: the caller knows some problem is active at the start (no start poll).
 template <typename T>
 void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int nu,
-         int check_every, int xzero, const EpiArgs& start, hipStream_t s) {
+         int check_every, int xzero, const EpiArgs& start, hipStream_t s,
+         bool known_active = false) {
   Level& L0 = op->lev[0];
   const dim3 g = grid_of(L0, op->batch);
   const Faces<T> F = faces_of<T>(op, 0);
@@ -900,7 +930,7 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     op->tail = false;
     if (defl) defl_end<T>(op, x, s);
   };
-  if (!any_active(op, ctl, s)) {
+  if (!known_active && !any_active(op, ctl, s)) {
     done_();
     return;
   }
@@ -923,20 +953,26 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 1);
   });
   ck_launch();
-  // iterations in blocks of check_every; the kernels themselves stop working on a
-  // problem once it has converged, so a block may overrun the last useful iteration
+  // iterations between polls: check_every first, then as next_poll predicts; the kernels
+  // themselves stop working on a problem once it has converged, so iterations past the
+  // last useful one only cost their launches.  Captured graphs hold one iteration.
   const bool graphs = op->use_graphs && !op->prof.on;
-  for (int done = 0; done <= ctl.max_iter; done += check_every) {
-    const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter, defl ? 1 : 0,
-                       op->tail ? 1 : 0, {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
-    if (graphs)
-      run_graph(op, key, s, [&](hipStream_t cs) {
-        pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, cs);
-      });
-    else
-      pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, s);
-    if (!any_active(op, ctl, s)) break;
+  std::vector<double> rr_prev(B, -1.0);
+  int step = check_every;
+  for (int done = 0; done <= ctl.max_iter; done += step) {
+    if (graphs) {
+      const GraphKey key{(int)sizeof(T), nu, op->nu_c, 1, ctl.max_iter, defl ? 1 : 0,
+                         op->tail ? 1 : 0, {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
+      for (int i = 0; i < step; ++i)
+        run_graph(op, key, s, [&](hipStream_t cs) {
+          pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, 1, cs);
+        });
+    } else {
+      pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, step, s);
+    }
+    if (!any_active(op, ctl, s, true)) break;
     set_tail();
+    step = next_poll(op, check_every, step, rr_prev);
   }
   done_();
 }
@@ -1238,8 +1274,9 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
     ck_launch();
     hipLaunchKernelGGL(k_fill<float>, g, dim3(kBlock), 0, s, op->d32, cells, 0.0f);
     ck_launch();
+    // every problem still active in the refinement has work in its inner solve
     pcg<float>(op, ic, op->r32, op->d32, op->r32, op->z32, op->p32, op->q32, o.nu,
-               o.check_every, 1, istart, s);
+               o.check_every, 1, istart, s, true);
     hipLaunchKernelGGL(k_correct, g, dim3(kBlock), 0, s, p, op->d32, cells, oc.scal, oc.active);
     ck_launch();
     // an inner breakdown or an exhausted iteration budget ends the refinement of that
@@ -1363,10 +1400,9 @@ void free_op(mpp_op_s* op) {
   }
   if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
   for (hipEvent_t e : op->prof.pool) (void)hipEventDestroy(e);
-  delete[] op->h_active;
-  delete[] op->h_iters;
-  delete[] op->h_status;
-  delete[] op->h_scal;
+  for (void* h : {(void*)op->h_active, (void*)op->h_iters, (void*)op->h_status,
+                  (void*)op->h_scal})
+    if (h) (void)hipHostFree(h);
   delete op;
 }
 
@@ -1393,10 +1429,15 @@ int mpp_build_operator(const mpp_desc* desc, const double* phi, const double* rh
   op->use_graphs = (desc->flags & MPP_FLAG_NO_GRAPHS) == 0;
   op->ws = workspace;
   op->ws_bytes = workspace_bytes;
-  op->h_active = new int[B];
-  op->h_iters = new int[B];
-  op->h_status = new int[B];
-  op->h_scal = new double[(size_t)B * kSlots];
+  // pinned host arrays for the polls and the results (small copies without staging)
+  if (hipHostMalloc((void**)&op->h_active, sizeof(int) * B, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&op->h_iters, sizeof(int) * B, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&op->h_status, sizeof(int) * B, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&op->h_scal, sizeof(double) * B * kSlots, hipHostMallocDefault) !=
+          hipSuccess) {
+    free_op(op);
+    return MPP_ENOMEM;
+  }
   int st;
   try {
     st = build_into(op, phi, host, reinterpret_cast<hipStream_t>(stream));
