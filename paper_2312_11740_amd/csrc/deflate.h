@@ -95,7 +95,9 @@ __global__ void k_ccl_round(int n, const uint8_t* __restrict__ code, const int* 
     }
     if (m < old) {
       atomicMin(&L[c], m);
-      atomicMin(&L[old], m);
+      // many cells of a component share `old`: the atomic only where it still lowers the
+      // label (the same result, without thousands of atomics on one word)
+      if (L[old] > m) atomicMin(&L[old], m);
       any = 1;
     }
   }
