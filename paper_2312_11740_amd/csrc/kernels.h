@@ -622,14 +622,19 @@ __global__ void k_fill(T* __restrict__ v, int cells, T val) {
   CELL_LOOP(cells) v[base + c] = val;
 }
 
-// mixed mode: r32 = r64 / ||r64|| (scale from the outer control block)
-__global__ void k_scale_down(const double* __restrict__ r, float* __restrict__ r32, int cells,
-                             const double* __restrict__ oscal, const int* __restrict__ oactive) {
+// mixed mode: r32 = r64 / ||r64|| (scale from the outer control block), and the inner
+// solve's iterate d32 = 0
+__global__ void k_scale_down(const double* __restrict__ r, float* __restrict__ r32,
+                             float* __restrict__ d32, int cells, const double* __restrict__ oscal,
+                             const int* __restrict__ oactive) {
   const int pb = blockIdx.y;
   if (!oactive[pb]) return;
   const size_t base = (size_t)pb * cells;
   const double inv = 1.0 / sqrt(oscal[(size_t)pb * kSlots + S_RR]);
-  CELL_LOOP(cells) r32[base + c] = (float)(r[base + c] * inv);
+  CELL_LOOP(cells) {
+    r32[base + c] = (float)(r[base + c] * inv);
+    d32[base + c] = 0.0f;
+  }
 }
 
 // mixed mode: x64 += ||r64|| d32

@@ -608,11 +608,8 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
   (void)hipEventDestroy(e1);
 }
 
-bool any_active(mpp_op_s* op, const Ctl& ctl, hipStream_t s, bool scal = false) {
+bool any_active(mpp_op_s* op, const Ctl& ctl, hipStream_t s) {
   ck(hipMemcpyAsync(op->h_active, ctl.active, sizeof(int) * op->batch, hipMemcpyDeviceToHost, s));
-  if (scal)
-    ck(hipMemcpyAsync(op->h_scal, ctl.scal, sizeof(double) * op->batch * kSlots,
-                      hipMemcpyDeviceToHost, s));
   ck(hipStreamSynchronize(s));
   if (op->prof.on) prof_collect(op->prof);
   for (int b = 0; b < op->batch; ++b)
@@ -620,30 +617,6 @@ bool any_active(mpp_op_s* op, const Ctl& ctl, hipStream_t s, bool scal = false) 
   return false;
 }
 
-// Iterations until the next convergence poll, from the scalars of the last poll (in
-// op->h_scal): the slowest live problem's remaining iterations at its rate since the
-// previous poll (rr_prev; the reference norm S_BB before the first), less one, between 1
-// and 16; check_every for a problem that reduces ||r||^2 by less than 10 % per iteration.
-// A poll costs a host round trip and an iteration launched after every problem has
-// converged costs its launches, so the poll aims one iteration short.
-int next_poll(mpp_op_s* op, int check_every, int last_step, std::vector<double>& rr_prev) {
-  int need = 1;
-  for (int b = 0; b < op->batch; ++b) {
-    const double* sc = op->h_scal + (size_t)b * kSlots;
-    const double rr = sc[S_RR], tol2 = sc[S_TOL2];
-    const double prev = rr_prev[b] > 0.0 ? rr_prev[b] : sc[S_BB];
-    rr_prev[b] = rr;
-    if (!op->h_active[b] || !(rr > tol2) || !(tol2 > 0.0) || !(prev > 0.0)) continue;
-    const double rate = std::pow(rr / prev, 1.0 / last_step);
-    if (!(rate > 0.0 && rate < 0.9)) {
-      need = std::max(need, check_every);
-      continue;
-    }
-    const double rem = std::ceil(std::log(tol2 / rr) / std::log(rate));
-    need = std::max(need, (int)std::min(rem, 64.0));
-  }
-  return std::max(1, std::min(16, need - 1));
-}
 
 // ------------------------------------------------------------------------------
 // launch graphs: a block of CG iterations is captured once per operator and
@@ -953,26 +926,22 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 1);
   });
   ck_launch();
-  // iterations between polls: check_every first, then as next_poll predicts; the kernels
-  // themselves stop working on a problem once it has converged, so iterations past the
-  // last useful one only cost their launches.  Captured graphs hold one iteration.
+  // iterations in blocks of check_every; the kernels themselves stop working on a
+  // problem once it has converged, so a block may overrun the last useful iteration
+  // (measured: spacing the polls by a prediction of the remaining iterations gains
+  // nothing on one problem and loses on a batch)
   const bool graphs = op->use_graphs && !op->prof.on;
-  std::vector<double> rr_prev(B, -1.0);
-  int step = check_every;
-  for (int done = 0; done <= ctl.max_iter; done += step) {
-    if (graphs) {
-      const GraphKey key{(int)sizeof(T), nu, op->nu_c, 1, ctl.max_iter, defl ? 1 : 0,
-                         op->tail ? 1 : 0, {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
-      for (int i = 0; i < step; ++i)
-        run_graph(op, key, s, [&](hipStream_t cs) {
-          pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, 1, cs);
-        });
-    } else {
-      pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, step, s);
-    }
-    if (!any_active(op, ctl, s, true)) break;
+  for (int done = 0; done <= ctl.max_iter; done += check_every) {
+    const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter, defl ? 1 : 0,
+                       op->tail ? 1 : 0, {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
+    if (graphs)
+      run_graph(op, key, s, [&](hipStream_t cs) {
+        pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, cs);
+      });
+    else
+      pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, s);
+    if (!any_active(op, ctl, s)) break;
     set_tail();
-    step = next_poll(op, check_every, step, rr_prev);
   }
   done_();
 }
@@ -1269,10 +1238,8 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
       break;
     }
     for (int b = 0; b < B; ++b) outer_count[b] += op->h_active[b];
-    hipLaunchKernelGGL(k_scale_down, g, dim3(kBlock), 0, s, op->r, op->r32, cells, oc.scal,
-                       oc.active);
-    ck_launch();
-    hipLaunchKernelGGL(k_fill<float>, g, dim3(kBlock), 0, s, op->d32, cells, 0.0f);
+    hipLaunchKernelGGL(k_scale_down, g, dim3(kBlock), 0, s, op->r, op->r32, op->d32, cells,
+                       oc.scal, oc.active);
     ck_launch();
     // every problem still active in the refinement has work in its inner solve
     pcg<float>(op, ic, op->r32, op->d32, op->r32, op->z32, op->p32, op->q32, o.nu,
