@@ -353,8 +353,40 @@ __device__ inline int band_pairs(const Faces<double>& F, const uint8_t* __restri
   return np;
 }
 
+// The band marked from the light-cell list: a cell of region l with a face neighbour of
+// another label marks itself and that neighbour (a cell is in the band exactly when
+// band_pairs finds a neighbour of another label, and one of the two is in a region).
+// mask: a byte per cell, zero on entry.
+__global__ void k_band_mark(const uint8_t* __restrict__ lab, int n, const int* __restrict__ list,
+                            const int* __restrict__ lcount, int lcap, const int* __restrict__ dk,
+                            uint8_t* __restrict__ mask) {
+  const int b = blockIdx.y;
+  if (dk[b] <= 0) return;
+  const int cells = n * n * n;
+  const size_t base = (size_t)b * cells;
+  const int nn = n * n;
+  const int* Lst = list + (size_t)b * lcap;
+  const int cnt = lcount[b];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const int c = Lst[q];
+    const int l = lab[base + c];
+    if (l == 0) continue;
+    int i, j, k;
+    ijk(c, n, i, j, k);
+    const int nb[6] = {c - 1, c + 1, c - n, c + n, c - nn, c + nn};
+    const bool in[6] = {i > 0, i < n - 1, j > 0, j < n - 1, k > 0, k < n - 1};
+    bool edge = false;
+    for (int f = 0; f < 6; ++f)
+      if (in[f] && lab[base + nb[f]] != l) {
+        mask[base + nb[f]] = 1;
+        edge = true;
+      }
+    if (edge) mask[base + c] = 1;
+  }
+}
+
 __global__ void __launch_bounds__(kDefThreads)
-    k_band_count(Faces<double> F, const uint8_t* __restrict__ lab, int n, const int* __restrict__ dk,
+    k_band_count(const uint8_t* __restrict__ mask, int n, const int* __restrict__ dk,
                  int* __restrict__ counts, int nblk) {
   const int b = blockIdx.y;
   const int cells = n * n * n;
@@ -362,12 +394,9 @@ __global__ void __launch_bounds__(kDefThreads)
   __shared__ int sh[kDefThreads / 64];
   int cnt = 0;
   if (dk[b] > 0) {
-    const double inv_h2 = (double)n * (double)n;
     const int c0 = blockIdx.x * kDefChunk;
-    uint8_t pl[kDefPairs];
-    double pv[kDefPairs];
     for (int c = c0 + threadIdx.x; c < min(c0 + kDefChunk, cells); c += kDefThreads)
-      cnt += band_pairs(F, lab, b, base, c, n, inv_h2, pl, pv) > 0;
+      cnt += mask[base + c] != 0;
   }
   int v = cnt;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -383,8 +412,9 @@ __global__ void __launch_bounds__(kDefThreads)
 // Writes the band cells in cell order.  A problem whose band does not fit its capacity,
 // or has a cell with more than kDefPairs regions around it, gets overflow[b] = 1.
 __global__ void __launch_bounds__(kDefThreads)
-    k_band_write(Faces<double> F, const uint8_t* __restrict__ lab, int n, const int* __restrict__ dk,
-                 const int* __restrict__ offs, int nblk, Defl D, int* __restrict__ overflow) {
+    k_band_write(Faces<double> F, const uint8_t* __restrict__ lab, const uint8_t* __restrict__ mask,
+                 int n, const int* __restrict__ dk, const int* __restrict__ offs, int nblk, Defl D,
+                 int* __restrict__ overflow) {
   const int b = blockIdx.y;
   if (dk[b] <= 0) return;
   const int cells = n * n * n;
@@ -397,7 +427,8 @@ __global__ void __launch_bounds__(kDefThreads)
     const int c = s0 + threadIdx.x;
     uint8_t pl[kDefPairs] = {0, 0, 0, 0};
     double pv[kDefPairs] = {0.0, 0.0, 0.0, 0.0};
-    const int np = c < cells ? band_pairs(F, lab, b, base, c, n, inv_h2, pl, pv) : 0;
+    const int np =
+        c < cells && mask[base + c] ? band_pairs(F, lab, b, base, c, n, inv_h2, pl, pv) : 0;
     int total = 0;
     const int r = block_rank(np > 0, total, sh);
     if (np > 0) {

@@ -742,11 +742,16 @@ void build_deflation(mpp_op_s* op, hipStream_t s) {
   // the band in cell order, E = Z^T A Z, its inverse; a problem that does not fit is
   // not deflated
   const Faces<double> F = faces_of<double>(op, 0);
-  hipLaunchKernelGGL(k_band_count, dim3(nblk, B), dim3(kDefThreads), 0, s, F, D.lab, n, D.k, counts,
+  // (the labels of the propagation are done with: their array holds the band mask)
+  uint8_t* mask = reinterpret_cast<uint8_t*>(lab);
+  hipLaunchKernelGGL(k_u8_fill, dim3(1024), dim3(256), 0, s, mask, op->cells * B);
+  hipLaunchKernelGGL(k_band_mark, dim3(lblk, B), dim3(256), 0, s, D.lab, n, D.light, D.lcount,
+                     D.lcap, D.k, mask);
+  hipLaunchKernelGGL(k_band_count, dim3(nblk, B), dim3(kDefThreads), 0, s, mask, n, D.k, counts,
                      nblk);
   hipLaunchKernelGGL(k_scan_counts, dim3(B), dim3(1024), 0, s, counts, nblk, op->defl_total);
-  hipLaunchKernelGGL(k_band_write, dim3(nblk, B), dim3(kDefThreads), 0, s, F, D.lab, n, D.k, counts,
-                     nblk, D, op->defl_over);
+  hipLaunchKernelGGL(k_band_write, dim3(nblk, B), dim3(kDefThreads), 0, s, F, D.lab, mask, n, D.k,
+                     counts, nblk, D, op->defl_over);
   hipLaunchKernelGGL(k_band_done, gb, dim3(256), 0, s, D.bcount, op->defl_total, D.cap, B);
   ck_launch();
   hipLaunchKernelGGL(k_defl_e, dim3(kDefMax, B), dim3(kDefThreads), 0, s, D, op->defl_e);
