@@ -268,14 +268,18 @@ template <typename T>
 void launch_resid_restrict(const mpp_op_s* op, int l, Faces<T> F, const T* rhs, const T* x, T* bc,
                            const int* active, hipStream_t s) {
   const int n = op->lev[l].n;
-  const StTiles tl = st_tiles(n, kStKZ);
+  // chunks of 16 planes, shorter (down to 2) while the grid would have fewer than 2048
+  // blocks: on the coarse levels the kernel is latency-bound and wants every compute unit
+  int kz = kStKZ;
+  while (kz > 2 && (long)st_tiles(n, kz).ntiles * op->batch < 2048) kz /= 2;
+  const StTiles tl = st_tiles(n, kz);
   const dim3 grid(st_grid(tl), op->batch);
   if (l == 0)
-    hipLaunchKernelGGL((k_resid_restrict_z<T, true>), grid, dim3(kStThreads), 0, s, F, n, tl,
-                       kStKZ, rhs, x, bc, active);
+    hipLaunchKernelGGL((k_resid_restrict_z<T, true>), grid, dim3(kStThreads), 0, s, F, n, tl, kz,
+                       rhs, x, bc, active);
   else
-    hipLaunchKernelGGL((k_resid_restrict_z<T, false>), grid, dim3(kStThreads), 0, s, F, n, tl,
-                       kStKZ, rhs, x, bc, active);
+    hipLaunchKernelGGL((k_resid_restrict_z<T, false>), grid, dim3(kStThreads), 0, s, F, n, tl, kz,
+                       rhs, x, bc, active);
 }
 
 // ------------------------------------------------------------------------------
