@@ -146,7 +146,8 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
       op->pstride = std::max(op->pstride, rb_grid(pr_tiles(sizes[l], kz)));
     }
   }
-  op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kStKZ)));
+  for (int kz = 2; kz <= kStKZ; kz *= 2)   // every chunk size st_kz may pick
+    op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kz)));
   // the band correction of a deflated CG appends its partials after a producer's
   op->pstride += kDefBandBlocks;
   op->partials = cv.take<double>((size_t)B * op->pstride);
@@ -240,13 +241,23 @@ void finish_sums(mpp_op_s* op, const Ctl& ctl, const EpiArgs& e, int nparts, hip
 // ------------------------------------------------------------------------------
 // y = A x on the finest level, with x.y block partials when dot; returns the number
 // of partials written (0 without dot).
+// z-chunk of the column-marching stencil kernels: 16 planes, shorter (down to 2) while
+// the grid would have fewer than 2048 blocks (small grids are latency-bound and want
+// every compute unit)
+int st_kz(int n, int batch) {
+  int kz = kStKZ;
+  while (kz > 2 && (long)st_tiles(n, kz).ntiles * batch < 2048) kz /= 2;
+  return kz;
+}
+
 template <typename T>
 int launch_apply(const mpp_op_s* op, Faces<T> F, const T* x, T* y, const Ctl& ctl, int dot,
                  const int* active, hipStream_t s) {
   const int n = op->lev[0].n;
-  const StTiles tl = st_tiles(n, kStKZ);
+  const int kz = st_kz(n, op->batch);
+  const StTiles tl = st_tiles(n, kz);
   const dim3 grid(st_grid(tl), op->batch);
-  hipLaunchKernelGGL((k_stencil_z<T, 0>), grid, dim3(kStThreads), 0, s, F, n, tl, kStKZ, x,
+  hipLaunchKernelGGL((k_stencil_z<T, 0>), grid, dim3(kStThreads), 0, s, F, n, tl, kz, x,
                      (const T*)nullptr, y, ctl, dot, 0, active);
   return dot ? (int)grid.x : 0;
 }
@@ -256,9 +267,10 @@ template <typename T>
 int launch_residual(const mpp_op_s* op, Faces<T> F, const T* rhs, const T* x, T* r,
                     const Ctl& ctl, int xzero, hipStream_t s) {
   const int n = op->lev[0].n;
-  const StTiles tl = st_tiles(n, kStKZ);
+  const int kz = st_kz(n, op->batch);
+  const StTiles tl = st_tiles(n, kz);
   const dim3 grid(st_grid(tl), op->batch);
-  hipLaunchKernelGGL((k_stencil_z<T, 1>), grid, dim3(kStThreads), 0, s, F, n, tl, kStKZ, x, rhs,
+  hipLaunchKernelGGL((k_stencil_z<T, 1>), grid, dim3(kStThreads), 0, s, F, n, tl, kz, x, rhs,
                      r, ctl, 1, xzero, (const int*)nullptr);
   return (int)grid.x;
 }
@@ -268,10 +280,7 @@ template <typename T>
 void launch_resid_restrict(const mpp_op_s* op, int l, Faces<T> F, const T* rhs, const T* x, T* bc,
                            const int* active, hipStream_t s) {
   const int n = op->lev[l].n;
-  // chunks of 16 planes, shorter (down to 2) while the grid would have fewer than 2048
-  // blocks: on the coarse levels the kernel is latency-bound and wants every compute unit
-  int kz = kStKZ;
-  while (kz > 2 && (long)st_tiles(n, kz).ntiles * op->batch < 2048) kz /= 2;
+  const int kz = st_kz(n, op->batch);
   const StTiles tl = st_tiles(n, kz);
   const dim3 grid(st_grid(tl), op->batch);
   if (l == 0)
