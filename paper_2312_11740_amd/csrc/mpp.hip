@@ -141,7 +141,8 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
   for (int l = 0; l < L; ++l) {   // every sweep kernel the tuner may pick
     for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2)
       op->pstride = std::max(op->pstride, rb_grid(rb_tiles(sizes[l], B, kz)));
-    op->pstride = std::max(op->pstride, grid3(tiles3(sizes[l])));
+    for (int shape = 0; shape < k3Shapes; ++shape)
+      op->pstride = std::max(op->pstride, grid3(tiles3(sizes[l], shape)));
     for (int kz = 2; kz <= 2 * kRbKZ; kz *= 2) {
       op->pstride = std::max(op->pstride, rb_grid(pr_tiles(sizes[l], kz)));
     }
@@ -375,15 +376,16 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
             const Ctl* dctl = nullptr, int* dot_parts = nullptr);
 
 // One fused sweep on level l with the kernel the tuner picked for it: kz > 0 the
-// z-marching kernel with chunks of kz planes (0: its default), kz = -1 the 3D-tile
-// kernel, kz <= -2 the pair-per-thread kernel with chunks of -kz planes (finest level,
-// even n).  Returns the grid size (the number of dot partials).
+// z-marching kernel with chunks of kz planes (0: its default), kz = -1, -2, -3 the
+// 3D-tile kernel with tile shape 0, 1, 2, kz <= -4 the pair-per-thread kernel with
+// chunks of -kz planes (finest level, even n).  Returns the grid size (the number of dot
+// partials).
 template <typename T, int MODE, bool FINE>
 int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs, const T* in,
               const T* ec, T* out, int c1, const Ctl& ctl, int dot, const int* active,
               hipStream_t s) {
   const int n = op->lev[l].n, B = op->batch;
-  if (kz <= -2) {
+  if (kz <= -4) {
     if constexpr (FINE) {
       if (n % 2 == 0) {
         const RbTiles tl = pr_tiles(n, -kz);
@@ -396,10 +398,18 @@ int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs
     throw HipError{hipErrorInvalidValue};   // the pair kernel only runs on an even finest level
   }
   if (kz < 0) {
-    const Tiles3 t3 = tiles3(n);
+    const int shape = -kz - 1;
+    const Tiles3 t3 = tiles3(n, shape);
     const dim3 grid(grid3(t3), B);
-    hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE>), grid, dim3(k3Threads), 0, s, F, n, t3, rhs,
-                       in, ec, out, c1, ctl, dot, active);
+    if (shape == 0)
+      hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE, 0>), grid, dim3(Shape3<0>::Threads), 0, s,
+                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, active);
+    else if (shape == 1)
+      hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE, 1>), grid, dim3(Shape3<1>::Threads), 0, s,
+                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, active);
+    else
+      hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE, 2>), grid, dim3(Shape3<2>::Threads), 0, s,
+                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, active);
     return (int)grid.x;
   }
   const RbTiles tl = rb_tiles(n, B, kz);
@@ -528,16 +538,18 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     for (int l = 0; l < op->nlev; ++l) op->kz_tail[w][l] = op->kz[w][l];
     return;
   }
-  // MPP_SWEEP=march, =tile or =pair[K] fixes the sweep kernel of every level (no timing;
-  // pair: the pair kernel with K-plane chunks (default 16) on an even finest level,
-  // z-marching below)
+  // MPP_SWEEP=march, =tile[S] or =pair[K] fixes the sweep kernel of every level (no
+  // timing; tile: the 3D-tile kernel with tile shape S (default 0); pair: the pair kernel
+  // with K-plane chunks (default 16) on an even finest level, z-marching below)
   const char* force = std::getenv("MPP_SWEEP");
-  if (force && (std::strcmp(force, "march") == 0 || std::strcmp(force, "tile") == 0 ||
+  if (force && (std::strcmp(force, "march") == 0 || std::strncmp(force, "tile", 4) == 0 ||
                 std::strncmp(force, "pair", 4) == 0)) {
-    for (int l = 0; l < op->nlev; ++l) op->kz[w][l] = force[0] == 't' ? -1 : 0;
+    const int shape = force[0] == 't' ? std::min(std::max(std::atoi(force + 4), 0), k3Shapes - 1)
+                                      : 0;
+    for (int l = 0; l < op->nlev; ++l) op->kz[w][l] = force[0] == 't' ? -1 - shape : 0;
     if (force[0] == 'p' && op->lev[0].n % 2 == 0) {
       const int kz = std::atoi(force + 4);
-      op->kz[w][0] = -(kz >= 2 && kz <= 2 * kRbKZ ? kz : 16);
+      op->kz[w][0] = -(kz >= 4 && kz <= 2 * kRbKZ ? kz : 16);
     }
     for (int l = 0; l < op->nlev; ++l) op->kz_tail[w][l] = op->kz[w][l];
     return;
@@ -581,11 +593,12 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     F.sig = T(0);
     float best = 1e30f;
     int best_kz = 0;
-    // candidates: the z-marching kernel with chunks of 2 .. 32 planes, the 3D-tile kernel,
-    // on an even finest level the pair kernel with chunks of 4 .. 32 planes
+    // candidates: the z-marching kernel with chunks of 2 .. 32 planes, the 3D-tile kernel
+    // in its three tile shapes, on an even finest level the pair kernel with chunks of
+    // 4 .. 32 planes
     std::vector<int> cands;
     for (int kz = 2; kz <= 2 * kRbKZ && kz <= L.n; kz *= 2) cands.push_back(kz);
-    cands.push_back(-1);
+    for (int shape = 0; shape < k3Shapes; ++shape) cands.push_back(-1 - shape);
     if (l == 0 && L.n % 2 == 0)
       for (int kz = 4; kz <= 2 * kRbKZ && kz <= L.n; kz *= 2) cands.push_back(-kz);
     // two rounds over the candidates, each candidate's better round counts (a single

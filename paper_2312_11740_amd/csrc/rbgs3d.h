@@ -3,52 +3,78 @@
 // Same semantics as the z-marching sweep (two one-colour half sweeps, out of place):
 //   x1  = x_in with every c1 cell set to (sum_f w_f x_in[nb] - h^2 b) / sum_f w_f,
 //   out = x1  with every c2 cell set to (sum_f w_f x1[nb]  - h^2 b) / sum_f w_f.
-// A block owns a 32 x 8 x 8 tile.  It issues every load of its inputs together
-// (x_in on the tile and a two-cell ring, b and the finest-level code on the tile and a
-// one-cell ring), so each block has ~40 KB in flight instead of one plane; then the
-// c1 values on tile + ring, a barrier, the c2 values on the tile.  The ring reads of
-// neighbouring tiles hit L2 (tiles are handed out in x-fastest order per XCD).
+// A block owns a tile of SX x SY x SZ cells (32 x 8 x 8 with 512 threads; on small
+// grids, where the sweep is latency-bound, 16 x 8 x 4 with 256 threads or 8 x 8 x 4 with
+// 128 give more blocks).  It issues every load of its inputs together (x_in on the tile
+// and a two-cell ring, b and the finest-level code on the tile and a one-cell ring), so
+// each block has its whole input in flight instead of one plane; then the c1 values on
+// tile + ring, a barrier, the c2 values on the tile.  The ring reads of neighbouring
+// tiles hit L2 (tiles are handed out in x-fastest order per XCD).
 #pragma once
 
 #include "rbgs.h"
 
 namespace mpp {
 
-constexpr int k3X = 32, k3Y = 8, k3Z = 8;
-constexpr int k3Threads = 512;
-constexpr int k3XX = k3X + 4, k3XY = k3Y + 4, k3XZ = k3Z + 4;   // x_in tile, 2-cell ring
-constexpr int k3BX = k3X + 2, k3BY = k3Y + 2, k3BZ = k3Z + 2;   // b / c1 tile, 1-cell ring
-constexpr int k3NX = k3XX * k3XY * k3XZ;
-constexpr int k3NB = k3BX * k3BY * k3BZ;
+// tile shapes: 0 = 32 x 8 x 8 / 512 threads, 1 = 16 x 8 x 4 / 256, 2 = 8 x 8 x 4 / 128
+template <int SHAPE>
+struct Shape3;
+template <>
+struct Shape3<0> {
+  static constexpr int X = 32, Y = 8, Z = 8, Threads = 512;
+};
+template <>
+struct Shape3<1> {
+  static constexpr int X = 16, Y = 8, Z = 4, Threads = 256;
+};
+template <>
+struct Shape3<2> {
+  static constexpr int X = 8, Y = 8, Z = 4, Threads = 128;
+};
+constexpr int k3Shapes = 3;
 
 struct Tiles3 {
   int tx, ty, tz, ntiles;
 };
 
-inline Tiles3 tiles3(int n) {
+inline Tiles3 tiles3(int n, int shape = 0) {
+  const int X = shape == 0 ? Shape3<0>::X : (shape == 1 ? Shape3<1>::X : Shape3<2>::X);
+  const int Y = shape == 0 ? Shape3<0>::Y : (shape == 1 ? Shape3<1>::Y : Shape3<2>::Y);
+  const int Z = shape == 0 ? Shape3<0>::Z : (shape == 1 ? Shape3<1>::Z : Shape3<2>::Z);
   Tiles3 t;
-  t.tx = (n + k3X - 1) / k3X;
-  t.ty = (n + k3Y - 1) / k3Y;
-  t.tz = (n + k3Z - 1) / k3Z;
+  t.tx = (n + X - 1) / X;
+  t.ty = (n + Y - 1) / Y;
+  t.tz = (n + Z - 1) / Z;
   t.ntiles = t.tx * t.ty * t.tz;
   return t;
 }
 
 inline int grid3(const Tiles3& t) { return 8 * ((t.ntiles + 7) / 8); }
 
-template <typename T>
+template <typename T, int SHAPE>
 struct Lds3 {
-  T x[k3NX];
-  T c1[k3NB];
-  T b[k3NB];
-  uint8_t code[k3NB];
+  static constexpr int XX = Shape3<SHAPE>::X + 4, XY = Shape3<SHAPE>::Y + 4,
+                       XZ = Shape3<SHAPE>::Z + 4;   // x_in tile, 2-cell ring
+  static constexpr int BX = Shape3<SHAPE>::X + 2, BY = Shape3<SHAPE>::Y + 2,
+                       BZ = Shape3<SHAPE>::Z + 2;   // b / c1 tile, 1-cell ring
+  static constexpr int NX = XX * XY * XZ, NB = BX * BY * BZ;
+  T x[NX];
+  T c1[NB];
+  T b[NB];
+  uint8_t code[NB];
 };
 
-template <typename T, int MODE, bool FINE>
-__global__ void __launch_bounds__(k3Threads)
+template <typename T, int MODE, bool FINE, int SHAPE>
+__global__ void __launch_bounds__(Shape3<SHAPE>::Threads)
     k_rb_sweep3d(Faces<T> F, int n, Tiles3 tl, const T* __restrict__ rhs,
                  const T* __restrict__ xin, const T* __restrict__ ec, T* __restrict__ xout,
                  int c1, Ctl ctl, int dot, const int* __restrict__ active) {
+  using Sh = Shape3<SHAPE>;
+  using Ld = Lds3<T, SHAPE>;
+  constexpr int k3X = Sh::X, k3Y = Sh::Y, k3Z = Sh::Z, k3Threads = Sh::Threads;
+  constexpr int k3XX = Ld::XX, k3XY = Ld::XY;
+  constexpr int k3BX = Ld::BX, k3BY = Ld::BY, k3BZ = Ld::BZ;
+  constexpr int k3NX = Ld::NX, k3NB = Ld::NB;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const int tile = xcd_tile(blockIdx.x, tl.ntiles);
@@ -56,7 +82,7 @@ __global__ void __launch_bounds__(k3Threads)
     if (dot && threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = 0.0;
     return;
   }
-  __shared__ Lds3<T> S;
+  __shared__ Ld S;
   const int tid = threadIdx.x;
   const int i0 = (tile % tl.tx) * k3X;
   const int j0 = ((tile / tl.tx) % tl.ty) * k3Y;

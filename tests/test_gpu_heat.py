@@ -142,7 +142,7 @@ def test_heat_full_size_residual_by_the_oracle():
 
 
 def test_shifted_sweep_kernels_agree_and_pressure_is_restored(monkeypatch):
-    # every sweep kernel (z-marching, 3D tile, pair) applies the shifted operator the same
+    # every sweep kernel (z-marching, 3D tiles of each shape, pair) applies the shifted operator the same
     # way: heat solves agree to rounding; a pressure solve on the same operator after a
     # heat solve equals one on a fresh operator bit for bit (shift and coarsest inverse
     # restored)
@@ -152,7 +152,7 @@ def test_shifted_sweep_kernels_agree_and_pressure_is_restored(monkeypatch):
     f = field((n, n, n), 13) - 0.5
     kn, kp, dt = 0.05, 1.0, 50.0 / (n * n)     # d = 50: residual floor ~1.3e-13
     ref, _, _ = O.heat_step(O.heat_faces(phi, kn, kp), t0, dt, tol=2.5e-12)
-    for kind in ("march", "tile", "pair"):
+    for kind in ("march", "tile", "tile1", "tile2", "pair"):
         monkeypatch.setenv("MPP_SWEEP", kind)
         op = heat_op(phi, kn, kp)
         p_fresh, _ = op.solve(to_dev(f), rtol=1e-10)

@@ -400,21 +400,23 @@ def test_autotuned_chunks_do_not_change_the_answer():
 
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_sweep_kernels_agree(mode, monkeypatch):
-    """The z-marching, 3D-tile and pair-per-thread sweep kernels compute the same half
-    sweeps with the same arithmetic: V-cycles agree to the last bit; solves agree to
-    rounding (the dot products folded into the sweeps are summed in per-tile groups)."""
+    """The z-marching, 3D-tile (three tile shapes) and pair-per-thread sweep kernels
+    compute the same half sweeps with the same arithmetic: V-cycles agree to the last bit;
+    solves agree to rounding (the dot products folded into the sweeps are summed in
+    per-tile groups)."""
     pr = G.rising_bubble_problem(5, n=64)
     phi, f = to_dev(pr.phi), to_dev(pr.f)
     r = to_dev(np.random.default_rng(3).standard_normal((64, 64, 64)))
     out = {}
-    for kind in ("march", "tile", "pair"):
+    kinds = ("march", "tile", "tile1", "tile2", "pair")
+    for kind in kinds:
         monkeypatch.setenv("MPP_SWEEP", kind)
         op = M.Operator(phi, pr.rho_neg, pr.rho_pos, pr.sigma)
         z = op.vcycle(r)
         p, info = op.solve(f, mode=mode)
         out[kind] = (to_host(z), to_host(p), info[0].iters)
         op.close()
-    for kind in ("tile", "pair"):
+    for kind in kinds[1:]:
         assert np.array_equal(out["march"][0], out[kind][0]), kind
         assert rel2(out[kind][1], out["march"][1]) <= 1e-12, kind
         assert abs(out["march"][2] - out[kind][2]) <= 1, kind
@@ -424,14 +426,15 @@ def test_sweep_kernels_agree(mode, monkeypatch):
 def test_pair_sweep_kernel_ragged_and_batched(n, monkeypatch):
     """The pair kernel on sizes that leave part of a tile outside the domain (20 and 36:
     tiles of 4 rows out of 8 along y; 144: a second tile along x with 8 of its 64
-    pairs inside), batched: V-cycles equal the z-marching kernel's bit for bit, and mixed
+    pairs inside), batched: V-cycles equal the z-marching kernel's bit for bit, as do the
+    small-tile shapes of the 3D-tile kernel (ragged tiles on every level), and mixed
     solves meet the oracle."""
     cases = [bubbles_case(n, 40 + s) for s in range(3)]
     phi = np.stack([c[0] for c in cases])
     f = np.stack([c[1] for c in cases])
     r = to_dev(np.random.default_rng(4).standard_normal((3, n, n, n)))
     z = {}
-    for kind in ("march", "pair"):
+    for kind in ("march", "pair", "tile1", "tile2"):
         monkeypatch.setenv("MPP_SWEEP", kind)
         op = M.Operator(to_dev(phi), [c[2] for c in cases], [c[3] for c in cases],
                         [c[4] for c in cases])
@@ -442,7 +445,8 @@ def test_pair_sweep_kernel_ragged_and_batched(n, monkeypatch):
             for b in range(3):
                 check_solution(phi[b], f[b], *cases[b][2:], ph[b], infos[b])
         op.close()
-    assert np.array_equal(z["march"], z["pair"])
+    for kind in ("pair", "tile1", "tile2"):
+        assert np.array_equal(z["march"], z[kind]), kind
 
 
 @pytest.mark.parametrize("sign", [-1.0, 1.0])
