@@ -91,12 +91,15 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         op.update(phis[t], prm["rho_neg"], prm["rho_pos"], prm["sigma"])
+        start_zero = zero
         if net is not None:
             p, fell = op.learned_guess(net, fs[t], sweeps=guess_sweeps, out=p,
                                        judge="deflated" if deflate else "plain")
             if t >= warmup:
                 fallbacks += sum(fell)
-        p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu,
+            # a guess replaced by zero: the solve starts from zero (p is only its output)
+            start_zero = all(fell)
+        p, info = op.solve(fs[t], p=p, zero=start_zero, rtol=prm["rtol"], mode=mode, nu=nu,
                            nu_coarse=NU_COARSE, check_every=check_every, deflate=deflate)
         if t >= warmup:
             infos.append(info[0])
@@ -113,12 +116,14 @@ def run_profiled(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
     op = M.Operator(phis[0], prm["rho_neg"], prm["rho_pos"], prm["sigma"], workspace=ws)
     for t in range(warmup + steps):
         op.update(phis[t], prm["rho_neg"], prm["rho_pos"], prm["sigma"])
+        start_zero = zero
         if net is not None:
-            p, _ = op.learned_guess(net, fs[t], sweeps=2, out=p,
-                                    judge="deflated" if deflate else "plain")
+            p, fell = op.learned_guess(net, fs[t], sweeps=2, out=p,
+                                       judge="deflated" if deflate else "plain")
+            start_zero = all(fell)
         if t >= warmup:
             op.profile_start()
-        p, info = op.solve(fs[t], p=None if zero else p, rtol=prm["rtol"], mode=mode, nu=nu,
+        p, info = op.solve(fs[t], p=p, zero=start_zero, rtol=prm["rtol"], mode=mode, nu=nu,
                            nu_coarse=NU_COARSE, deflate=deflate)
         if t >= warmup:
             for k, v in op.profile_stop().items():

@@ -651,11 +651,12 @@ __global__ void __launch_bounds__(64) k_defl_coef(Defl D, int mode, const int* _
 }
 
 // r += g (A Z coef) on the band, g = scal[slot] of the problem or -1 (slot < 0); the
-// change of ||r||^2 goes to the partials after the producer's (offset off)
+// change of ||r||^2 goes to the partials after the producer's (offset off).  store = 0:
+// only the change of ||r||^2, r left as it is.
 template <typename T>
 __global__ void __launch_bounds__(kDefThreads)
     k_band_fix(T* __restrict__ r, int cells, Defl D, Ctl ctl, int slot, int off,
-               const int* __restrict__ active) {
+               const int* __restrict__ active, int store = 1) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   const int k = D.k[b];
@@ -678,7 +679,7 @@ __global__ void __launch_bounds__(kDefThreads)
       const size_t c = base + D.bcell[e0 + q];
       const T old = r[c];
       const T nv = (T)((double)old + g * u);
-      r[c] = nv;
+      if (store) r[c] = nv;
       delta += (double)nv * (double)nv - (double)old * (double)old;
     }
   }

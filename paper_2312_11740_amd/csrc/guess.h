@@ -141,17 +141,20 @@ __global__ void k_guess_prolong(const float* __restrict__ y, const double* __res
   p[idx] = s * rms64[q] / ((double)nc * nc);
 }
 
-// p *= alpha with alpha = (p.b) / (p.Ap) from the slots (0 when p.Ap is 0 or either
-// dot is not finite): the multiple of p closest to the solution in the energy norm
+// p = alpha (p - mean) with alpha = (p.b) / (p.Ap) from the slots (0 when p.Ap is 0 or
+// either dot is not finite): the zero-mean multiple of p closest to the solution in the
+// energy norm
+// (p.b and p.Ap do not depend on the mean, b having zero mean and A annihilating
+// constants, so the mean, scal[slot_mean], is removed in the same pass)
 __global__ void k_energy_scale(double* __restrict__ p, int cells, const double* __restrict__ scal,
-                               int slot_pb, int slot_pap, int slots) {
+                               int slot_pb, int slot_pap, int slot_mean, int slots) {
   const int q = blockIdx.y;
   const double* sc = scal + (size_t)q * slots;
-  const double pb = sc[slot_pb], pap = sc[slot_pap];
+  const double pb = sc[slot_pb], pap = sc[slot_pap], mean = sc[slot_mean];
   const double a = (pap != 0.0 && isfinite(pb) && isfinite(pap)) ? pb / pap : 0.0;
   double* pq = p + (size_t)q * cells;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x)
-    pq[c] *= a;
+    pq[c] = a * (pq[c] - mean);
 }
 
 }  // namespace mpp

@@ -1784,7 +1784,14 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
       hipLaunchKernelGGL(k_guess_prolong<0>, pgrid, dim3(256), 0, s, net->y, net->rms64, net->n, r, p);
     ck_launch();
     Ctl& ctl = op->inner;
-    remove_mean(op, ctl, p, s);
+    // the mean of p (removed by the energy scaling below)
+    EpiArgs em = epi(E_STORE_MEAN);
+    em.slot = S_SUM;
+    em.inv_cells = 1.0 / (double)L0.cells;
+    hipLaunchKernelGGL(k_sum<double>, grid_of(L0, B), dim3(kBlock), 0, s, (const double*)p,
+                       (int)L0.cells, ctl, em);
+    ck_launch();
+    finish_sums(op, ctl, em, L0.bpp, s);
     // scale along p to the energy-norm optimum: alpha = (p.b) / (p.Ap)
     const Faces<double> F = faces_of<double>(op, 0);
     const dim3 g = grid_of(L0, B);
@@ -1800,7 +1807,7 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
     finish_sums(op, ctl, e2, launch_apply<double>(op, F, p, op->q, ctl, 1, nullptr, s), s);
     ck_launch();
     hipLaunchKernelGGL(k_energy_scale, g, dim3(kBlock), 0, s, p, (int)L0.cells, ctl.scal,
-                       (int)S_RZ, (int)S_PQ, (int)kSlots);
+                       (int)S_RZ, (int)S_PQ, (int)S_SUM, (int)kSlots);
     ck_launch();
     // red-black sweeps on A p = b, alternating between p and a scratch vector
     double* bufs[2] = {p, op->q};
@@ -1832,17 +1839,17 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
       hipLaunchKernelGGL(k_band_sums<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
                          (const double*)p, cells, D, (const int*)nullptr);
       hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 1, (const int*)nullptr);
+      // (norms only: the band corrections are not stored)
       hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         op->r, cells, D, ctl, -1, parts, (const int*)nullptr);
+                         op->r, cells, D, ctl, -1, parts, (const int*)nullptr, 0);
       ck_launch();
       es.slot = S_RR;
       finish_sums(op, ctl, es, parts + kDefBandBlocks, s);
       hipLaunchKernelGGL(k_dot<double>, g, dim3(kBlock), 0, s, (const double*)op->b,
                          (const double*)op->b, cells, ctl, es, (const int*)nullptr);
-      ck(hipMemcpyAsync(op->z, op->b, sizeof(double) * work, hipMemcpyDeviceToDevice, s));
       hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 0, (const int*)nullptr);
       hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         op->z, cells, D, ctl, -1, L0.bpp, (const int*)nullptr);
+                         op->b, cells, D, ctl, -1, L0.bpp, (const int*)nullptr, 0);
       ck_launch();
       es.slot = S_BB;
       finish_sums(op, ctl, es, L0.bpp + kDefBandBlocks, s);
