@@ -110,12 +110,13 @@ __global__ void __launch_bounds__(kNetThreads)
 #pragma unroll
     for (int u = 0; u < NT; ++u) acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int kb = 0; kb < KB; ++kb) {
+  // operands of K step kb (weights of the NT column tiles, im2col rows of the kConvMT
+  // cell tiles); the loads of step kb + 1 are issued before the products of step kb, so
+  // that their latency overlaps the matrix-core work (same products, same order)
+  auto load = [&](int kb, bf16x8 (&bw)[NT], bf16x8 (&a)[kConvMT]) {
     const int k0 = kb * 32 + 8 * g;
-    bf16x8 bw[NT];
 #pragma unroll
     for (int u = 0; u < NT; ++u) bw[u] = ld8(w + (size_t)(16 * u + r16) * Kp + k0);
-    bf16x8 a[kConvMT];
     if (k0 < K) {
       const int tap = k0 / CI, c = k0 % CI;
       int dx, dy, dz;
@@ -131,10 +132,22 @@ __global__ void __launch_bounds__(kNetThreads)
 #pragma unroll
       for (int t = 0; t < kConvMT; ++t) a[t] = zero8();
     }
+  };
+  auto product = [&](const bf16x8 (&bw)[NT], const bf16x8 (&a)[kConvMT]) {
 #pragma unroll
     for (int t = 0; t < kConvMT; ++t)
 #pragma unroll
       for (int u = 0; u < NT; ++u) acc[t][u] = mfma(a[t], bw[u], acc[t][u]);
+  };
+  bf16x8 bw0[NT], a0[kConvMT], bw1[NT], a1[kConvMT];
+  load(0, bw0, a0);
+  for (int kb = 0; kb < KB; kb += 2) {
+    if (kb + 1 < KB) load(kb + 1, bw1, a1);
+    product(bw0, a0);
+    if (kb + 1 < KB) {
+      if (kb + 2 < KB) load(kb + 2, bw0, a0);
+      product(bw1, a1);
+    }
   }
   const size_t base = (size_t)b * cells;
 #pragma unroll
