@@ -573,10 +573,11 @@ __global__ void __launch_bounds__(kDefThreads)
 // (A Z)^T v over the band: per-block partials part[b][blk][j]
 template <typename T>
 __global__ void __launch_bounds__(kDefThreads)
-    k_band_sums(const T* __restrict__ v, int cells, Defl D, const int* __restrict__ active) {
-  const int b = blockIdx.y;
+    k_band_sums(const T* __restrict__ v, int cells, Defl D, Sel sel) {
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int k = D.k[b];
-  if (k <= 0 || (active && !active[b])) return;
+  if (k <= 0) return;
   __shared__ double acc[kDefMax][kDefThreads];
   for (int j = 0; j < k; ++j) acc[j][threadIdx.x] = 0.0;
   const int cnt = D.bcount[b];
@@ -656,9 +657,9 @@ __global__ void __launch_bounds__(64) k_defl_coef(Defl D, int mode, const int* _
 template <typename T>
 __global__ void __launch_bounds__(kDefThreads)
     k_band_fix(T* __restrict__ r, int cells, Defl D, Ctl ctl, int slot, int off,
-               const int* __restrict__ active, int store = 1) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
+               Sel sel, int store = 1) {
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int k = D.k[b];
   double delta = 0.0;
   if (k > 0) {
@@ -694,10 +695,11 @@ __global__ void __launch_bounds__(kDefThreads)
 template <typename T>
 __global__ void __launch_bounds__(kDefThreads)
     k_region_add(T* __restrict__ x, const uint8_t* __restrict__ lab, int cells, Defl D, int proj,
-                 const int* __restrict__ active) {
-  const int b = blockIdx.y;
+                 Sel sel) {
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int k = D.k[b];
-  if (k <= 0 || (active && !active[b])) return;
+  if (k <= 0) return;
   __shared__ double a[kDefMax];
   __shared__ double s[kDefMax];
   if (proj) {
@@ -726,8 +728,8 @@ __global__ void __launch_bounds__(kDefThreads)
 // The CG epilogue of p.q with deflation: p.(P q) = p.q - a.s with s = (A Z)^T p (the band
 // partials) and a = E^{-1} s kept in coef; then alpha and the breakdown check as E_PQ.
 __global__ void __launch_bounds__(1024) k_finish_pq_defl(Ctl ctl, int nparts, EpiArgs e, Defl D) {
-  const int b = blockIdx.x;
-  if (e.only_active && !ctl.active[b]) return;
+  const int b = row_problem(ctl.list, blockIdx.x);
+  if (b < 0 || (e.only_active && !ctl.active[b])) return;
   __shared__ double sh[16];
   __shared__ double s[kDefMax];
   const double* P = ctl.partials + (size_t)b * ctl.pstride;

@@ -138,8 +138,8 @@ __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& 
 }
 
 __global__ void __launch_bounds__(1024) k_finish(Ctl ctl, int nparts, EpiArgs e) {
-  const int b = blockIdx.x;
-  if (e.only_active && !ctl.active[b]) return;
+  const int b = row_problem(ctl.list, blockIdx.x);
+  if (b < 0 || (e.only_active && !ctl.active[b])) return;
   __shared__ double sh[16];
   const double* P = ctl.partials + (size_t)b * ctl.pstride;
   // four independent loads in flight per thread, fixed order of the sums
@@ -578,9 +578,9 @@ __global__ void k_sum(const T* __restrict__ v, int cells, Ctl ctl, EpiArgs e) {
 // ------------------------------------------------------------------------------
 template <typename T>
 __global__ void k_dot(const T* __restrict__ a, const T* __restrict__ bv, int cells, Ctl ctl,
-                      EpiArgs e, const int* __restrict__ active) {
-  const int pb = blockIdx.y;
-  if (active && !active[pb]) return;
+                      EpiArgs e, Sel sel) {
+  const int pb = sel_problem(sel, blockIdx.y);
+  if (pb < 0) return;
   const size_t base = (size_t)pb * cells;
   double acc = 0.0;
   CELL_LOOP(cells) acc += (double)a[base + c] * (double)bv[base + c];
@@ -591,8 +591,8 @@ __global__ void k_dot(const T* __restrict__ a, const T* __restrict__ bv, int cel
 template <typename T>
 __global__ void k_update_p(const T* __restrict__ z, T* __restrict__ p, int cells, Ctl ctl,
                            int first) {
-  const int pb = blockIdx.y;
-  if (!ctl.active[pb]) return;
+  const int pb = sel_problem(sel_of(ctl), blockIdx.y);
+  if (pb < 0) return;
   const size_t base = (size_t)pb * cells;
   const T beta = (T)ctl.scal[(size_t)pb * kSlots + S_BETA];
   CELL_LOOP(cells) p[base + c] = first ? z[base + c] : z[base + c] + beta * p[base + c];
@@ -602,8 +602,8 @@ __global__ void k_update_p(const T* __restrict__ z, T* __restrict__ p, int cells
 template <typename T>
 __global__ void k_update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                             const T* __restrict__ q, int cells, Ctl ctl, EpiArgs e) {
-  const int pb = blockIdx.y;
-  if (!ctl.active[pb]) return;
+  const int pb = sel_problem(sel_of(ctl), blockIdx.y);
+  if (pb < 0) return;
   const size_t base = (size_t)pb * cells;
   const T alpha = (T)ctl.scal[(size_t)pb * kSlots + S_ALPHA];
   double acc = 0.0;
@@ -657,6 +657,32 @@ __global__ void k_stop_failed(int B, const int* __restrict__ istatus, int* __res
     ostatus[b] = istatus[b];
     oactive[b] = 0;
   }
+}
+
+// list = [count, the problems whose active flag is set, in ascending order]: the row map
+// of the CG iterations (one block of 1024 threads; a wave ballot and the counts of the
+// waves before it place each problem)
+__global__ void __launch_bounds__(1024)
+    k_live_list(const int* __restrict__ active, int B, int* __restrict__ list) {
+  __shared__ int wcount[16];
+  __shared__ int base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) base = 0;
+  for (int c0 = 0; c0 < B; c0 += 1024) {
+    const int b = c0 + (int)threadIdx.x;
+    const int on = (b < B && active[b]) ? 1 : 0;
+    const unsigned long long m = __ballot(on);
+    if (lane == 0) wcount[w] = __popcll(m);
+    __syncthreads();
+    int at = base + __popcll(m & ((1ull << lane) - 1ull));
+    for (int q = 0; q < w; ++q) at += wcount[q];
+    if (on) list[1 + at] = b;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 16; ++q) base += wcount[q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) list[0] = base;
 }
 
 }  // namespace mpp
@@ -919,10 +945,9 @@ __device__ void small_copy_in(const SmallCycle<T>& S, T* lds, int pb) {
 }
 
 template <typename T, bool FL>
-__global__ void __launch_bounds__(kSmallBlock) k_small_cycle(SmallCycle<T> S,
-                                                             const int* __restrict__ active) {
-  const int pb = blockIdx.x;
-  if (active && !active[pb]) return;
+__global__ void __launch_bounds__(kSmallBlock) k_small_cycle(SmallCycle<T> S, Sel sel) {
+  const int pb = sel_problem(sel, blockIdx.x);
+  if (pb < 0) return;
   __shared__ __align__(16) unsigned char lds_raw[kSmallLdsBytes];
   __shared__ double sb[kMaxCoarse];
   T* const lds = reinterpret_cast<T*>(lds_raw);

@@ -177,6 +177,8 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     op->defl_over = cv.take<int>((size_t)B);
   }
   op->tail_mask = cv.take<int>((size_t)B);
+  op->live = cv.take<int>((size_t)B + 1);
+  op->rows = B;
   op->counters = cv.take<unsigned>((size_t)B);
   for (Ctl* c : {&op->outer, &op->inner}) {
     c->scal = cv.take<double>((size_t)B * kSlots);
@@ -186,6 +188,7 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
     c->partials = op->partials;
     c->counters = op->counters;
     c->pstride = op->pstride;
+    c->list = nullptr;
   }
   return cv.off + 256;
 }
@@ -223,6 +226,9 @@ template <> float* lvl_x<float>(Level& L) { return L.x32; }
 
 inline dim3 grid_of(const Level& lv, int B) { return dim3(lv.bpp, B); }
 
+// block rows of a launch: every problem's, or with a list the rows of the CG iterations
+inline int rows_of(const mpp_op_s* op, const int* list) { return list ? op->rows : op->batch; }
+
 EpiArgs epi(int kind) {
   EpiArgs e{};
   e.kind = kind;
@@ -233,7 +239,7 @@ EpiArgs epi(int kind) {
 // Adds the block partials of the preceding producer launch per problem and runs the
 // epilogue (one block per problem).
 void finish_sums(mpp_op_s* op, const Ctl& ctl, const EpiArgs& e, int nparts, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish, dim3(op->batch), dim3(1024), 0, s, ctl, nparts, e);
+  hipLaunchKernelGGL(k_finish, dim3(rows_of(op, ctl.list)), dim3(1024), 0, s, ctl, nparts, e);
   ck_launch();
 }
 
@@ -253,13 +259,13 @@ int st_kz(int n, int batch) {
 
 template <typename T>
 int launch_apply(const mpp_op_s* op, Faces<T> F, const T* x, T* y, const Ctl& ctl, int dot,
-                 const int* active, hipStream_t s) {
-  const int n = op->lev[0].n;
-  const int kz = st_kz(n, op->batch);
+                 Sel sel, hipStream_t s) {
+  const int n = op->lev[0].n, rows = rows_of(op, sel.list);
+  const int kz = st_kz(n, rows);
   const StTiles tl = st_tiles(n, kz);
-  const dim3 grid(st_grid(tl), op->batch);
+  const dim3 grid(st_grid(tl), rows);
   hipLaunchKernelGGL((k_stencil_z<T, 0>), grid, dim3(kStThreads), 0, s, F, n, tl, kz, x,
-                     (const T*)nullptr, y, ctl, dot, 0, active);
+                     (const T*)nullptr, y, ctl, dot, 0, sel);
   return dot ? (int)grid.x : 0;
 }
 
@@ -272,24 +278,24 @@ int launch_residual(const mpp_op_s* op, Faces<T> F, const T* rhs, const T* x, T*
   const StTiles tl = st_tiles(n, kz);
   const dim3 grid(st_grid(tl), op->batch);
   hipLaunchKernelGGL((k_stencil_z<T, 1>), grid, dim3(kStThreads), 0, s, F, n, tl, kz, x, rhs,
-                     r, ctl, 1, xzero, (const int*)nullptr);
+                     r, ctl, 1, xzero, Sel{});
   return (int)grid.x;
 }
 
 // coarse rhs of level l+1 from the residual of level l
 template <typename T>
 void launch_resid_restrict(const mpp_op_s* op, int l, Faces<T> F, const T* rhs, const T* x, T* bc,
-                           const int* active, hipStream_t s) {
-  const int n = op->lev[l].n;
-  const int kz = st_kz(n, op->batch);
+                           Sel sel, hipStream_t s) {
+  const int n = op->lev[l].n, rows = rows_of(op, sel.list);
+  const int kz = st_kz(n, rows);
   const StTiles tl = st_tiles(n, kz);
-  const dim3 grid(st_grid(tl), op->batch);
+  const dim3 grid(st_grid(tl), rows);
   if (l == 0)
     hipLaunchKernelGGL((k_resid_restrict_z<T, true>), grid, dim3(kStThreads), 0, s, F, n, tl, kz,
-                       rhs, x, bc, active);
+                       rhs, x, bc, sel);
   else
     hipLaunchKernelGGL((k_resid_restrict_z<T, false>), grid, dim3(kStThreads), 0, s, F, n, tl, kz,
-                       rhs, x, bc, active);
+                       rhs, x, bc, sel);
 }
 
 // ------------------------------------------------------------------------------
@@ -372,7 +378,7 @@ template <> double* level0_tmp<double>(mpp_op_s* op) { return op->q; }
 template <> float* level0_tmp<float>(mpp_op_s* op) { return op->q32; }
 
 template <typename T>
-void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, hipStream_t s,
+void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, Sel sel, hipStream_t s,
             const Ctl* dctl = nullptr, int* dot_parts = nullptr);
 
 // One fused sweep on level l with the kernel the tuner picked for it: kz > 0 the
@@ -382,16 +388,16 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
 // partials).
 template <typename T, int MODE, bool FINE>
 int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs, const T* in,
-              const T* ec, T* out, int c1, const Ctl& ctl, int dot, const int* active,
+              const T* ec, T* out, int c1, const Ctl& ctl, int dot, Sel sel,
               hipStream_t s) {
-  const int n = op->lev[l].n, B = op->batch;
+  const int n = op->lev[l].n, B = rows_of(op, sel.list);
   if (kz <= -4) {
     if constexpr (FINE) {
       if (n % 2 == 0) {
         const RbTiles tl = pr_tiles(n, -kz);
         const dim3 grid(rb_grid(tl), B);
         hipLaunchKernelGGL((k_rb_pair<T, MODE>), grid, dim3(kPrThreads), 0, s, F, n, tl, rhs,
-                           in, ec, out, c1, ctl, dot, active);
+                           in, ec, out, c1, ctl, dot, sel);
         return (int)grid.x;
       }
     }
@@ -403,19 +409,19 @@ int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs
     const dim3 grid(grid3(t3), B);
     if (shape == 0)
       hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE, 0>), grid, dim3(Shape3<0>::Threads), 0, s,
-                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, active);
+                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, sel);
     else if (shape == 1)
       hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE, 1>), grid, dim3(Shape3<1>::Threads), 0, s,
-                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, active);
+                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, sel);
     else
       hipLaunchKernelGGL((k_rb_sweep3d<T, MODE, FINE, 2>), grid, dim3(Shape3<2>::Threads), 0, s,
-                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, active);
+                         F, n, t3, rhs, in, ec, out, c1, ctl, dot, sel);
     return (int)grid.x;
   }
-  const RbTiles tl = rb_tiles(n, B, kz);
+  const RbTiles tl = rb_tiles(n, op->batch, kz);
   const dim3 grid(rb_grid(tl), B);
   hipLaunchKernelGGL((k_rb_sweep<T, MODE, FINE>), grid, dim3(kRbThreads), 0, s, F, n, tl, rhs, in,
-                     ec, out, c1, ctl, dot, active);
+                     ec, out, c1, ctl, dot, sel);
   return (int)grid.x;
 }
 
@@ -423,7 +429,7 @@ int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs
 // scratch array so that the last one lands in x; the prolongation is folded into the
 // first post-smoothing sweep and r.z (b.x) into the last one when dot_parts is given.
 template <typename T>
-void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active,
+void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, Sel sel,
                   hipStream_t s, const Ctl* dctl, int* dot_parts) {
   Level& L = op->lev[l];
   Level& Lc = op->lev[l + 1];
@@ -437,7 +443,7 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
   auto launch = [&](int sw, const T* in, int c1, int mode, int dot) {
     const T* ecv = lvl_x<T>(Lc);
 #define MPP_RB(MD, FN) \
-  nparts = launch_rb<T, MD, FN>(op, l, kz, F, rhs, in, ecv, dst(sw), c1, ctl, dot, active, s)
+  nparts = launch_rb<T, MD, FN>(op, l, kz, F, rhs, in, ecv, dst(sw), c1, ctl, dot, sel, s)
     if (fine) {
       if (mode == 1) MPP_RB(1, true); else if (mode == 2) MPP_RB(2, true); else MPP_RB(0, true);
     } else {
@@ -456,7 +462,7 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
   sweep(0, nullptr, 0, 1, 0);
   for (int q = 1; q < nu; ++q) sweep(q, dst(q - 1), 0, 0, 0);
   const T* xpre = dst(nu - 1);
-  auto restrict_ = [&] { launch_resid_restrict<T>(op, l, F, rhs, xpre, lvl_b<T>(Lc), active, s); };
+  auto restrict_ = [&] { launch_resid_restrict<T>(op, l, F, rhs, xpre, lvl_b<T>(Lc), sel, s); };
   if (fine)
     timed(op, K_RESID_RESTRICT, alg_bytes(op, K_RESID_RESTRICT, sizeof(T)), s, restrict_);
   else
@@ -464,9 +470,9 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
   ck_launch();
   if (fine)
     timed(op, K_COARSE_VCYCLE, 0.0, s,
-          [&] { vcycle<T>(op, 1, lvl_b<T>(Lc), lvl_x<T>(Lc), op->nu_c, active, s); });
+          [&] { vcycle<T>(op, 1, lvl_b<T>(Lc), lvl_x<T>(Lc), op->nu_c, sel, s); });
   else
-    vcycle<T>(op, l + 1, lvl_b<T>(Lc), lvl_x<T>(Lc), op->nu_c, active, s);
+    vcycle<T>(op, l + 1, lvl_b<T>(Lc), lvl_x<T>(Lc), op->nu_c, sel, s);
   const int want = dot_parts ? 1 : 0;
   sweep(nu, xpre, 1, 2, (nu == 1) ? want : 0);
   for (int q = nu + 1; q < 2 * nu; ++q) sweep(q, dst(q - 1), 1, 0, (q == 2 * nu - 1) ? want : 0);
@@ -474,13 +480,13 @@ void vcycle_fused(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* ac
 }
 
 template <typename T>
-void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, hipStream_t s,
+void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, Sel sel, hipStream_t s,
             const Ctl* dctl, int* dot_parts) {
   Level& L = op->lev[l];
-  const int B = op->batch;
+  const int B = rows_of(op, sel.list);
   if (dot_parts) *dot_parts = 0;
   if (l < op->nlev - 1 && L.cells > (size_t)kSmallCells) {
-    vcycle_fused<T>(op, l, rhs, x, nu, active, s, l == 0 ? dctl : nullptr,
+    vcycle_fused<T>(op, l, rhs, x, nu, sel, s, l == 0 ? dctl : nullptr,
                     l == 0 ? dot_parts : nullptr);
     return;
   }
@@ -503,9 +509,9 @@ void vcycle(mpp_op_s* op, int l, const T* rhs, T* x, int nu, const int* active, 
   if (fixed > (size_t)kSmallLdsBytes || S.nlev > 3 || S.m > kSmallBlock)
     throw HipError{hipErrorInvalidValue};
   if (fixed + fb <= (size_t)kSmallLdsBytes)
-    hipLaunchKernelGGL((k_small_cycle<T, true>), dim3(B), dim3(kSmallBlock), 0, s, S, active);
+    hipLaunchKernelGGL((k_small_cycle<T, true>), dim3(B), dim3(kSmallBlock), 0, s, S, sel);
   else
-    hipLaunchKernelGGL((k_small_cycle<T, false>), dim3(B), dim3(kSmallBlock), 0, s, S, active);
+    hipLaunchKernelGGL((k_small_cycle<T, false>), dim3(B), dim3(kSmallBlock), 0, s, S, sel);
   ck_launch();
 }
 
@@ -555,10 +561,12 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     return;
   }
   const int B = op->batch;
-  // the tail schedule is timed with problem 0 alone active
+  // the tail schedule is timed with problem 0 alone active, listed on one row
   if (B > 1) {
     hipLaunchKernelGGL(k_int_fill, dim3((B + 255) / 256), dim3(256), 0, s, op->tail_mask, B, 0);
     hipLaunchKernelGGL(k_int_fill, dim3(1), dim3(1), 0, s, op->tail_mask, 1, 1);
+    hipLaunchKernelGGL(k_live_list, dim3(1), dim3(1024), 0, s, (const int*)op->tail_mask, B,
+                       op->live);
     ck_launch();
   }
   hipEvent_t e0, e1;
@@ -569,7 +577,8 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     Level& L = op->lev[l];
     if (L.cells <= (size_t)kSmallCells) break;
     int* slot = tail ? &op->kz_tail[w][l] : &op->kz[w][l];
-    const int* mask = tail ? op->tail_mask : nullptr;
+    const Sel mask = tail ? Sel{op->tail_mask, op->live} : Sel{};
+    op->rows = tail ? 1 : B;
     const TuneKey key{op->n, B, (int)sizeof(T), L.n, tail};
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
@@ -635,6 +644,7 @@ void ensure_tuned(mpp_op_s* op, hipStream_t s) {
     g_tune.emplace(key, best_kz);   // the first tuning of a shape wins
     *slot = g_tune[key];
   }
+  op->rows = B;
   if (B == 1)
     for (int l = 0; l < op->nlev; ++l) op->kz_tail[w][l] = op->kz[w][l];
   (void)hipEventDestroy(e0);
@@ -804,10 +814,10 @@ void defl_start(mpp_op_s* op, Ctl& ctl, const T* rhs, const T* x, T* r, int xzer
   hipLaunchKernelGGL(k_defl_zb, dim3(B), dim3(64), 0, s, D, op->defl_rblk, (const int*)nullptr);
   if (!xzero)
     hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, x, cells,
-                       D, (const int*)nullptr);
+                       D, Sel{});
   hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, xzero ? 0 : 1, (const int*)nullptr);
   hipLaunchKernelGGL(k_band_fix<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, r, cells, D,
-                     ctl, -1, off, (const int*)nullptr);
+                     ctl, -1, off, Sel{});
   ck_launch();
 }
 
@@ -815,12 +825,12 @@ void defl_start(mpp_op_s* op, Ctl& ctl, const T* rhs, const T* x, T* r, int xzer
 template <typename T>
 void defl_project(mpp_op_s* op, const Ctl& ctl, T* z, hipStream_t s) {
   const Defl& D = op->defl;
-  const int B = op->batch, cells = (int)op->lev[0].cells;
+  const int rows = rows_of(op, ctl.list), cells = (int)op->lev[0].cells;
   timed(op, K_DEFL, 0.0, s, [&] {
-    hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, z, cells, D,
-                       ctl.active);
-    hipLaunchKernelGGL(k_region_add<T>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s, z, D.lab,
-                       cells, D, 1, ctl.active);
+    hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, rows), dim3(kDefThreads), 0, s, z,
+                       cells, D, sel_of(ctl));
+    hipLaunchKernelGGL(k_region_add<T>, dim3(op->defl_rblk, rows), dim3(kDefThreads), 0, s, z,
+                       D.lab, cells, D, 1, sel_of(ctl));
   });
   ck_launch();
 }
@@ -831,10 +841,10 @@ void defl_end(mpp_op_s* op, T* x, hipStream_t s) {
   const Defl& D = op->defl;
   const int B = op->batch, cells = (int)op->lev[0].cells;
   hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s, x, cells, D,
-                     (const int*)nullptr);
+                     Sel{});
   hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 1, (const int*)nullptr);
   hipLaunchKernelGGL(k_region_add<T>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s, x, D.lab,
-                     cells, D, 0, (const int*)nullptr);
+                     cells, D, 0, Sel{});
   ck_launch();
 }
 
@@ -849,11 +859,11 @@ void vcycle_dot(mpp_op_s* op, Ctl& ctl, const T* r, T* z, int nu, const EpiArgs&
                 hipStream_t s) {
   const Level& L0 = op->lev[0];
   int parts = 0;
-  vcycle<T>(op, 0, r, z, nu, ctl.active, s, &ctl, &parts);
+  vcycle<T>(op, 0, r, z, nu, sel_of(ctl), s, &ctl, &parts);
   if (parts == 0) {
     timed(op, K_DOT, alg_bytes(op, K_DOT, sizeof(T)), s, [&] {
-      hipLaunchKernelGGL(k_dot<T>, grid_of(L0, op->batch), dim3(kBlock), 0, s, r, z,
-                         (int)L0.cells, ctl, erz, ctl.active);
+      hipLaunchKernelGGL(k_dot<T>, grid_of(L0, rows_of(op, ctl.list)), dim3(kBlock), 0, s, r, z,
+                         (int)L0.cells, ctl, erz, sel_of(ctl));
     });
     ck_launch();
     parts = L0.bpp;
@@ -865,21 +875,28 @@ template <typename T>
 void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu, int iters,
                     hipStream_t s) {
   Level& L0 = op->lev[0];
-  const dim3 g = grid_of(L0, op->batch);
+  const int rows = rows_of(op, ctl.list);
+  const dim3 g = grid_of(L0, rows);
   const Faces<T> F = faces_of<T>(op, 0);
   const int cells = (int)L0.cells;
   const EpiArgs erz = epi(E_RZ), epq = epi(E_PQ), err = epi(E_RR_ITER);
   const bool defl = op->defl_use;
+  // the row map of this block of iterations from the flags as they stand
+  if (ctl.list) {
+    hipLaunchKernelGGL(k_live_list, dim3(1), dim3(1024), 0, s, (const int*)ctl.active, op->batch,
+                       op->live);
+    ck_launch();
+  }
   for (int it = 0; it < iters; ++it) {
     int parts = 0;
     timed(op, K_APPLY_DOT, alg_bytes(op, K_APPLY_DOT, sizeof(T)), s,
-          [&] { parts = launch_apply<T>(op, F, p, q, ctl, 1, ctl.active, s); });
+          [&] { parts = launch_apply<T>(op, F, p, q, ctl, 1, sel_of(ctl), s); });
     ck_launch();
     if (defl) {   // p.(P q) = p.q - a.s, s = (A Z)^T p over the band, a = E^{-1} s
       timed(op, K_DEFL, 0.0, s, [&] {
-        hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, op->batch), dim3(kDefThreads), 0,
-                           s, p, cells, op->defl, ctl.active);
-        hipLaunchKernelGGL(k_finish_pq_defl, dim3(op->batch), dim3(1024), 0, s, ctl, parts, epq,
+        hipLaunchKernelGGL(k_band_sums<T>, dim3(kDefBandBlocks, rows), dim3(kDefThreads), 0, s, p,
+                           cells, op->defl, sel_of(ctl));
+        hipLaunchKernelGGL(k_finish_pq_defl, dim3(rows), dim3(1024), 0, s, ctl, parts, epq,
                            op->defl);
       });
       ck_launch();
@@ -892,8 +909,8 @@ void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu
     ck_launch();
     if (defl) {   // r += alpha (A Z) a on the band (r -= alpha P q), ||r||^2 corrected
       timed(op, K_DEFL, 0.0, s, [&] {
-        hipLaunchKernelGGL(k_band_fix<T>, dim3(kDefBandBlocks, op->batch), dim3(kDefThreads), 0, s,
-                           r, cells, op->defl, ctl, (int)S_ALPHA, L0.bpp, ctl.active);
+        hipLaunchKernelGGL(k_band_fix<T>, dim3(kDefBandBlocks, rows), dim3(kDefThreads), 0, s, r,
+                           cells, op->defl, ctl, (int)S_ALPHA, L0.bpp, sel_of(ctl));
       });
       ck_launch();
       finish_sums(op, ctl, err, L0.bpp + kDefBandBlocks, s);
@@ -915,7 +932,6 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
          int check_every, int xzero, const EpiArgs& start, hipStream_t s,
          bool known_active = false) {
   Level& L0 = op->lev[0];
-  const dim3 g = grid_of(L0, op->batch);
   const Faces<T> F = faces_of<T>(op, 0);
   const int cells = (int)L0.cells;
   int parts = 0;
@@ -936,8 +952,19 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     parts += kDefBandBlocks;
   }
   finish_sums(op, ctl, start_, parts, s);
+  // the row map and the schedule of the iterations end with them, however pcg is left
+  struct Unlist {
+    mpp_op_s* op;
+    Ctl& c;
+    ~Unlist() {
+      c.list = nullptr;
+      op->rows = op->batch;
+      op->tail = false;
+    }
+  } unlist{op, ctl};
   // the iterate of a deflated CG takes its component in the regions at the end
   auto done_ = [&] {
+    ctl.list = nullptr;
     op->tail = false;
     if (defl) defl_end<T>(op, x, s);
   };
@@ -945,23 +972,40 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     done_();
     return;
   }
-  // few live problems of a batch: the tail schedule (more, smaller tiles per problem)
-  // (MPP_TAIL=0 keeps the full-batch schedule throughout)
+  // Once the live count of the last poll rounded up to a power of two is below the batch,
+  // the iterations serve the problems listed in op->live (rebuilt from the active flags
+  // at the start of every block of iterations) on that many block rows: the list never
+  // holds more, since problems only leave.  Before that every problem keeps its row (a
+  // list would launch as many rows and add a load to every block's start).  Few live
+  // problems of a batch also take the tail schedule (more, smaller tiles per problem).
+  // MPP_COMPACT=0 keeps every problem's row throughout, MPP_TAIL=0 the full-batch tiles.
   const int B = op->batch;
   const char* tail_env = std::getenv("MPP_TAIL");
   const bool tail_ok = B > 1 && !(tail_env && tail_env[0] == '0');
-  auto set_tail = [&] {
+  const char* compact_env = std::getenv("MPP_COMPACT");
+  const bool compact = !(compact_env && compact_env[0] == '0');
+  auto set_sched = [&] {
     int live = 0;
     for (int b = 0; b < B; ++b) live += op->h_active[b] != 0;
+    int rows = 1;
+    while (rows < live) rows *= 2;
+    op->rows = compact ? std::min(rows, B) : B;
     op->tail = tail_ok && live <= std::max(1, B / 8);
+    ctl.list = op->rows < B ? op->live : nullptr;
   };
-  set_tail();
+  set_sched();
+  if (ctl.list) {
+    hipLaunchKernelGGL(k_live_list, dim3(1), dim3(1024), 0, s, (const int*)ctl.active, B,
+                       op->live);
+    ck_launch();
+  }
   EpiArgs erz = epi(E_RZ);
   erz.first = 1;
   vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
   if (defl) defl_project<T>(op, ctl, z, s);
   timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
-    hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 1);
+    hipLaunchKernelGGL(k_update_p<T>, grid_of(L0, op->rows), dim3(kBlock), 0, s, z, p, cells, ctl,
+                       1);
   });
   ck_launch();
   // iterations in blocks of check_every; the kernels themselves stop working on a
@@ -971,7 +1015,8 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
   const bool graphs = op->use_graphs && !op->prof.on;
   for (int done = 0; done <= ctl.max_iter; done += check_every) {
     const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter, defl ? 1 : 0,
-                       op->tail ? 1 : 0, {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
+                       op->tail ? 1 : 0, op->rows, {(const void*)ctl.scal, x, r, z, p, q},
+                       op->shift};
     if (graphs)
       run_graph(op, key, s, [&](hipStream_t cs) {
         pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, cs);
@@ -979,7 +1024,7 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     else
       pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, s);
     if (!any_active(op, ctl, s)) break;
-    set_tail();
+    set_sched();
   }
   done_();
 }
@@ -1124,7 +1169,7 @@ void heat_pcg(mpp_op_s* op, Ctl& ctl, double* x, int check_every, hipStream_t s)
   ck_launch();
   // nu = 0 marks these graphs apart from the pressure solve's (nu >= 1)
   const bool graphs = op->use_graphs && !op->prof.on;
-  const GraphKey key{8, 0, 0, check_every, ctl.max_iter, 0, 0,
+  const GraphKey key{8, 0, 0, check_every, ctl.max_iter, 0, 0, op->batch,
                      {(const void*)ctl.scal, x, op->r, op->z, op->p, op->q}};
   for (int done = 0; done < ctl.max_iter; done += check_every) {
     if (graphs)
@@ -1265,7 +1310,7 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
       timed(op, K_DEFL, 0.0, s, [&] {
         defl_start<double>(op, oc, op->b, p, op->r, 0, parts, s);
         hipLaunchKernelGGL(k_region_add<double>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s,
-                           p, op->defl.lab, cells, op->defl, 0, (const int*)nullptr);
+                           p, op->defl.lab, cells, op->defl, 0, Sel{});
       });
       ck_launch();
       parts += kDefBandBlocks;
@@ -1560,7 +1605,7 @@ int mpp_apply_stencil(mpp_op op, const double* x, double* y, void* stream) {
   try {
     use_shift(op, 0.0, s);
     timed(op, K_APPLY, alg_bytes(op, K_APPLY, sizeof(double)), s, [&] {
-      launch_apply<double>(op, faces_of<double>(op, 0), x, y, op->outer, 0, nullptr, s);
+      launch_apply<double>(op, faces_of<double>(op, 0), x, y, op->outer, 0, Sel{}, s);
     });
     ck_launch();
   } catch (HipError& e) {
@@ -1593,7 +1638,7 @@ int mpp_vcycle(mpp_op op, const double* r, double* z, int nu, void* stream) {
     use_shift(op, 0.0, s);
     ensure_tuned<double>(op, s);
     op->nu_c = nu;
-    vcycle<double>(op, 0, r, z, nu, nullptr, s);
+    vcycle<double>(op, 0, r, z, nu, Sel{}, s);
   } catch (HipError& e) {
     return status_of(e.e);
   }
@@ -1799,12 +1844,12 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
     e1.slot = S_RZ;
     e1.inv_cells = 1.0;
     hipLaunchKernelGGL(k_dot<double>, g, dim3(kBlock), 0, s, (const double*)p, (const double*)op->b,
-                       (int)L0.cells, ctl, e1, (const int*)nullptr);
+                       (int)L0.cells, ctl, e1, Sel{});
     ck_launch();
     finish_sums(op, ctl, e1, L0.bpp, s);
     EpiArgs e2 = e1;
     e2.slot = S_PQ;
-    finish_sums(op, ctl, e2, launch_apply<double>(op, F, p, op->q, ctl, 1, nullptr, s), s);
+    finish_sums(op, ctl, e2, launch_apply<double>(op, F, p, op->q, ctl, 1, Sel{}, s), s);
     ck_launch();
     hipLaunchKernelGGL(k_energy_scale, g, dim3(kBlock), 0, s, p, (int)L0.cells, ctl.scal,
                        (int)S_RZ, (int)S_PQ, (int)S_SUM, (int)kSlots);
@@ -1814,7 +1859,7 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
     for (int q = 0; q < sweeps; ++q) {
       launch_rb<double, 0, true>(op, 0, op->kz[0][0], F, (const double*)op->b,
                                  (const double*)bufs[q & 1], (const double*)nullptr,
-                                 bufs[(q + 1) & 1], 0, ctl, 0, (const int*)nullptr, s);
+                                 bufs[(q + 1) & 1], 0, ctl, 0, Sel{}, s);
       ck_launch();
     }
     if (sweeps & 1)
@@ -1837,19 +1882,19 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
                          (const double*)op->b, D.lab, cells, D, (const int*)nullptr);
       hipLaunchKernelGGL(k_defl_zb, dim3(B), dim3(64), 0, s, D, op->defl_rblk, (const int*)nullptr);
       hipLaunchKernelGGL(k_band_sums<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         (const double*)p, cells, D, (const int*)nullptr);
+                         (const double*)p, cells, D, Sel{});
       hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 1, (const int*)nullptr);
       // (norms only: the band corrections are not stored)
       hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         op->r, cells, D, ctl, -1, parts, (const int*)nullptr, 0);
+                         op->r, cells, D, ctl, -1, parts, Sel{}, 0);
       ck_launch();
       es.slot = S_RR;
       finish_sums(op, ctl, es, parts + kDefBandBlocks, s);
       hipLaunchKernelGGL(k_dot<double>, g, dim3(kBlock), 0, s, (const double*)op->b,
-                         (const double*)op->b, cells, ctl, es, (const int*)nullptr);
+                         (const double*)op->b, cells, ctl, es, Sel{});
       hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 0, (const int*)nullptr);
       hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         op->b, cells, D, ctl, -1, L0.bpp, (const int*)nullptr, 0);
+                         op->b, cells, D, ctl, -1, L0.bpp, Sel{}, 0);
       ck_launch();
       es.slot = S_BB;
       finish_sums(op, ctl, es, L0.bpp + kDefBandBlocks, s);
@@ -2314,7 +2359,7 @@ void amr_precondition(const mpp_amr_s* a, mpp_op coarse, const double* phi0, con
   use_shift(coarse, 0.0, s);
   ensure_tuned<double>(coarse, s);
   coarse->nu_c = 2;
-  vcycle<double>(coarse, 0, W.rc, W.zc, 2, nullptr, s);
+  vcycle<double>(coarse, 0, W.rc, W.zc, 2, Sel{}, s);
   amr_launch_vec<AV_CADD>(a, V, W, s);
   for (int i = 0; i < kAmrNu; ++i) {
     az();

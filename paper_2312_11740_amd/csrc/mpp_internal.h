@@ -42,7 +42,31 @@ struct Ctl {
   unsigned* counters;   // [B] arrival counters of the last-block reductions (kept 0)
   int pstride;
   int max_iter;
+  const int* list;      // while CG iterates: the problems its launches serve (Sel), else nullptr
 };
+
+// The problems a launch serves.  Block row y (blockIdx.y; blockIdx.x for the kernels with
+// one block per problem) serves problem y, or with a list problem list[1 + y] while
+// y < list[0] and nothing on the rows past that; a problem whose active flag is 0 is
+// skipped.  A listed launch has as many rows as the live count of the last poll rounded
+// up to a power of two (never fewer than the list holds), so the late iterations of a
+// batch, with few live problems, launch few rows.
+struct Sel {
+  const int* active = nullptr;   // [B] flags; nullptr: no problem skipped
+  const int* list = nullptr;     // [1 + B] count, then problem indices in ascending order
+};
+
+__host__ __device__ inline Sel sel_of(const Ctl& c) { return Sel{c.active, c.list}; }
+
+__device__ inline int row_problem(const int* list, int row) {
+  return list ? (row < list[0] ? list[1 + row] : -1) : row;
+}
+
+// the problem of block row `row`, -1: the row has nothing to do
+__device__ inline int sel_problem(const Sel& s, int row) {
+  const int b = row_problem(s.list, row);
+  return (b < 0 || (s.active && !s.active[b])) ? -1 : b;
+}
 
 // Face coefficients of one level, in precision T.  On the finest level `code`
 // holds per cell: bits 0..5 set when the -x,+x,-y,+y,-z,+z face is crossed by the
@@ -143,12 +167,13 @@ struct Prof {
 // A captured block of CG iterations and what it was captured for.
 struct GraphKey {
   int tsize, nu, nu_c, iters, max_iter;
-  int defl, tail;
+  int defl, tail, rows;
   const void* ptr[6];
   double shift = 0.0;   // the operator's diagonal shift (a kernel argument in the graph)
   bool operator==(const GraphKey& o) const {
     if (tsize != o.tsize || nu != o.nu || nu_c != o.nu_c || iters != o.iters ||
-        max_iter != o.max_iter || defl != o.defl || tail != o.tail || shift != o.shift)
+        max_iter != o.max_iter || defl != o.defl || tail != o.tail || rows != o.rows ||
+        shift != o.shift)
       return false;
     for (int q = 0; q < 6; ++q)
       if (ptr[q] != o.ptr[q]) return false;
@@ -176,6 +201,8 @@ struct mpp_op_s {
   int kz_tail[2][mpp::kMaxLevels] = {};
   bool tail = false;                // the CG block being run uses kz_tail
   int* tail_mask = nullptr;         // [B] device: problem 0 active (tuning the tail)
+  int* live = nullptr;              // [1 + B] device: the list of the CG iterations (Sel)
+  int rows = 0;                     // block rows of the listed launches
   bool tuned[2] = {false, false};
   int nu_c = 2;                     // sweeps per level below the finest
   int n = 0, batch = 0, nlev = 0;

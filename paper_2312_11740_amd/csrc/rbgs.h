@@ -113,9 +113,9 @@ template <typename T, int MODE, bool FINE>
 __global__ void __launch_bounds__(kRbThreads)
     k_rb_sweep(Faces<T> F, int n, RbTiles tl, const T* __restrict__ rhs,
                const T* __restrict__ xin, const T* __restrict__ ec, T* __restrict__ xout, int c1,
-               Ctl ctl, int dot, const int* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
+               Ctl ctl, int dot, Sel sel) {
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int tile = xcd_tile(blockIdx.x, tl.ntiles);
   if (tile < 0) {
     if (dot && threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = 0.0;

@@ -68,15 +68,15 @@ template <typename T, int MODE, bool FINE, int SHAPE>
 __global__ void __launch_bounds__(Shape3<SHAPE>::Threads)
     k_rb_sweep3d(Faces<T> F, int n, Tiles3 tl, const T* __restrict__ rhs,
                  const T* __restrict__ xin, const T* __restrict__ ec, T* __restrict__ xout,
-                 int c1, Ctl ctl, int dot, const int* __restrict__ active) {
+                 int c1, Ctl ctl, int dot, Sel sel) {
   using Sh = Shape3<SHAPE>;
   using Ld = Lds3<T, SHAPE>;
   constexpr int k3X = Sh::X, k3Y = Sh::Y, k3Z = Sh::Z, k3Threads = Sh::Threads;
   constexpr int k3XX = Ld::XX, k3XY = Ld::XY;
   constexpr int k3BX = Ld::BX, k3BY = Ld::BY, k3BZ = Ld::BZ;
   constexpr int k3NX = Ld::NX, k3NB = Ld::NB;
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int tile = xcd_tile(blockIdx.x, tl.ntiles);
   if (tile < 0) {
     if (dot && threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = 0.0;

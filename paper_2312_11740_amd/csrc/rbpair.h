@@ -93,7 +93,7 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     k_rb_pair(Faces<T> F, int n, RbTiles tl, const T* __restrict__ rhs, const T* __restrict__ xin,
               const T* __restrict__ ec, T* __restrict__ xout, int c1, Ctl ctl, int dot,
-              const int* __restrict__ active) {
+              Sel sel) {
   using V = typename PairOf<T>::V;
   constexpr int TX = kPrTX, TY = kPrTY;
   constexpr int XH = TY + 4, CH = TY + 2;   // rows of the x_in and c1 tiles
@@ -101,8 +101,8 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   constexpr int XPL = XH * XP, CPL = CH * XP;   // one parity of one plane
   constexpr int XSL = 2 * XPL, CSL = 2 * CPL;   // one plane (slot)
   constexpr unsigned TS = sizeof(T);
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int tile = xcd_tile(blockIdx.x, tl.ntiles);
   if (tile < 0) {
     if (dot && threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = 0.0;

@@ -102,9 +102,9 @@ template <typename T, int KIND>
 __global__ void __launch_bounds__(kStThreads)
     k_stencil_z(Faces<T> F, int n, StTiles tl, int kz, const T* __restrict__ x,
                 const T* __restrict__ bvec, T* __restrict__ y, Ctl ctl, int dot, int xzero,
-                const int* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
+                Sel sel) {
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int tile = xcd_tile(blockIdx.x, tl.ntiles);
   if (tile < 0) {
     if (dot && threadIdx.x == 0) ctl.partials[(size_t)b * ctl.pstride + blockIdx.x] = 0.0;
@@ -162,10 +162,9 @@ __global__ void __launch_bounds__(kStThreads)
 template <typename T, bool FINE>
 __global__ void __launch_bounds__(kStThreads)
     k_resid_restrict_z(Faces<T> F, int n, StTiles tl, int kz, const T* __restrict__ bvec,
-                       const T* __restrict__ x, T* __restrict__ bc,
-                       const int* __restrict__ active) {
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
+                       const T* __restrict__ x, T* __restrict__ bc, Sel sel) {
+  const int b = sel_problem(sel, blockIdx.y);
+  if (b < 0) return;
   const int tile = xcd_tile(blockIdx.x, tl.ntiles);
   if (tile < 0) return;
   __shared__ T part[kStZ / 2][kStTY][kStTX / 2];

@@ -388,6 +388,37 @@ def test_batched_tail_schedule_agrees(mode, monkeypatch):
         check_solution(*cases[b], out["1"][0][b], out["1"][1][b])
 
 
+@pytest.mark.parametrize("mode,deflate", [("fp64", False), ("fp64", True), ("mixed", True)])
+def test_batched_row_map_agrees(mode, deflate, monkeypatch):
+    """The CG iterations of a batch serve a list of the live problems on as many block
+    rows as the last poll's live count rounded up to a power of two (rows 16 .. 1 here):
+    every problem gets the same iterations as with a row per problem, the answers agree
+    to rounding (the stencil kernels' z-chunks follow the rows, and with them the grouping
+    of the dot products) and every problem meets the oracle."""
+    n, B = 32, 16
+    # four hard problems (ratio 1000) among twelve easy ones (ratio 2); the hard ones
+    # are not the first rows, so the list moves them
+    hard = (2, 7, 9, 14)
+    cases = [bubbles_case(n, 500 + s, ratio=1000.0 if s in hard else 2.0) for s in range(B)]
+    phi = to_dev(np.stack([c[0] for c in cases]))
+    f = to_dev(np.stack([c[1] for c in cases]))
+    out = {}
+    for compact in ("0", "1"):
+        monkeypatch.setenv("MPP_COMPACT", compact)
+        op = M.Operator(phi, [c[2] for c in cases], [c[3] for c in cases],
+                        [c[4] for c in cases])
+        p, infos = op.solve(f, rtol=1e-10, mode=mode, deflate=deflate)
+        out[compact] = (to_host(p), infos)
+        op.close()
+    its = [i.iters for i in out["1"][1]]
+    print("iterations", its)
+    assert max(its) >= min(its) + 2       # problems left the list while others iterated
+    for b in range(B):
+        assert abs(out["0"][1][b].iters - its[b]) <= 1, b
+        assert rel2(out["1"][0][b], out["0"][0][b]) <= 1e-9, b
+        check_solution(*cases[b], out["1"][0][b], out["1"][1][b])
+
+
 def test_autotuned_chunks_do_not_change_the_answer():
     # the tuner only picks tile shapes: solutions agree with the default shapes
     import os
