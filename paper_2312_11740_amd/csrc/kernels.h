@@ -622,19 +622,40 @@ __global__ void k_fill(T* __restrict__ v, int cells, T val) {
   CELL_LOOP(cells) v[base + c] = val;
 }
 
-// mixed mode: r32 = r64 / ||r64|| (scale from the outer control block), and the inner
-// solve's iterate d32 = 0
+// mixed mode: r32 = r64 / ||r64|| (scale from the outer control block), the inner
+// solve's iterate d32 = 0, and ||r32||^2 block partials into the inner control block
+// (zero for a problem the outer loop no longer refines): the inner solve starts from
+// d32 = 0, so r32 is its residual and these are its start partials
 __global__ void k_scale_down(const double* __restrict__ r, float* __restrict__ r32,
                              float* __restrict__ d32, int cells, const double* __restrict__ oscal,
-                             const int* __restrict__ oactive) {
+                             const int* __restrict__ oactive, Ctl ictl) {
   const int pb = blockIdx.y;
-  if (!oactive[pb]) return;
+  if (!oactive[pb]) {
+    if (threadIdx.x == 0) ictl.partials[(size_t)pb * ictl.pstride + blockIdx.x] = 0.0;
+    return;
+  }
   const size_t base = (size_t)pb * cells;
   const double inv = 1.0 / sqrt(oscal[(size_t)pb * kSlots + S_RR]);
+  double acc = 0.0;
   CELL_LOOP(cells) {
-    r32[base + c] = (float)(r[base + c] * inv);
+    const float v = (float)(r[base + c] * inv);
+    r32[base + c] = v;
     d32[base + c] = 0.0f;
+    acc += (double)v * (double)v;
   }
+  block_partial(acc, ictl, pb);
+}
+
+// A control block back to its start: active flags, iteration counts, statuses and the
+// scalar slots zero (one launch instead of four fills)
+__global__ void k_ctl_reset(Ctl ctl, int B) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < B) {
+    ctl.active[t] = 0;
+    ctl.iters[t] = 0;
+    ctl.status[t] = 0;
+  }
+  if (t < B * kSlots) ctl.scal[t] = 0.0;
 }
 
 // mixed mode: x64 += ||r64|| d32

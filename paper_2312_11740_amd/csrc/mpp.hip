@@ -927,17 +927,21 @@ void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu
 }
 
 // known_active: the caller knows some problem is active at the start (no start poll).
+// given_parts > 0: the caller has r = rhs (x = 0) and that many ||r||^2 block partials in
+// place (no residual launch).
 template <typename T>
 void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int nu,
          int check_every, int xzero, const EpiArgs& start, hipStream_t s,
-         bool known_active = false) {
+         bool known_active = false, int given_parts = 0) {
   Level& L0 = op->lev[0];
   const Faces<T> F = faces_of<T>(op, 0);
   const int cells = (int)L0.cells;
-  int parts = 0;
-  timed(op, K_RESIDUAL, alg_bytes(op, K_RESIDUAL, sizeof(T)), s,
-        [&] { parts = launch_residual<T>(op, F, rhs, x, r, ctl, xzero, s); });
-  ck_launch();
+  int parts = given_parts;
+  if (parts == 0) {
+    timed(op, K_RESIDUAL, alg_bytes(op, K_RESIDUAL, sizeof(T)), s,
+          [&] { parts = launch_residual<T>(op, F, rhs, x, r, ctl, xzero, s); });
+    ck_launch();
+  }
   const bool defl = op->defl_use;
   EpiArgs start_ = start;
   if (defl) {   // CG on the deflated system: r <- P r
@@ -1031,10 +1035,9 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
 
 void reset_ctl(mpp_op_s* op, Ctl& ctl, int max_iter, hipStream_t s) {
   const int B = op->batch;
-  ck(hipMemsetAsync(ctl.active, 0, sizeof(int) * B, s));
-  ck(hipMemsetAsync(ctl.iters, 0, sizeof(int) * B, s));
-  ck(hipMemsetAsync(ctl.status, 0, sizeof(int) * B, s));
-  ck(hipMemsetAsync(ctl.scal, 0, sizeof(double) * B * kSlots, s));
+  ctl.list = nullptr;
+  hipLaunchKernelGGL(k_ctl_reset, dim3((B * kSlots + 255) / 256), dim3(256), 0, s, ctl, B);
+  ck_launch();
   ctl.max_iter = max_iter;
 }
 
@@ -1272,7 +1275,9 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
   // the iterate lives in the workspace (captured launch graphs refer to it); the
   // caller's p is copied in and out
   double* const p = op->x;
-  if (o.guess == MPP_GUESS_ZERO) {
+  // from zero the first residual is b itself (no reads of the iterate)
+  const bool zero_start = o.guess == MPP_GUESS_ZERO;
+  if (zero_start) {
     hipLaunchKernelGGL(k_fill<double>, g, dim3(kBlock), 0, s, p, cells, 0.0);
     ck_launch();
   } else {
@@ -1281,7 +1286,8 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
   EpiArgs start = epi(E_START);
   if (o.mode == MPP_MODE_FP64) {
     for (int restart = 0; restart < 4; ++restart) {
-      pcg<double>(op, oc, op->b, p, op->r, op->z, op->p, op->q, o.nu, o.check_every, 0, start, s);
+      pcg<double>(op, oc, op->b, p, op->r, op->z, op->p, op->q, o.nu, o.check_every,
+                  (restart == 0 && zero_start) ? 1 : 0, start, s);
       // true residual; re-arms the problems that are not there yet
       finish_sums(op, oc, start,
                   launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s), s);
@@ -1300,7 +1306,8 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
   istart.outer_rtol = o.rtol;
   bool settled = false;
   for (int outer = 0; outer < 40; ++outer) {
-    int parts = launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, 0, s);
+    const int xzero = (outer == 0 && zero_start) ? 1 : 0;
+    int parts = launch_residual<double>(op, faces_of<double>(op, 0), op->b, p, op->r, oc, xzero, s);
     ck_launch();
     if (op->defl_use) {
       // the regions' share of the correction in FP64: x += Z E^{-1} Z^T (b - A x) and
@@ -1308,7 +1315,7 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
       // per-region constants of the solution (in FP32 they would limit the true
       // residual reduction of a refinement step to about 1e-4)
       timed(op, K_DEFL, 0.0, s, [&] {
-        defl_start<double>(op, oc, op->b, p, op->r, 0, parts, s);
+        defl_start<double>(op, oc, op->b, p, op->r, xzero, parts, s);
         hipLaunchKernelGGL(k_region_add<double>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s,
                            p, op->defl.lab, cells, op->defl, 0, Sel{});
       });
@@ -1322,11 +1329,12 @@ void solve_core(mpp_op_s* op, const mpp_solve_opts& o, const double* user_p,
     }
     for (int b = 0; b < B; ++b) outer_count[b] += op->h_active[b];
     hipLaunchKernelGGL(k_scale_down, g, dim3(kBlock), 0, s, op->r, op->r32, op->d32, cells,
-                       oc.scal, oc.active);
+                       oc.scal, oc.active, ic);
     ck_launch();
-    // every problem still active in the refinement has work in its inner solve
+    // every problem still active in the refinement has work in its inner solve, which
+    // starts from d32 = 0 with the partials of ||r32||^2 in place
     pcg<float>(op, ic, op->r32, op->d32, op->r32, op->z32, op->p32, op->q32, o.nu,
-               o.check_every, 1, istart, s, true);
+               o.check_every, 1, istart, s, true, (int)L0.bpp);
     hipLaunchKernelGGL(k_correct, g, dim3(kBlock), 0, s, p, op->d32, cells, oc.scal, oc.active);
     ck_launch();
     // an inner breakdown or an exhausted iteration budget ends the refinement of that
