@@ -871,15 +871,19 @@ void vcycle_dot(mpp_op_s* op, Ctl& ctl, const T* r, T* z, int nu, const EpiArgs&
   finish_sums(op, ctl, erz, parts, s);
 }
 
+// `iters` CG iterations, each from z = V(r) to the convergence test on the updated
+// residual, so that a block of iterations ends with the test the host polls (a block
+// launched after the last useful test would run only kernels with nothing to do).
+// first: the block starts the CG (p = z, no beta).
 template <typename T>
 void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu, int iters,
-                    hipStream_t s) {
+                    bool first, hipStream_t s) {
   Level& L0 = op->lev[0];
   const int rows = rows_of(op, ctl.list);
   const dim3 g = grid_of(L0, rows);
   const Faces<T> F = faces_of<T>(op, 0);
   const int cells = (int)L0.cells;
-  const EpiArgs erz = epi(E_RZ), epq = epi(E_PQ), err = epi(E_RR_ITER);
+  const EpiArgs epq = epi(E_PQ), err = epi(E_RR_ITER);
   const bool defl = op->defl_use;
   // the row map of this block of iterations from the flags as they stand
   if (ctl.list) {
@@ -888,6 +892,15 @@ void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu
     ck_launch();
   }
   for (int it = 0; it < iters; ++it) {
+    const int f1 = (first && it == 0) ? 1 : 0;
+    EpiArgs erz = epi(E_RZ);
+    erz.first = f1;
+    vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
+    if (defl) defl_project<T>(op, ctl, z, s);
+    timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
+      hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, f1);
+    });
+    ck_launch();
     int parts = 0;
     timed(op, K_APPLY_DOT, alg_bytes(op, K_APPLY_DOT, sizeof(T)), s,
           [&] { parts = launch_apply<T>(op, F, p, q, ctl, 1, sel_of(ctl), s); });
@@ -917,12 +930,6 @@ void pcg_iterations(mpp_op_s* op, Ctl& ctl, T* x, T* r, T* z, T* p, T* q, int nu
     } else {
       finish_sums(op, ctl, err, L0.bpp, s);
     }
-    vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
-    if (defl) defl_project<T>(op, ctl, z, s);
-    timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
-      hipLaunchKernelGGL(k_update_p<T>, g, dim3(kBlock), 0, s, z, p, cells, ctl, 0);
-    });
-    ck_launch();
   }
 }
 
@@ -933,9 +940,7 @@ template <typename T>
 void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int nu,
          int check_every, int xzero, const EpiArgs& start, hipStream_t s,
          bool known_active = false, int given_parts = 0) {
-  Level& L0 = op->lev[0];
   const Faces<T> F = faces_of<T>(op, 0);
-  const int cells = (int)L0.cells;
   int parts = given_parts;
   if (parts == 0) {
     timed(op, K_RESIDUAL, alg_bytes(op, K_RESIDUAL, sizeof(T)), s,
@@ -998,35 +1003,22 @@ void pcg(mpp_op_s* op, Ctl& ctl, const T* rhs, T* x, T* r, T* z, T* p, T* q, int
     ctl.list = op->rows < B ? op->live : nullptr;
   };
   set_sched();
-  if (ctl.list) {
-    hipLaunchKernelGGL(k_live_list, dim3(1), dim3(1024), 0, s, (const int*)ctl.active, B,
-                       op->live);
-    ck_launch();
-  }
-  EpiArgs erz = epi(E_RZ);
-  erz.first = 1;
-  vcycle_dot<T>(op, ctl, r, z, nu, erz, s);
-  if (defl) defl_project<T>(op, ctl, z, s);
-  timed(op, K_UPDATE_P, alg_bytes(op, K_UPDATE_P, sizeof(T)), s, [&] {
-    hipLaunchKernelGGL(k_update_p<T>, grid_of(L0, op->rows), dim3(kBlock), 0, s, z, p, cells, ctl,
-                       1);
-  });
-  ck_launch();
   // iterations in blocks of check_every; the kernels themselves stop working on a
   // problem once it has converged, so a block may overrun the last useful iteration
   // (measured: spacing the polls by a prediction of the remaining iterations gains
   // nothing on one problem and loses on a batch)
   const bool graphs = op->use_graphs && !op->prof.on;
   for (int done = 0; done <= ctl.max_iter; done += check_every) {
+    const bool first = done == 0;
     const GraphKey key{(int)sizeof(T), nu, op->nu_c, check_every, ctl.max_iter, defl ? 1 : 0,
-                       op->tail ? 1 : 0, op->rows, {(const void*)ctl.scal, x, r, z, p, q},
-                       op->shift};
+                       op->tail ? 1 : 0, op->rows, first ? 1 : 0,
+                       {(const void*)ctl.scal, x, r, z, p, q}, op->shift};
     if (graphs)
       run_graph(op, key, s, [&](hipStream_t cs) {
-        pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, cs);
+        pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, first, cs);
       });
     else
-      pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, s);
+      pcg_iterations<T>(op, ctl, x, r, z, p, q, nu, check_every, first, s);
     if (!any_active(op, ctl, s)) break;
     set_sched();
   }
@@ -1172,7 +1164,7 @@ void heat_pcg(mpp_op_s* op, Ctl& ctl, double* x, int check_every, hipStream_t s)
   ck_launch();
   // nu = 0 marks these graphs apart from the pressure solve's (nu >= 1)
   const bool graphs = op->use_graphs && !op->prof.on;
-  const GraphKey key{8, 0, 0, check_every, ctl.max_iter, 0, 0, op->batch,
+  const GraphKey key{8, 0, 0, check_every, ctl.max_iter, 0, 0, op->batch, 0,
                      {(const void*)ctl.scal, x, op->r, op->z, op->p, op->q}};
   for (int done = 0; done < ctl.max_iter; done += check_every) {
     if (graphs)

@@ -167,13 +167,13 @@ struct Prof {
 // A captured block of CG iterations and what it was captured for.
 struct GraphKey {
   int tsize, nu, nu_c, iters, max_iter;
-  int defl, tail, rows;
+  int defl, tail, rows, first;
   const void* ptr[6];
   double shift = 0.0;   // the operator's diagonal shift (a kernel argument in the graph)
   bool operator==(const GraphKey& o) const {
     if (tsize != o.tsize || nu != o.nu || nu_c != o.nu_c || iters != o.iters ||
         max_iter != o.max_iter || defl != o.defl || tail != o.tail || rows != o.rows ||
-        shift != o.shift)
+        first != o.first || shift != o.shift)
       return false;
     for (int q = 0; q < 6; ++q)
       if (ptr[q] != o.ptr[q]) return false;
