@@ -444,6 +444,8 @@ __global__ void __launch_bounds__(1024) k_coarse_factor(const double* __restrict
   // small coarsest levels (the usual 4^3) are factored in LDS
   constexpr int kLdsM = 64;
   __shared__ double Ms[kLdsM * kLdsM], Xs[kLdsM * kLdsM];
+  __shared__ double Ms2[kLdsM * kLdsM], Xs2[kLdsM * kLdsM];   // the other buffer of [M | I]
+  const double* Xfin = Xs;   // LDS: the buffer holding M^{-1} at the end
   const bool lds = m <= kLdsM;
   double* M = lds ? Ms : work + bm;
   double* X = lds ? Xs : inv + bm;
@@ -469,26 +471,33 @@ __global__ void __launch_bounds__(1024) k_coarse_factor(const double* __restrict
   __syncthreads();
   if (lds) {
     // Gauss-Jordan on [M | I] in LDS, every thread on every pivot (M is symmetric
-    // positive definite: no pivoting needed)
-    __shared__ double fac[kLdsM];
+    // positive definite: no pivoting needed).  Each pivot step reads one buffer of
+    // [M | I] and writes the other, so one barrier per step separates them.
     for (int q = threadIdx.x; q < m * m; q += blockDim.x) X[q] = (q / m == q % m) ? 1.0 : 0.0;
     // thread t owns column t % (2m) of [M | I] and rows t / (2m), + rows_step, ...
     const int tw = 2 * m, col = threadIdx.x % tw, row0 = threadIdx.x / tw;
     const int rows_step = blockDim.x / tw;
     const bool has_col = (int)threadIdx.x < rows_step * tw;
-    double* cp = col < m ? M + col : X + (col - m);   // this column, stride m
+    double *Ma = Ms, *Xa = Xs, *Mb = Ms2, *Xb = Xs2;
     __syncthreads();
     for (int k = 0; k < m; ++k) {
-      // reads of pivot row and column before the barrier, writes after it
-      const double pinv = 1.0 / M[(size_t)k * m + k];
-      if ((int)threadIdx.x < m) fac[threadIdx.x] = M[(size_t)threadIdx.x * m + k];
-      const double pk = has_col ? cp[(size_t)k * m] * pinv : 0.0;   // pivot row, scaled
-      __syncthreads();
-      if (has_col)
+      const double pinv = 1.0 / Ma[(size_t)k * m + k];
+      if (has_col) {
+        const double* ca = col < m ? Ma + col : Xa + (col - m);   // this column, stride m
+        double* cb = col < m ? Mb + col : Xb + (col - m);
+        const double pk = ca[(size_t)k * m] * pinv;               // pivot row, scaled
         for (int i = row0; i < m; i += rows_step)
-          cp[(size_t)i * m] = i == k ? pk : cp[(size_t)i * m] - fac[i] * pk;
+          cb[(size_t)i * m] = i == k ? pk : ca[(size_t)i * m] - Ma[(size_t)i * m + k] * pk;
+      }
       __syncthreads();
+      double* t = Ma;
+      Ma = Mb;
+      Mb = t;
+      t = Xa;
+      Xa = Xb;
+      Xb = t;
     }
+    Xfin = Xa;
   } else {
   // left-looking Cholesky, lower triangle of M
   __shared__ double piv;
@@ -526,7 +535,7 @@ __global__ void __launch_bounds__(1024) k_coarse_factor(const double* __restrict
   }
   if (lds) {
     __syncthreads();
-    for (int q = threadIdx.x; q < m * m; q += blockDim.x) inv[bm + q] = Xs[q];
+    for (int q = threadIdx.x; q < m * m; q += blockDim.x) inv[bm + q] = Xfin[q];
   }
 }
 
@@ -612,6 +621,20 @@ __global__ void k_update_xr(T* __restrict__ x, T* __restrict__ r, const T* __res
     const T rc = r[base + c] - alpha * q[base + c];
     r[base + c] = rc;
     acc += (double)rc * (double)rc;
+  }
+  block_partial(acc, ctl, pb);
+}
+
+// r = rhs with ||r||^2 block partials: the residual of a zero iterate
+template <typename T>
+__global__ void k_copy_sq(const T* __restrict__ rhs, T* __restrict__ r, int cells, Ctl ctl) {
+  const int pb = blockIdx.y;
+  const size_t base = (size_t)pb * cells;
+  double acc = 0.0;
+  CELL_LOOP(cells) {
+    const T v = rhs[base + c];
+    r[base + c] = v;
+    acc += (double)v * (double)v;
   }
   block_partial(acc, ctl, pb);
 }

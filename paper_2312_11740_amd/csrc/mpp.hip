@@ -273,6 +273,12 @@ int launch_apply(const mpp_op_s* op, Faces<T> F, const T* x, T* y, const Ctl& ct
 template <typename T>
 int launch_residual(const mpp_op_s* op, Faces<T> F, const T* rhs, const T* x, T* r,
                     const Ctl& ctl, int xzero, hipStream_t s) {
+  if (xzero) {   // r = rhs: a streaming copy
+    const Level& L0 = op->lev[0];
+    hipLaunchKernelGGL(k_copy_sq<T>, grid_of(L0, op->batch), dim3(kBlock), 0, s, rhs, r,
+                       (int)L0.cells, ctl);
+    return L0.bpp;
+  }
   const int n = op->lev[0].n;
   const int kz = st_kz(n, op->batch);
   const StTiles tl = st_tiles(n, kz);
