@@ -105,40 +105,46 @@ __global__ void k_feat_write(const double* __restrict__ coarse, const double* __
 }
 
 // p[fine cell] = rms h^2 * trilinear interpolation of y at the cell's centre (cell-centred
-// coarse values, clamped at the walls; h = 1 / nc).  Grid: (cells of a problem / 256,
-// problems); R as for k_feat_coarsen.
+// coarse values, clamped at the walls; h = 1 / nc).  Grid: (rows of a problem = nf^2,
+// problems), a block per row of nf cells along x: the row's y and z weights and coarse
+// rows are the block's, each thread adds up x cells; R as for k_feat_coarsen.
 template <int R>
 __global__ void k_guess_prolong(const float* __restrict__ y, const double* __restrict__ rms64,
                                 int nc, int r_arg, double* __restrict__ p) {
   const int r = R > 0 ? R : r_arg;
-  const unsigned nf = (unsigned)(nc * r);
-  const unsigned cf = nf * nf * nf;
-  const unsigned l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= cf) return;
+  const int nf = nc * r;
+  const int row = blockIdx.x;   // j + nf k
   const int q = blockIdx.y;
-  const size_t idx = (size_t)q * cf + l;
-  const int fi[3] = {(int)(l % nf), (int)((l / nf) % nf), (int)(l / (nf * nf))};
-  int i0[3], i1[3];
-  double w1[3];
-  for (int a = 0; a < 3; ++a) {
-    const double u = (fi[a] + 0.5) / r - 0.5;
+  const int fj = row % nf, fk = row / nf;
+  auto axis = [&](int f, int& i0, int& i1, double& w1) {
+    const double u = (f + 0.5) / r - 0.5;
     const double fl = floor(u);
-    w1[a] = u - fl;
+    w1 = u - fl;
     const int lo = (int)fl;
-    i0[a] = lo < 0 ? 0 : (lo > nc - 1 ? nc - 1 : lo);
-    i1[a] = lo + 1 < 0 ? 0 : (lo + 1 > nc - 1 ? nc - 1 : lo + 1);
-  }
+    i0 = lo < 0 ? 0 : (lo > nc - 1 ? nc - 1 : lo);
+    i1 = lo + 1 < 0 ? 0 : (lo + 1 > nc - 1 ? nc - 1 : lo + 1);
+  };
+  int j0, j1, k0, k1;
+  double wy, wz;
+  axis(fj, j0, j1, wy);
+  axis(fk, k0, k1, wz);
   const float* yq = y + (size_t)q * nc * nc * nc;
-  double s = 0.0;
-  for (int cz = 0; cz < 2; ++cz)
-    for (int cy = 0; cy < 2; ++cy)
-      for (int cx = 0; cx < 2; ++cx) {
-        const double w = (cx ? w1[0] : 1.0 - w1[0]) * (cy ? w1[1] : 1.0 - w1[1]) *
-                         (cz ? w1[2] : 1.0 - w1[2]);
-        const int X = cx ? i1[0] : i0[0], Y = cy ? i1[1] : i0[1], Z = cz ? i1[2] : i0[2];
-        s += w * (double)yq[((size_t)Z * nc + Y) * nc + X];
-      }
-  p[idx] = s * rms64[q] / ((double)nc * nc);
+  const double scale = rms64[q] / ((double)nc * nc);
+  double* pr = p + (size_t)q * nf * nf * nf + (size_t)row * nf;
+  for (int fi = threadIdx.x; fi < nf; fi += blockDim.x) {
+    int i0, i1;
+    double wx;
+    axis(fi, i0, i1, wx);
+    double s = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const double w = (cx ? wx : 1.0 - wx) * (cy ? wy : 1.0 - wy) * (cz ? wz : 1.0 - wz);
+          const int X = cx ? i1 : i0, Y = cy ? j1 : j0, Z = cz ? k1 : k0;
+          s += w * (double)yq[((size_t)Z * nc + Y) * nc + X];
+        }
+    pr[fi] = s * scale;
+  }
 }
 
 // p = alpha (p - mean) with alpha = (p.b) / (p.Ap) from the slots (0 when p.Ap is 0 or
@@ -146,15 +152,21 @@ __global__ void k_guess_prolong(const float* __restrict__ y, const double* __res
 // energy norm
 // (p.b and p.Ap do not depend on the mean, b having zero mean and A annihilating
 // constants, so the mean, scal[slot_mean], is removed in the same pass)
+// (p32, optional: an FP32 copy of the result for the sweeps that follow)
 __global__ void k_energy_scale(double* __restrict__ p, int cells, const double* __restrict__ scal,
-                               int slot_pb, int slot_pap, int slot_mean, int slots) {
+                               int slot_pb, int slot_pap, int slot_mean, int slots,
+                               float* __restrict__ p32) {
   const int q = blockIdx.y;
   const double* sc = scal + (size_t)q * slots;
   const double pb = sc[slot_pb], pap = sc[slot_pap], mean = sc[slot_mean];
   const double a = (pap != 0.0 && isfinite(pb) && isfinite(pap)) ? pb / pap : 0.0;
   double* pq = p + (size_t)q * cells;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x)
-    pq[c] = a * (pq[c] - mean);
+  float* p32q = p32 ? p32 + (size_t)q * cells : nullptr;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x) {
+    const double v = a * (pq[c] - mean);
+    pq[c] = v;
+    if (p32q) p32q[c] = (float)v;
+  }
 }
 
 }  // namespace mpp

@@ -62,6 +62,7 @@ enum Epi {
   E_RZ,              // beta = total / rz (0 on the first iteration), rz = total
   E_PQ,              // alpha = rz / total; breakdown check
   E_RR_ITER,         // rr = total; ++iters; active = rr > tol2 && iters < max
+  E_ADD,             // scal[slot] += total
 };
 
 struct EpiArgs {
@@ -85,6 +86,7 @@ __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& 
   double* s = ctl.scal + (size_t)b * kSlots;
   switch (e.kind) {
     case E_STORE_MEAN: s[e.slot] = tot * e.inv_cells; break;
+    case E_ADD: s[e.slot] += tot; break;
     case E_MEAN: s[S_MEAN] = tot * e.inv_cells; break;
     case E_BB:
       s[S_BB] = tot;
@@ -555,9 +557,10 @@ __global__ void k_rhs_sum(const double* __restrict__ f, const double* __restrict
   block_partial(acc, ctl, pb);
 }
 
-// v -= scal[S_MEAN]; optional sum of squares into an epilogue
+// v -= scal[S_MEAN]; optional sum of squares into an epilogue; v32 (optional): an FP32
+// copy of the result
 __global__ void k_sub_mean_sq(double* __restrict__ v, int cells, Ctl ctl, EpiArgs e, int slot,
-                              int want_sq) {
+                              int want_sq, float* __restrict__ v32 = nullptr) {
   const int pb = blockIdx.y;
   const size_t base = (size_t)pb * cells;
   const double mean = ctl.scal[(size_t)pb * kSlots + slot];
@@ -565,9 +568,16 @@ __global__ void k_sub_mean_sq(double* __restrict__ v, int cells, Ctl ctl, EpiArg
   CELL_LOOP(cells) {
     const double x = v[base + c] - mean;
     v[base + c] = x;
+    if (v32) v32[base + c] = (float)x;
     acc += x * x;
   }
   if (want_sq) block_partial(acc, ctl, pb);
+}
+
+// x = (double) x32
+__global__ void k_widen(const float* __restrict__ x32, double* __restrict__ x, int cells) {
+  const size_t base = (size_t)blockIdx.y * cells;
+  CELL_LOOP(cells) x[base + c] = (double)x32[base + c];
 }
 
 template <typename T>
@@ -594,6 +604,28 @@ __global__ void k_dot(const T* __restrict__ a, const T* __restrict__ bv, int cel
   double acc = 0.0;
   CELL_LOOP(cells) acc += (double)a[base + c] * (double)bv[base + c];
   block_partial(acc, ctl, pb);
+}
+
+// The sum of p and p.b in one pass: per problem, the block partials of the sum at
+// [0, gridDim.x) of its partials row and those of p.b right after them
+__global__ void k_sum_dot(const double* __restrict__ p, const double* __restrict__ b, int cells,
+                          Ctl ctl) {
+  const int q = blockIdx.y;
+  const size_t base = (size_t)q * cells;
+  double s1 = 0.0, s2 = 0.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += gridDim.x * blockDim.x) {
+    const double v = p[base + c];
+    s1 += v;
+    s2 += v * b[base + c];
+  }
+  __shared__ double sh[16];
+  const double t1 = block_sum(s1, sh);
+  const double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    double* P = ctl.partials + (size_t)q * ctl.pstride;
+    P[blockIdx.x] = t1;
+    P[gridDim.x + blockIdx.x] = t2;
+  }
 }
 
 // p = z + beta p   (first: p = z)

@@ -149,6 +149,8 @@ size_t layout(mpp_op_s* op, const mpp_desc* d, char* base) {
   }
   for (int kz = 2; kz <= kStKZ; kz *= 2)   // every chunk size st_kz may pick
     op->pstride = std::max(op->pstride, st_grid(st_tiles(sizes[0], kz)));
+  // the learned guess's sum and dot share a pass: two sets of finest-level partials
+  op->pstride = std::max(op->pstride, 2 * op->lev[0].bpp);
   // the band correction of a deflated CG appends its partials after a producer's
   op->pstride += kDefBandBlocks;
   op->partials = cv.take<double>((size_t)B * op->pstride);
@@ -1041,7 +1043,7 @@ void reset_ctl(mpp_op_s* op, Ctl& ctl, int max_iter, hipStream_t s) {
 
 // b = f + jterm - mean, into `out`; S_MEAN of ctl
 void make_rhs(mpp_op_s* op, Ctl& ctl, const double* f, double* out, hipStream_t s,
-              double rtol, bool want_bb) {
+              double rtol, bool want_bb, float* out32 = nullptr) {
   const Level& L0 = op->lev[0];
   const dim3 g = grid_of(L0, op->batch);
   const int cells = (int)L0.cells;
@@ -1053,7 +1055,7 @@ void make_rhs(mpp_op_s* op, Ctl& ctl, const double* f, double* out, hipStream_t 
   EpiArgs eb = epi(E_BB);
   eb.rtol2 = rtol * rtol;
   hipLaunchKernelGGL(k_sub_mean_sq, g, dim3(kBlock), 0, s, out, cells, ctl, eb, (int)S_MEAN,
-                     want_bb ? 1 : 0);
+                     want_bb ? 1 : 0, out32);
   ck_launch();
   if (want_bb) finish_sums(op, ctl, eb, L0.bpp, s);
 }
@@ -1069,7 +1071,8 @@ void remove_mean(mpp_op_s* op, Ctl& ctl, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_sum<double>, g, dim3(kBlock), 0, s, x, cells, ctl, e);
   ck_launch();
   finish_sums(op, ctl, e, L0.bpp, s);
-  hipLaunchKernelGGL(k_sub_mean_sq, g, dim3(kBlock), 0, s, x, cells, ctl, e, (int)S_SUM, 0);
+  hipLaunchKernelGGL(k_sub_mean_sq, g, dim3(kBlock), 0, s, x, cells, ctl, e, (int)S_SUM, 0,
+                     (float*)nullptr);
   ck_launch();
 }
 
@@ -1771,7 +1774,8 @@ void net_inputs(mpp_op_s* op, mpp_net_s* net, const double* f, const double* p, 
   const int B = op->batch, nc = net->n, r = op->n / net->n;
   const int cells_c = nc * nc * nc;
   reset_ctl(op, op->inner, 1, s);
-  make_rhs(op, op->inner, f, op->b, s, 0.0, true);
+  // (with an FP32 copy of b in r32 for the guess's sweeps)
+  make_rhs(op, op->inner, f, op->b, s, 0.0, true, op->r32);
   const dim3 cgrid((unsigned)((cells_c + 255) / 256), B);
   const unsigned nb = (unsigned)(((size_t)cells_c * B + 255) / 256);
   // the per-workgroup partial sums of the rms go to the prediction buffer, which the
@@ -1821,55 +1825,63 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
   try {
     use_shift(op, 0.0, s);
     ensure_tuned<double>(op, s);
+    ensure_tuned<float>(op, s);
     // the deflated judge needs the regions (their build uses the scratch vectors below)
     const bool dj = judge == MPP_JUDGE_DEFLATED;
     if (dj && !op->defl_ready) build_deflation(op, s);
     net_inputs(op, net, f, nullptr, net->x4, nullptr, s);
     const int st = mppnet::forward(net, net->x4, net->y, B, s);
     if (st != MPP_OK) return st;
-    const size_t work = L0.cells * B;
-    const dim3 pgrid((unsigned)((L0.cells + 255) / 256), B);
+    // a block per row of the fine grid
+    const int nf = op->n;
+    const dim3 pgrid((unsigned)nf * (unsigned)nf, B);
+    const dim3 pblk(nf >= 256 ? 256 : 64 * ((nf + 63) / 64));
     if (r == 4)
-      hipLaunchKernelGGL(k_guess_prolong<4>, pgrid, dim3(256), 0, s, net->y, net->rms64, net->n, r, p);
+      hipLaunchKernelGGL(k_guess_prolong<4>, pgrid, pblk, 0, s, net->y, net->rms64, net->n, r, p);
     else
-      hipLaunchKernelGGL(k_guess_prolong<0>, pgrid, dim3(256), 0, s, net->y, net->rms64, net->n, r, p);
+      hipLaunchKernelGGL(k_guess_prolong<0>, pgrid, pblk, 0, s, net->y, net->rms64, net->n, r, p);
     ck_launch();
     Ctl& ctl = op->inner;
-    // the mean of p (removed by the energy scaling below)
+    // the mean of p (removed by the energy scaling below) and p.b in one pass, then p.Ap
+    // (no A p stored): alpha = (p.b) / (p.Ap) scales p to the energy-norm optimum
+    const Faces<double> F = faces_of<double>(op, 0);
+    const dim3 g = grid_of(L0, B);
+    hipLaunchKernelGGL(k_sum_dot, g, dim3(kBlock), 0, s, (const double*)p, (const double*)op->b,
+                       (int)L0.cells, ctl);
+    ck_launch();
     EpiArgs em = epi(E_STORE_MEAN);
     em.slot = S_SUM;
     em.inv_cells = 1.0 / (double)L0.cells;
-    hipLaunchKernelGGL(k_sum<double>, grid_of(L0, B), dim3(kBlock), 0, s, (const double*)p,
-                       (int)L0.cells, ctl, em);
-    ck_launch();
     finish_sums(op, ctl, em, L0.bpp, s);
-    // scale along p to the energy-norm optimum: alpha = (p.b) / (p.Ap)
-    const Faces<double> F = faces_of<double>(op, 0);
-    const dim3 g = grid_of(L0, B);
     EpiArgs e1 = epi(E_STORE_MEAN);
     e1.slot = S_RZ;
     e1.inv_cells = 1.0;
-    hipLaunchKernelGGL(k_dot<double>, g, dim3(kBlock), 0, s, (const double*)p, (const double*)op->b,
-                       (int)L0.cells, ctl, e1, Sel{});
-    ck_launch();
-    finish_sums(op, ctl, e1, L0.bpp, s);
+    Ctl shifted = ctl;   // the p.b partials follow the sum's
+    shifted.partials += L0.bpp;
+    finish_sums(op, shifted, e1, L0.bpp, s);
     EpiArgs e2 = e1;
     e2.slot = S_PQ;
-    finish_sums(op, ctl, e2, launch_apply<double>(op, F, p, op->q, ctl, 1, Sel{}, s), s);
+    finish_sums(op, ctl, e2, launch_apply<double>(op, F, p, (double*)nullptr, ctl, 1, Sel{}, s),
+                s);
     ck_launch();
     hipLaunchKernelGGL(k_energy_scale, g, dim3(kBlock), 0, s, p, (int)L0.cells, ctl.scal,
-                       (int)S_RZ, (int)S_PQ, (int)S_SUM, (int)kSlots);
+                       (int)S_RZ, (int)S_PQ, (int)S_SUM, (int)kSlots,
+                       sweeps > 0 ? op->z32 : (float*)nullptr);
     ck_launch();
-    // red-black sweeps on A p = b, alternating between p and a scratch vector
-    double* bufs[2] = {p, op->q};
-    for (int q = 0; q < sweeps; ++q) {
-      launch_rb<double, 0, true>(op, 0, op->kz[0][0], F, (const double*)op->b,
-                                 (const double*)bufs[q & 1], (const double*)nullptr,
-                                 bufs[(q + 1) & 1], 0, ctl, 0, Sel{}, s);
+    // red-black sweeps on A p = b in FP32 (b in r32 from the right-hand side's assembly,
+    // p in z32 from the scaling), alternating between z32 and q32, then p in FP64
+    if (sweeps > 0) {
+      float* bufs[2] = {op->z32, op->q32};
+      for (int q = 0; q < sweeps; ++q) {
+        launch_rb<float, 0, true>(op, 0, op->kz[1][0], faces_of<float>(op, 0),
+                                  (const float*)op->r32, (const float*)bufs[q & 1],
+                                  (const float*)nullptr, bufs[(q + 1) & 1], 0, ctl, 0, Sel{}, s);
+        ck_launch();
+      }
+      hipLaunchKernelGGL(k_widen, g, dim3(kBlock), 0, s, (const float*)bufs[sweeps & 1], p,
+                         (int)L0.cells);
       ck_launch();
     }
-    if (sweeps & 1)
-      ck(hipMemcpyAsync(p, op->q, sizeof(double) * work, hipMemcpyDeviceToDevice, s));
     if (!dj) {
       // fallback check on ||b - A p|| against ||b||
       finish_sums(op, ctl, epi(E_START),
@@ -1896,14 +1908,14 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
       ck_launch();
       es.slot = S_RR;
       finish_sums(op, ctl, es, parts + kDefBandBlocks, s);
-      hipLaunchKernelGGL(k_dot<double>, g, dim3(kBlock), 0, s, (const double*)op->b,
-                         (const double*)op->b, cells, ctl, es, Sel{});
+      // ||b||^2 is in S_BB from the right-hand side's assembly: only the band's change
       hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 0, (const int*)nullptr);
       hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         op->b, cells, D, ctl, -1, L0.bpp, Sel{}, 0);
+                         op->b, cells, D, ctl, -1, 0, Sel{}, 0);
       ck_launch();
-      es.slot = S_BB;
-      finish_sums(op, ctl, es, L0.bpp + kDefBandBlocks, s);
+      EpiArgs ea = epi(E_ADD);
+      ea.slot = S_BB;
+      finish_sums(op, ctl, ea, kDefBandBlocks, s);
     }
     ck(hipMemcpyAsync(op->h_scal, ctl.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
     ck(hipStreamSynchronize(s));

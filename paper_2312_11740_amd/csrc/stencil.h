@@ -96,7 +96,7 @@ __device__ inline void load_batch(const T* xb, const uint8_t* cb, int off, int i
 }
 
 // KIND 0: y = A x (+ x.y partials when dot);  KIND 1: y = b - A x (+ ||y||^2 partials),
-// with x taken as 0 when xzero.  Threads own columns of a 64 x 4 tile and handle its
+// with x taken as 0 when xzero.  y = nullptr: the partials only.  Threads own columns of a 64 x 4 tile and handle its
 // z-chunk in batches of kStZ planes.
 template <typename T, int KIND>
 __global__ void __launch_bounds__(kStThreads)
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(kStThreads)
           out = bv[h] - ax;
           if (dot) acc += (double)out * (double)out;
         }
-        y[cell] = out;
+        if (y) y[cell] = out;
       }
     }
   }
