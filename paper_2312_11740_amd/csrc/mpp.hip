@@ -1865,13 +1865,15 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
                 s);
     ck_launch();
     hipLaunchKernelGGL(k_energy_scale, g, dim3(kBlock), 0, s, p, (int)L0.cells, ctl.scal,
-                       (int)S_RZ, (int)S_PQ, (int)S_SUM, (int)kSlots,
-                       sweeps > 0 ? op->z32 : (float*)nullptr);
+                       (int)S_RZ, (int)S_PQ, (int)S_SUM, (int)kSlots, op->z32);
     ck_launch();
     // red-black sweeps on A p = b in FP32 (b in r32 from the right-hand side's assembly,
-    // p in z32 from the scaling), alternating between z32 and q32, then p in FP64
+    // p in z32 from the scaling), alternating between z32 and q32, then p in FP64; pf: the
+    // guess in FP32 (p holds exactly its values)
+    float* pf = op->z32;
     if (sweeps > 0) {
       float* bufs[2] = {op->z32, op->q32};
+      pf = bufs[sweeps & 1];
       for (int q = 0; q < sweeps; ++q) {
         launch_rb<float, 0, true>(op, 0, op->kz[1][0], faces_of<float>(op, 0),
                                   (const float*)op->r32, (const float*)bufs[q & 1],
@@ -1882,10 +1884,13 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
                          (int)L0.cells);
       ck_launch();
     }
+    // the judge's residual norms in FP32 arithmetic (FP64 sums) on the same values: r in
+    // d32 from b in r32 and the guess in pf
+    const Faces<float> F32 = faces_of<float>(op, 0);
     if (!dj) {
       // fallback check on ||b - A p|| against ||b||
       finish_sums(op, ctl, epi(E_START),
-                  launch_residual<double>(op, F, op->b, p, op->r, ctl, 0, s), s);
+                  launch_residual<float>(op, F32, op->r32, pf, op->d32, ctl, 0, s), s);
       ck_launch();
     } else {
       // the deflated solve starts from P (b - A p) with the guess and from P b without it:
@@ -1895,16 +1900,16 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
       const int cells = (int)L0.cells;
       EpiArgs es = epi(E_STORE_MEAN);
       es.inv_cells = 1.0;
-      const int parts = launch_residual<double>(op, F, op->b, p, op->r, ctl, 0, s);
+      const int parts = launch_residual<float>(op, F32, op->r32, pf, op->d32, ctl, 0, s);
       hipLaunchKernelGGL(k_region_sums<double>, dim3(op->defl_rblk, B), dim3(kDefThreads), 0, s,
                          (const double*)op->b, D.lab, cells, D, (const int*)nullptr);
       hipLaunchKernelGGL(k_defl_zb, dim3(B), dim3(64), 0, s, D, op->defl_rblk, (const int*)nullptr);
-      hipLaunchKernelGGL(k_band_sums<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         (const double*)p, cells, D, Sel{});
+      hipLaunchKernelGGL(k_band_sums<float>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
+                         (const float*)pf, cells, D, Sel{});
       hipLaunchKernelGGL(k_defl_coef, dim3(B), dim3(64), 0, s, D, 1, (const int*)nullptr);
       // (norms only: the band corrections are not stored)
-      hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
-                         op->r, cells, D, ctl, -1, parts, Sel{}, 0);
+      hipLaunchKernelGGL(k_band_fix<float>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
+                         op->d32, cells, D, ctl, -1, parts, Sel{}, 0);
       ck_launch();
       es.slot = S_RR;
       finish_sums(op, ctl, es, parts + kDefBandBlocks, s);
