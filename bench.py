@@ -100,7 +100,8 @@ def run_sequence(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
             # a guess replaced by zero: the solve starts from zero (p is only its output)
             start_zero = all(fell)
         p, info = op.solve(fs[t], p=p, zero=start_zero, rtol=prm["rtol"], mode=mode, nu=nu,
-                           nu_coarse=NU_COARSE, check_every=check_every, deflate=deflate)
+                           nu_coarse=NU_COARSE, check_every=check_every, deflate=deflate,
+                           reuse_rhs=net is not None)
         if t >= warmup:
             infos.append(info[0])
     torch.cuda.synchronize()
@@ -124,7 +125,7 @@ def run_profiled(M, torch, ws, phis, fs, prm, mode, nu, steps, warmup, net=None,
         if t >= warmup:
             op.profile_start()
         p, info = op.solve(fs[t], p=p, zero=start_zero, rtol=prm["rtol"], mode=mode, nu=nu,
-                           nu_coarse=NU_COARSE, deflate=deflate)
+                           nu_coarse=NU_COARSE, deflate=deflate, reuse_rhs=net is not None)
         if t >= warmup:
             for k, v in op.profile_stop().items():
                 s = stats.setdefault(k, dict(launches=0, ms=0.0, bytes=0.0))

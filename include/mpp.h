@@ -100,7 +100,11 @@ typedef struct {
                            * needs, between inner_rtol and 1/2 */
     int32_t deflate;      /* 1: deflate the regions of the lighter phase (below), 0: plain
                            * MG-PCG */
-    int32_t reserved;     /* 0 */
+    int32_t reuse_rhs;    /* 1: when the previous call on this operator was
+                           * mpp_learned_guess with the same f (whose contents the caller
+                           * has not changed since), take the right-hand side that call
+                           * assembled instead of assembling it again; otherwise, or 0,
+                           * assemble it from f */
 } mpp_solve_opts;
 
 /* Deflation (opts->deflate = 1).  Every connected region of the lighter phase (a bubble,

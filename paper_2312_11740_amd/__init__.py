@@ -48,7 +48,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("guess", ctypes.c_int32), ("nu", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("nu_coarse", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("deflate", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("deflate", ctypes.c_int32), ("reuse_rhs", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -342,14 +342,18 @@ class Operator:
         return [sizes[i] for i in range(nl.value)]
 
     def solve(self, f, p=None, rtol=1e-10, mode="fp64", max_iter=500, nu=2, check_every=2,
-              inner_rtol=1e-5, raise_on_error=True, nu_coarse=0, deflate=True, zero=False):
+              inner_rtol=1e-5, raise_on_error=True, nu_coarse=0, deflate=True, zero=False,
+              reuse_rhs=False):
         """Returns (p, [Info per problem]).  p: optional initial guess (overwritten); with
         zero=True p is only the output array and the solve starts from zero.  deflate:
-        deflate the lighter phase's regions (mpp_solve_opts.deflate)."""
+        deflate the lighter phase's regions (mpp_solve_opts.deflate).  reuse_rhs: take the
+        right-hand side the preceding learned_guess with this f assembled
+        (mpp_solve_opts.reuse_rhs)."""
         _check_field(f, self.shape, "f")
         opts = SolveOpts()
         load_library().mpp_default_opts(ctypes.byref(opts))
         opts.deflate = 1 if deflate else 0
+        opts.reuse_rhs = 1 if reuse_rhs else 0
         opts.rtol, opts.max_iter, opts.nu = float(rtol), int(max_iter), int(nu)
         opts.check_every, opts.inner_rtol = int(check_every), float(inner_rtol)
         opts.nu_coarse = int(nu_coarse)

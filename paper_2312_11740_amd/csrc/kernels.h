@@ -62,7 +62,6 @@ enum Epi {
   E_RZ,              // beta = total / rz (0 on the first iteration), rz = total
   E_PQ,              // alpha = rz / total; breakdown check
   E_RR_ITER,         // rr = total; ++iters; active = rr > tol2 && iters < max
-  E_ADD,             // scal[slot] += total
 };
 
 struct EpiArgs {
@@ -86,7 +85,6 @@ __device__ inline void finish(const Ctl& ctl, int b, double tot, const EpiArgs& 
   double* s = ctl.scal + (size_t)b * kSlots;
   switch (e.kind) {
     case E_STORE_MEAN: s[e.slot] = tot * e.inv_cells; break;
-    case E_ADD: s[e.slot] += tot; break;
     case E_MEAN: s[S_MEAN] = tot * e.inv_cells; break;
     case E_BB:
       s[S_BB] = tot;
@@ -699,6 +697,18 @@ __global__ void k_scale_down(const double* __restrict__ r, float* __restrict__ r
     acc += (double)v * (double)v;
   }
   block_partial(acc, ictl, pb);
+}
+
+// The right-hand side's mean and norm from another control block (one that assembled the
+// same right-hand side): S_MEAN, S_BB and S_TOL2 = rtol2 S_BB, as the assembly's epilogues
+__global__ void k_take_rhs(Ctl dst, const double* __restrict__ src_scal, int B, double rtol2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double* sc = src_scal + (size_t)b * kSlots;
+  double* d = dst.scal + (size_t)b * kSlots;
+  d[S_MEAN] = sc[S_MEAN];
+  d[S_BB] = sc[S_BB];
+  d[S_TOL2] = rtol2 * sc[S_BB];
 }
 
 // A control block back to its start: active flags, iteration counts, statuses and the

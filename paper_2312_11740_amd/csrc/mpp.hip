@@ -1202,7 +1202,7 @@ void mpp_default_opts(mpp_solve_opts* o) {
   o->check_every = 2;
   o->inner_rtol = 1e-5;
   o->deflate = 1;
-  o->reserved = 0;
+  o->reuse_rhs = 0;
 }
 
 size_t mpp_workspace_bytes(const mpp_desc* desc) {
@@ -1251,6 +1251,7 @@ bool opts_valid(const mpp_solve_opts& o) {
     return false;
   if (o.mode == MPP_MODE_MIXED && !(o.inner_rtol > 0.0 && o.inner_rtol < 1.0)) return false;
   if (o.deflate != 0 && o.deflate != 1) return false;
+  if (o.reuse_rhs != 0 && o.reuse_rhs != 1) return false;
   return true;
 }
 
@@ -1516,6 +1517,7 @@ int mpp_update_operator(mpp_op op, const double* phi, const double* rho_neg,
   if (!op || !phi) return MPP_EINVAL;
   std::vector<double> host;
   if (!read_params(op->batch, rho_neg, rho_pos, sigma, host)) return MPP_EINVAL;
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     return build_into(op, phi, host, reinterpret_cast<hipStream_t>(stream));
   } catch (HipError& e) {
@@ -1573,6 +1575,7 @@ void mpp_destroy_operator(mpp_op op) {
 int mpp_deflation_info(mpp_op op, uint8_t* labels, int32_t* k, double* E, void* stream) {
   if (!op || !k) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     if (!op->defl_ready) build_deflation(op, s);
     const int B = op->batch;
@@ -1611,6 +1614,7 @@ int mpp_levels(mpp_op op, int32_t* nlevels, int32_t* sizes) {
 int mpp_apply_stencil(mpp_op op, const double* x, double* y, void* stream) {
   if (!op || !x || !y || x == y) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     use_shift(op, 0.0, s);
     timed(op, K_APPLY, alg_bytes(op, K_APPLY, sizeof(double)), s, [&] {
@@ -1626,6 +1630,7 @@ int mpp_apply_stencil(mpp_op op, const double* x, double* y, void* stream) {
 int mpp_rhs(mpp_op op, const double* f, double* b, double* mean_out, void* stream) {
   if (!op || !f || !b) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     make_rhs(op, op->inner, f, b, s, 0.0, false);
     if (mean_out) {
@@ -1643,6 +1648,7 @@ int mpp_rhs(mpp_op op, const double* f, double* b, double* mean_out, void* strea
 int mpp_vcycle(mpp_op op, const double* r, double* z, int nu, void* stream) {
   if (!op || !r || !z || r == z || nu < 1) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     use_shift(op, 0.0, s);
     ensure_tuned<double>(op, s);
@@ -1676,6 +1682,10 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
   if (!op || !f || !p || !opts || !info || f == p) return MPP_EINVAL;
   if (!opts_valid(*opts)) return MPP_EINVAL;
   const mpp_solve_opts& o = *opts;
+  // the right-hand side of the learned guess just made for this f: b as it stands, the
+  // mean and norm from the inner control block
+  const bool reuse = o.reuse_rhs == 1 && op->guess_f == f;
+  op->guess_f = nullptr;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int B = op->batch;
   std::vector<int> outer_count(B, 0);
@@ -1684,7 +1694,13 @@ int mpp_solve(mpp_op op, const double* f, double* p, const mpp_solve_opts* opts,
     use_shift(op, 0.0, s);
     Ctl& oc = op->outer;
     reset_ctl(op, oc, o.max_iter, s);
-    make_rhs(op, oc, f, op->b, s, o.rtol, true);
+    if (reuse) {
+      hipLaunchKernelGGL(k_take_rhs, dim3((B + 255) / 256), dim3(256), 0, s, oc,
+                         (const double*)op->inner.scal, B, o.rtol * o.rtol);
+      ck_launch();
+    } else {
+      make_rhs(op, oc, f, op->b, s, o.rtol, true);
+    }
     solve_core(op, o, p, outer_count, istatus, s);
     remove_mean(op, oc, op->x, s);
     finish_solve(op, o.mode == MPP_MODE_MIXED, p, s);
@@ -1717,6 +1733,7 @@ int mpp_heat_solve(mpp_op op, const double* t_old, const double* src, double dt,
   // multigrid solves (A - I/dt) T = -(T_old + dt f) / dt; dt = 0 (T = T_old) goes to the
   // Jacobi form, which is exact there
   const bool mg = !jacobi && dt > 0.0;
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     Ctl& oc = op->outer;
     reset_ctl(op, oc, o.max_iter, s);
@@ -1804,6 +1821,7 @@ int mpp_net_features(mpp_net net, mpp_op op, const double* f, const double* p, u
                      float* t, float* rms, void* stream) {
   if (!net || !op || !f || !x || (t && !p) || !net_fits(op, net)) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     net_inputs(op, net, f, t ? p : nullptr, x, t, s);
     if (rms)
@@ -1822,6 +1840,7 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int B = op->batch, r = op->n / net->n;
   const Level& L0 = op->lev[0];
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     use_shift(op, 0.0, s);
     ensure_tuned<double>(op, s);
@@ -1918,18 +1937,22 @@ int mpp_learned_guess(mpp_op op, mpp_net net, const double* f, double* p, int32_
       hipLaunchKernelGGL(k_band_fix<double>, dim3(kDefBandBlocks, B), dim3(kDefThreads), 0, s,
                          op->b, cells, D, ctl, -1, 0, Sel{}, 0);
       ck_launch();
-      EpiArgs ea = epi(E_ADD);
-      ea.slot = S_BB;
+      EpiArgs ea = epi(E_STORE_MEAN);
+      ea.slot = S_BAND;
+      ea.inv_cells = 1.0;
       finish_sums(op, ctl, ea, kDefBandBlocks, s);
     }
     ck(hipMemcpyAsync(op->h_scal, ctl.scal, sizeof(double) * B * kSlots, hipMemcpyDeviceToHost, s));
     ck(hipStreamSynchronize(s));
     for (int q = 0; q < B; ++q) {
       const double* sc = op->h_scal + (size_t)q * kSlots;
-      const bool bad = !(std::isfinite(sc[S_RR]) && sc[S_RR] < sc[S_BB]);
+      // ||P b||^2 = ||b||^2 + the band's change on the deflated system
+      const double bb = dj ? sc[S_BB] + sc[S_BAND] : sc[S_BB];
+      const bool bad = !(std::isfinite(sc[S_RR]) && sc[S_RR] < bb);
       if (bad) ck(hipMemsetAsync(p + (size_t)q * L0.cells, 0, sizeof(double) * L0.cells, s));
       if (fell_back) fell_back[q] = bad ? 1 : 0;
     }
+    op->guess_f = f;   // b, S_MEAN and S_BB of the inner control block are f's
   } catch (HipError& e) {
     return status_of(e.e);
   }
@@ -2011,6 +2034,7 @@ int mpp_divergence(mpp_op op, const double* ux, const double* uy, const double* 
   if (!op || !ux || !uy || !uz || !f || !(dt > 0.0) || !std::isfinite(dt)) return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const Level& L0 = op->lev[0];
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     hipLaunchKernelGGL(k_divergence, grid_of(L0, op->batch), dim3(kBlock), 0, s, ux, uy, uz, op->n,
                        (int)L0.cells, dt, f);
@@ -2027,6 +2051,7 @@ int mpp_project(mpp_op op, const double* phi, const double* p, double dt, double
     return MPP_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const Level& L0 = op->lev[0];
+  op->guess_f = nullptr;   // the learned guess's right-hand side is no longer current
   try {
     hipLaunchKernelGGL(k_project, grid_of(L0, op->batch), dim3(kBlock), 0, s, phi, op->kappa, p,
                        op->rho, op->n, (int)L0.cells, dt, ux, uy, uz);

@@ -29,6 +29,7 @@ enum Slot {
   S_SUM,        // scratch sum (means)
   S_DT,         // heat diffusion: the time step (read by the kernels, so captured
                 //   iteration graphs stay valid for any dt)
+  S_BAND,       // learned guess: the band's change of ||b||^2 on the deflated system
   kSlots = 16
 };
 
@@ -248,4 +249,7 @@ struct mpp_op_s {
   double* h_scal = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // f of the last call on the operator when that was a learned guess (its right-hand side
+  // is then in b, its mean and norm in the inner control block), else nullptr
+  const double* guess_f = nullptr;
 };

@@ -81,6 +81,7 @@ def test_default_opts_and_strerror():
     o = M.SolveOpts()
     L.mpp_default_opts(ctypes.byref(o))
     assert o.rtol == 1e-10 and o.mode == M.MODE_FP64 and o.nu == 2
+    assert o.deflate == 1 and o.reuse_rhs == 0
     assert M.strerror(M.ENOTCONVERGED) == "not converged within max_iter"
 
 

@@ -498,3 +498,35 @@ def test_deflated_judge_keeps_the_guess_or_zero():
         assert O.rel_residual(d["faces"], d["b"], ph[b]) <= 1.05e-10
         po, _ = O.solve_mg_pcg(d["faces"], d["b"], tol=1e-13)
         assert rel2(ph[b], po) <= 1e-8
+
+
+def test_solve_reuses_the_guess_right_hand_side():
+    """mpp_solve_opts.reuse_rhs: a solve right after the learned guess on the same f takes
+    the right-hand side that guess assembled, with the same bits as assembling it again;
+    after any other call on the operator, or for another f, the solve assembles it."""
+    nf, nn = 64, 16
+    seeds = [41, 42]
+    phi, f, rn, rp, sg = problem_batch(nf, seeds)
+    op = M.Operator(to_dev(phi), rn, rp, sg)
+    net = make_net(nn, len(seeds), params_case(3))
+    fd = to_dev(f)
+    g, fell = op.learned_guess(net, fd, sweeps=2, judge="deflated")
+    g1, g2 = g.clone(), g.clone()
+    p1, i1 = op.solve(fd, g1, rtol=1e-10, mode="mixed", reuse_rhs=True)   # taken from the guess
+    p2, i2 = op.solve(fd, g2, rtol=1e-10, mode="mixed", reuse_rhs=True)   # assembled
+    assert torch.equal(p1, p2)
+    for a, b in zip(i1, i2):
+        assert (a.iters, a.removed_mean, a.bnorm, a.rel_resid) == \
+            (b.iters, b.removed_mean, b.bnorm, b.rel_resid)
+    # a guess for f, then a solve for another right-hand side: assembled from that one
+    f3 = fd * 0.5 + 1.0
+    op.learned_guess(net, fd, sweeps=2, judge="deflated")
+    p3, i3 = op.solve(f3, rtol=1e-10, mode="mixed", reuse_rhs=True)
+    p4, i4 = op.solve(f3, rtol=1e-10, mode="mixed")
+    assert torch.equal(p3, p4)
+    assert [a.removed_mean for a in i3] == [a.removed_mean for a in i4]
+    ph = to_host(p1)
+    for b in range(len(seeds)):
+        d = O.pipeline(phi[b], f[b], rn[b], rp[b], sg[b])
+        assert i1[b].status == M.OK
+        assert O.rel_residual(d["faces"], d["b"], ph[b]) <= 1.05e-10
