@@ -558,13 +558,15 @@ int mpp_net_features(mpp_net net, mpp_op op, const double *f, const double *p, u
  * operator's grid by trilinear interpolation of the cell values (clamped at the
  * walls), its mean removed, scaled by (p.b) / (p.Ap) (the multiple of the prediction
  * closest to the solution in the energy norm, so never farther than zero), then
- * `sweeps` (0..8) red-black Gauss-Seidel sweeps on A p = b.  The solver judges the
- * guess against a zero start as the solve will see them: judge MPP_JUDGE_PLAIN compares
- * ||b - A p|| with ||b|| (for a solve without deflation), MPP_JUDGE_DEFLATED compares
- * ||P (b - A p)|| with ||P b|| (for a deflated solve; P as in the deflation note above).
+ * `sweeps` (0..8) red-black Gauss-Seidel sweeps on A p = b in FP32 (p then holds FP32
+ * values).  The solver judges the guess against a zero start as the solve will see
+ * them: judge MPP_JUDGE_PLAIN compares ||b - A p|| with ||b|| (for a solve without
+ * deflation), MPP_JUDGE_DEFLATED compares ||P (b - A p)|| with ||P b|| (for a deflated
+ * solve; P as in the deflation note above); the residual is taken in FP32 arithmetic.
  * A problem whose guess is not finite or does not start below the zero start gets p = 0
  * instead and fell_back[b] = 1 (host int32 [batch], may be NULL).  p: device FP64
- * [batch][(r n)^3]. */
+ * [batch][(r n)^3].  The right-hand side assembled here can serve the next mpp_solve
+ * on the same f (mpp_solve_opts.reuse_rhs). */
 #define MPP_JUDGE_PLAIN 0
 #define MPP_JUDGE_DEFLATED 1
 int mpp_learned_guess(mpp_op op, mpp_net net, const double *f, double *p, int32_t sweeps,
