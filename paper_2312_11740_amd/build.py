@@ -47,6 +47,26 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+C_CONSUMER = os.path.join(ROOT, "tests", "c_abi", "solve_from_c")
+
+
+def build_c_consumer(verbose: bool = False) -> str:
+    """Compiles the plain C program of the ABI test (gcc, linked to libmpp.so and the HIP
+    runtime; libmpp.so found next to the package through the binary's rpath)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", INCLUDE, C_CONSUMER + ".c",
+           "-o", C_CONSUMER + ".tmp", "-L", HERE, "-lmpp", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", "-Wl,-rpath,$ORIGIN/../../paper_2312_11740_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(C_CONSUMER + ".tmp", C_CONSUMER)
+    return C_CONSUMER
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_c_consumer(verbose=True))
     sys.exit(0)
