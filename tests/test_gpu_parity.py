@@ -520,6 +520,31 @@ def test_solve_wide_batch_small_problems():
         check_solution(q.phi, q.f, q.rho_neg, q.rho_pos, q.sigma, ph[b], infos[b])
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_batch_above_1024_problems(mode):
+    """1100 problems of 16^3 with density ratios 2, 100 and 1000: the list of live
+    problems is built over more flags than one 1024-thread pass covers, and problems past
+    the first 1024 meet the oracle like the first ones."""
+    n, B = 16, 1100
+    cases = [bubbles_case(n, 900 + s, count=1 + s % 2, ratio=(2.0, 100.0, 1000.0)[s % 3])
+             for s in range(B)]
+    phi = to_dev(np.stack([c[0] for c in cases]))
+    f = to_dev(np.stack([c[1] for c in cases]))
+    op = M.Operator(phi, [c[2] for c in cases], [c[3] for c in cases], [c[4] for c in cases])
+    # a poll every iteration and no deflation: the live count falls below 512 while
+    # problems still iterate (iteration counts spread with the density ratio)
+    p, infos = op.solve(f, rtol=1e-10, mode=mode, check_every=1, deflate=False)
+    ph = to_host(p)
+    its = [i.iters for i in infos]
+    print(mode, "iterations min %d max %d" % (min(its), max(its)), flush=True)
+    assert all(i.status == M.OK and i.rel_resid <= 1e-10 for i in infos)
+    # at least B - 1024 problems done before the last iteration: that one ran on a list
+    assert sum(i < max(its) for i in its) >= B - 1024
+    for b in (0, 1, 1023, 1024, 1025, 1099):
+        check_solution(*cases[b], ph[b], infos[b])
+    op.close()
+
+
 def test_mixed_batch_one_problem_out_of_budget_others_converge():
     """Residual refinement stops per problem: in a batch where one problem (20 bubbles at
     density ratio 1000) runs out of the inner iteration budget, the other (one phase) still
