@@ -404,8 +404,12 @@ int launch_rb(const mpp_op_s* op, int l, int kz, const Faces<T>& F, const T* rhs
       if (n % 2 == 0) {
         const RbTiles tl = pr_tiles(n, -kz);
         const dim3 grid(rb_grid(tl), B);
-        hipLaunchKernelGGL((k_rb_pair<T, MODE>), grid, dim3(kPrThreads), 0, s, F, n, tl, rhs,
-                           in, ec, out, c1, ctl, dot, sel);
+        if (F.sig != T(0))
+          hipLaunchKernelGGL((k_rb_pair<T, MODE, true>), grid, dim3(kPrThreads), 0, s, F, n, tl,
+                             rhs, in, ec, out, c1, ctl, dot, sel);
+        else
+          hipLaunchKernelGGL((k_rb_pair<T, MODE, false>), grid, dim3(kPrThreads), 0, s, F, n, tl,
+                             rhs, in, ec, out, c1, ctl, dot, sel);
         return (int)grid.x;
       }
     }

@@ -89,7 +89,9 @@ struct PrWaves {
 };
 
 
-template <typename T, int MODE>
+// SH: the operator carries a diagonal shift (F.sig != 0); a compile-time switch, so that
+// the unshifted sweep carries no branch on it
+template <typename T, int MODE, bool SH>
 __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     k_rb_pair(Faces<T> F, int n, RbTiles tl, const T* __restrict__ rhs, const T* __restrict__ xin,
               const T* __restrict__ ec, T* __restrict__ xout, int c1, Ctl ctl, int dot,
@@ -128,12 +130,15 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   const T hr0 = h2 / ir0, hr1 = h2 / ir1;
   // diagonal shift times h^2; with a shift every cell takes the coded update
   const T sh2 = F.sig * h2;
-  const bool shifted = sh2 != T(0);
   // shifted operator, cell without a crossed face: x = (sum - hr b) / (faces + sig hr)
   const T shr0 = F.sig * hr0, shr1 = F.sig * hr1;
   const T inv6 = T(1) / T(6), inv5 = T(1) / T(5), inv4 = T(1) / T(4), inv3 = T(1) / T(3);
-  auto inv_of = [&](int walls) {
-    return walls <= 0 ? inv6 : (walls == 1 ? inv5 : (walls == 2 ? inv4 : inv3));
+  auto inv_of = [&](int walls) {   // selects, no branches
+    T r = inv3;
+    r = walls == 2 ? inv4 : r;
+    r = walls == 1 ? inv5 : r;
+    r = walls <= 0 ? inv6 : r;
+    return r;
   };
   const V vzero = {T(0), T(0)};
 
@@ -205,7 +210,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   const char* eb = reinterpret_cast<const char*>(ec + basec);
   auto issue_x = [&](int Lx, bool live, XLoad& d) {   // x_in of plane Lx at xq
     if (MODE == 1) return;
-    const bool pl = live && Lx >= 0 && Lx < n;
+    const bool pl = live && (unsigned)Lx < (unsigned)n;
     const auto rx = plane_rsrc(xq, pl ? plane_bytes : 0u);
     d.a = buf_ld_pair<T>(rx, own_b);
     if (w < 5) d.r = buf_ld_pair<T>(rx, xr_b);
@@ -234,7 +239,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     }
   };
   auto issue_b = [&](int Lb, bool live, BLoad& d) {   // b and codes of plane Lb at bq, cq
-    const bool pl = live && Lb >= 0 && Lb < n;
+    const bool pl = live && (unsigned)Lb < (unsigned)n;
     const auto rbr = plane_rsrc(bq, pl ? plane_bytes : 0u);
     const auto rcr = plane_rsrc(cq, pl ? code_bytes : 0u);
     d.bo = buf_ld_pair<T>(rbr, own_b);
@@ -273,7 +278,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const T sum = ((xw + xe) + (xs + xn)) + (xd + xu);
     const T hr = (cd & 64u) ? hr1 : hr0;
     T v;
-    if (shifted) {
+    if (SH) {
       // the face count from the reciprocal the caller passes (1/6, 1/5, 1/4 or 1/3)
       const T cnt = inv == inv6 ? T(6) : (inv == inv5 ? T(5) : (inv == inv4 ? T(4) : T(3)));
       v = (sum - hr * bb) / (cnt + ((cd & 64u) ? shr1 : shr0));
@@ -332,7 +337,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     lds_barrier();
 
     // ---- c1 values of plane L: the wave's row, then the ring ----
-    const bool pl = L >= 0 && L < n;
+    const bool pl = (unsigned)L < (unsigned)n;
     const bool zwL = L == 0 || L == n - 1;
     {
       const int o = (c1 + j + L) & 1;   // wave-uniform: which cell of the pair
@@ -408,7 +413,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     // ---- c2 values of plane L - 1 and the output pair; the store is issued in every
     //      step and dropped outside the chunk and the domain ----
     const int k = L - 1;
-    const bool kin = k >= k0 && k < k1;
+    const bool kin = (unsigned)(k - k0) < (unsigned)(k1 - k0);
     {
       const int o2 = ((c1 + j + k) & 1) ^ 1;   // wave-uniform: the c2 cell of the pair
       const bool zwk = k == 0 || k == n - 1;
