@@ -326,7 +326,15 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   bq += plane_bytes;
   cq += code_bytes;
 
-  for (int L = k0 - 1; L <= k1; ++L) {
+  // colour parity of the wave's rows on plane L (flips every step) and the LDS element
+  // offsets that depend on it, relative to the lane's own x and c1 positions
+  int o = (c1 + j + k0 - 1) & 1;
+  const int rowx = (w + 2) * XP + p + 1, rowc = (w + 1) * XP + p + 1;
+  for (int L = k0 - 1; L <= k1; ++L, o ^= 1) {
+    const int x_own = o ? XPL : 0;               // own parity, same pair
+    const int x_oth = o ? 0 : XPL - 1;           // other parity, west neighbour's pair
+    const int c_own = o ? CPL : 0;
+    const int c_oth = o ? 1 : CPL - 1;           // other parity, the x neighbour not in the pair
     commit_x(xp, xl);   // x_in of plane L + 1
     const BLoad cur = bn;
     issue_x(L + 2, L < k1, xl);
@@ -340,24 +348,24 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const bool pl = (unsigned)L < (unsigned)n;
     const bool zwL = L == 0 || L == n - 1;
     {
-      const int o = (c1 + j + L) & 1;   // wave-uniform: which cell of the pair
+      // o: wave-uniform, which cell of the pair
       T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
       if (MODE != 1) {
-        const T* xo = sx + xl0 + (1 - o) * XPL + (w + 2) * XP + p + o;   // other parity, west
+        const T* xo = sx + xl0 + x_oth + rowx;   // other parity, west
         xw = xo[0];
         xe = xo[1];
-        const T* xs0 = sx + xl0 + o * XPL + (w + 2) * XP + p + 1;
+        const T* xs0 = sx + xl0 + x_own + rowx;
         xs = xs0[-XP];
         xn = xs0[XP];
-        xd = sx[xm + o * XPL + (w + 2) * XP + p + 1];
-        xu = sx[xp + o * XPL + (w + 2) * XP + p + 1];
+        xd = sx[xm + x_own + rowx];
+        xu = sx[xp + x_own + rowx];
       }
       const T inv = o ? (zwL ? iz1 : in1) : (zwL ? iz0 : in0);
       const T bb = o ? cur.bo.y : cur.bo.x;
       const unsigned cd = (cur.co >> (8 * o)) & 255u;
       T v = relax(cd, pbL, own_off + o, i + o, j, L, inv, xw, xe, xs, xn, xd, xu, bb);
       v = pl && col_ok && j < n ? v : T(0);
-      sc[cl0 + o * CPL + (w + 1) * XP + p + 1] = v;
+      sc[cl0 + c_own + rowc] = v;
       c1own = v;
     }
     if (w >= 5) {
@@ -415,20 +423,19 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const int k = L - 1;
     const bool kin = (unsigned)(k - k0) < (unsigned)(k1 - k0);
     {
-      const int o2 = ((c1 + j + k) & 1) ^ 1;   // wave-uniform: the c2 cell of the pair
+      const int o2 = o;   // wave-uniform: the c2 cell of the pair on plane k = L - 1
       const bool zwk = k == 0 || k == n - 1;
       // slot(k) = cm, slot(k - 1) = cp, slot(k + 1) = cl0
-      const T* cl = sc + cm + o2 * CPL + (w + 1) * XP + p + 1;
+      const T* cl = sc + cm + c_own + rowc;
       // the c1 neighbour along x that is not the lane's own c1 cell
-      const T xo = sc[cm + (1 - o2) * CPL + (w + 1) * XP + p + 2 * o2];
+      const T xo = sc[cm + c_oth + rowc];
       const T xw = o2 ? c1prev : xo;
       const T xe = o2 ? xo : c1prev;
       const T inv = o2 ? (zwk ? iz1 : in1) : (zwk ? iz0 : in0);
       const T bb = o2 ? bprev.y : bprev.x;
       const unsigned cd = kin ? (cprev >> (8 * o2)) & 255u : 0u;
       const T v2 = relax(cd, pbL - nn, own_off + o2, i + o2, j, k, inv, xw, xe, cl[-XP], cl[XP],
-                         sc[cp + o2 * CPL + (w + 1) * XP + p + 1],
-                         sc[cl0 + o2 * CPL + (w + 1) * XP + p + 1], bb);
+                         sc[cp + c_own + rowc], sc[cl0 + c_own + rowc], bb);
       V out;
       out.x = o2 ? c1prev : v2;
       out.y = o2 ? v2 : c1prev;
