@@ -244,14 +244,16 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const auto rcr = plane_rsrc(cq, pl ? code_bytes : 0u);
     d.bo = buf_ld_pair<T>(rbr, own_b);
     d.co = __builtin_amdgcn_raw_buffer_load_b16(rcr, own_b / TS, 0, 0);
-    if (w == 5 || w == 6) {
-      d.br = buf_ld_pair<T>(rbr, rb0);
-      d.cr0 = __builtin_amdgcn_raw_buffer_load_b16(rcr, rb0 / TS, 0, 0);
-    } else if (w == 7) {
-      d.br.x = buf_ld<T>(rbr, rb0);
-      d.br.y = buf_ld<T>(rbr, rb1);
-      d.cr0 = __builtin_amdgcn_raw_buffer_load_b8(rcr, rb0 / TS, 0, 0);
-      d.cr1 = __builtin_amdgcn_raw_buffer_load_b8(rcr, rb1 / TS, 0, 0);
+    if (w >= 5) {   // one test for the waves without ring work
+      if (w < 7) {
+        d.br = buf_ld_pair<T>(rbr, rb0);
+        d.cr0 = __builtin_amdgcn_raw_buffer_load_b16(rcr, rb0 / TS, 0, 0);
+      } else {
+        d.br.x = buf_ld<T>(rbr, rb0);
+        d.br.y = buf_ld<T>(rbr, rb1);
+        d.cr0 = __builtin_amdgcn_raw_buffer_load_b8(rcr, rb0 / TS, 0, 0);
+        d.cr1 = __builtin_amdgcn_raw_buffer_load_b8(rcr, rb1 / TS, 0, 0);
+      }
     }
   };
 
@@ -346,7 +348,9 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
 
     // ---- c1 values of plane L: the wave's row, then the ring ----
     const bool pl = (unsigned)L < (unsigned)n;
-    const bool zwL = L == 0 || L == n - 1;
+    // plane L at a z wall: L == 0 or n - 1 (planes outside the domain also test true;
+    // their values are zeroed)
+    const bool zwL = (unsigned)(L - 1) >= (unsigned)(n - 2);
     {
       // o: wave-uniform, which cell of the pair
       T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
@@ -424,7 +428,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const bool kin = (unsigned)(k - k0) < (unsigned)(k1 - k0);
     {
       const int o2 = o;   // wave-uniform: the c2 cell of the pair on plane k = L - 1
-      const bool zwk = k == 0 || k == n - 1;
+      const bool zwk = (unsigned)(k - 1) >= (unsigned)(n - 2);   // as zwL (k outside: dropped)
       // slot(k) = cm, slot(k - 1) = cp, slot(k + 1) = cl0
       const T* cl = sc + cm + c_own + rowc;
       // the c1 neighbour along x that is not the lane's own c1 cell
