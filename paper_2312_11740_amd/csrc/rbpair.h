@@ -221,9 +221,8 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
       if (w < 5) d.er = buf_ld<T>(re, xr_eb);
     }
   };
-  auto commit_x = [&](int xs, const XLoad& d) {   // into the x_in slot at element xs
+  auto commit_x = [&](T* dst, const XLoad& d) {   // into the x_in slot at dst
     if (MODE == 1) return;
-    T* dst = sx + xs;
     V a = d.a, r = d.r;
     if (MODE == 2) {
       a.x += d.ea;
@@ -307,8 +306,13 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   T c1own = T(0), c1prev = T(0);
   double acc = 0.0;
   // LDS slots (element offsets) of planes L - 1, L, L + 1 for the first step L = k0 - 1
-  int xm = ((k0 + 1) % 3) * XSL, xl0 = ((k0 + 2) % 3) * XSL, xp = (k0 % 3) * XSL;
-  int cm = ((k0 + 1) % 3) * CSL, cl0 = ((k0 + 2) % 3) * CSL, cp = (k0 % 3) * CSL;
+  // (as LDS pointers, rotated every step)
+  T* xm = sx + ((k0 + 1) % 3) * XSL;
+  T* xl0 = sx + ((k0 + 2) % 3) * XSL;
+  T* xp = sx + (k0 % 3) * XSL;
+  T* cm = sc + ((k0 + 1) % 3) * CSL;
+  T* cl0 = sc + ((k0 + 2) % 3) * CSL;
+  T* cp = sc + (k0 % 3) * CSL;
   size_t pbL = base + (size_t)(k0 - 1) * nn;   // index of plane L's first cell
 
   // prologue: x_in of planes k0 - 2 and k0 - 1 into LDS, x_in of k0 and b of k0 - 1 in
@@ -355,21 +359,21 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
       // o: wave-uniform, which cell of the pair
       T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
       if (MODE != 1) {
-        const T* xo = sx + xl0 + x_oth + rowx;   // other parity, west
+        const T* xo = xl0 + x_oth + rowx;   // other parity, west
         xw = xo[0];
         xe = xo[1];
-        const T* xs0 = sx + xl0 + x_own + rowx;
+        const T* xs0 = xl0 + x_own + rowx;
         xs = xs0[-XP];
         xn = xs0[XP];
-        xd = sx[xm + x_own + rowx];
-        xu = sx[xp + x_own + rowx];
+        xd = xm[x_own + rowx];
+        xu = xp[x_own + rowx];
       }
       const T inv = o ? (zwL ? iz1 : in1) : (zwL ? iz0 : in0);
       const T bb = o ? cur.bo.y : cur.bo.x;
       const unsigned cd = (cur.co >> (8 * o)) & 255u;
       T v = relax(cd, pbL, own_off + o, i + o, j, L, inv, xw, xe, xs, xn, xd, xu, bb);
       v = pl && col_ok && j < n ? v : T(0);
-      sc[cl0 + c_own + rowc] = v;
+      cl0[c_own + rowc] = v;
       c1own = v;
     }
     if (w >= 5) {
@@ -405,20 +409,20 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
       T xw = T(0), xe = T(0), xs = T(0), xn = T(0), xd = T(0), xu = T(0);
       if (MODE != 1 && (w < 7 || p < TY)) {
         // west and east: the other parity, pairs pr - 1 + par and pr + par
-        const T* xo = sx + xl0 + (1 - par) * XPL + xr * XP + pr - 1 + par;
+        const T* xo = xl0 + (1 - par) * XPL + xr * XP + pr - 1 + par;
         xw = xo[0];
         xe = xo[1];
-        const T* xs0 = sx + xl0 + par * XPL + xr * XP + pr;
+        const T* xs0 = xl0 + par * XPL + xr * XP + pr;
         xs = xs0[-XP];
         xn = xs0[XP];
-        xd = sx[xm + par * XPL + xr * XP + pr];
-        xu = sx[xp + par * XPL + xr * XP + pr];
+        xd = xm[par * XPL + xr * XP + pr];
+        xu = xp[par * XPL + xr * XP + pr];
       }
       const int walls = (ic == 0) + (ic == n - 1) + (jc == 0) + (jc == n - 1) + zwL;
       T v = relax(ok ? cd : 0u, pbL, (unsigned)(ic + n * jc), ic, jc, L, inv_of(walls), xw, xe, xs,
                   xn, xd, xu, bb);
       v = pl && ok ? v : T(0);
-      if (w < 7 || p < TY) sc[cl0 + par * CPL + cr * XP + pr] = v;
+      if (w < 7 || p < TY) cl0[par * CPL + cr * XP + pr] = v;
     }
     lds_barrier();
 
@@ -430,16 +434,16 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
       const int o2 = o;   // wave-uniform: the c2 cell of the pair on plane k = L - 1
       const bool zwk = (unsigned)(k - 1) >= (unsigned)(n - 2);   // as zwL (k outside: dropped)
       // slot(k) = cm, slot(k - 1) = cp, slot(k + 1) = cl0
-      const T* cl = sc + cm + c_own + rowc;
+      const T* cl = cm + c_own + rowc;
       // the c1 neighbour along x that is not the lane's own c1 cell
-      const T xo = sc[cm + c_oth + rowc];
+      const T xo = cm[c_oth + rowc];
       const T xw = o2 ? c1prev : xo;
       const T xe = o2 ? xo : c1prev;
       const T inv = o2 ? (zwk ? iz1 : in1) : (zwk ? iz0 : in0);
       const T bb = o2 ? bprev.y : bprev.x;
       const unsigned cd = kin ? (cprev >> (8 * o2)) & 255u : 0u;
       const T v2 = relax(cd, pbL - nn, own_off + o2, i + o2, j, k, inv, xw, xe, cl[-XP], cl[XP],
-                         sc[cp + c_own + rowc], sc[cl0 + c_own + rowc], bb);
+                         cp[c_own + rowc], cl0[c_own + rowc], bb);
       V out;
       out.x = o2 ? c1prev : v2;
       out.y = o2 ? v2 : c1prev;
@@ -453,7 +457,8 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     oq += plane_bytes;
     pbL += nn;
     // rotate: L - 1 <- L, L <- L + 1, L + 1 <- L + 2
-    const int tx = xm, tc = cm;
+    T* const tx = xm;
+    T* const tc = cm;
     xm = xl0;
     xl0 = xp;
     xp = tx;
