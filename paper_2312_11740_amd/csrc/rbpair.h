@@ -208,9 +208,9 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   const char* cq = reinterpret_cast<const char*>(F.code + base) + (ptrdiff_t)(k0 - 1) * code_bytes;
   char* oq = reinterpret_cast<char*>(xout + base) + (ptrdiff_t)(k0 - 2) * plane_bytes;
   const char* eb = reinterpret_cast<const char*>(ec + basec);
-  auto issue_x = [&](int Lx, bool live, XLoad& d) {   // x_in of plane Lx at xq
+  // pl: plane Lx is inside the domain and needed (the callers test both at once)
+  auto issue_x = [&](int Lx, bool pl, XLoad& d) {   // x_in of plane Lx at xq
     if (MODE == 1) return;
-    const bool pl = live && (unsigned)Lx < (unsigned)n;
     const auto rx = plane_rsrc(xq, pl ? plane_bytes : 0u);
     d.a = buf_ld_pair<T>(rx, own_b);
     if (w < 5) d.r = buf_ld_pair<T>(rx, xr_b);
@@ -237,8 +237,7 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
       dst[XPL + xr_row * XP + xr_pair] = r.y;
     }
   };
-  auto issue_b = [&](int Lb, bool live, BLoad& d) {   // b and codes of plane Lb at bq, cq
-    const bool pl = live && (unsigned)Lb < (unsigned)n;
+  auto issue_b = [&](int Lb, bool pl, BLoad& d) {   // b and codes of plane Lb at bq, cq
     const auto rbr = plane_rsrc(bq, pl ? plane_bytes : 0u);
     const auto rcr = plane_rsrc(cq, pl ? code_bytes : 0u);
     d.bo = buf_ld_pair<T>(rbr, own_b);
@@ -319,19 +318,20 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
   // flight
   if (MODE != 1) {
     XLoad xa = xl, xc = xl;
-    issue_x(k0 - 2, true, xa);
+    issue_x(k0 - 2, (unsigned)(k0 - 2) < (unsigned)n, xa);
     xq += plane_bytes;
-    issue_x(k0 - 1, true, xc);
+    issue_x(k0 - 1, (unsigned)(k0 - 1) < (unsigned)n, xc);
     xq += plane_bytes;
     commit_x(xm, xa);
     commit_x(xl0, xc);
   }
-  issue_x(k0, true, xl);
+  issue_x(k0, k0 < n, xl);
   xq += plane_bytes;
-  issue_b(k0 - 1, true, bn);
+  issue_b(k0 - 1, (unsigned)(k0 - 1) < (unsigned)n, bn);
   bq += plane_bytes;
   cq += code_bytes;
 
+  const unsigned xlim = (unsigned)min(n, k1 + 2), blim = (unsigned)min(n, k1 + 1);
   // colour parity of the wave's rows on plane L (flips every step) and the LDS element
   // offsets that depend on it, relative to the lane's own x and c1 positions
   int o = (c1 + j + k0 - 1) & 1;
@@ -343,8 +343,9 @@ __global__ void __launch_bounds__(kPrThreads, PrWaves<T>::value)
     const int c_oth = o ? 1 : CPL - 1;           // other parity, the x neighbour not in the pair
     commit_x(xp, xl);   // x_in of plane L + 1
     const BLoad cur = bn;
-    issue_x(L + 2, L < k1, xl);
-    issue_b(L + 1, L < k1, bn);
+    // planes L + 2 and L + 1 while L < k1, inside the domain
+    issue_x(L + 2, (unsigned)(L + 2) < xlim, xl);
+    issue_b(L + 1, (unsigned)(L + 1) < blim, bn);
     xq += plane_bytes;
     bq += plane_bytes;
     cq += code_bytes;
